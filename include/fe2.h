@@ -1,0 +1,221 @@
+/*
+ * fe2.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of the monolithic FE^2 scheme of Hesch, Schmidt and Schuss, "Variational
+ * formulation and monolithic solution of computational homogenization
+ * methods" (arXiv:2312.12771).  Equation numbers follow the paper.
+ *
+ * For every macroscopic Gauss point b the library assembles the RVE attached
+ * to b (Sec. 3, Eqs. (34)-(35)), reduces it with the periodic null space
+ * (condition (iii) of Eq. (15)), solves the RVE system and condenses it to the
+ * homogenized stress and tangent that enter the macro Newton step of the
+ * generalized null-space scheme (Sec. 4.2, Eqs. (46)-(49)); the macro tangent
+ * is then assembled and solved in FP64 and the fluctuations are updated.
+ *
+ * Conventions (all entry points)
+ *   - Host arrays passed to fe2_setup are read during the call and copied;
+ *     the caller keeps ownership.
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller,
+ *     contiguous float64 unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on that stream and return without waiting, except
+ *     where a host scalar is returned (fe2_newton_step waits for its norms).
+ *   - Return values: FE2_OK (0) or FE2_CONVERGED (1) on success, a negative
+ *     fe2_status on failure.  No exception crosses the ABI.  A failed call
+ *     leaves the handle usable unless it returns FE2_ESTATE.  fe2_last_error()
+ *     gives a human-readable reason for the last failure of this thread.
+ *   - A handle is not thread-safe; use one handle per host thread.
+ *
+ * Numbering
+ *   - Macro DOFs are node-major: dof = node*dim + component.
+ *   - RVE b = element * 2^dim + g, Gauss points xi fastest (2 per direction).
+ *   - RVE fields use the periodic node numbering of an n1 x n2 (x n3) grid,
+ *     node (i,j,k) -> i + n1*(j + n2*k), DOF = node*dim + component; the
+ *     corner node 0 carries the pinned fluctuation (always 0 in outputs).
+ *     fe2_query(FE2_Q_FIELD_LEN) gives the total length over all RVEs and
+ *     FE2_Q_FIELD_OFFSETS the per-RVE offsets (in units of doubles).
+ *   - Macro kinematic components nF: small strain Voigt [11,22,12] (2D,
+ *     engineering shear) or [11,22,33,23,13,12] (3D); finite strain the
+ *     row-major deformation gradient [F11,F12,F21,F22].
+ */
+#ifndef FE2_H
+#define FE2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FE2_ABI_VERSION 1
+
+typedef enum fe2_status {
+  FE2_OK = 0,
+  FE2_CONVERGED = 1,   /* fe2_newton_step: residual below tolerance, no update made */
+  FE2_EINVAL = -1,     /* invalid argument or descriptor */
+  FE2_ENOMEM = -2,     /* device or host allocation failed */
+  FE2_EHIP = -3,       /* a HIP runtime call failed */
+  FE2_ENOCONV = -4,    /* an RVE solve missed its tolerance (see FE2_Q_FAILED_RVES) */
+  FE2_ESTATE = -5,     /* handle unusable (earlier fatal error) */
+  FE2_ENOTSUP = -6     /* combination not implemented */
+} fe2_status;
+
+enum { FE2_SMALL_STRAIN = 0, FE2_FINITE_STRAIN = 1 };
+enum { FE2_LINEAR_ISO = 0, FE2_NEO_HOOKE = 1, FE2_MOONEY_RIVLIN = 2 };
+enum { FE2_PREC_FP64 = 0, FE2_PREC_FP32_IR = 1 };
+enum { FE2_SOLVER_AUTO = 0, FE2_SOLVER_PCG_JACOBI = 1, FE2_SOLVER_PCG_FFT = 2 };
+enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
+
+/*
+ * Problem description (Sec. 2 and Sec. 5.2 problem statement: macro body,
+ * boundary data and loads, RVE with its phases and micro boundary condition,
+ * discretisation, tolerances).
+ *
+ *  struct_size      sizeof(fe2_problem_desc) (ABI check)
+ *  dim              2 (Q4, plane strain) or 3 (hex8)
+ *  kinematics       FE2_SMALL_STRAIN or FE2_FINITE_STRAIN (2D only)
+ *  material         FE2_LINEAR_ISO (small strain), FE2_NEO_HOOKE or
+ *                   FE2_MOONEY_RIVLIN (finite strain)
+ *  n_nodes, X       macro node coordinates [n_nodes][dim]
+ *  n_elems, conn    macro connectivity [n_elems][2^dim] (Q4 counter-clockwise;
+ *                   hex8 bottom face then top face)
+ *  n_dir, dir_dofs, dir_vals   prescribed DOFs (strictly increasing) and their
+ *                   values at load factor 1
+ *  f_ext            external nodal forces at load factor 1 [n_nodes*dim] or NULL
+ *  n_rve            number of RVEs = n_elems * 2^dim
+ *  rve_res          RVE resolutions [n_rve][dim], every entry >= 2
+ *  rve_off          offsets into phase_id [n_rve+1]
+ *  phase_id         phase (0 or 1) of every RVE element, lexicographic
+ *  n_phase_params   parameters per phase: 2 (lambda, mu) for FE2_LINEAR_ISO
+ *                   and FE2_NEO_HOOKE, 3 (alpha, beta, kappa) for
+ *                   FE2_MOONEY_RIVLIN (the law of Eq. (59))
+ *  phase_params     [n_rve][2][n_phase_params]
+ *  rve_size         side length of the cubic RVE cell (|Omega| = rve_size^dim)
+ *  precision        FE2_PREC_FP64 (plain FP64 RVE solves) or FE2_PREC_FP32_IR
+ *                   (FP32 PCG with FP64 residual refinement)
+ *  solver           FE2_SOLVER_AUTO, _PCG_JACOBI or _PCG_FFT
+ *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
+ *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
+ *                   solve must reach
+ *  inner_tol        relative tolerance of one FP32 PCG sweep (FP32_IR only)
+ *  newton_tol       macro convergence: ||[R_macro; R_micro]|| <= newton_tol *
+ *                   ||F_int||
+ *  micro_tol        classical scheme: inner RVE Newton stops when
+ *                   ||r_b|| <= micro_tol * max(1, ||r_b at entry||)
+ *  max_pcg_it, max_ir, max_micro_it   iteration caps
+ */
+typedef struct fe2_problem_desc {
+  int32_t struct_size;
+  int32_t dim, kinematics, material;
+  int32_t n_nodes;
+  const double* X;
+  int32_t n_elems;
+  const int32_t* conn;
+  int32_t n_dir;
+  const int32_t* dir_dofs;
+  const double* dir_vals;
+  const double* f_ext;
+  int32_t n_rve;
+  const int32_t* rve_res;
+  const int64_t* rve_off;
+  const uint8_t* phase_id;
+  int32_t n_phase_params;
+  const double* phase_params;
+  double rve_size;
+  int32_t precision, solver, scheme;
+  double rve_tol, inner_tol, newton_tol, micro_tol;
+  int32_t max_pcg_it, max_ir, max_micro_it;
+} fe2_problem_desc;
+
+typedef struct fe2_ctx* fe2_handle;
+
+/* Build a handle on the current HIP device: copies the description to HBM,
+ * builds the reference-element tables, the macro Gauss-point geometry and the
+ * RVE work lists on the device (Sec. 3, Eqs. (25)-(29): macro basis and the
+ * tensor-product fluctuation numbering), and zeroes the state (q = X, w~ = 0,
+ * load factor 0).  Errors: FE2_EINVAL for an inconsistent description,
+ * FE2_ENOTSUP for unsupported combinations, FE2_ENOMEM, FE2_EHIP. */
+int fe2_setup(const fe2_problem_desc* desc, void* stream, fe2_handle* out);
+
+/* Macro gradient at every Gauss point (Eq. (11): F_b = I + grad u, small
+ * strain eps_b = sym grad u) and RVE element integration at the current
+ * (q, w~): micro residual r_b (Eq. (35)) in the periodic numbering, the
+ * integral of the micro stress (Eq. (17)) and, for finite strain, the micro
+ * tangents used by the next solve.  Results stay in the handle
+ * (fe2_get_rve_data). */
+int fe2_assemble_rve(fe2_handle h, void* stream);
+
+/* Solve K_ww [X_F | x_r] = [K_wF | r_b] for every RVE (the RVE blocks of L in
+ * Eq. (42), reduced by the periodic null space) and condense (Eqs. (46)-(48)):
+ *   Cbar_b = (K_FF - K_wF^T X_F) / |Omega|,
+ *   Phat_b = (int P~ - K_wF^T x_r) / |Omega|.
+ * Uses the data of the last fe2_assemble_rve.  Outputs: Cbar_dev
+ * [n_rve][nF][nF], Phat_dev [n_rve][nF] (either may be NULL).  Returns
+ * FE2_ENOCONV when an RVE missed rve_tol (results are still written). */
+int fe2_condense(fe2_handle h, double* Cbar_dev, double* Phat_dev, void* stream);
+
+/* One macro Newton iteration at target load factor `load_factor`
+ * (generalized scheme: Eqs. (46)-(49); classical: Eqs. (43)-(45) with inner
+ * RVE equilibration first).  Steps: macro gradients, RVE integration,
+ * residual norms; if the handle's load factor already equals load_factor and
+ * the norm satisfies newton_tol the call returns FE2_CONVERGED without an
+ * update; otherwise RVE solves and condensation, FP64 macro assembly with the
+ * prescribed increment (load_factor - current) * dir_vals, FP64 banded
+ * Cholesky solve, update of q and w~ (dw_b = -(x_r + X_F dF_b)).
+ * norms_host (may be NULL) receives 4 doubles describing the state the call
+ * started from: ||[R_macro(free); R_micro]||, ||R_macro(free)||,
+ * ||R_micro||, ||F_int|| (R_micro,b = eta_b J_b / |Omega| r_b).  Waits for
+ * the norms on `stream`. */
+int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* stream);
+
+/* Copy the state: u_dev [n_nodes*dim] macro displacement q - X; w_dev
+ * [FE2_Q_FIELD_LEN] fluctuations (either may be NULL). */
+int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream);
+
+/* Overwrite the state (either pointer may be NULL = keep) and set the load
+ * factor the prescribed values currently satisfy. */
+int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev,
+                  double load_factor, void* stream);
+
+/* Intermediate results of the last assembly / condensation / step, copied to
+ * caller memory:
+ *   FE2_D_MACRO_GRAD  [n_rve][nF]        eps_b or F_b (a2)
+ *   FE2_D_RESIDUAL    [FIELD_LEN]        r_b, periodic numbering (a3/a4)
+ *   FE2_D_PBAR        [n_rve][nF]        int P~ / |Omega|
+ *   FE2_D_SOLUTION    [FIELD_LEN*(nF+1)] per RVE nF+1 consecutive fields:
+ *                                        X_F columns then x_r (a5)
+ *   FE2_D_RVE_ITERS   [n_rve] (as double) PCG iterations of the last solve
+ *   FE2_D_RVE_RELRES  [n_rve]            final relative FP64 residual
+ *   FE2_D_MACRO_RHS   [n_nodes*dim]      condensed right-hand side
+ *                                        sum G^T Phat - lambda f_ext (a7)
+ *   FE2_D_MACRO_RTRUE [n_nodes*dim]      true residual sum G^T Pbar - lambda f_ext
+ *   FE2_D_MACRO_DU    [n_nodes*dim]      last macro increment (a8)
+ *   FE2_D_MACRO_KDENSE [ndof*ndof]       assembled macro tangent before
+ *                                        Dirichlet elimination, dense (only
+ *                                        when ndof <= 4096)
+ *   FE2_D_CBAR, FE2_D_PHAT               as written by fe2_condense */
+enum {
+  FE2_D_MACRO_GRAD = 0, FE2_D_RESIDUAL = 1, FE2_D_PBAR = 2, FE2_D_SOLUTION = 3,
+  FE2_D_RVE_ITERS = 4, FE2_D_RVE_RELRES = 5, FE2_D_MACRO_RHS = 6,
+  FE2_D_MACRO_RTRUE = 7, FE2_D_MACRO_DU = 8, FE2_D_MACRO_KDENSE = 9,
+  FE2_D_CBAR = 10, FE2_D_PHAT = 11
+};
+int fe2_get_data(fe2_handle h, int which, double* dst_dev, void* stream);
+
+/* Integer properties of a handle. */
+enum {
+  FE2_Q_NF = 0, FE2_Q_FIELD_LEN = 1, FE2_Q_NDOF = 2, FE2_Q_BANDWIDTH = 3,
+  FE2_Q_FAILED_RVES = 4, FE2_Q_N_RVE = 5, FE2_Q_FIELD_OFFSETS = 6 /* into int64 out[n_rve+1] */
+};
+int fe2_query(fe2_handle h, int which, int64_t* out);
+
+/* Release all device memory of the handle (waits for its work). */
+int fe2_destroy(fe2_handle h);
+
+const char* fe2_strerror(int status);
+const char* fe2_last_error(void);
+int fe2_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE2_H */

@@ -1,0 +1,676 @@
+// C ABI of libfe2 (see include/fe2.h): handle management, setup and the
+// per-step orchestration of the RVE and macro kernels on a HIP stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "macro.hpp"
+
+namespace fe2 {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return FE2_OK;
+  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    return FE2_ENOMEM;
+  }
+  return FE2_OK;
+}
+
+template <typename T>
+int upload(T** p, const T* src, size_t n, hipStream_t s) {
+  int rc = dalloc(p, n);
+  if (rc) return rc;
+  if (n) FE2_HIP_CHECK(hipMemcpyAsync(*p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  return FE2_OK;
+}
+
+inline unsigned nblk(size_t n, unsigned bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+struct RveClass {
+  int n1 = 0, n2 = 0;
+  double rho = 0.0;
+  std::vector<int> rves;
+  int* d_list = nullptr;
+  double* d_tab = nullptr;   // kv[10] | KwF[24] | KFF[9] | err
+};
+
+}  // namespace
+}  // namespace fe2
+
+using namespace fe2;
+
+struct fe2_ctx {
+  // description
+  int dim = 0, kin = 0, mat = 0, nF = 0, nen = 0, n_gp = 0;
+  int n_nodes = 0, n_elems = 0, n_rve = 0, ndof = 0, bw = 0, nnz = 0, n_pp = 0;
+  int precision = 0, solver = 0, scheme = 0;
+  double rve_size = 1.0, volume = 1.0;
+  double rve_tol = 1e-10, inner_tol = 1e-4, newton_tol = 1e-10, micro_tol = 1e-13;
+  int max_pcg_it = 2000, max_ir = 8, max_micro_it = 30;
+  bool broken = false;
+  // macro
+  int *conn = nullptr, *is_dir = nullptr, *vec_ptr = nullptr, *vec_src = nullptr;
+  int *nz_ptr = nullptr, *nz_col = nullptr, *nzc_ptr = nullptr, *nzc_src = nullptr;
+  double *X = nullptr, *dNdX = nullptr, *wdet = nullptr, *f_ext = nullptr, *dir_full = nullptr;
+  // RVE batch
+  int64_t* phase_off = nullptr;
+  uint8_t* phase = nullptr;
+  double* params = nullptr;
+  int64_t* foff = nullptr;
+  std::vector<int64_t> h_foff;
+  int64_t field_len = 0;
+  std::vector<RveClass> classes;
+  // state and results
+  double lam = 0.0;
+  double *u = nullptr, *w = nullptr, *r = nullptr, *Xs = nullptr;
+  double *Cbar = nullptr, *Phat = nullptr, *Pbar = nullptr, *mgrad = nullptr, *rnorm2 = nullptr;
+  double *relres = nullptr, *iters = nullptr;
+  int* fail_count = nullptr;
+  int* info = nullptr;
+  double *f_true = nullptr, *f_hat = nullptr, *ke = nullptr, *band = nullptr, *rhs = nullptr;
+  double *du = nullptr, *r_true = nullptr, *f_int = nullptr, *norms_dev = nullptr, *kdense = nullptr;
+  double* norms_host = nullptr;   // pinned [4]
+  int* flag_host = nullptr;       // pinned [2]
+  int last_failed = 0;
+
+  MacroArgs margs() const {
+    MacroArgs m{};
+    m.n_rve = n_rve;
+    m.dim = dim;
+    m.nen = nen;
+    m.n_gp = n_gp;
+    m.nF = nF;
+    m.kin = kin;
+    m.n_elems = n_elems;
+    m.ndof = ndof;
+    m.bw = bw;
+    m.conn = conn;
+    m.X = X;
+    m.dNdX = dNdX;
+    m.wdet = wdet;
+    m.f_ext = f_ext;
+    m.is_dir = is_dir;
+    m.dir_full = dir_full;
+    m.vec_ptr = vec_ptr;
+    m.vec_src = vec_src;
+    m.nz_ptr = nz_ptr;
+    m.nz_col = nz_col;
+    m.nzc_ptr = nzc_ptr;
+    m.nzc_src = nzc_src;
+    return m;
+  }
+
+  Lin2DArgs largs(const RveClass& c, int flags) const {
+    Lin2DArgs a{};
+    a.n1 = c.n1;
+    a.n2 = c.n2;
+    a.rve_list = c.d_list;
+    a.phase_off = phase_off;
+    a.phase = phase;
+    a.params = params;
+    a.kv64 = c.d_tab;
+    a.KwF64 = c.d_tab + 10;
+    a.KFF64 = c.d_tab + 34;
+    a.macro = mgrad;
+    a.foff = foff;
+    a.w = w;
+    a.r = r;
+    a.X = Xs;
+    a.Cbar = Cbar;
+    a.Phat = Phat;
+    a.Pbar = Pbar;
+    a.rnorm2 = rnorm2;
+    a.relres = relres;
+    a.iters = iters;
+    a.fail_count = fail_count;
+    a.fft_tab = nullptr;
+    a.volume = volume;
+    a.tol = rve_tol;
+    a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : inner_tol;
+    a.max_it = max_pcg_it;
+    a.max_ir = max_ir;
+    a.flags = flags;
+    return a;
+  }
+};
+
+namespace {
+
+void free_ctx(fe2_ctx* h) {
+  if (!h) return;
+  void* ptrs[] = {h->conn, h->is_dir, h->vec_ptr, h->vec_src, h->nz_ptr, h->nz_col, h->nzc_ptr,
+                  h->nzc_src, h->X, h->dNdX, h->wdet, h->f_ext, h->dir_full, h->phase_off,
+                  h->phase, h->params, h->foff, h->u, h->w, h->r, h->Xs, h->Cbar, h->Phat,
+                  h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
+                  h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
+                  h->norms_dev, h->kdense};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& c : h->classes) {
+    if (c.d_list) (void)hipFree(c.d_list);
+    if (c.d_tab) (void)hipFree(c.d_tab);
+  }
+  if (h->norms_host) (void)hipHostFree(h->norms_host);
+  if (h->flag_host) (void)hipHostFree(h->flag_host);
+  delete h;
+}
+
+int validate(const fe2_problem_desc* d) {
+  if (!d) return set_error("null descriptor"), FE2_EINVAL;
+  if (d->struct_size != static_cast<int32_t>(sizeof(fe2_problem_desc)))
+    return set_error("struct_size does not match this library's fe2_problem_desc"), FE2_EINVAL;
+  if (d->dim != 2 && d->dim != 3) return set_error("dim must be 2 or 3"), FE2_EINVAL;
+  if (d->n_nodes <= 0 || d->n_elems <= 0 || !d->X || !d->conn)
+    return set_error("empty macro mesh"), FE2_EINVAL;
+  const int ngp = d->dim == 2 ? 4 : 8;
+  if (d->n_rve != d->n_elems * ngp) return set_error("n_rve must equal n_elems * 2^dim"), FE2_EINVAL;
+  if (!d->rve_res || !d->rve_off || !d->phase_id || !d->phase_params)
+    return set_error("missing RVE arrays"), FE2_EINVAL;
+  if (d->n_dir < 0 || (d->n_dir > 0 && (!d->dir_dofs || !d->dir_vals)))
+    return set_error("bad Dirichlet arrays"), FE2_EINVAL;
+  if (!(d->rve_size > 0.0)) return set_error("rve_size must be positive"), FE2_EINVAL;
+  if (d->precision != FE2_PREC_FP64 && d->precision != FE2_PREC_FP32_IR)
+    return set_error("unknown precision"), FE2_EINVAL;
+  if (!(d->rve_tol > 0.0) || !(d->newton_tol >= 0.0)) return set_error("tolerances must be positive"), FE2_EINVAL;
+  if (d->max_pcg_it <= 0 || d->max_ir < 0) return set_error("iteration caps must be positive"), FE2_EINVAL;
+  for (int k = 0; k < d->n_elems * (1 << d->dim); ++k)
+    if (d->conn[k] < 0 || d->conn[k] >= d->n_nodes) return set_error("connectivity out of range"), FE2_EINVAL;
+  for (int k = 0; k < d->n_dir; ++k) {
+    if (d->dir_dofs[k] < 0 || d->dir_dofs[k] >= d->n_nodes * d->dim)
+      return set_error("Dirichlet DOF out of range"), FE2_EINVAL;
+    if (k && d->dir_dofs[k] <= d->dir_dofs[k - 1])
+      return set_error("Dirichlet DOFs must be strictly increasing"), FE2_EINVAL;
+  }
+  if (d->rve_off[0] != 0) return set_error("rve_off[0] must be 0"), FE2_EINVAL;
+  for (int b = 0; b < d->n_rve; ++b) {
+    int64_t ne = 1;
+    for (int c = 0; c < d->dim; ++c) {
+      if (d->rve_res[b * d->dim + c] < 2) return set_error("RVE resolution below 2"), FE2_EINVAL;
+      ne *= d->rve_res[b * d->dim + c];
+    }
+    if (d->rve_off[b + 1] - d->rve_off[b] != ne)
+      return set_error("rve_off inconsistent with rve_res at RVE " + std::to_string(b)), FE2_EINVAL;
+  }
+  for (int64_t k = 0; k < d->rve_off[d->n_rve]; ++k)
+    if (d->phase_id[k] > 1) return set_error("phase ids must be 0 or 1"), FE2_EINVAL;
+  return FE2_OK;
+}
+
+// Macro sparsity, element-entry gather lists and half bandwidth.
+int build_macro_lists(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
+  const int dim = h->dim, nen = h->nen, nd = nen * dim, ne = h->n_elems, ndof = h->ndof;
+  std::vector<std::vector<int>> vec_rows(ndof);
+  std::map<std::pair<int, int>, std::vector<int>> nz;
+  int bw = 0;
+  for (int e = 0; e < ne; ++e) {
+    int edof[24];
+    for (int a = 0; a < nen; ++a)
+      for (int c = 0; c < dim; ++c) edof[a * dim + c] = d->conn[e * nen + a] * dim + c;
+    for (int la = 0; la < nd; ++la) {
+      vec_rows[edof[la]].push_back(e * nd + la);
+      for (int lb = 0; lb < nd; ++lb) {
+        nz[{edof[la], edof[lb]}].push_back((e * nd + la) * nd + lb);
+        bw = std::max(bw, std::abs(edof[la] - edof[lb]));
+      }
+    }
+  }
+  std::vector<int> vptr(ndof + 1, 0), vsrc;
+  for (int i = 0; i < ndof; ++i) {
+    vptr[i + 1] = vptr[i] + static_cast<int>(vec_rows[i].size());
+    vsrc.insert(vsrc.end(), vec_rows[i].begin(), vec_rows[i].end());
+  }
+  std::vector<int> zptr(ndof + 1, 0), zcol, cptr(1, 0), csrc;
+  for (auto& kv : nz) {
+    zptr[kv.first.first + 1]++;
+    zcol.push_back(kv.first.second);
+    csrc.insert(csrc.end(), kv.second.begin(), kv.second.end());
+    cptr.push_back(static_cast<int>(csrc.size()));
+  }
+  for (int i = 0; i < ndof; ++i) zptr[i + 1] += zptr[i];
+  h->bw = bw;
+  h->nnz = static_cast<int>(zcol.size());
+  int rc;
+  if ((rc = upload(&h->vec_ptr, vptr.data(), vptr.size(), s))) return rc;
+  if ((rc = upload(&h->vec_src, vsrc.data(), vsrc.size(), s))) return rc;
+  if ((rc = upload(&h->nz_ptr, zptr.data(), zptr.size(), s))) return rc;
+  if ((rc = upload(&h->nz_col, zcol.data(), zcol.size(), s))) return rc;
+  if ((rc = upload(&h->nzc_ptr, cptr.data(), cptr.size(), s))) return rc;
+  if ((rc = upload(&h->nzc_src, csrc.data(), csrc.size(), s))) return rc;
+  // the host vectors die here: wait for the copies
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  return FE2_OK;
+}
+
+int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
+  h->dim = d->dim;
+  h->kin = d->kinematics;
+  h->mat = d->material;
+  h->nen = 1 << d->dim;
+  h->n_gp = 1 << d->dim;
+  h->nF = d->kinematics == FE2_SMALL_STRAIN ? (d->dim == 2 ? 3 : 6) : d->dim * d->dim;
+  h->n_nodes = d->n_nodes;
+  h->n_elems = d->n_elems;
+  h->n_rve = d->n_rve;
+  h->ndof = d->n_nodes * d->dim;
+  h->n_pp = d->n_phase_params;
+  h->precision = d->precision;
+  h->solver = d->solver;
+  h->scheme = d->scheme;
+  h->rve_size = d->rve_size;
+  h->volume = std::pow(d->rve_size, d->dim);
+  h->rve_tol = d->rve_tol;
+  h->inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-4;
+  h->newton_tol = d->newton_tol;
+  h->micro_tol = d->micro_tol;
+  h->max_pcg_it = d->max_pcg_it;
+  h->max_ir = d->max_ir;
+  h->max_micro_it = d->max_micro_it;
+
+  // supported combinations
+  if (h->dim != 2 || h->kin != FE2_SMALL_STRAIN || h->mat != FE2_LINEAR_ISO || h->n_pp != 2) {
+    set_error("this build supports 2D small-strain linear isotropic RVEs");
+    return FE2_ENOTSUP;
+  }
+  if (h->scheme != FE2_SCHEME_GENERALIZED) {
+    set_error("only the generalized scheme is available for this kinematics");
+    return FE2_ENOTSUP;
+  }
+
+  // RVE classes: (n1, n2, lambda/mu)
+  std::map<std::tuple<int, int, double>, int> key2cls;
+  for (int b = 0; b < h->n_rve; ++b) {
+    const int n1 = d->rve_res[b * 2], n2 = d->rve_res[b * 2 + 1];
+    const double* p = d->phase_params + static_cast<size_t>(b) * 2 * h->n_pp;
+    if (!(p[1] > 0.0) || !(p[3] > 0.0)) return set_error("shear moduli must be positive"), FE2_EINVAL;
+    const double rho0 = p[0] / p[1], rho1 = p[2] / p[3];
+    if (std::fabs(rho0 - rho1) > 1e-12 * std::fabs(rho0))
+      return set_error("both phases of an RVE must share lambda/mu"), FE2_ENOTSUP;
+    if (!lin2d_supported(n1, n2))
+      return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" +
+                       std::to_string(n2)),
+             FE2_ENOTSUP;
+    auto key = std::make_tuple(n1, n2, rho0);
+    auto it = key2cls.find(key);
+    int ci;
+    if (it == key2cls.end()) {
+      ci = static_cast<int>(h->classes.size());
+      key2cls[key] = ci;
+      RveClass c;
+      c.n1 = n1;
+      c.n2 = n2;
+      c.rho = rho0;
+      h->classes.push_back(c);
+    } else {
+      ci = it->second;
+    }
+    h->classes[ci].rves.push_back(b);
+  }
+
+  int rc;
+  if ((rc = upload(&h->X, d->X, static_cast<size_t>(h->n_nodes) * h->dim, s))) return rc;
+  if ((rc = upload(&h->conn, d->conn, static_cast<size_t>(h->n_elems) * h->nen, s))) return rc;
+  {
+    std::vector<int> isd(h->ndof, 0);
+    std::vector<double> dv(h->ndof, 0.0);
+    for (int k = 0; k < d->n_dir; ++k) {
+      isd[d->dir_dofs[k]] = 1;
+      dv[d->dir_dofs[k]] = d->dir_vals[k];
+    }
+    if ((rc = upload(&h->is_dir, isd.data(), isd.size(), s))) return rc;
+    if ((rc = upload(&h->dir_full, dv.data(), dv.size(), s))) return rc;
+    FE2_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  if (d->f_ext && (rc = upload(&h->f_ext, d->f_ext, h->ndof, s))) return rc;
+  const int64_t n_ph = d->rve_off[h->n_rve];
+  if ((rc = upload(&h->phase_off, d->rve_off, static_cast<size_t>(h->n_rve) + 1, s))) return rc;
+  if ((rc = upload(&h->phase, d->phase_id, static_cast<size_t>(n_ph), s))) return rc;
+  if ((rc = upload(&h->params, d->phase_params, static_cast<size_t>(h->n_rve) * 2 * h->n_pp, s))) return rc;
+  h->h_foff.assign(h->n_rve + 1, 0);
+  for (int b = 0; b < h->n_rve; ++b) {
+    int64_t nn = 1;
+    for (int c = 0; c < h->dim; ++c) nn *= d->rve_res[b * h->dim + c];
+    h->h_foff[b + 1] = h->h_foff[b] + nn * h->dim;
+  }
+  h->field_len = h->h_foff[h->n_rve];
+  if ((rc = upload(&h->foff, h->h_foff.data(), h->h_foff.size(), s))) return rc;
+  if ((rc = build_macro_lists(h, d, s))) return rc;
+
+  // device state and work buffers
+  const size_t nr = h->n_rve, nF = h->nF, nd = static_cast<size_t>(h->nen) * h->dim;
+  if ((rc = dalloc(&h->dNdX, nr * h->nen * h->dim))) return rc;
+  if ((rc = dalloc(&h->wdet, nr))) return rc;
+  if ((rc = dalloc(&h->u, h->ndof))) return rc;
+  if ((rc = dalloc(&h->w, h->field_len))) return rc;
+  if ((rc = dalloc(&h->r, h->field_len))) return rc;
+  if ((rc = dalloc(&h->Xs, static_cast<size_t>(h->field_len) * (nF + 1)))) return rc;
+  if ((rc = dalloc(&h->Cbar, nr * nF * nF))) return rc;
+  if ((rc = dalloc(&h->Phat, nr * nF))) return rc;
+  if ((rc = dalloc(&h->Pbar, nr * nF))) return rc;
+  if ((rc = dalloc(&h->mgrad, nr * nF))) return rc;
+  if ((rc = dalloc(&h->rnorm2, nr))) return rc;
+  if ((rc = dalloc(&h->relres, nr))) return rc;
+  if ((rc = dalloc(&h->iters, nr))) return rc;
+  if ((rc = dalloc(&h->fail_count, 1))) return rc;
+  if ((rc = dalloc(&h->info, 1))) return rc;
+  if ((rc = dalloc(&h->f_true, static_cast<size_t>(h->n_elems) * nd))) return rc;
+  if ((rc = dalloc(&h->f_hat, static_cast<size_t>(h->n_elems) * nd))) return rc;
+  if ((rc = dalloc(&h->ke, static_cast<size_t>(h->n_elems) * nd * nd))) return rc;
+  if ((rc = dalloc(&h->band, static_cast<size_t>(h->ndof) * (h->bw + 1)))) return rc;
+  if ((rc = dalloc(&h->rhs, h->ndof))) return rc;
+  if ((rc = dalloc(&h->du, h->ndof))) return rc;
+  if ((rc = dalloc(&h->r_true, h->ndof))) return rc;
+  if ((rc = dalloc(&h->f_int, h->ndof))) return rc;
+  if ((rc = dalloc(&h->norms_dev, 4))) return rc;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->norms_host), 4 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 2 * sizeof(int)) != hipSuccess)
+    return set_error("pinned host allocation failed"), FE2_ENOMEM;
+  if (band_solve_lds(h->bw) > 160 * 1024)
+    return set_error("macro half bandwidth " + std::to_string(h->bw) + " exceeds the LDS panel"), FE2_ENOTSUP;
+
+  // zero state
+  hipLaunchKernelGGL(k_fill, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->u, static_cast<size_t>(h->ndof), 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(std::min<unsigned>(4096, nblk(h->field_len, 256))), dim3(256), 0, s, h->w,
+                     static_cast<size_t>(h->field_len), 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(std::min<unsigned>(4096, nblk(h->field_len * (nF + 1), 256))), dim3(256), 0, s,
+                     h->Xs, static_cast<size_t>(h->field_len) * (nF + 1), 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(nr * nF, 256)), dim3(256), 0, s, h->Pbar, nr * nF, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->du, static_cast<size_t>(h->ndof), 0.0);
+  FE2_HIP_CHECK(hipGetLastError());
+
+  // macro geometry
+  MacroArgs m = h->margs();
+  hipLaunchKernelGGL(k_macro_geometry, dim3(nblk(nr, 128)), dim3(128), 0, s, m);
+  FE2_HIP_CHECK(hipGetLastError());
+
+  // RVE classes: work lists and reference tables
+  for (auto& c : h->classes) {
+    if ((rc = upload(&c.d_list, c.rves.data(), c.rves.size(), s))) return rc;
+    if ((rc = dalloc(&c.d_tab, 44))) return rc;
+    hipLaunchKernelGGL(k_ref_tables_2d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, h->rve_size / c.n2, c.rho,
+                       c.d_tab);
+    FE2_HIP_CHECK(hipGetLastError());
+    double err = 0.0;
+    FE2_HIP_CHECK(hipMemcpyAsync(&err, c.d_tab + 43, sizeof(double), hipMemcpyDeviceToHost, s));
+    FE2_HIP_CHECK(hipStreamSynchronize(s));
+    if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
+  }
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  h->lam = 0.0;
+  return FE2_OK;
+}
+
+int assemble_impl(fe2_ctx* h, hipStream_t s) {
+  MacroArgs m = h->margs();
+  hipLaunchKernelGGL(k_macro_grad, dim3(nblk(h->n_rve, 128)), dim3(128), 0, s, m, h->u, h->mgrad);
+  FE2_HIP_CHECK(hipGetLastError());
+  for (auto& c : h->classes) {
+    Lin2DArgs a = h->largs(c, RVE_ASSEMBLE);
+    int rc = launch_lin2d(a, static_cast<int>(c.rves.size()), h->precision, 3, s);
+    if (rc) return rc;
+  }
+  return FE2_OK;
+}
+
+int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->fail_count, static_cast<size_t>(1), 0);
+  for (auto& c : h->classes) {
+    Lin2DArgs a = h->largs(c, RVE_SOLVE);
+    int rc = launch_lin2d(a, static_cast<int>(c.rves.size()), h->precision, nrhs, s);
+    if (rc) return rc;
+  }
+  return FE2_OK;
+}
+
+// Macro residual vectors and norms of the current assembly (no solve).
+int residual_impl(fe2_ctx* h, double lam, hipStream_t s) {
+  MacroArgs m = h->margs();
+  const int nd = h->nen * h->dim;
+  hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(static_cast<size_t>(h->n_elems) * nd, 128)), dim3(128), 0, s, m,
+                     h->Pbar, h->f_true);
+  hipLaunchKernelGGL(k_macro_rows_vec, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->f_true,
+                     static_cast<const double*>(nullptr), lam, h->r_true, h->f_int, static_cast<double*>(nullptr));
+  hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, s, m, h->r_true, h->f_int, h->rnorm2, h->volume,
+                     h->norms_dev);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
+  MacroArgs m = h->margs();
+  const int nd = h->nen * h->dim;
+  const size_t ne_rows = static_cast<size_t>(h->n_elems) * nd;
+  hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(ne_rows, 128)), dim3(128), 0, s, m, h->Phat, h->f_hat);
+  hipLaunchKernelGGL(k_macro_elem_mat, dim3(nblk(ne_rows, 64)), dim3(64), 0, s, m, h->Cbar, h->ke);
+  hipLaunchKernelGGL(k_macro_rows_vec, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->f_true, h->f_hat, lam,
+                     static_cast<double*>(nullptr), static_cast<double*>(nullptr), h->rhs);
+  const size_t nband = static_cast<size_t>(h->ndof) * (h->bw + 1);
+  hipLaunchKernelGGL(k_fill, dim3(std::min<unsigned>(4096, nblk(nband, 256))), dim3(256), 0, s, h->band, nband, 0.0);
+  hipLaunchKernelGGL(k_macro_rows_band, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->ke, dlam, h->band, h->rhs,
+                     h->kdense);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->info, static_cast<size_t>(1), 0);
+  FE2_HIP_CHECK(hipGetLastError());
+  const size_t lds = band_solve_lds(h->bw);
+  if (lds > 64 * 1024)
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_cholesky_solve),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  FE2_HIP_CHECK(hipMemcpyAsync(h->du, h->rhs, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_band_cholesky_solve, dim3(1), dim3(1024), lds, s, h->ndof, h->bw, h->band, h->du, h->info);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
+  MacroArgs m = h->margs();
+  hipLaunchKernelGGL(k_axpy, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->ndof, h->du, h->u);
+  hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+#define FE2_GUARD(h)                                                  \
+  do {                                                                \
+    if (!(h)) return set_error("null handle"), FE2_EINVAL;            \
+    if ((h)->broken) return set_error("handle is unusable"), FE2_ESTATE; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int fe2_abi_version(void) { return FE2_ABI_VERSION; }
+
+const char* fe2_last_error(void) { return g_last_error.c_str(); }
+
+const char* fe2_strerror(int st) {
+  switch (st) {
+    case FE2_OK: return "ok";
+    case FE2_CONVERGED: return "converged";
+    case FE2_EINVAL: return "invalid argument";
+    case FE2_ENOMEM: return "out of memory";
+    case FE2_EHIP: return "HIP runtime error";
+    case FE2_ENOCONV: return "RVE solve did not converge";
+    case FE2_ESTATE: return "handle unusable";
+    case FE2_ENOTSUP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+int fe2_setup(const fe2_problem_desc* desc, void* stream, fe2_handle* out) {
+  if (!out) return set_error("null output handle"), FE2_EINVAL;
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc) return rc;
+  fe2_ctx* h = new (std::nothrow) fe2_ctx();
+  if (!h) return set_error("host allocation failed"), FE2_ENOMEM;
+  rc = setup_impl(h, desc, static_cast<hipStream_t>(stream));
+  if (rc) {
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    free_ctx(h);
+    return rc;
+  }
+  *out = h;
+  return FE2_OK;
+}
+
+int fe2_assemble_rve(fe2_handle h, void* stream) {
+  FE2_GUARD(h);
+  return assemble_impl(h, static_cast<hipStream_t>(stream));
+}
+
+int fe2_condense(fe2_handle h, double* Cbar_dev, double* Phat_dev, void* stream) {
+  FE2_GUARD(h);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = solve_impl(h, h->nF + 1, s);
+  if (rc) return rc;
+  const size_t nr = h->n_rve;
+  if (Cbar_dev)
+    FE2_HIP_CHECK(hipMemcpyAsync(Cbar_dev, h->Cbar, nr * h->nF * h->nF * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (Phat_dev)
+    FE2_HIP_CHECK(hipMemcpyAsync(Phat_dev, h->Phat, nr * h->nF * sizeof(double), hipMemcpyDeviceToDevice, s));
+  FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  h->last_failed = h->flag_host[0];
+  return h->last_failed ? (set_error(std::to_string(h->last_failed) + " RVE solves missed rve_tol"), FE2_ENOCONV)
+                        : FE2_OK;
+}
+
+int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* stream) {
+  FE2_GUARD(h);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  // a2-a4 at the current state and the residual norms (a10)
+  if ((rc = assemble_impl(h, s))) return rc;
+  if ((rc = residual_impl(h, load_factor, s))) return rc;
+  FE2_HIP_CHECK(hipMemcpyAsync(h->norms_host, h->norms_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  if (norms_host) std::memcpy(norms_host, h->norms_host, 4 * sizeof(double));
+  const double dlam = load_factor - h->lam;
+  if (dlam == 0.0 && h->norms_host[0] <= h->newton_tol * h->norms_host[3]) return FE2_CONVERGED;
+  // a5-a6: RVE solves; the residual column is dropped when every RVE
+  // residual is exactly zero (first iteration from the reference state)
+  const int nrhs = h->norms_host[2] == 0.0 ? h->nF : h->nF + 1;
+  if ((rc = solve_impl(h, nrhs, s))) return rc;
+  // a7-a8: macro assembly and banded Cholesky solve with the increment
+  if ((rc = macro_solve_impl(h, load_factor, dlam, s))) return rc;
+  // a9: update
+  if ((rc = update_impl(h, nrhs > h->nF, s))) return rc;
+  FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host + 1, h->info, sizeof(int), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  h->lam = load_factor;
+  h->last_failed = h->flag_host[0];
+  if (h->flag_host[1] != 0)
+    return set_error("macro tangent not positive definite at pivot " + std::to_string(h->flag_host[1])),
+           FE2_ENOCONV;
+  if (h->last_failed) return set_error(std::to_string(h->last_failed) + " RVE solves missed rve_tol"), FE2_ENOCONV;
+  return FE2_OK;
+}
+
+int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream) {
+  FE2_GUARD(h);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (u_dev) FE2_HIP_CHECK(hipMemcpyAsync(u_dev, h->u, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
+  if (w_dev) FE2_HIP_CHECK(hipMemcpyAsync(w_dev, h->w, sizeof(double) * h->field_len, hipMemcpyDeviceToDevice, s));
+  return FE2_OK;
+}
+
+int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev, double load_factor, void* stream) {
+  FE2_GUARD(h);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (u_dev) FE2_HIP_CHECK(hipMemcpyAsync(h->u, u_dev, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
+  if (w_dev) FE2_HIP_CHECK(hipMemcpyAsync(h->w, w_dev, sizeof(double) * h->field_len, hipMemcpyDeviceToDevice, s));
+  h->lam = load_factor;
+  return FE2_OK;
+}
+
+int fe2_get_data(fe2_handle h, int which, double* dst, void* stream) {
+  FE2_GUARD(h);
+  if (!dst) return set_error("null destination"), FE2_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nr = h->n_rve, nF = h->nF;
+  const double* src = nullptr;
+  size_t n = 0;
+  switch (which) {
+    case FE2_D_MACRO_GRAD: src = h->mgrad; n = nr * nF; break;
+    case FE2_D_RESIDUAL: src = h->r; n = h->field_len; break;
+    case FE2_D_PBAR: src = h->Pbar; n = nr * nF; break;
+    case FE2_D_SOLUTION: src = h->Xs; n = static_cast<size_t>(h->field_len) * (nF + 1); break;
+    case FE2_D_RVE_ITERS: src = h->iters; n = nr; break;
+    case FE2_D_RVE_RELRES: src = h->relres; n = nr; break;
+    case FE2_D_MACRO_RHS: src = h->rhs; n = h->ndof; break;
+    case FE2_D_MACRO_RTRUE: src = h->r_true; n = h->ndof; break;
+    case FE2_D_MACRO_DU: src = h->du; n = h->ndof; break;
+    case FE2_D_CBAR: src = h->Cbar; n = nr * nF * nF; break;
+    case FE2_D_PHAT: src = h->Phat; n = nr * nF; break;
+    case FE2_D_MACRO_KDENSE: {
+      if (h->ndof > 4096) return set_error("dense macro tangent only for ndof <= 4096"), FE2_EINVAL;
+      const size_t nn = static_cast<size_t>(h->ndof) * h->ndof;
+      if (!h->kdense) {
+        int rc = dalloc(&h->kdense, nn);
+        if (rc) return rc;
+      }
+      // rebuild from the element matrices of the last step (no Dirichlet change)
+      MacroArgs m = h->margs();
+      hipLaunchKernelGGL(k_fill, dim3(std::min<unsigned>(4096, nblk(nn, 256))), dim3(256), 0, s, h->kdense, nn, 0.0);
+      const size_t nband = static_cast<size_t>(h->ndof) * (h->bw + 1);
+      double* scratch_band = nullptr;
+      double* scratch_rhs = nullptr;
+      int rc = dalloc(&scratch_band, nband);
+      if (rc) return rc;
+      if ((rc = dalloc(&scratch_rhs, h->ndof))) {
+        (void)hipFree(scratch_band);
+        return rc;
+      }
+      hipLaunchKernelGGL(k_fill, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, scratch_rhs,
+                         static_cast<size_t>(h->ndof), 0.0);
+      hipLaunchKernelGGL(k_macro_rows_band, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->ke, 0.0, scratch_band,
+                         scratch_rhs, h->kdense);
+      FE2_HIP_CHECK(hipMemcpyAsync(dst, h->kdense, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+      FE2_HIP_CHECK(hipStreamSynchronize(s));
+      (void)hipFree(scratch_band);
+      (void)hipFree(scratch_rhs);
+      return FE2_OK;
+    }
+    default: return set_error("unknown data selector"), FE2_EINVAL;
+  }
+  FE2_HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return FE2_OK;
+}
+
+int fe2_query(fe2_handle h, int which, int64_t* out) {
+  FE2_GUARD(h);
+  if (!out) return set_error("null output"), FE2_EINVAL;
+  switch (which) {
+    case FE2_Q_NF: *out = h->nF; return FE2_OK;
+    case FE2_Q_FIELD_LEN: *out = h->field_len; return FE2_OK;
+    case FE2_Q_NDOF: *out = h->ndof; return FE2_OK;
+    case FE2_Q_BANDWIDTH: *out = h->bw; return FE2_OK;
+    case FE2_Q_FAILED_RVES: *out = h->last_failed; return FE2_OK;
+    case FE2_Q_N_RVE: *out = h->n_rve; return FE2_OK;
+    case FE2_Q_FIELD_OFFSETS: std::memcpy(out, h->h_foff.data(), h->h_foff.size() * sizeof(int64_t)); return FE2_OK;
+    default: return set_error("unknown query"), FE2_EINVAL;
+  }
+}
+
+int fe2_destroy(fe2_handle h) {
+  if (!h) return FE2_OK;
+  (void)hipDeviceSynchronize();
+  free_ctx(h);
+  return FE2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal declarations shared by the HIP translation units of libfe2.
+// Device code targets gfx950 (CDNA4, 64-wide wavefronts) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fe2.h"
+
+namespace fe2 {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define FE2_HIP_CHECK(expr)                                                    \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess) {                                                    \
+      ::fe2::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));      \
+      return FE2_EHIP;                                                         \
+    }                                                                          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV values over the work-group; every thread receives the totals.
+// s_red must hold NW*NV doubles.  Deterministic: fixed order of the
+// butterfly within a wave and of the waves.
+template <int NV, int NW>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* s_red) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s_red[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += s_red[w * NV + i];
+    v[i] = t;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+enum RveFlags : int {
+  RVE_ASSEMBLE = 1,   // element integration: r_b, int P~ (a3)
+  RVE_SOLVE = 2,      // PCG + refinement + condensation (a5, a6)
+  RVE_WARM = 4,       // start from the solution stored in X
+  RVE_RCOL = 8,       // solve the residual column (nF+1 right-hand sides)
+  RVE_FFT = 16        // homogeneous-reference (FFT) preconditioner
+};
+
+// One launch handles the RVEs of one resolution class (same n1 x n2 and same
+// lambda/mu ratio, hence the same reference element tables).
+struct Lin2DArgs {
+  int n1, n2;
+  const int* rve_list;          // RVE ids of this launch
+  const int64_t* phase_off;     // [n_rve+1]
+  const uint8_t* phase;         // phase id per RVE element
+  const double* params;         // [n_rve][2][2] (lambda, mu)
+  const double* kv64;           // [10] distinct entries of the element stiffness, mu = 1
+  const double* KwF64;          // [8*3] element coupling, mu = 1
+  const double* KFF64;          // [9] element integral of C, mu = 1
+  const double* macro;          // [n_rve][3] macro strain
+  const int64_t* foff;          // [n_rve+1] field offsets (doubles)
+  const double* w;              // state fluctuation (periodic numbering)
+  double* r;                    // RVE residual (written by ASSEMBLE)
+  double* X;                    // solutions, (nF+1) fields per RVE
+  double* Cbar;                 // [n_rve][3][3]
+  double* Phat;                 // [n_rve][3]
+  double* Pbar;                 // [n_rve][3]
+  double* rnorm2;               // [n_rve] ||r_b||^2
+  double* relres;               // [n_rve] final relative FP64 residual
+  double* iters;                // [n_rve] PCG iterations
+  int* fail_count;              // RVEs that missed tol
+  const float* fft_tab;         // spectral preconditioner table (RVE_FFT)
+  double volume;
+  double tol, tol_in;
+  int max_it, max_ir;
+  int flags;
+};
+
+// Launchers (rve_lin2d.hip)
+int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
+                 hipStream_t s);
+size_t lin2d_lds_bytes(int n1, int n2, int nrhs);
+bool lin2d_supported(int n1, int n2);
+
+}  // namespace fe2

@@ -1,0 +1,484 @@
+// Macro side of the monolithic FE^2 step (FP64 throughout), Hesch, Schmidt,
+// Schuss, arXiv:2312.12771:
+//   * reference tables of the RVE box element (setup);
+//   * macro Gauss-point geometry and the macro gradient at every RVE
+//     (Eqs. (25)-(28), (11));
+//   * element tangents and residuals from the condensed Cbar_b, Phat_b and
+//     the averaged Pbar_b (Eqs. (35), (39), (48));
+//   * deterministic row-gather assembly into band storage with Dirichlet
+//     elimination;
+//   * banded Cholesky factorisation and solve in one work-group (the macro
+//     system of Eq. (48));
+//   * fluctuation update dw_b = -(x_r + X_F dF_b) (Eq. (49)) and the residual
+//     norms of the convergence test.
+#include "macro.hpp"
+
+namespace fe2 {
+
+// ---------------------------------------------------------------------------
+// setup: reference tables of a box element (2D: Q4, plane strain)
+// ---------------------------------------------------------------------------
+// K_ref = sum_gp w B^T C0 B, KwF = sum_gp w B^T C0, KFF = sum_gp w C0 with
+// C0 = C(lambda = rho, mu = 1); then the ten distinct entries of K_ref and a
+// consistency flag (every entry equals sign * kv[id]).
+__global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double g = 0.57735026918962576451;   // 1/sqrt(3)
+  const double C[3][3] = {{rho + 2.0, rho, 0.0}, {rho, rho + 2.0, 0.0}, {0.0, 0.0, 1.0}};
+  const double xa[4] = {-1, 1, 1, -1}, ya[4] = {-1, -1, 1, 1};
+  double K[8][8] = {};
+  double KwF[8][3] = {};
+  double KFF[3][3] = {};
+  const double wt = 0.25 * h1 * h2;
+  for (int gy = 0; gy < 2; ++gy)
+    for (int gx = 0; gx < 2; ++gx) {
+      const double xi = gx ? g : -g, eta = gy ? g : -g;
+      double B[3][8] = {};
+      for (int a = 0; a < 4; ++a) {
+        const double dx = 0.25 * xa[a] * (1.0 + ya[a] * eta) * (2.0 / h1);
+        const double dy = 0.25 * ya[a] * (1.0 + xa[a] * xi) * (2.0 / h2);
+        B[0][2 * a] = dx;
+        B[1][2 * a + 1] = dy;
+        B[2][2 * a] = dy;
+        B[2][2 * a + 1] = dx;
+      }
+      for (int r = 0; r < 8; ++r) {
+        double CB[3];
+        for (int i = 0; i < 3; ++i) CB[i] = C[i][0] * B[0][r] + C[i][1] * B[1][r] + C[i][2] * B[2][r];
+        for (int c = 0; c < 8; ++c) K[r][c] += wt * (CB[0] * B[0][c] + CB[1] * B[1][c] + CB[2] * B[2][c]);
+        for (int j = 0; j < 3; ++j) KwF[r][j] += wt * CB[j];
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) KFF[i][j] += wt * C[i][j];
+    }
+  double kv[10] = {};
+  bool seen[10] = {};
+  double err = 0.0, scale = 0.0;
+  for (int r = 0; r < 8; ++r)
+    for (int c = 0; c < 8; ++c) {
+      const int id = kref_id(r, c);
+      const double v = kref_sign(r, c) * K[r][c];
+      if (!seen[id]) {
+        kv[id] = v;
+        seen[id] = true;
+      }
+      err = fmax(err, fabs(v - kv[id]));
+      scale = fmax(scale, fabs(K[r][c]));
+    }
+  // layout: kv[10] | KwF[24] | KFF[9] | consistency error
+  for (int t = 0; t < 10; ++t) out[t] = kv[t];
+  for (int r = 0; r < 8; ++r)
+    for (int j = 0; j < 3; ++j) out[10 + 3 * r + j] = KwF[r][j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[34 + 3 * i + j] = KFF[i][j];
+  out[43] = err / scale;
+}
+
+// ---------------------------------------------------------------------------
+// macro Gauss-point geometry (setup)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ref_node(int dim, int a, double* xa) {
+  const int cx = (a & 3) == 1 || (a & 3) == 2;
+  const int cy = (a & 3) >= 2;
+  xa[0] = cx ? 1.0 : -1.0;
+  xa[1] = cy ? 1.0 : -1.0;
+  if (dim == 3) xa[2] = a >= 4 ? 1.0 : -1.0;
+}
+
+__global__ void k_macro_geometry(MacroArgs m) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= m.n_rve) return;
+  const int dim = m.dim, nen = m.nen, ngp = m.n_gp;
+  const int e = b / ngp, g = b % ngp;
+  const double gq = 0.57735026918962576451;
+  double xi[3];
+  xi[0] = (g & 1) ? gq : -gq;
+  xi[1] = (g & 2) ? gq : -gq;
+  xi[2] = (g & 4) ? gq : -gq;
+  double dxi[8][3];
+  for (int a = 0; a < nen; ++a) {
+    double na[3];
+    ref_node(dim, a, na);
+    for (int J = 0; J < dim; ++J) {
+      double v = (dim == 2) ? 0.25 : 0.125;
+      for (int K = 0; K < dim; ++K) v *= (K == J) ? na[K] : (1.0 + na[K] * xi[K]);
+      dxi[a][J] = v;
+    }
+  }
+  double Jm[3][3] = {};
+  for (int a = 0; a < nen; ++a) {
+    const int node = m.conn[e * nen + a];
+    for (int i = 0; i < dim; ++i)
+      for (int J = 0; J < dim; ++J) Jm[i][J] += m.X[node * dim + i] * dxi[a][J];
+  }
+  double inv[3][3], det;
+  if (dim == 2) {
+    det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+    inv[0][0] = Jm[1][1] / det;
+    inv[0][1] = -Jm[0][1] / det;
+    inv[1][0] = -Jm[1][0] / det;
+    inv[1][1] = Jm[0][0] / det;
+  } else {
+    det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
+          Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
+          Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+    inv[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) / det;
+    inv[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+    inv[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+    inv[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) / det;
+    inv[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+    inv[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+    inv[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) / det;
+    inv[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+    inv[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+  }
+  // dN/dX_J = sum_K dN/dxi_K (J^-1)_KJ
+  for (int a = 0; a < nen; ++a)
+    for (int J = 0; J < dim; ++J) {
+      double v = 0.0;
+      for (int K = 0; K < dim; ++K) v += dxi[a][K] * inv[K][J];
+      m.dNdX[(static_cast<size_t>(b) * nen + a) * dim + J] = v;
+    }
+  m.wdet[b] = det;
+}
+
+// macro strain-displacement (small) or gradient (finite) operator entry
+// B[i][col] of RVE b, col = a*dim + c.
+__device__ __forceinline__ double macro_B(const MacroArgs& m, int b, int i, int col) {
+  const int dim = m.dim;
+  const int a = col / dim, c = col % dim;
+  const double* d = m.dNdX + (static_cast<size_t>(b) * m.nen + a) * dim;
+  if (m.kin == FE2_FINITE_STRAIN) {   // row (p, J) = dim*p + J: dN_a/dX_J if p == c
+    const int p = i / dim, J = i % dim;
+    return p == c ? d[J] : 0.0;
+  }
+  if (dim == 2) {
+    switch (i) {
+      case 0: return c == 0 ? d[0] : 0.0;
+      case 1: return c == 1 ? d[1] : 0.0;
+      default: return c == 0 ? d[1] : d[0];
+    }
+  }
+  switch (i) {   // [11, 22, 33, 23, 13, 12]
+    case 0: return c == 0 ? d[0] : 0.0;
+    case 1: return c == 1 ? d[1] : 0.0;
+    case 2: return c == 2 ? d[2] : 0.0;
+    case 3: return c == 1 ? d[2] : (c == 2 ? d[1] : 0.0);
+    case 4: return c == 0 ? d[2] : (c == 2 ? d[0] : 0.0);
+    default: return c == 0 ? d[1] : (c == 1 ? d[0] : 0.0);
+  }
+}
+
+// a2: macro gradient of every RVE from the displacement u = q - X.
+__global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= m.n_rve) return;
+  const int e = b / m.n_gp;
+  const int nd = m.nen * m.dim;
+  for (int i = 0; i < m.nF; ++i) {
+    double v = 0.0;
+    for (int col = 0; col < nd; ++col) {
+      const int node = m.conn[e * m.nen + col / m.dim];
+      v += macro_B(m, b, i, col) * u[node * m.dim + col % m.dim];
+    }
+    if (m.kin == FE2_FINITE_STRAIN && (i / m.dim) == (i % m.dim)) v += 1.0;
+    out[static_cast<size_t>(b) * m.nF + i] = v;
+  }
+}
+
+// a7 (part): element residual vectors  f = sum_g wdet B^T P  for P = Pbar
+// (true residual) and P = Phat (condensed right-hand side).  One thread per
+// (element, row).
+__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f) {
+  const int nd = m.nen * m.dim;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_elems * nd) return;
+  const int e = t / nd, row = t % nd;
+  double v = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int b = e * m.n_gp + g;
+    double s = 0.0;
+    for (int i = 0; i < m.nF; ++i) s += macro_B(m, b, i, row) * P[static_cast<size_t>(b) * m.nF + i];
+    v += m.wdet[b] * s;
+  }
+  f[t] = v;
+}
+
+// a7 (part): element tangents  k = sum_g wdet B^T Cbar B, one thread per
+// (element, row).
+__global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke) {
+  const int nd = m.nen * m.dim;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_elems * nd) return;
+  const int e = t / nd, row = t % nd;
+  const int nF = m.nF;
+  double acc[24];
+  for (int c = 0; c < nd; ++c) acc[c] = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int b = e * m.n_gp + g;
+    const double* C = Cb + static_cast<size_t>(b) * nF * nF;
+    double tj[9];
+    for (int j = 0; j < nF; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < nF; ++i) s += macro_B(m, b, i, row) * C[i * nF + j];
+      tj[j] = s * m.wdet[b];
+    }
+    for (int c = 0; c < nd; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < nF; ++j) s += tj[j] * macro_B(m, b, j, c);
+      acc[c] += s;
+    }
+  }
+  for (int c = 0; c < nd; ++c) ke[static_cast<size_t>(t) * nd + c] = acc[c];
+}
+
+// Row-wise residual gather: R_true = F_int - lam f_ext, F_int, and the
+// condensed right-hand side rhs = lam f_ext - sum f_hat (Dirichlet rows get
+// their prescribed increment later).  One thread per DOF; contributions in a
+// fixed order (deterministic).
+__global__ void k_macro_rows_vec(MacroArgs m, const double* __restrict__ f_true,
+                                 const double* __restrict__ f_hat, double lam,
+                                 double* __restrict__ r_true, double* __restrict__ f_int,
+                                 double* __restrict__ rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.ndof) return;
+  double ft = 0.0, fh = 0.0;
+  for (int k = m.vec_ptr[i]; k < m.vec_ptr[i + 1]; ++k) {
+    const int src = m.vec_src[k];
+    ft += f_true[src];
+    if (f_hat) fh += f_hat[src];
+  }
+  const double fe = m.f_ext ? lam * m.f_ext[i] : 0.0;
+  if (f_int) f_int[i] = ft;
+  if (r_true) r_true[i] = ft - fe;
+  if (rhs) rhs[i] = fe - fh;
+}
+
+// Band assembly with Dirichlet elimination.  Row i gathers every nonzero
+// K_ij from the element matrices; free/free entries with j <= i go to the
+// lower band L[j*(bw+1) + (i-j)], free/Dirichlet entries move to the
+// right-hand side, Dirichlet rows become identity rows with rhs = du_D.
+__global__ void k_macro_rows_band(MacroArgs m, const double* __restrict__ ke, double dlam,
+                                  double* __restrict__ band, double* __restrict__ rhs,
+                                  double* __restrict__ kdense) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.ndof) return;
+  const int bw1 = m.bw + 1;
+  const bool diri = m.is_dir[i] != 0;
+  double corr = 0.0;
+  for (int k = m.nz_ptr[i]; k < m.nz_ptr[i + 1]; ++k) {
+    const int j = m.nz_col[k];
+    double v = 0.0;
+    for (int s = m.nzc_ptr[k]; s < m.nzc_ptr[k + 1]; ++s) v += ke[m.nzc_src[s]];
+    if (kdense) kdense[static_cast<size_t>(i) * m.ndof + j] = v;
+    if (diri) continue;
+    if (m.is_dir[j]) {
+      corr += v * dlam * m.dir_full[j];
+    } else if (j <= i) {
+      band[static_cast<size_t>(j) * bw1 + (i - j)] = v;
+    }
+  }
+  if (diri) {
+    band[static_cast<size_t>(i) * bw1] = 1.0;
+    rhs[i] = dlam * m.dir_full[i];
+  } else {
+    rhs[i] -= corr;
+  }
+}
+
+__global__ void k_fill(double* p, size_t n, double v) {
+  for (size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; t < n;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[t] = v;
+}
+
+__global__ void k_fill_i(int* p, size_t n, int v) {
+  for (size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; t < n;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// banded Cholesky factorisation and solve, one work-group
+// ---------------------------------------------------------------------------
+// Right-looking, panel width NB.  The panel (rows k0 .. k0+kb+bw-1, columns
+// k0 .. k0+kb-1) is factored in LDS, written back, used for the forward
+// substitution and for the rank-kb update of the trailing band window, which
+// stays in global memory (L2-resident: bw*bw doubles).  The backward
+// substitution runs panel by panel from the last one.
+constexpr int CH_NB = 32;
+constexpr int CH_WG = 1024;
+
+__global__ void __launch_bounds__(CH_WG) k_band_cholesky_solve(int n, int bw, double* __restrict__ band,
+                                                               double* __restrict__ y, int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int bw1 = bw + 1;
+  const int mmax = bw + CH_NB;
+  double* P = reinterpret_cast<double*>(smem);          // [CH_NB][mmax] column-major panel
+  double* yv = P + static_cast<size_t>(CH_NB) * mmax;    // [mmax] right-hand side window
+  const int tid = threadIdx.x;
+  auto A = [&](int i, int j) -> double& { return band[static_cast<size_t>(j) * bw1 + (i - j)]; };
+
+  for (int k0 = 0; k0 < n; k0 += CH_NB) {
+    const int kb = min(CH_NB, n - k0);
+    const int m = min(n - k0, kb + bw);   // rows of the panel
+    // load panel and rhs window
+    for (int t = tid; t < kb * m; t += CH_WG) {
+      const int c = t / m, r = t % m;
+      const int i = k0 + r, j = k0 + c;
+      P[c * mmax + r] = (i >= j && i - j <= bw) ? A(i, j) : 0.0;
+    }
+    for (int r = tid; r < m; r += CH_WG) yv[r] = y[k0 + r];
+    __syncthreads();
+    // factor the panel column by column, with the forward substitution
+    for (int c = 0; c < kb; ++c) {
+      const double d = P[c * mmax + c];
+      if (d <= 0.0) {
+        if (tid == 0) *info = k0 + c + 1;
+        return;
+      }
+      const double s = sqrt(d);
+      __syncthreads();
+      for (int r = c + tid; r < m; r += CH_WG) P[c * mmax + r] = (r == c) ? s : P[c * mmax + r] / s;
+      __syncthreads();
+      const double yc = yv[c] / s;
+      // update remaining panel columns and the rhs window
+      for (int t = tid; t < (kb - c - 1) * (m - c - 1) + (m - c - 1); t += CH_WG) {
+        if (t < (kb - c - 1) * (m - c - 1)) {
+          const int cc = c + 1 + t / (m - c - 1);
+          const int r = c + 1 + t % (m - c - 1);
+          if (r >= cc) P[cc * mmax + r] -= P[c * mmax + r] * P[c * mmax + cc];
+        } else {
+          const int r = c + 1 + (t - (kb - c - 1) * (m - c - 1));
+          yv[r] -= P[c * mmax + r] * yc;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) yv[c] = yc;
+      __syncthreads();
+    }
+    // write the panel back and the finished rhs entries; keep the rest
+    for (int t = tid; t < kb * m; t += CH_WG) {
+      const int c = t / m, r = t % m;
+      const int i = k0 + r, j = k0 + c;
+      if (i >= j && i - j <= bw) A(i, j) = P[c * mmax + r];
+    }
+    for (int r = tid; r < m; r += CH_WG) y[k0 + r] = yv[r];
+    // trailing update A(i, j) -= sum_c P(i, c) P(j, c), k0+kb <= j <= i < k0+m
+    const int tw = m - kb;   // trailing window size
+    for (int t = tid; t < tw * tw; t += CH_WG) {
+      const int jj = t / tw, ii = t % tw;
+      if (ii < jj) continue;
+      const int i = k0 + kb + ii, j = k0 + kb + jj;
+      if (i - j > bw) continue;
+      double s = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < kb; ++c) s += P[c * mmax + kb + ii] * P[c * mmax + kb + jj];
+      A(i, j) -= s;
+    }
+    __syncthreads();
+  }
+  // backward substitution L^T x = y, panel by panel from the end
+  const int npan = (n + CH_NB - 1) / CH_NB;
+  for (int pidx = npan - 1; pidx >= 0; --pidx) {
+    const int k0 = pidx * CH_NB;
+    const int kb = min(CH_NB, n - k0);
+    const int m = min(n - k0, kb + bw);
+    for (int t = tid; t < kb * m; t += CH_WG) {
+      const int c = t / m, r = t % m;
+      const int i = k0 + r, j = k0 + c;
+      P[c * mmax + r] = (i >= j && i - j <= bw) ? A(i, j) : 0.0;
+    }
+    for (int r = tid; r < m; r += CH_WG) yv[r] = y[k0 + r];
+    __syncthreads();
+    // y_c -= sum_{r >= kb} L(r, c) x_r   (x_r final for r beyond the panel)
+    for (int c = tid; c < kb; c += CH_WG) {
+      double s = 0.0;
+      for (int r = kb; r < m; ++r) s += P[c * mmax + r] * yv[r];
+      yv[c] -= s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int c = kb - 1; c >= 0; --c) {
+        double s = yv[c];
+        for (int r = c + 1; r < kb; ++r) s -= P[c * mmax + r] * yv[r];
+        yv[c] = s / P[c * mmax + c];
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < kb; c += CH_WG) y[k0 + c] = yv[c];
+    __syncthreads();
+  }
+}
+
+size_t band_solve_lds(int bw) { return (static_cast<size_t>(CH_NB) * (bw + CH_NB) + bw + CH_NB) * 8; }
+
+// ---------------------------------------------------------------------------
+// update and norms
+// ---------------------------------------------------------------------------
+__global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+// a9: dF_b = B_b du_e; w_b -= x_r + X_F dF_b (generalized) or X_F dF_b
+// (classical predictor).  One work-group per RVE.
+__global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
+                           const double* __restrict__ X, double* __restrict__ w, int use_xr) {
+  const int b = blockIdx.x;
+  __shared__ double dF[9];
+  const int e = b / m.n_gp;
+  const int nd = m.nen * m.dim;
+  if (threadIdx.x < m.nF) {
+    const int i = threadIdx.x;
+    double v = 0.0;
+    for (int col = 0; col < nd; ++col) {
+      const int node = m.conn[e * m.nen + col / m.dim];
+      v += macro_B(m, b, i, col) * du[node * m.dim + col % m.dim];
+    }
+    dF[i] = v;
+  }
+  __syncthreads();
+  const int64_t fo = foff[b];
+  const int64_t flen = foff[b + 1] - fo;
+  const double* Xb = X + fo * (m.nF + 1);
+  for (int64_t t = threadIdx.x; t < flen; t += blockDim.x) {
+    double dw = use_xr ? Xb[m.nF * flen + t] : 0.0;
+    for (int j = 0; j < m.nF; ++j) dw += Xb[j * flen + t] * dF[j];
+    w[fo + t] -= dw;
+  }
+}
+
+// Norms of the convergence test: out = [||[R_free; R_micro]||, ||R_free||,
+// ||R_micro||, ||F_int||] with R_micro,b = wdet_b / |Omega| r_b.
+__global__ void __launch_bounds__(1024) k_norms(MacroArgs m, const double* __restrict__ r_true,
+                                                const double* __restrict__ f_int,
+                                                const double* __restrict__ rnorm2, double volume,
+                                                double* __restrict__ out) {
+  __shared__ double red[3][16];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < m.ndof; i += blockDim.x) {
+    if (!m.is_dir[i]) s[0] += r_true[i] * r_true[i];
+    s[2] += f_int[i] * f_int[i];
+  }
+  for (int b = threadIdx.x; b < m.n_rve; b += blockDim.x) {
+    const double sc = m.wdet[b] / volume;
+    s[1] += sc * sc * rnorm2[b];
+  }
+  for (int k = 0; k < 3; ++k) s[k] = wave_sum(s[k]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) red[k][wid] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int w = 0; w < static_cast<int>(blockDim.x + 63) / 64; ++w)
+      for (int k = 0; k < 3; ++k) t[k] += red[k][w];
+    out[0] = sqrt(t[0] + t[1]);
+    out[1] = sqrt(t[0]);
+    out[2] = sqrt(t[1]);
+    out[3] = sqrt(t[2]);
+  }
+}
+
+}  // namespace fe2

@@ -1,0 +1,51 @@
+// Macro-side kernels of libfe2 (FP64): geometry, gradients, assembly,
+// banded Cholesky, update and norms.
+#pragma once
+
+#include "elem2d.hpp"
+#include "fe2_internal.hpp"
+
+namespace fe2 {
+
+struct MacroArgs {
+  int n_rve, dim, nen, n_gp, nF, kin, n_elems, ndof, bw;
+  const int* conn;        // [n_elems][nen]
+  const double* X;        // [n_nodes][dim]
+  double* dNdX;           // [n_rve][nen][dim]
+  double* wdet;           // [n_rve]
+  const double* f_ext;    // [ndof] or null
+  const int* is_dir;      // [ndof]
+  const double* dir_full; // [ndof] prescribed value at load factor 1 (0 on free DOFs)
+  const int* vec_ptr;     // [ndof+1] row -> element-vector entries
+  const int* vec_src;     //          index e*nd + a
+  const int* nz_ptr;      // [ndof+1] row -> nonzero columns
+  const int* nz_col;
+  const int* nzc_ptr;     // [nnz+1] nonzero -> element-matrix entries
+  const int* nzc_src;     //          index (e*nd + a)*nd + c
+};
+
+__global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out);
+__global__ void k_macro_geometry(MacroArgs m);
+__global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* __restrict__ out);
+__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f);
+__global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke);
+__global__ void k_macro_rows_vec(MacroArgs m, const double* __restrict__ f_true,
+                                 const double* __restrict__ f_hat, double lam,
+                                 double* __restrict__ r_true, double* __restrict__ f_int,
+                                 double* __restrict__ rhs);
+__global__ void k_macro_rows_band(MacroArgs m, const double* __restrict__ ke, double dlam,
+                                  double* __restrict__ band, double* __restrict__ rhs,
+                                  double* __restrict__ kdense);
+__global__ void k_fill(double* p, size_t n, double v);
+__global__ void k_fill_i(int* p, size_t n, int v);
+__global__ void k_band_cholesky_solve(int n, int bw, double* __restrict__ band,
+                                      double* __restrict__ y, int* __restrict__ info);
+size_t band_solve_lds(int bw);
+__global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y);
+__global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
+                           const double* __restrict__ X, double* __restrict__ w, int use_xr);
+__global__ void k_norms(MacroArgs m, const double* __restrict__ r_true,
+                        const double* __restrict__ f_int, const double* __restrict__ rnorm2,
+                        double volume, double* __restrict__ out);
+
+}  // namespace fe2

@@ -1,0 +1,572 @@
+// RVE element integration, periodic null-space solve and condensation for
+// two-dimensional small-strain RVEs (Q4, plane strain, linear isotropic
+// phases), one work-group per RVE.
+//
+// Method (Hesch, Schmidt, Schuss, arXiv:2312.12771):
+//   * micro residual r_b = K_wF eps_b + K_ww w_b and stress integral
+//     int sigma~ = K_FF eps_b + K_wF^T w_b (Eqs. (34)-(35), (17));
+//   * solve K_ww [X_F | x_r] = [K_wF | r_b] (the RVE block of L in Eq. (42))
+//     with the periodic null space of condition (iii) in Eq. (15): periodic
+//     node identification and a pinned corner node;
+//   * condensation Cbar = (K_FF - K_wF^T X_F)/|Omega|,
+//     Phat = (int sigma~ - K_wF^T x_r)/|Omega| (Eqs. (46)-(48)).
+//
+// GPU design
+//   * Every RVE element has stiffness mu_e * K_ref (all phases of a
+//     resolution class share lambda/mu).  K_ref of the bilinear box element
+//     has ten distinct entries; the operator is applied matrix-free from those
+//     ten scalars (held in scalar registers) and one scale per element in LDS.
+//   * Each thread owns a 2x2 block of nodes and gathers the 4x4 neighbourhood
+//     of the search direction.  Vectors live in LDS with a one-node periodic
+//     halo, so the neighbourhood is a contiguous window addressed from one
+//     base register with immediate offsets; node-centric gather, no scatter,
+//     no atomics, deterministic.
+//   * RVE sizes are compile-time template parameters.
+//   * PCG state lives in registers and LDS; HBM is touched only for phase ids,
+//     the state w and the outputs.
+//   * Precision: the inner PCG runs in TI (float for the FP32_IR form, double
+//     for plain FP64).  An outer refinement loop forms the true residual in
+//     FP64 from the FP64 solution kept in the output buffer; the condensation
+//     uses the FP64 residual to correct the Schur product (energy form, error
+//     quadratic in the solve error).
+#include "elem2d.hpp"
+#include "fe2_internal.hpp"
+
+namespace fe2 {
+
+namespace {
+
+constexpr int NF = 3;
+
+// Element q (0..3) around an owned node (di, dj): position of the element's
+// lower-left node in the 3x3 element neighbourhood and the local corner the
+// node occupies in it.
+__host__ __device__ constexpr int elem_ea(int di, int q) { return di + ((q == 1 || q == 2) ? 1 : 0); }
+__host__ __device__ constexpr int elem_ec(int dj, int q) { return dj + (q >= 2 ? 1 : 0); }
+__host__ __device__ constexpr int elem_cc(int q) { return (q + 2) & 3; }
+
+template <typename V>
+__device__ __forceinline__ V kfma(const V (&kv)[10], int r, int c, V x, V acc) {
+  return kref_sign(r, c) > 0 ? fma(kv[kref_id(r, c)], x, acc) : fma(-kv[kref_id(r, c)], x, acc);
+}
+
+// Padded (halo) layout of a periodic N1 x N2 nodal or element field:
+// entry (i, j), i in [-1, N1], j in [-1, N2], at (j+1)*PW + (i+1).  Odd
+// sizes get one more unused column/row so that the 4x4 window of the last,
+// partial 2x2 block stays inside the array.
+__host__ __device__ constexpr int pad_w(int n) { return n + 2 + (n & 1); }
+template <int N1, int N2>
+struct Pad {
+  static constexpr int PW = pad_w(N1);
+  static constexpr int PN = pad_w(N1) * pad_w(N2);
+  static __host__ __device__ constexpr int at(int i, int j) { return (j + 1) * PW + (i + 1); }
+};
+
+// Write value v of real node/element (i, j) and its halo images.
+template <int N1, int N2, typename V>
+__device__ __forceinline__ void put_halo(V* f, int i, int j, V v) {
+  using P = Pad<N1, N2>;
+  f[P::at(i, j)] = v;
+  const int ig = (i == 0) ? N1 : ((i == N1 - 1) ? -1 : -2);
+  const int jg = (j == 0) ? N2 : ((j == N2 - 1) ? -1 : -2);
+  if (ig != -2) f[P::at(ig, j)] = v;
+  if (jg != -2) f[P::at(i, jg)] = v;
+  if (ig != -2 && jg != -2) f[P::at(ig, jg)] = v;
+}
+
+// y = K v for the four nodes of the owned block.  pb points at the padded
+// entry of node (i0-1, j0-1) of component x (component y follows at +PN);
+// eb at the padded element (i0-1, j0-1).
+template <int N1, int N2, typename V>
+__device__ __forceinline__ void mv_block(const V* __restrict__ pb, const V* __restrict__ eb,
+                                         const V (&kv)[10], V (&y)[4][2]) {
+  using P = Pad<N1, N2>;
+  V ux[4][4], uy[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ux[c][a] = pb[c * P::PW + a];
+      uy[c][a] = pb[P::PN + c * P::PW + a];
+    }
+  V se[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) se[c][a] = eb[c * P::PW + a];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int di = k & 1, dj = k >> 1;
+    V acc0 = V(0), acc1 = V(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ea = elem_ea(di, q), ec = elem_ec(dj, q), cc = elem_cc(q);
+      V t0 = V(0), t1 = V(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const V vx = ux[ec + cyo(m)][ea + cxo(m)];
+        const V vy = uy[ec + cyo(m)][ea + cxo(m)];
+        t0 = kfma(kv, 2 * cc, 2 * m, vx, t0);
+        t0 = kfma(kv, 2 * cc, 2 * m + 1, vy, t0);
+        t1 = kfma(kv, 2 * cc + 1, 2 * m, vx, t1);
+        t1 = kfma(kv, 2 * cc + 1, 2 * m + 1, vy, t1);
+      }
+      acc0 = fma(se[ec][ea], t0, acc0);
+      acc1 = fma(se[ec][ea], t1, acc1);
+    }
+    y[k][0] = acc0;
+    y[k][1] = acc1;
+  }
+}
+
+template <int N1, int N2>
+__device__ __forceinline__ double elem_scale(const double* __restrict__ eb, int di, int dj, int q) {
+  return eb[elem_ec(dj, q) * Pad<N1, N2>::PW + elem_ea(di, q)];
+}
+
+// Column j of K_wF at owned node (di, dj), component d.
+template <int N1, int N2>
+__device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const double (&KwF)[8 * NF],
+                                           int di, int dj, int d, int j) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s += elem_scale<N1, N2>(eb, di, dj, q) * KwF[(2 * elem_cc(q) + d) * NF + j];
+  return s;
+}
+
+// Work-group sum with two alternating reduction buffers (one barrier each).
+template <int NV, int NW>
+__device__ __forceinline__ void wg_sum(double (&v)[NV], double* s_red, int& parity) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  double* buf = s_red + parity * (NW * NV);
+  parity ^= 1;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += buf[w * NV + i];
+    v[i] = t;
+  }
+}
+
+}  // namespace
+
+// LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
+// one search direction [2][PN] in TI aliased with the FP64 staging [2][PN].
+__host__ __device__ constexpr size_t lin2d_red_doubles(int nw, int nrhs) {
+  return 2 * static_cast<size_t>(nw) * (2 * NF * nrhs > 5 ? 2 * NF * nrhs : 5);
+}
+__host__ __device__ constexpr size_t lin2d_vec_offset(int n1, int n2, int wg, int nrhs) {
+  return ((lin2d_red_doubles(wg / 64, nrhs) * 8 + static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 12) + 15) &
+         ~static_cast<size_t>(15);
+}
+__host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs) {
+  return lin2d_vec_offset(n1, n2, wg, nrhs) + 2 * static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 8;
+}
+
+template <typename TI, int NRHS, int N1, int N2, int WG>
+__global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
+  using P = Pad<N1, N2>;
+  constexpr int NW = WG / 64;
+  constexpr int NN = N1 * N2;
+  constexpr int NB1 = (N1 + 1) / 2, NB2 = (N2 + 1) / 2;
+  static_assert(NB1 * NB2 <= WG, "work-group too small for the RVE");
+  const int tid = threadIdx.x;
+  const int b = a.rve_list[blockIdx.x];
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* s_red = reinterpret_cast<double*>(smem);
+  double* s_sc = s_red + lin2d_red_doubles(NW, NRHS);                    // [PN] FP64
+  float* s_sc32 = reinterpret_cast<float*>(s_sc + P::PN);                 // [PN] FP32
+  unsigned char* s_vec = smem + lin2d_vec_offset(N1, N2, WG, NRHS);
+  TI* s_p = reinterpret_cast<TI*>(s_vec);          // [2][PN] search direction
+  double* s_st = reinterpret_cast<double*>(s_vec);  // [2][PN] FP64 staging (aliases s_p)
+  int parity = 0;
+
+  // ---- reference element scalars (uniform: scalar registers) -------------
+  double kv64[10];
+  TI kvI[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    kv64[t] = a.kv64[t];
+    kvI[t] = static_cast<TI>(kv64[t]);
+  }
+  double KwF[8 * NF];
+#pragma unroll
+  for (int t = 0; t < 8 * NF; ++t) KwF[t] = a.KwF64[t];
+
+  // ---- ownership of a 2x2 node block -------------------------------------
+  const bool own = tid < NB1 * NB2;
+  const int I = own ? tid % NB1 : 0;
+  const int J = own ? tid / NB1 : 0;
+  const int i0 = 2 * I, j0 = 2 * J;
+  bool exists[4], dof[4];
+  int pidx[4];   // padded index of each owned node
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = i0 + (k & 1), j = j0 + (k >> 1);
+    exists[k] = own && i < N1 && j < N2;
+    dof[k] = exists[k] && (i | j) != 0;   // corner node 0 is pinned
+    pidx[k] = P::at(i, j);
+  }
+  const int base = P::at(i0 - 1, j0 - 1);
+  auto node_of = [&](int k) { return (j0 + (k >> 1)) * N1 + i0 + (k & 1); };
+
+  // ---- element scales (mu of the phase), padded --------------------------
+  const double* par = a.params + static_cast<size_t>(b) * 4;
+  const double mu0 = par[1], mu1 = par[3];
+  const uint8_t* ph = a.phase + a.phase_off[b];
+  double ssum = 0.0;
+  for (int e = tid; e < NN; e += WG) {
+    const double s = ph[e] ? mu1 : mu0;
+    const int i = e % N1, j = e / N1;
+    put_halo<N1, N2>(s_sc, i, j, s);
+    put_halo<N1, N2>(s_sc32, i, j, static_cast<float>(s));
+    ssum += s;
+  }
+  __syncthreads();
+  const double* eb = s_sc + base;
+  const TI* ebI;
+  if constexpr (sizeof(TI) == 4) ebI = reinterpret_cast<const TI*>(s_sc32 + base);
+  else ebI = reinterpret_cast<const TI*>(s_sc + base);
+
+  const int64_t fo = a.foff[b];
+  constexpr int64_t flen = 2 * NN;
+  double* Xb = a.X + fo * (NF + 1);
+  const double V = a.volume;
+  double eps[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) eps[j] = a.macro[static_cast<size_t>(b) * NF + j];
+
+  auto stage = [&](const double* src) {   // periodic field -> padded FP64 staging
+    for (int n = tid; n < NN; n += WG) {
+      const int i = n % N1, j = n / N1;
+      put_halo<N1, N2>(s_st, i, j, src[2 * n]);
+      put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
+    }
+  };
+
+  // ---- a3: residual and stress integral at (eps_b, w_b) ------------------
+  double Pint[NF];
+  if (a.flags & RVE_ASSEMBLE) {
+    stage(a.w + fo);
+    __syncthreads();
+    double y[4][2];
+    mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+    double red[5] = {0.0, 0.0, 0.0, 0.0, ssum};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!exists[k]) continue;
+      const int di = k & 1, dj = k >> 1;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        double rv = 0.0;
+        if (dof[k]) {
+          rv = y[k][d];
+#pragma unroll
+          for (int j = 0; j < NF; ++j) rv += bF_entry<N1, N2>(eb, KwF, di, dj, d, j) * eps[j];
+        }
+        a.r[fo + 2 * node_of(k) + d] = rv;
+        red[0] += rv * rv;
+        const double wv = s_st[d * P::PN + pidx[k]];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) red[1 + j] += bF_entry<N1, N2>(eb, KwF, di, dj, d, j) * wv;
+      }
+    }
+    wg_sum<5, NW>(red, s_red, parity);
+    ssum = red[4];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      double kf = 0.0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) kf += a.KFF64[i * NF + j] * eps[j];
+      Pint[i] = ssum * kf + red[1 + i];
+    }
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) a.Pbar[static_cast<size_t>(b) * NF + i] = Pint[i] / V;
+      a.rnorm2[b] = red[0];
+    }
+  } else {
+    double red[1] = {ssum};
+    wg_sum<1, NW>(red, s_red, parity);
+    ssum = red[0];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
+  }
+  if (!(a.flags & RVE_SOLVE)) return;
+
+  // ---- a5: per column, FP64 refinement around the inner PCG --------------
+  TI dinv[4][2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int di = k & 1, dj = k >> 1;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      double dg = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 2 * elem_cc(q) + d;
+        dg += elem_scale<N1, N2>(eb, di, dj, q) * kv64[kref_id(r, r)];
+      }
+      dinv[k][d] = dof[k] ? static_cast<TI>(1.0 / dg) : TI(0);
+    }
+  }
+  const bool warm = (a.flags & RVE_WARM) != 0;
+  const double tin2 = a.tol_in * a.tol_in;
+  const double tol2 = a.tol * a.tol;
+  int iters = 0;
+  bool all_ok = true;
+  double worst = 0.0;
+
+#pragma unroll 1
+  for (int kc = 0; kc < NRHS; ++kc) {
+    double* xc = Xb + kc * flen;
+    bool xzero = !warm;
+    if (xzero) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (exists[k]) {
+          xc[2 * node_of(k)] = 0.0;
+          xc[2 * node_of(k) + 1] = 0.0;
+        }
+    }
+#pragma unroll 1
+    for (int sweep = 0;; ++sweep) {
+      // FP64 residual r = b - K x of this column
+      double y[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+      if (!xzero) {
+        __syncthreads();   // earlier readers of the staging buffer are done
+        stage(xc);
+        __syncthreads();
+        mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+      }
+      TI ri[4][2];
+      double red[2] = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int di = k & 1, dj = k >> 1;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          double r64 = 0.0;
+          if (dof[k]) {
+            const double bk = (kc < NF) ? bF_entry<N1, N2>(eb, KwF, di, dj, d, kc)
+                                        : a.r[fo + 2 * node_of(k) + d];
+            r64 = bk - y[k][d];
+            red[0] += r64 * r64;
+            red[1] += bk * bk;
+          }
+          ri[k][d] = static_cast<TI>(r64);
+        }
+      }
+      wg_sum<2, NW>(red, s_red, parity);
+      const double rel = red[1] > 0.0 ? sqrt(red[0] / red[1]) : 0.0;
+      if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
+        worst = rel > worst ? rel : worst;
+        break;
+      }
+      if (sweep >= a.max_ir) {
+        worst = rel > worst ? rel : worst;
+        all_ok = false;
+        break;
+      }
+      // ---- inner PCG on K d = r (precision TI, Jacobi preconditioner) -----
+      __syncthreads();   // staging reads finished before s_p is written
+      TI xi[4][2];
+      double rz, r0;
+      {
+        double red2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            xi[k][d] = TI(0);
+            const TI z = dinv[k][d] * ri[k][d];
+            if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), z);
+            red2[0] += static_cast<double>(ri[k][d]) * static_cast<double>(z);
+            red2[1] += static_cast<double>(ri[k][d]) * static_cast<double>(ri[k][d]);
+          }
+        wg_sum<2, NW>(red2, s_red, parity);
+        rz = red2[0];
+        r0 = red2[1];
+      }
+#pragma unroll 1
+      for (int it = 0; it < a.max_it; ++it) {
+        __syncthreads();   // search direction visible
+        ++iters;
+        TI q[4][2];
+        mv_block<N1, N2, TI>(s_p + base, ebI, kvI, q);
+        TI pown[4][2];
+        double pq[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            pown[k][d] = s_p[d * P::PN + pidx[k]];
+            if (!dof[k]) q[k][d] = TI(0);
+            pq[0] += static_cast<double>(pown[k][d]) * static_cast<double>(q[k][d]);
+          }
+        wg_sum<1, NW>(pq, s_red, parity);
+        const TI alpha = static_cast<TI>(rz / pq[0]);
+        double red2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            xi[k][d] = fma(alpha, pown[k][d], xi[k][d]);
+            ri[k][d] = fma(-alpha, q[k][d], ri[k][d]);
+            const double rv = static_cast<double>(ri[k][d]);
+            red2[0] += rv * static_cast<double>(dinv[k][d] * ri[k][d]);
+            red2[1] += rv * rv;
+          }
+        wg_sum<2, NW>(red2, s_red, parity);
+        if (red2[1] <= tin2 * r0) break;
+        const TI beta = static_cast<TI>(red2[0] / rz);
+        rz = red2[0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            if (exists[k])
+              put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1),
+                               fma(beta, pown[k][d], dinv[k][d] * ri[k][d]));
+      }
+      // x64 += x_inner (FP64 accumulation in the output column)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+          if (exists[k]) xc[2 * node_of(k) + d] += static_cast<double>(xi[k][d]);
+      xzero = false;
+    }
+  }
+  if constexpr (NRHS == NF) {   // residual column not solved: x_r = 0
+    double* xc = Xb + NF * flen;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (exists[k]) {
+        xc[2 * node_of(k)] = 0.0;
+        xc[2 * node_of(k) + 1] = 0.0;
+      }
+  }
+
+  // ---- a6: condensation (energy form) from a final FP64 pass -------------
+  //   G1[i][j] = b_i . x_j,  G2[i][j] = x_i . (b_j - K x_j)
+  double G[2 * NF * NRHS];
+#pragma unroll
+  for (int i = 0; i < 2 * NF * NRHS; ++i) G[i] = 0.0;
+#pragma unroll 1
+  for (int jc = 0; jc < NRHS; ++jc) {
+    const double* xc = Xb + jc * flen;
+    __syncthreads();   // global writes of X visible, staging free
+    stage(xc);
+    __syncthreads();
+    double y[4][2];
+    mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+    double g1[NF] = {0.0, 0.0, 0.0}, g2[NF] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!dof[k]) continue;
+      const int di = k & 1, dj = k >> 1;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const double bj = (jc < NF) ? bF_entry<N1, N2>(eb, KwF, di, dj, d, jc)
+                                    : a.r[fo + 2 * node_of(k) + d];
+        const double xj = s_st[d * P::PN + pidx[k]];
+        const double res = bj - y[k][d];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          g1[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj;
+          const double xi_ = (i == jc) ? xj : Xb[i * flen + 2 * node_of(k) + d];
+          g2[i] += xi_ * res;
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < NRHS; ++jj)
+      if (jj == jc) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          G[i * NRHS + jj] = g1[i];
+          G[NF * NRHS + i * NRHS + jj] = g2[i];
+        }
+      }
+  }
+  wg_sum<2 * NF * NRHS, NW>(G, s_red, parity);
+  if (tid == 0) {
+    a.relres[b] = worst;
+    a.iters[b] = static_cast<double>(iters);
+    if (!all_ok) atomicAdd(a.fail_count, 1);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        a.Cbar[static_cast<size_t>(b) * NF * NF + i * NF + j] =
+            (ssum * a.KFF64[i * NF + j] - G[i * NRHS + j] - G[NF * NRHS + i * NRHS + j]) / V;
+      double ph_i = Pint[i];
+      if constexpr (NRHS > NF) ph_i -= G[i * NRHS + NF] + G[NF * NRHS + i * NRHS + NF];
+      a.Phat[static_cast<size_t>(b) * NF + i] = ph_i / V;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch: dispatch on the compile-time RVE size
+// ---------------------------------------------------------------------------
+static constexpr int wg_for(int n1, int n2) {
+  return 64 * ((((n1 + 1) / 2) * ((n2 + 1) / 2) + 63) / 64);
+}
+
+size_t lin2d_lds_bytes(int n1, int n2, int nrhs) {
+  return lin2d_lds_bytes_t(n1, n2, wg_for(n1, n2), nrhs);
+}
+
+template <typename TI, int NRHS, int N1, int N2>
+static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
+  constexpr int WG = wg_for(N1, N2);
+  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS);
+  static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
+  auto kern = &k_lin2d<TI, NRHS, N1, N2, WG>;
+  if (lds > 64 * 1024)
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(n_launch), dim3(WG), lds, s, a);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+template <int N1, int N2>
+static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
+  if (precision == FE2_PREC_FP64)
+    return nrhs == 3 ? launch_t<double, 3, N1, N2>(a, n_launch, s) : launch_t<double, 4, N1, N2>(a, n_launch, s);
+  return nrhs == 3 ? launch_t<float, 3, N1, N2>(a, n_launch, s) : launch_t<float, 4, N1, N2>(a, n_launch, s);
+}
+
+#define FE2_LIN2D_SIZES(X) X(4, 4) X(6, 10) X(8, 8) X(10, 10) X(15, 15) X(16, 16) X(17, 17) X(30, 30) X(32, 32) X(48, 48)
+
+bool lin2d_supported(int n1, int n2) {
+#define FE2_CASE(A, B) if (n1 == A && n2 == B) return true;
+  FE2_LIN2D_SIZES(FE2_CASE)
+#undef FE2_CASE
+  return false;
+}
+
+int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
+  if (n_launch <= 0) return FE2_OK;
+#define FE2_CASE(A, B) \
+  if (a.n1 == A && a.n2 == B) return launch_n<A, B>(a, n_launch, precision, nrhs, s);
+  FE2_LIN2D_SIZES(FE2_CASE)
+#undef FE2_CASE
+  set_error("RVE resolution has no compiled 2D kernel");
+  return FE2_ENOTSUP;
+}
+
+}  // namespace fe2

@@ -1,0 +1,257 @@
+"""Python binding of libfe2 (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/fe2.h with the
+same name; all arithmetic of the hot path runs in the library's HIP kernels.
+Device buffers are torch tensors (float64, contiguous, on the current HIP
+device) and streams are torch streams.  Importing this module fails loudly
+when the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe2.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: run paper_2312_12771_amd/build.py "
+                      "(or __graft_entry__.build()) first")
+_lib = C.CDLL(LIB_PATH)
+
+# status codes and enums (include/fe2.h)
+FE2_OK, FE2_CONVERGED = 0, 1
+FE2_EINVAL, FE2_ENOMEM, FE2_EHIP, FE2_ENOCONV, FE2_ESTATE, FE2_ENOTSUP = -1, -2, -3, -4, -5, -6
+FE2_SMALL_STRAIN, FE2_FINITE_STRAIN = 0, 1
+FE2_LINEAR_ISO, FE2_NEO_HOOKE, FE2_MOONEY_RIVLIN = 0, 1, 2
+FE2_PREC_FP64, FE2_PREC_FP32_IR = 0, 1
+FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT = 0, 1, 2
+FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
+(FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
+ FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
+ FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT) = range(12)
+(FE2_Q_NF, FE2_Q_FIELD_LEN, FE2_Q_NDOF, FE2_Q_BANDWIDTH, FE2_Q_FAILED_RVES,
+ FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS) = range(7)
+
+_KIN = {"small": FE2_SMALL_STRAIN, "finite": FE2_FINITE_STRAIN}
+_MAT = {"linear": FE2_LINEAR_ISO, "neohooke": FE2_NEO_HOOKE,
+        "mooney_rivlin": FE2_MOONEY_RIVLIN}
+_PREC = {"fp64": FE2_PREC_FP64, "fp32_ir": FE2_PREC_FP32_IR}
+
+
+class fe2_problem_desc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32),
+        ("dim", C.c_int32), ("kinematics", C.c_int32), ("material", C.c_int32),
+        ("n_nodes", C.c_int32), ("X", C.POINTER(C.c_double)),
+        ("n_elems", C.c_int32), ("conn", C.POINTER(C.c_int32)),
+        ("n_dir", C.c_int32), ("dir_dofs", C.POINTER(C.c_int32)),
+        ("dir_vals", C.POINTER(C.c_double)),
+        ("f_ext", C.POINTER(C.c_double)),
+        ("n_rve", C.c_int32), ("rve_res", C.POINTER(C.c_int32)),
+        ("rve_off", C.POINTER(C.c_int64)), ("phase_id", C.POINTER(C.c_uint8)),
+        ("n_phase_params", C.c_int32), ("phase_params", C.POINTER(C.c_double)),
+        ("rve_size", C.c_double),
+        ("precision", C.c_int32), ("solver", C.c_int32), ("scheme", C.c_int32),
+        ("rve_tol", C.c_double), ("inner_tol", C.c_double),
+        ("newton_tol", C.c_double), ("micro_tol", C.c_double),
+        ("max_pcg_it", C.c_int32), ("max_ir", C.c_int32), ("max_micro_it", C.c_int32),
+    ]
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_sig = {
+    "fe2_setup": (C.c_int, [C.POINTER(fe2_problem_desc), _vp, C.POINTER(_vp)]),
+    "fe2_assemble_rve": (C.c_int, [_vp, _vp]),
+    "fe2_condense": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "fe2_newton_step": (C.c_int, [_vp, C.c_double, _dp, _vp]),
+    "fe2_get_state": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "fe2_set_state": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp]),
+    "fe2_get_data": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "fe2_query": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int64)]),
+    "fe2_destroy": (C.c_int, [_vp]),
+    "fe2_strerror": (C.c_char_p, [C.c_int]),
+    "fe2_last_error": (C.c_char_p, []),
+    "fe2_abi_version": (C.c_int, []),
+}
+for _n, (_r, _a) in _sig.items():
+    _f = getattr(_lib, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+
+
+class FE2Error(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.fe2_last_error().decode()
+        super().__init__(f"{where}: {_lib.fe2_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str, allow=(FE2_OK,)):
+    if status not in allow:
+        raise FE2Error(status, where)
+    return status
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("device buffers must be contiguous float64 tensors on the GPU")
+    return _vp(t.data_ptr())
+
+
+class Handle:
+    """Owns an fe2_handle; ``close()`` (or garbage collection) destroys it."""
+
+    def __init__(self, ptr: _vp):
+        self._ptr = ptr
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("handle is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr is not None:
+            _lib.fe2_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def fe2_setup(problem, precision: str = "fp64", solver: str = "auto",
+              scheme: str = "generalized", rve_tol: float = 1e-10, inner_tol: float = 1e-4,
+              newton_tol: float = 1e-10, micro_tol: float = 1e-13, max_pcg_it: int = 4000,
+              max_ir: int = 8, max_micro_it: int = 30, stream=None) -> Handle:
+    """Create a handle from a problem description (any object with the
+    attributes of workloads.Problem)."""
+    keep = dict(
+        X=_arr(problem.X, np.float64), conn=_arr(problem.conn, np.int32),
+        dd=_arr(problem.dir_dofs, np.int32), dv=_arr(problem.dir_vals, np.float64),
+        fe=_arr(problem.f_ext, np.float64), res=_arr(problem.rve_res, np.int32),
+        off=_arr(problem.rve_off, np.int64), ph=_arr(problem.phase_id, np.uint8),
+        pp=_arr(problem.phase_params, np.float64))
+    d = fe2_problem_desc()
+    d.struct_size = C.sizeof(fe2_problem_desc)
+    d.dim = int(problem.dim)
+    d.kinematics = _KIN[problem.kinematics]
+    d.material = _MAT[problem.material]
+    d.n_nodes = keep["X"].shape[0]
+    d.X = keep["X"].ctypes.data_as(_dp)
+    d.n_elems = keep["conn"].shape[0]
+    d.conn = keep["conn"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.n_dir = keep["dd"].size
+    d.dir_dofs = keep["dd"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.dir_vals = keep["dv"].ctypes.data_as(_dp)
+    d.f_ext = keep["fe"].ctypes.data_as(_dp) if np.any(keep["fe"]) else C.cast(None, _dp)
+    d.n_rve = keep["res"].shape[0]
+    d.rve_res = keep["res"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.rve_off = keep["off"].ctypes.data_as(C.POINTER(C.c_int64))
+    d.phase_id = keep["ph"].ctypes.data_as(C.POINTER(C.c_uint8))
+    d.n_phase_params = keep["pp"].shape[2]
+    d.phase_params = keep["pp"].ctypes.data_as(_dp)
+    d.rve_size = float(problem.rve_size)
+    d.precision = _PREC[precision]
+    d.solver = {"auto": FE2_SOLVER_AUTO, "jacobi": FE2_SOLVER_PCG_JACOBI,
+                "fft": FE2_SOLVER_PCG_FFT}[solver]
+    d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL}[scheme]
+    d.rve_tol, d.inner_tol, d.newton_tol, d.micro_tol = rve_tol, inner_tol, newton_tol, micro_tol
+    d.max_pcg_it, d.max_ir, d.max_micro_it = max_pcg_it, max_ir, max_micro_it
+    out = _vp()
+    _check(_lib.fe2_setup(C.byref(d), _stream_ptr(stream), C.byref(out)), "fe2_setup")
+    return Handle(out)
+
+
+def fe2_assemble_rve(h: Handle, stream=None):
+    return _check(_lib.fe2_assemble_rve(h.ptr, _stream_ptr(stream)), "fe2_assemble_rve")
+
+
+def fe2_condense(h: Handle, Cbar=None, Phat=None, stream=None, allow_noconv=False):
+    allow = (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,)
+    return _check(_lib.fe2_condense(h.ptr, _dev_ptr(Cbar), _dev_ptr(Phat), _stream_ptr(stream)),
+                  "fe2_condense", allow)
+
+
+def fe2_newton_step(h: Handle, load_factor: float, stream=None):
+    """Returns (status, norms[4]) with status FE2_OK or FE2_CONVERGED."""
+    norms = np.zeros(4)
+    st = _lib.fe2_newton_step(h.ptr, float(load_factor), norms.ctypes.data_as(_dp),
+                              _stream_ptr(stream))
+    _check(st, "fe2_newton_step", (FE2_OK, FE2_CONVERGED))
+    return st, norms
+
+
+def fe2_get_state(h: Handle, u=None, w=None, stream=None):
+    return _check(_lib.fe2_get_state(h.ptr, _dev_ptr(u), _dev_ptr(w), _stream_ptr(stream)),
+                  "fe2_get_state")
+
+
+def fe2_set_state(h: Handle, u=None, w=None, load_factor: float = 0.0, stream=None):
+    return _check(_lib.fe2_set_state(h.ptr, _dev_ptr(u), _dev_ptr(w), float(load_factor),
+                                     _stream_ptr(stream)), "fe2_set_state")
+
+
+def fe2_get_data(h: Handle, which: int, dst, stream=None):
+    return _check(_lib.fe2_get_data(h.ptr, int(which), _dev_ptr(dst), _stream_ptr(stream)),
+                  "fe2_get_data")
+
+
+def fe2_query(h: Handle, which: int):
+    if which == FE2_Q_FIELD_OFFSETS:
+        n = fe2_query(h, FE2_Q_N_RVE)
+        out = np.zeros(n + 1, dtype=np.int64)
+        _check(_lib.fe2_query(h.ptr, which, out.ctypes.data_as(C.POINTER(C.c_int64))), "fe2_query")
+        return out
+    v = C.c_int64()
+    _check(_lib.fe2_query(h.ptr, int(which), C.byref(v)), "fe2_query")
+    return int(v.value)
+
+
+def fe2_destroy(h: Handle):
+    h.close()
+
+
+def abi_version() -> int:
+    return int(_lib.fe2_abi_version())
+
+
+# --------------------------------------------------------------------------
+# host-side driver: load stepping around fe2_newton_step
+# --------------------------------------------------------------------------
+
+def solve(h: Handle, load_factors, max_it: int = 20, stream=None, history: Optional[list] = None):
+    """Load stepping: for every load factor call fe2_newton_step until it
+    reports convergence.  Raises RuntimeError when a step exceeds max_it."""
+    for lam in load_factors:
+        h_step = []
+        for it in range(max_it + 1):
+            st, norms = fe2_newton_step(h, lam, stream)
+            h_step.append(norms)
+            if st == FE2_CONVERGED:
+                break
+        else:
+            raise RuntimeError(f"no convergence at load factor {lam}")
+        if history is not None:
+            history.append(h_step)
+    return h

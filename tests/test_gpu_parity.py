@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every hot-path row is compared element by element on the same seeded inputs:
+macro gradients (a2), RVE residual and stress integral (a3) in the periodic
+numbering (a4), RVE solutions (a5), condensed tangent and stress (a6), macro
+right-hand side and increment (a7, a8), fluctuation update (a9) and the
+residual norms (a10).  Tolerances: 1e-10 relative for the plain FP64 path and
+for the FP32 PCG with FP64 refinement driven to rve_tol = 1e-11; the looser
+mixed form used by the benchmark (rve_tol = 1e-4, energy-form condensation)
+must stay within 1e-6 on Cbar.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import macro as M
+from oracle import rve as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe2():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2312_12771_amd import fe2 as f
+    return f
+
+
+def dz(n):
+    return torch.zeros(int(n), dtype=torch.float64, device="cuda")
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def get(fe2, h, which, n):
+    t = dz(n)
+    fe2.fe2_get_data(h, which, t)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def random_state(p, seed, amp=1e-3):
+    """A nonzero macro displacement and periodic fluctuation (corner 0)."""
+    rng = np.random.default_rng(seed)
+    u = amp * rng.standard_normal(p.n_dofs)
+    ws = []
+    for b in range(p.n_rve):
+        w = amp * rng.standard_normal(int(np.prod(p.rve_res[b])) * p.dim)
+        w[:p.dim] = 0.0
+        ws.append(w)
+    return u, ws
+
+
+def set_state(fe2, h, u, ws, lam=0.0):
+    fe2.fe2_set_state(h, u=torch.tensor(u, device="cuda"),
+                      w=torch.tensor(np.concatenate(ws), device="cuda"), load_factor=lam)
+
+
+def small_problem(name, **kw):
+    return W.config(name, **kw)
+
+
+CASES = [
+    ("cfg1", dict(macro=(2, 2))),                       # 8x8 laminate
+    ("cfg2", dict(macro=(2, 1), rve=15)),               # odd size: ragged 2x2 blocks
+    ("cfg2", dict(macro=(1, 1), rve=32)),               # the benchmark RVE size
+    ("cfg3", dict(macro=(3, 3), resolutions=(16, 32, 48))),  # uneven batch, 3 classes
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_rows_a2_to_a6_at_nonzero_state(fe2, name, kw, prec):
+    p = small_problem(name, **kw)
+    u, ws = random_state(p, 7)
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    set_state(fe2, h, u, ws)
+    fe2.fe2_assemble_rve(h)
+    nF = fe2.fe2_query(h, fe2.FE2_Q_NF)
+    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
+    off = fe2.fe2_query(h, fe2.FE2_Q_FIELD_OFFSETS)
+    mg = get(fe2, h, fe2.FE2_D_MACRO_GRAD, p.n_rve * nF).reshape(p.n_rve, nF)
+    res = get(fe2, h, fe2.FE2_D_RESIDUAL, flen)
+    pbar = get(fe2, h, fe2.FE2_D_PBAR, p.n_rve * nF).reshape(p.n_rve, nF)
+    Cb, Ph = dz(p.n_rve * nF * nF), dz(p.n_rve * nF)
+    fe2.fe2_condense(h, Cb, Ph)
+    torch.cuda.synchronize()
+    Cb = Cb.cpu().numpy().reshape(p.n_rve, nF, nF)
+    Ph = Ph.cpu().numpy().reshape(p.n_rve, nF)
+    sol = get(fe2, h, fe2.FE2_D_SOLUTION, flen * (nF + 1))
+    geo = M.macro_geometry(p)
+    for b in range(p.n_rve):
+        macro = M.macro_gradient(p, geo, u, b)
+        assert rel(mg[b], macro) < 1e-13
+        c = R.homogenize_rve(p, b, macro, ws[b])
+        s = c.system
+        fl = off[b + 1] - off[b]
+        assert rel(res[off[b]:off[b + 1]], R.expand(s, s.r)) < 1e-11
+        assert rel(pbar[b], c.P_bar) < 1e-12
+        assert rel(Cb[b], c.C) < 1e-10, (b, Cb[b], c.C)
+        assert rel(Ph[b], c.P_hat) < 1e-10
+        Xb = sol[off[b] * (nF + 1):off[b + 1] * (nF + 1)].reshape(nF + 1, fl)
+        for j in range(nF):
+            assert rel(Xb[j], R.expand(s, c.X_F[:, j])) < 1e-9
+        assert rel(Xb[nF], R.expand(s, c.x_r)) < 1e-9
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_rows_a7_to_a10_one_newton_step(fe2, prec):
+    """One generalized Newton iteration from a nonzero state with a pending
+    load increment: macro right-hand side, increment, updated u and w~ and
+    the norms of the linearisation state against the oracle step."""
+    p = small_problem("cfg2", macro=(3, 2), rve=16)
+    u, ws = random_state(p, 11, amp=2e-4)
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    set_state(fe2, h, u, ws, lam=0.25)
+    st, norms = fe2.fe2_newton_step(h, 0.5)
+    assert st == fe2.FE2_OK
+    du = get(fe2, h, fe2.FE2_D_MACRO_DU, p.n_dofs)
+    u_gpu, w_gpu = dz(p.n_dofs), dz(fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN))
+    fe2.fe2_get_state(h, u_gpu, w_gpu)
+    torch.cuda.synchronize()
+    geo = M.macro_geometry(p)
+    state = M.State(u=u.copy(), w=[w.copy() for w in ws], lam=0.25)
+    nrm, du_o, _, _ = M.generalized_step(p, geo, state, 0.5)
+    assert rel(du, du_o) < 1e-9
+    assert rel(u_gpu.cpu().numpy(), state.u) < 1e-12
+    assert rel(w_gpu.cpu().numpy(), np.concatenate(state.w)) < 1e-9
+    for a, b in zip(norms, [nrm.total, nrm.macro, nrm.micro, nrm.scale]):
+        assert abs(a - b) <= 1e-10 * max(abs(b), 1e-300)
+    h.close()
+
+
+def test_macro_tangent_dense_matches_oracle(fe2):
+    p = small_problem("cfg1", macro=(3, 2))
+    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-12)
+    fe2.fe2_newton_step(h, 1.0)
+    K = get(fe2, h, fe2.FE2_D_MACRO_KDENSE, p.n_dofs ** 2).reshape(p.n_dofs, p.n_dofs)
+    geo = M.macro_geometry(p)
+    st0 = M.initial_state(p)
+    conds = M.linearize(p, geo, st0)
+    Ko, _, _, _ = M.macro_system(p, geo, conds, 1.0)
+    assert rel(K, Ko.toarray()) < 1e-11
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_cfg1_end_to_end_closed_form(fe2, prec):
+    """Full configuration 1: macro displacement equals the closed-form
+    uniaxial field and every RVE carries the laminate tangent."""
+    p = W.config("cfg1")
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    hist = []
+    fe2.solve(h, p.load_factors, history=hist)
+    assert len(hist[0]) == 2        # linear: one update, then converged
+    u = dz(p.n_dofs)
+    fe2.fe2_get_state(h, u=u)
+    Cb = get(fe2, h, fe2.FE2_D_CBAR, p.n_rve * 9).reshape(p.n_rve, 3, 3)
+    u = u.cpu().numpy()
+    ex = np.zeros_like(u)
+    ex[0::2] = 1e-3 * p.X[:, 0]
+    ex[1::2] = -3.0 / 7.0 * 1e-3 * p.X[:, 1]
+    assert rel(u, ex) < 1e-10
+    Cex = np.array([[500 / 77, 150 / 143, 0], [150 / 143, 350 / 143, 0], [0, 0, 100 / 143]])
+    for b in range(p.n_rve):
+        assert rel(Cb[b], Cex) < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_cfg2_reduced_end_to_end(fe2, prec):
+    """Configuration 2 recipe on a 4x4 macro mesh (64 RVEs of 32x32): the
+    converged macro displacement and fluctuations match the oracle."""
+    p = W.config("cfg2", macro=(4, 4))
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    fe2.solve(h, p.load_factors)
+    u, w = dz(p.n_dofs), dz(fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN))
+    fe2.fe2_get_state(h, u, w)
+    torch.cuda.synchronize()
+    st, _ = M.solve(p)
+    assert rel(u.cpu().numpy(), st.u) < 1e-10
+    assert rel(w.cpu().numpy(), np.concatenate(st.w)) < 1e-8
+    h.close()
+
+
+def test_mixed_benchmark_tolerance_meets_cbar_target(fe2):
+    """The benchmark's mixed form (FP32 PCG to 1e-4, energy-form
+    condensation) keeps Cbar within 1e-6 of the oracle."""
+    p = W.config("cfg2", macro=(2, 2))
+    h = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-4, inner_tol=1e-4)
+    fe2.fe2_assemble_rve(h)
+    Cb = dz(p.n_rve * 9)
+    fe2.fe2_condense(h, Cb)
+    Cb = Cb.cpu().numpy().reshape(p.n_rve, 3, 3)
+    for b in range(p.n_rve):
+        c = R.homogenize_rve(p, b, np.zeros(3))
+        err = np.linalg.norm(Cb[b] - c.C) / np.linalg.norm(c.C)
+        assert err < 1e-6, (b, err)
+    h.close()
+
+
+def test_homogeneous_rve_exact(fe2):
+    """Both phases equal: Cbar is the phase stiffness and no iteration is
+    needed (zero right-hand sides)."""
+    p = W.config("cfg2", macro=(1, 1), rve=8)
+    p.phase_params[:, 1, :] = p.phase_params[:, 0, :]
+    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-12)
+    fe2.fe2_assemble_rve(h)
+    Cb = dz(4 * 9)
+    fe2.fe2_condense(h, Cb)
+    lam, mu = p.phase_params[0, 0]
+    C = np.array([[lam + 2 * mu, lam, 0], [lam, lam + 2 * mu, 0], [0, 0, mu]])
+    for b in range(4):
+        assert rel(Cb.cpu().numpy().reshape(4, 3, 3)[b], C) < 1e-14
+    iters = get(fe2, h, fe2.FE2_D_RVE_ITERS, 4)
+    assert np.all(iters == 0)
+    h.close()
+
+
+def test_unsupported_and_invalid_inputs_fail_loudly(fe2):
+    p = W.config("cfg2", macro=(1, 1), rve=12)   # no compiled kernel for 12x12
+    with pytest.raises(fe2.FE2Error) as e:
+        fe2.fe2_setup(p)
+    assert e.value.status == fe2.FE2_ENOTSUP
+    q = W.config("cfg1", macro=(1, 1))
+    q.phase_params[0, 1, 0] *= 2.0                # phases with different lambda/mu
+    with pytest.raises(fe2.FE2Error):
+        fe2.fe2_setup(q)
