@@ -4,8 +4,10 @@ Every hot-path row is compared element by element on the same seeded inputs:
 macro gradients (a2), RVE residual and stress integral (a3) in the periodic
 numbering (a4), RVE solutions (a5), condensed tangent and stress (a6), macro
 right-hand side and increment (a7, a8), fluctuation update (a9) and the
-residual norms (a10).  Tolerances: 1e-10 relative for the plain FP64 path and
-for the FP32 PCG with FP64 refinement driven to rve_tol = 1e-11; the looser
+residual norms (a10).  Tolerances: 1e-10 relative on Cbar, Phat and the macro
+displacement for the plain FP64 path and for the FP32 PCG with FP64
+refinement driven to a tight rve_tol; RVE solution vectors, whose error is
+bounded by cond(K_ww) * rve_tol, are compared at 1e-9 with rve_tol = 1e-13; the looser
 mixed form used by the benchmark (rve_tol = 1e-4, energy-form condensation)
 must stay within 1e-6 on Cbar.
 """
@@ -77,7 +79,8 @@ CASES = [
 def test_rows_a2_to_a6_at_nonzero_state(fe2, name, kw, prec):
     p = small_problem(name, **kw)
     u, ws = random_state(p, 7)
-    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    # solution vectors carry kappa * rve_tol; drive the residual to 1e-13
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-13)
     set_state(fe2, h, u, ws)
     fe2.fe2_assemble_rve(h)
     nF = fe2.fe2_query(h, fe2.FE2_Q_NF)
