@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Benchmark of the monolithic FE^2 hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2D plane-strain
+linear elasticity, macro 64x64 Q4 mesh with 2x2 Gauss points (16384 RVEs),
+RVE 32x32 Q4 with a centred circular inclusion of volume fraction 0.3,
+inclusion/matrix Young's modulus ratio lognormal(ln 10, 0.5) per macro
+element, nu = 0.3, uniaxial prescribed displacement 1e-3; seeded synthetic
+inputs (no dataset).
+
+One timed step = one monolithic Newton iteration from the reference state
+(a2-a10: macro gradients, RVE integration, residual norms, 16384 RVE solves
+and condensations, FP64 macro assembly, banded Cholesky solve, fluctuation
+update), preceded by a device-to-device reset of the state.  Two forms run:
+  * mixed: FP32 PCG + FP64 residual refinement, energy-form condensation,
+    rve_tol 1e-4 (the headline value; Cbar within 1e-6 of plain FP64);
+  * fp64:  the same solver in FP64 throughout, rve_tol 1e-7 (Cbar <= 1e-10).
+value = RVE solves/s of the mixed form (RVEs / GPU time of a2-a6, HIP
+events on the stream), ms_per_step = wall time of one macro Newton step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RVE solves/sec + macro Newton step time at 1e-6 C̄ error vs plain FP64"
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
+HBM_PEAK_GBS = 8000.0
+# algorithmic cost per RVE DOF and right-hand side:
+#   one PCG iteration: 64 flop operator (32 FMA, 2D Q4) + 13 flop vector ops
+#   one FP64 operator application (refinement residual / condensation): 66
+FLOP_PCG_ITER_DOF = 77.0
+FLOP_MV64_DOF = 66.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
+    h = fe2.fe2_setup(p, precision=precision, rve_tol=rve_tol, inner_tol=1e-5)
+    ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
+    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
+    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
+
+    def step():
+        fe2.fe2_set_state(h, zu, zw, 0.0)
+        st, _ = fe2.fe2_newton_step(h, 1.0)
+        assert st == fe2.FE2_OK
+
+    for _ in range(warmup):
+        step()
+    fe2.fe2_set_profiling(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = fe2.fe2_get_profile(h)
+    fe2.fe2_set_profiling(h, False)
+    n = p.n_rve
+    cbar = torch.zeros(n * 9, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_data(h, fe2.FE2_D_CBAR, cbar)
+    iters = torch.zeros(n, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_data(h, fe2.FE2_D_RVE_ITERS, iters)
+    mv64 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_data(h, fe2.FE2_D_RVE_MV64, mv64)
+    relres = torch.zeros(n, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_data(h, fe2.FE2_D_RVE_RELRES, relres)
+    torch.cuda.synchronize()
+    # a full linear solve to the Newton tolerance (informational)
+    fe2.fe2_set_state(h, zu, zw, 0.0)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    hist = []
+    fe2.solve(h, [1.0], history=hist)
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - ts) * 1e3
+    u = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_state(h, u=u)
+    torch.cuda.synchronize()
+    out = dict(
+        wall_ms_per_step=(t1 - t0) * 1e3 / steps,
+        gpu_ms=dict(assemble_norms=prof[0] / steps, rve_solve=prof[1] / steps,
+                    macro_assemble_solve=prof[2] / steps, update=prof[3] / steps,
+                    step=prof[4] / steps),
+        cbar=cbar.cpu().numpy().reshape(n, 3, 3),
+        iters=iters.cpu().numpy(), mv64=mv64.cpu().numpy(), relres=relres.cpu().numpy(),
+        newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(),
+        n_dof_rve=2 * np.prod(p.rve_res, axis=1) - 2)
+    h.close()
+    return out
+
+
+def cpu_baseline(p, seconds):
+    """The FP64 oracle (SciPy sparse LU per RVE) on the first RVEs of the same
+    workload, single-threaded, for about `seconds` of CPU time."""
+    from threadpoolctl import threadpool_limits
+    from oracle import rve as R
+    cb = {}
+    with threadpool_limits(limits=1):
+        R.homogenize_rve(p, 0, np.zeros(3))   # import/JIT warm-up outside the clock
+        t0 = time.perf_counter()
+        b = 0
+        while b < p.n_rve and (time.perf_counter() - t0 < seconds or b < 8):
+            cb[b] = R.homogenize_rve(p, b, np.zeros(3)).C
+            b += 1
+        el = time.perf_counter() - t0
+    return dict(value=len(cb) / el, n=len(cb), seconds=el, cbar=cb)
+
+
+def rel_frob(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="mixed,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+              "(the RVE batch would shard by macro elements across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2312_12771_amd import fe2
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    p = W.config("cfg2")
+    log(f"workload built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
+
+    forms = {}
+    if "fp64" in args.forms:
+        forms["fp64"] = run_form(fe2, torch, p, "fp64", 1e-7, args.steps, args.warmup)
+        log("fp64", forms["fp64"]["gpu_ms"], "wall", forms["fp64"]["wall_ms_per_step"])
+    if "mixed" in args.forms:
+        forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", 1e-4, args.steps, args.warmup)
+        log("mixed", forms["mixed"]["gpu_ms"], "wall", forms["mixed"]["wall_ms_per_step"])
+    head = forms.get("mixed") or forms["fp64"]
+    head_dtype = "f32" if "mixed" in forms else "f64"
+
+    def rve_rate(f):
+        return p.n_rve / ((f["gpu_ms"]["assemble_norms"] + f["gpu_ms"]["rve_solve"]) * 1e-3)
+
+    # roofline of the dominant kernel: the RVE solve launch (one per step)
+    k_ms = head["gpu_ms"]["rve_solve"]
+    flops = float(np.sum(head["iters"] * head["n_dof_rve"]) * FLOP_PCG_ITER_DOF
+                  + np.sum(head["mv64"] * head["n_dof_rve"]) * FLOP_MV64_DOF)
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_TFLOPS[head_dtype],
+                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4), traffic=None,
+                kernel="k_lin2d (RVE solve + condensation)", kernel_ms=round(k_ms, 4),
+                flop_per_launch=flops, pcg_iters_per_rve=float(np.mean(head["iters"])))
+
+    acc = {}
+    if "mixed" in forms and "fp64" in forms:
+        errs = [rel_frob(forms["mixed"]["cbar"][b], forms["fp64"]["cbar"][b]) for b in range(p.n_rve)]
+        acc["cbar_mixed_vs_fp64_max"] = max(errs)
+        acc["u_mixed_vs_fp64"] = float(np.abs(forms["mixed"]["u"] - forms["fp64"]["u"]).max()
+                                       / np.abs(forms["fp64"]["u"]).max())
+    cpu = None
+    if not args.no_cpu:
+        cb = cpu_baseline(p, args.cpu_seconds)
+        for k, f in forms.items():
+            acc[f"cbar_{k}_vs_oracle_max"] = max(rel_frob(f["cbar"][b], cb["cbar"][b]) for b in cb["cbar"])
+        cpu = dict(value=round(cb["value"], 3), unit="RVE solves/s", cores=1, kind="oracle",
+                   sample=f"first {cb['n']} RVEs of the same workload, SciPy sparse LU per RVE "
+                          f"(FP64, 4 right-hand sides), {cb['seconds']:.1f}s, BLAS threads 1")
+
+    line = {
+        "metric": METRIC,
+        "value": round(rve_rate(head), 1),
+        "unit": "RVE solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["wall_ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head_dtype + "+f64" if head_dtype == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D plane-strain linear, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 "
+                               "centred circle vf 0.3, E ratio lognormal(ln 10, 0.5) per macro element, "
+                               "nu 0.3, uniaxial 1e-3",
+                   "n_rve": p.n_rve, "rve": "32x32", "macro_dofs": p.n_dofs,
+                   "step": "one monolithic Newton iteration (a2-a10) from the reference state",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": {k: dict(rve_solves_per_s=round(rve_rate(f), 1),
+                          macro_newton_step_ms=round(f["wall_ms_per_step"], 4),
+                          gpu_phase_ms={kk: round(v, 4) for kk, v in f["gpu_ms"].items()},
+                          pcg_iters_per_rve=float(np.mean(f["iters"])),
+                          worst_rve_relres=float(np.max(f["relres"])),
+                          full_solve_ms=round(f["solve_ms"], 3),
+                          full_solve_newton_iterations=f["newton_iterations"])
+                  for k, f in forms.items()},
+        "accuracy": acc,
+    }
+    if "mixed" in forms and "fp64" in forms:
+        line["speedup_mixed_vs_fp64"] = dict(
+            rve_solves=round(rve_rate(forms["mixed"]) / rve_rate(forms["fp64"]), 3),
+            newton_step=round(forms["fp64"]["wall_ms_per_step"] / forms["mixed"]["wall_ms_per_step"], 3))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

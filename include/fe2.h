@@ -96,7 +96,9 @@ enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
  *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach
- *  inner_tol        relative tolerance of one FP32 PCG sweep (FP32_IR only)
+ *  inner_tol        floor of the relative tolerance of one FP32 PCG sweep
+ *                   (FP32_IR only; a sweep targets max(0.3*rve_tol, inner_tol),
+ *                   <= 0 selects 1e-5)
  *  newton_tol       macro convergence: ||[R_macro; R_micro]|| <= newton_tol *
  *                   ||F_int||
  *  micro_tol        classical scheme: inner RVE Newton stops when
@@ -172,7 +174,8 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
 int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream);
 
 /* Overwrite the state (either pointer may be NULL = keep) and set the load
- * factor the prescribed values currently satisfy. */
+ * factor the prescribed values currently satisfy.  The next RVE solve starts
+ * from zero (otherwise solves start from the previous X_F). */
 int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev,
                   double load_factor, void* stream);
 
@@ -192,12 +195,15 @@ int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev,
  *   FE2_D_MACRO_KDENSE [ndof*ndof]       assembled macro tangent before
  *                                        Dirichlet elimination, dense (only
  *                                        when ndof <= 4096)
- *   FE2_D_CBAR, FE2_D_PHAT               as written by fe2_condense */
+ *   FE2_D_CBAR, FE2_D_PHAT               as written by fe2_condense
+ *   FE2_D_RVE_MV64    [n_rve] (as double) FP64 operator applications of the
+ *                                        last solve (refinement residuals and
+ *                                        the condensation pass) */
 enum {
   FE2_D_MACRO_GRAD = 0, FE2_D_RESIDUAL = 1, FE2_D_PBAR = 2, FE2_D_SOLUTION = 3,
   FE2_D_RVE_ITERS = 4, FE2_D_RVE_RELRES = 5, FE2_D_MACRO_RHS = 6,
   FE2_D_MACRO_RTRUE = 7, FE2_D_MACRO_DU = 8, FE2_D_MACRO_KDENSE = 9,
-  FE2_D_CBAR = 10, FE2_D_PHAT = 11
+  FE2_D_CBAR = 10, FE2_D_PHAT = 11, FE2_D_RVE_MV64 = 12
 };
 int fe2_get_data(fe2_handle h, int which, double* dst_dev, void* stream);
 
@@ -207,6 +213,15 @@ enum {
   FE2_Q_FAILED_RVES = 4, FE2_Q_N_RVE = 5, FE2_Q_FIELD_OFFSETS = 6 /* into int64 out[n_rve+1] */
 };
 int fe2_query(fe2_handle h, int which, int64_t* out);
+
+/* Phase timing of fe2_newton_step with HIP events recorded on the caller's
+ * stream (tracing aid; off by default).  fe2_set_profiling(h, 1) enables and
+ * clears the accumulators.  fe2_get_profile copies and clears 6 doubles:
+ * accumulated milliseconds of [a2-a4 + norms, RVE solve and condensation
+ * (a5-a6), macro assembly and banded solve (a7-a8), update (a9), whole
+ * steps], and the number of timed steps that solved. */
+int fe2_set_profiling(fe2_handle h, int enable);
+int fe2_get_profile(fe2_handle h, double* out);
 
 /* Release all device memory of the handle (waits for its work). */
 int fe2_destroy(fe2_handle h);

@@ -84,8 +84,14 @@ struct fe2_ctx {
   double *f_true = nullptr, *f_hat = nullptr, *ke = nullptr, *band = nullptr, *rhs = nullptr;
   double *du = nullptr, *r_true = nullptr, *f_int = nullptr, *norms_dev = nullptr, *kdense = nullptr;
   double* norms_host = nullptr;   // pinned [4]
+  // phase timing (HIP events on the caller's stream)
+  bool prof = false;
+  hipEvent_t ev[8] = {};
+  double prof_ms[8] = {};   // assemble+norms, RVE solve, macro assemble+solve, update, steps, solve launches
+  double* mv64 = nullptr;
   int* flag_host = nullptr;       // pinned [2]
   int last_failed = 0;
+  bool have_solution = false;     // X holds the X_F of an earlier solve (warm start)
 
   MacroArgs margs() const {
     MacroArgs m{};
@@ -136,11 +142,12 @@ struct fe2_ctx {
     a.rnorm2 = rnorm2;
     a.relres = relres;
     a.iters = iters;
+    a.mv64 = mv64;
     a.fail_count = fail_count;
     a.fft_tab = nullptr;
     a.volume = volume;
     a.tol = rve_tol;
-    a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : inner_tol;
+    a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
     a.flags = flags;
@@ -157,13 +164,15 @@ void free_ctx(fe2_ctx* h) {
                   h->phase, h->params, h->foff, h->u, h->w, h->r, h->Xs, h->Cbar, h->Phat,
                   h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
-                  h->norms_dev, h->kdense};
+                  h->norms_dev, h->kdense, h->mv64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& c : h->classes) {
     if (c.d_list) (void)hipFree(c.d_list);
     if (c.d_tab) (void)hipFree(c.d_tab);
   }
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->flag_host) (void)hipHostFree(h->flag_host);
   delete h;
@@ -273,7 +282,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   h->rve_size = d->rve_size;
   h->volume = std::pow(d->rve_size, d->dim);
   h->rve_tol = d->rve_tol;
-  h->inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-4;
+  h->inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
   h->newton_tol = d->newton_tol;
   h->micro_tol = d->micro_tol;
   h->max_pcg_it = d->max_pcg_it;
@@ -364,6 +373,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if ((rc = dalloc(&h->rnorm2, nr))) return rc;
   if ((rc = dalloc(&h->relres, nr))) return rc;
   if ((rc = dalloc(&h->iters, nr))) return rc;
+  if ((rc = dalloc(&h->mv64, nr))) return rc;
   if ((rc = dalloc(&h->fail_count, 1))) return rc;
   if ((rc = dalloc(&h->info, 1))) return rc;
   if ((rc = dalloc(&h->f_true, static_cast<size_t>(h->n_elems) * nd))) return rc;
@@ -378,7 +388,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if (hipHostMalloc(reinterpret_cast<void**>(&h->norms_host), 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 2 * sizeof(int)) != hipSuccess)
     return set_error("pinned host allocation failed"), FE2_ENOMEM;
-  if (band_solve_lds(h->bw) > 160 * 1024)
+  if (band_cholesky_lds(h->bw) > 160 * 1024 - 64)
     return set_error("macro half bandwidth " + std::to_string(h->bw) + " exceeds the LDS panel"), FE2_ENOTSUP;
 
   // zero state
@@ -427,8 +437,10 @@ int assemble_impl(fe2_ctx* h, hipStream_t s) {
 
 int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->fail_count, static_cast<size_t>(1), 0);
+  const int flags = RVE_SOLVE | (h->have_solution ? RVE_WARM : 0);
+  h->have_solution = true;
   for (auto& c : h->classes) {
-    Lin2DArgs a = h->largs(c, RVE_SOLVE);
+    Lin2DArgs a = h->largs(c, flags);
     int rc = launch_lin2d(a, static_cast<int>(c.rves.size()), h->precision, nrhs, s);
     if (rc) return rc;
   }
@@ -463,12 +475,12 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
                      h->kdense);
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->info, static_cast<size_t>(1), 0);
   FE2_HIP_CHECK(hipGetLastError());
-  const size_t lds = band_solve_lds(h->bw);
-  if (lds > 64 * 1024)
-    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_cholesky_solve),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   FE2_HIP_CHECK(hipMemcpyAsync(h->du, h->rhs, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_band_cholesky_solve, dim3(1), dim3(1024), lds, s, h->ndof, h->bw, h->band, h->du, h->info);
+  const size_t lds = band_cholesky_lds(h->bw);
+  if (lds > 64 * 1024)
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_cholesky),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(k_band_cholesky, dim3(1), dim3(512), lds, s, h->ndof, h->bw, h->band, h->du, h->info);
   FE2_HIP_CHECK(hipGetLastError());
   return FE2_OK;
 }
@@ -552,27 +564,53 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   FE2_GUARD(h);
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc;
+  auto mark = [&](int i) {
+    if (h->prof) (void)hipEventRecord(h->ev[i], s);
+  };
   // a2-a4 at the current state and the residual norms (a10)
+  mark(0);
   if ((rc = assemble_impl(h, s))) return rc;
   if ((rc = residual_impl(h, load_factor, s))) return rc;
+  mark(1);
   FE2_HIP_CHECK(hipMemcpyAsync(h->norms_host, h->norms_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   FE2_HIP_CHECK(hipStreamSynchronize(s));
   if (norms_host) std::memcpy(norms_host, h->norms_host, 4 * sizeof(double));
   const double dlam = load_factor - h->lam;
-  if (dlam == 0.0 && h->norms_host[0] <= h->newton_tol * h->norms_host[3]) return FE2_CONVERGED;
+  if (dlam == 0.0 && h->norms_host[0] <= h->newton_tol * h->norms_host[3]) {
+    if (h->prof) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+      h->prof_ms[0] += ms;
+    }
+    return FE2_CONVERGED;
+  }
   // a5-a6: RVE solves; the residual column is dropped when every RVE
   // residual is exactly zero (first iteration from the reference state)
   const int nrhs = h->norms_host[2] == 0.0 ? h->nF : h->nF + 1;
+  mark(2);
   if ((rc = solve_impl(h, nrhs, s))) return rc;
+  mark(3);
   // a7-a8: macro assembly and banded Cholesky solve with the increment
   if ((rc = macro_solve_impl(h, load_factor, dlam, s))) return rc;
+  mark(4);
   // a9: update
   if ((rc = update_impl(h, nrhs > h->nF, s))) return rc;
+  mark(5);
   FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
   FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host + 1, h->info, sizeof(int), hipMemcpyDeviceToHost, s));
   FE2_HIP_CHECK(hipStreamSynchronize(s));
   h->lam = load_factor;
   h->last_failed = h->flag_host[0];
+  if (h->prof) {
+    float ms[5] = {};
+    (void)hipEventElapsedTime(&ms[0], h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&ms[1], h->ev[2], h->ev[3]);
+    (void)hipEventElapsedTime(&ms[2], h->ev[3], h->ev[4]);
+    (void)hipEventElapsedTime(&ms[3], h->ev[4], h->ev[5]);
+    (void)hipEventElapsedTime(&ms[4], h->ev[0], h->ev[5]);
+    for (int i = 0; i < 5; ++i) h->prof_ms[i] += ms[i];
+    h->prof_ms[5] += 1.0;
+  }
   if (h->flag_host[1] != 0)
     return set_error("macro tangent not positive definite at pivot " + std::to_string(h->flag_host[1])),
            FE2_ENOCONV;
@@ -590,6 +628,7 @@ int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream) {
 
 int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev, double load_factor, void* stream) {
   FE2_GUARD(h);
+  h->have_solution = false;   // a new state: start the next solve from zero
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (u_dev) FE2_HIP_CHECK(hipMemcpyAsync(h->u, u_dev, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
   if (w_dev) FE2_HIP_CHECK(hipMemcpyAsync(h->w, w_dev, sizeof(double) * h->field_len, hipMemcpyDeviceToDevice, s));
@@ -611,6 +650,7 @@ int fe2_get_data(fe2_handle h, int which, double* dst, void* stream) {
     case FE2_D_SOLUTION: src = h->Xs; n = static_cast<size_t>(h->field_len) * (nF + 1); break;
     case FE2_D_RVE_ITERS: src = h->iters; n = nr; break;
     case FE2_D_RVE_RELRES: src = h->relres; n = nr; break;
+    case FE2_D_RVE_MV64: src = h->mv64; n = nr; break;
     case FE2_D_MACRO_RHS: src = h->rhs; n = h->ndof; break;
     case FE2_D_MACRO_RTRUE: src = h->r_true; n = h->ndof; break;
     case FE2_D_MACRO_DU: src = h->du; n = h->ndof; break;
@@ -664,6 +704,23 @@ int fe2_query(fe2_handle h, int which, int64_t* out) {
     case FE2_Q_FIELD_OFFSETS: std::memcpy(out, h->h_foff.data(), h->h_foff.size() * sizeof(int64_t)); return FE2_OK;
     default: return set_error("unknown query"), FE2_EINVAL;
   }
+}
+
+int fe2_set_profiling(fe2_handle h, int enable) {
+  FE2_GUARD(h);
+  if (enable && !h->ev[0])
+    for (auto& e : h->ev) FE2_HIP_CHECK(hipEventCreate(&e));
+  h->prof = enable != 0;
+  for (double& v : h->prof_ms) v = 0.0;
+  return FE2_OK;
+}
+
+int fe2_get_profile(fe2_handle h, double* out) {
+  FE2_GUARD(h);
+  if (!out) return set_error("null output"), FE2_EINVAL;
+  std::memcpy(out, h->prof_ms, 6 * sizeof(double));
+  for (double& v : h->prof_ms) v = 0.0;
+  return FE2_OK;
 }
 
 int fe2_destroy(fe2_handle h) {

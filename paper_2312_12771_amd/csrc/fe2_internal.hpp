@@ -94,7 +94,8 @@ struct Lin2DArgs {
   double* Pbar;                 // [n_rve][3]
   double* rnorm2;               // [n_rve] ||r_b||^2
   double* relres;               // [n_rve] final relative FP64 residual
-  double* iters;                // [n_rve] PCG iterations
+  double* iters;                // [n_rve] inner PCG iterations (all columns)
+  double* mv64;                 // [n_rve] FP64 operator applications
   int* fail_count;              // RVEs that missed tol
   const float* fft_tab;         // spectral preconditioner table (RVE_FFT)
   double volume;

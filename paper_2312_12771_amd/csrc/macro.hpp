@@ -38,9 +38,9 @@ __global__ void k_macro_rows_band(MacroArgs m, const double* __restrict__ ke, do
                                   double* __restrict__ kdense);
 __global__ void k_fill(double* p, size_t n, double v);
 __global__ void k_fill_i(int* p, size_t n, int v);
-__global__ void k_band_cholesky_solve(int n, int bw, double* __restrict__ band,
-                                      double* __restrict__ y, int* __restrict__ info);
-size_t band_solve_lds(int bw);
+__global__ void k_band_cholesky(int n, int bw, double* __restrict__ band,
+                                double* __restrict__ y, int* __restrict__ info);
+size_t band_cholesky_lds(int bw);
 __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y);
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
                            const double* __restrict__ X, double* __restrict__ w, int use_xr);

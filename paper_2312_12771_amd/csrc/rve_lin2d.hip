@@ -323,14 +323,14 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
-  int iters = 0;
+  int iters = 0, nmv64 = 0;
   bool all_ok = true;
   double worst = 0.0;
 
 #pragma unroll 1
   for (int kc = 0; kc < NRHS; ++kc) {
     double* xc = Xb + kc * flen;
-    bool xzero = !warm;
+    bool xzero = !warm || kc >= NF;   // warm start: previous X_F; x_r from zero
     if (xzero) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         stage(xc);
         __syncthreads();
         mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+        ++nmv64;
       }
       TI ri[4][2];
       double red[2] = {0.0, 0.0};
@@ -471,6 +472,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     __syncthreads();
     double y[4][2];
     mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+    ++nmv64;
     double g1[NF] = {0.0, 0.0, 0.0}, g2[NF] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -504,6 +506,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   if (tid == 0) {
     a.relres[b] = worst;
     a.iters[b] = static_cast<double>(iters);
+    a.mv64[b] = static_cast<double>(nmv64);
     if (!all_ok) atomicAdd(a.fail_count, 1);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {

@@ -32,7 +32,7 @@ FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT = 0, 1, 2
 FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
 (FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
  FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
- FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT) = range(12)
+ FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64) = range(13)
 (FE2_Q_NF, FE2_Q_FIELD_LEN, FE2_Q_NDOF, FE2_Q_BANDWIDTH, FE2_Q_FAILED_RVES,
  FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS) = range(7)
 
@@ -74,6 +74,8 @@ _sig = {
     "fe2_get_data": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "fe2_query": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int64)]),
     "fe2_destroy": (C.c_int, [_vp]),
+    "fe2_set_profiling": (C.c_int, [_vp, C.c_int]),
+    "fe2_get_profile": (C.c_int, [_vp, _dp]),
     "fe2_strerror": (C.c_char_p, [C.c_int]),
     "fe2_last_error": (C.c_char_p, []),
     "fe2_abi_version": (C.c_int, []),
@@ -141,7 +143,7 @@ def _arr(a, dtype):
 
 
 def fe2_setup(problem, precision: str = "fp64", solver: str = "auto",
-              scheme: str = "generalized", rve_tol: float = 1e-10, inner_tol: float = 1e-4,
+              scheme: str = "generalized", rve_tol: float = 1e-10, inner_tol: float = 1e-5,
               newton_tol: float = 1e-10, micro_tol: float = 1e-13, max_pcg_it: int = 4000,
               max_ir: int = 8, max_micro_it: int = 30, stream=None) -> Handle:
     """Create a handle from a problem description (any object with the
@@ -226,6 +228,18 @@ def fe2_query(h: Handle, which: int):
     v = C.c_int64()
     _check(_lib.fe2_query(h.ptr, int(which), C.byref(v)), "fe2_query")
     return int(v.value)
+
+
+def fe2_set_profiling(h: Handle, enable: bool = True):
+    return _check(_lib.fe2_set_profiling(h.ptr, int(bool(enable))), "fe2_set_profiling")
+
+
+def fe2_get_profile(h: Handle):
+    """Accumulated ms of [assemble+norms, RVE solve, macro assemble+solve,
+    update, whole step] and the number of timed solving steps (cleared)."""
+    out = np.zeros(6)
+    _check(_lib.fe2_get_profile(h.ptr, out.ctypes.data_as(_dp)), "fe2_get_profile")
+    return out
 
 
 def fe2_destroy(h: Handle):
