@@ -120,6 +120,38 @@ struct fe2_ctx {
     return m;
   }
 
+  Fin2DArgs fargs(const RveClass& c, int flags) const {
+    Fin2DArgs a{};
+    a.n1 = c.n1;
+    a.n2 = c.n2;
+    a.rve_list = c.d_list;
+    a.phase_off = phase_off;
+    a.phase = phase;
+    a.params = params;
+    a.macro = mgrad;
+    a.foff = foff;
+    a.w = w;
+    a.r = r;
+    a.X = Xs;
+    a.Cbar = Cbar;
+    a.Phat = Phat;
+    a.Pbar = Pbar;
+    a.rnorm2 = rnorm2;
+    a.relres = relres;
+    a.iters = iters;
+    a.mv64 = mv64;
+    a.fail_count = fail_count;
+    a.h1 = rve_size / c.n1;
+    a.h2 = rve_size / c.n2;
+    a.volume = volume;
+    a.tol = rve_tol;
+    a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
+    a.max_it = max_pcg_it;
+    a.max_ir = max_ir;
+    a.flags = flags;
+    return a;
+  }
+
   Lin2DArgs largs(const RveClass& c, int flags) const {
     Lin2DArgs a{};
     a.n1 = c.n1;
@@ -290,25 +322,61 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   h->max_micro_it = d->max_micro_it;
 
   // supported combinations
-  if (h->dim != 2 || h->kin != FE2_SMALL_STRAIN || h->mat != FE2_LINEAR_ISO || h->n_pp != 2) {
-    set_error("this build supports 2D small-strain linear isotropic RVEs");
-    return FE2_ENOTSUP;
-  }
+  const bool finite = h->kin == FE2_FINITE_STRAIN;
+  if (h->dim != 2) return set_error("this build supports 2D RVEs"), FE2_ENOTSUP;
+  if (!finite && (h->mat != FE2_LINEAR_ISO || h->n_pp != 2))
+    return set_error("small strain takes FE2_LINEAR_ISO with (lambda, mu) per phase"), FE2_EINVAL;
+  if (finite && !((h->mat == FE2_NEO_HOOKE && h->n_pp == 2) || (h->mat == FE2_MOONEY_RIVLIN && h->n_pp == 3)))
+    return set_error("finite strain takes FE2_NEO_HOOKE (lambda, mu) or FE2_MOONEY_RIVLIN (alpha, beta, kappa)"),
+           FE2_EINVAL;
+  if (h->kin != FE2_SMALL_STRAIN && !finite) return set_error("unknown kinematics"), FE2_EINVAL;
   if (h->scheme != FE2_SCHEME_GENERALIZED) {
-    set_error("only the generalized scheme is available for this kinematics");
+    set_error("only the generalized scheme is available");
     return FE2_ENOTSUP;
   }
 
-  // RVE classes: (n1, n2, lambda/mu)
+  // Per-RVE material parameters as the kernels read them: (lambda, mu) per
+  // phase for small strain, (alpha, beta, kappa) of the Eq. (59) family for
+  // finite strain (Neo-Hooke: alpha = mu/2, beta = 0, kappa = lambda).
+  const int npk = finite ? 3 : 2;
+  std::vector<double> kpar(static_cast<size_t>(h->n_rve) * 2 * npk);
+  for (int b = 0; b < h->n_rve; ++b)
+    for (int q = 0; q < 2; ++q) {
+      const double* p = d->phase_params + (static_cast<size_t>(b) * 2 + q) * h->n_pp;
+      double* o = kpar.data() + (static_cast<size_t>(b) * 2 + q) * npk;
+      if (!finite || h->mat == FE2_NEO_HOOKE) {
+        if (!(p[1] > 0.0) || !(p[0] >= 0.0)) return set_error("need mu > 0 and lambda >= 0"), FE2_EINVAL;
+      }
+      if (!finite) {
+        o[0] = p[0];
+        o[1] = p[1];
+      } else if (h->mat == FE2_NEO_HOOKE) {
+        o[0] = 0.5 * p[1];
+        o[1] = 0.0;
+        o[2] = p[0];
+      } else {
+        if (!(p[0] + p[1] > 0.0) || !(p[1] >= 0.0) || !(p[2] >= 0.0) || !(p[0] + 2.0 * p[1] >= 0.0))
+          return set_error("Mooney-Rivlin phases need alpha + beta > 0, beta >= 0, kappa >= 0"), FE2_EINVAL;
+        o[0] = p[0];
+        o[1] = p[1];
+        o[2] = p[2];
+      }
+    }
+
+  // RVE classes: (n1, n2, lambda/mu) for small strain, (n1, n2) for finite
+  // strain (the finite-strain kernel evaluates the law per Gauss point)
   std::map<std::tuple<int, int, double>, int> key2cls;
   for (int b = 0; b < h->n_rve; ++b) {
     const int n1 = d->rve_res[b * 2], n2 = d->rve_res[b * 2 + 1];
-    const double* p = d->phase_params + static_cast<size_t>(b) * 2 * h->n_pp;
-    if (!(p[1] > 0.0) || !(p[3] > 0.0)) return set_error("shear moduli must be positive"), FE2_EINVAL;
-    const double rho0 = p[0] / p[1], rho1 = p[2] / p[3];
-    if (std::fabs(rho0 - rho1) > 1e-12 * std::fabs(rho0))
-      return set_error("both phases of an RVE must share lambda/mu"), FE2_ENOTSUP;
-    if (!lin2d_supported(n1, n2))
+    double rho0 = 0.0;
+    if (!finite) {
+      const double* p = kpar.data() + static_cast<size_t>(b) * 4;
+      rho0 = p[0] / p[1];
+      const double rho1 = p[2] / p[3];
+      if (std::fabs(rho0 - rho1) > 1e-12 * std::fabs(rho0))
+        return set_error("both phases of an RVE must share lambda/mu"), FE2_ENOTSUP;
+    }
+    if (!(finite ? fin2d_supported(n1, n2) : lin2d_supported(n1, n2)))
       return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" +
                        std::to_string(n2)),
              FE2_ENOTSUP;
@@ -347,7 +415,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   const int64_t n_ph = d->rve_off[h->n_rve];
   if ((rc = upload(&h->phase_off, d->rve_off, static_cast<size_t>(h->n_rve) + 1, s))) return rc;
   if ((rc = upload(&h->phase, d->phase_id, static_cast<size_t>(n_ph), s))) return rc;
-  if ((rc = upload(&h->params, d->phase_params, static_cast<size_t>(h->n_rve) * 2 * h->n_pp, s))) return rc;
+  if ((rc = upload(&h->params, kpar.data(), kpar.size(), s))) return rc;
   h->h_foff.assign(h->n_rve + 1, 0);
   for (int b = 0; b < h->n_rve; ++b) {
     int64_t nn = 1;
@@ -409,6 +477,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   // RVE classes: work lists and reference tables
   for (auto& c : h->classes) {
     if ((rc = upload(&c.d_list, c.rves.data(), c.rves.size(), s))) return rc;
+    if (finite) continue;
     if ((rc = dalloc(&c.d_tab, 44))) return rc;
     hipLaunchKernelGGL(k_ref_tables_2d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, h->rve_size / c.n2, c.rho,
                        c.d_tab);
@@ -428,8 +497,9 @@ int assemble_impl(fe2_ctx* h, hipStream_t s) {
   hipLaunchKernelGGL(k_macro_grad, dim3(nblk(h->n_rve, 128)), dim3(128), 0, s, m, h->u, h->mgrad);
   FE2_HIP_CHECK(hipGetLastError());
   for (auto& c : h->classes) {
-    Lin2DArgs a = h->largs(c, RVE_ASSEMBLE);
-    int rc = launch_lin2d(a, static_cast<int>(c.rves.size()), h->precision, 3, s);
+    const int n = static_cast<int>(c.rves.size());
+    int rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, RVE_ASSEMBLE), n, h->precision, h->nF, s)
+                                         : launch_lin2d(h->largs(c, RVE_ASSEMBLE), n, h->precision, h->nF, s);
     if (rc) return rc;
   }
   return FE2_OK;
@@ -440,8 +510,9 @@ int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
   const int flags = RVE_SOLVE | (h->have_solution ? RVE_WARM : 0);
   h->have_solution = true;
   for (auto& c : h->classes) {
-    Lin2DArgs a = h->largs(c, flags);
-    int rc = launch_lin2d(a, static_cast<int>(c.rves.size()), h->precision, nrhs, s);
+    const int n = static_cast<int>(c.rves.size());
+    int rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, flags), n, h->precision, nrhs, s)
+                                         : launch_lin2d(h->largs(c, flags), n, h->precision, nrhs, s);
     if (rc) return rc;
   }
   return FE2_OK;

@@ -104,10 +104,41 @@ struct Lin2DArgs {
   int flags;
 };
 
-// Launchers (rve_lin2d.hip)
+// Finite-strain 2D RVEs (plane strain, polyconvex phases).  One launch
+// handles the RVEs of one resolution.
+struct Fin2DArgs {
+  int n1, n2;
+  const int* rve_list;          // RVE ids of this launch
+  const int64_t* phase_off;     // [n_rve+1]
+  const uint8_t* phase;         // phase id per RVE element
+  const double* params;         // [n_rve][2][3] (alpha, beta, kappa)
+  const double* macro;          // [n_rve][4] macro gradient F_b, row-major
+  const int64_t* foff;          // [n_rve+1] field offsets (doubles)
+  const double* w;              // state fluctuation (periodic numbering)
+  double* r;                    // RVE residual (written by ASSEMBLE)
+  double* X;                    // solutions, (nF+1) fields per RVE
+  double* Cbar;                 // [n_rve][4][4]
+  double* Phat;                 // [n_rve][4]
+  double* Pbar;                 // [n_rve][4]
+  double* rnorm2;               // [n_rve] ||r_b||^2
+  double* relres;               // [n_rve] final relative FP64 residual
+  double* iters;                // [n_rve] inner PCG iterations (all columns)
+  double* mv64;                 // [n_rve] FP64 operator applications
+  int* fail_count;              // RVEs that missed tol (or lost J > 0)
+  double h1, h2;                // element edge lengths
+  double volume;
+  double tol, tol_in;
+  int max_it, max_ir;
+  int flags;
+};
+
+// Launchers (rve_lin2d.hip, rve_fin2d.hip)
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
 size_t lin2d_lds_bytes(int n1, int n2, int nrhs);
 bool lin2d_supported(int n1, int n2);
+int launch_fin2d(const Fin2DArgs& a, int n_launch, int precision, int nrhs,
+                 hipStream_t s);
+bool fin2d_supported(int n1, int n2);
 
 }  // namespace fe2

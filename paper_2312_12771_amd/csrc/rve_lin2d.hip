@@ -29,49 +29,19 @@
 //     FP64 from the FP64 solution kept in the output buffer; the condensation
 //     uses the FP64 residual to correct the Schur product (energy form, error
 //     quadratic in the solve error).
-#include "elem2d.hpp"
-#include "fe2_internal.hpp"
+#include "rve2d_common.hpp"
 
 namespace fe2 {
+
+using namespace rve2d;
 
 namespace {
 
 constexpr int NF = 3;
 
-// Element q (0..3) around an owned node (di, dj): position of the element's
-// lower-left node in the 3x3 element neighbourhood and the local corner the
-// node occupies in it.
-__host__ __device__ constexpr int elem_ea(int di, int q) { return di + ((q == 1 || q == 2) ? 1 : 0); }
-__host__ __device__ constexpr int elem_ec(int dj, int q) { return dj + (q >= 2 ? 1 : 0); }
-__host__ __device__ constexpr int elem_cc(int q) { return (q + 2) & 3; }
-
 template <typename V>
 __device__ __forceinline__ V kfma(const V (&kv)[10], int r, int c, V x, V acc) {
   return kref_sign(r, c) > 0 ? fma(kv[kref_id(r, c)], x, acc) : fma(-kv[kref_id(r, c)], x, acc);
-}
-
-// Padded (halo) layout of a periodic N1 x N2 nodal or element field:
-// entry (i, j), i in [-1, N1], j in [-1, N2], at (j+1)*PW + (i+1).  Odd
-// sizes get one more unused column/row so that the 4x4 window of the last,
-// partial 2x2 block stays inside the array.
-__host__ __device__ constexpr int pad_w(int n) { return n + 2 + (n & 1); }
-template <int N1, int N2>
-struct Pad {
-  static constexpr int PW = pad_w(N1);
-  static constexpr int PN = pad_w(N1) * pad_w(N2);
-  static __host__ __device__ constexpr int at(int i, int j) { return (j + 1) * PW + (i + 1); }
-};
-
-// Write value v of real node/element (i, j) and its halo images.
-template <int N1, int N2, typename V>
-__device__ __forceinline__ void put_halo(V* f, int i, int j, V v) {
-  using P = Pad<N1, N2>;
-  f[P::at(i, j)] = v;
-  const int ig = (i == 0) ? N1 : ((i == N1 - 1) ? -1 : -2);
-  const int jg = (j == 0) ? N2 : ((j == N2 - 1) ? -1 : -2);
-  if (ig != -2) f[P::at(ig, j)] = v;
-  if (jg != -2) f[P::at(i, jg)] = v;
-  if (ig != -2 && jg != -2) f[P::at(ig, jg)] = v;
 }
 
 // y = K v for the four nodes of the owned block.  pb points at the padded
@@ -132,29 +102,6 @@ __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const 
 #pragma unroll
   for (int q = 0; q < 4; ++q) s += elem_scale<N1, N2>(eb, di, dj, q) * KwF[(2 * elem_cc(q) + d) * NF + j];
   return s;
-}
-
-// Work-group sum with two alternating reduction buffers (one barrier each).
-template <int NV, int NW>
-__device__ __forceinline__ void wg_sum(double (&v)[NV], double* s_red, int& parity) {
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  double* buf = s_red + parity * (NW * NV);
-  parity ^= 1;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) t += buf[w * NV + i];
-    v[i] = t;
-  }
 }
 
 }  // namespace
@@ -416,6 +363,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
             pq[0] += static_cast<double>(pown[k][d]) * static_cast<double>(q[k][d]);
           }
         wg_sum<1, NW>(pq, s_red, parity);
+        if (!(pq[0] > 0.0)) break;   // breakdown (exact solution or loss of definiteness)
         const TI alpha = static_cast<TI>(rz / pq[0]);
         double red2[2] = {0.0, 0.0};
 #pragma unroll
@@ -429,7 +377,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
             red2[1] += rv * rv;
           }
         wg_sum<2, NW>(red2, s_red, parity);
-        if (red2[1] <= tin2 * r0) break;
+        if (red2[1] <= tin2 * r0 || !(red2[0] > 0.0)) break;
         const TI beta = static_cast<TI>(red2[0] / rz);
         rz = red2[0];
 #pragma unroll
