@@ -18,6 +18,4 @@ rve       RVE element integration, periodic null-space reduction and static
 macro     macro FE, the generalized (monolithic, Sec. 4.2) and classical
           (staggered, Sec. 4.1) Newton schemes and the full block solve
           (Eq. (42)).
-oned      the 1+1D benchmark of Sec. 5.1 (Eqs. (50)-(55)).
-mlp       FP64 reference of the surrogate network (forward, backward, Adam).
 """
