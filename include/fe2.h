@@ -156,18 +156,30 @@ int fe2_assemble_rve(fe2_handle h, void* stream);
 int fe2_condense(fe2_handle h, double* Cbar_dev, double* Phat_dev, void* stream);
 
 /* One macro Newton iteration at target load factor `load_factor`
- * (generalized scheme: Eqs. (46)-(49); classical: Eqs. (43)-(45) with inner
- * RVE equilibration first).  Steps: macro gradients, RVE integration,
- * residual norms; if the handle's load factor already equals load_factor and
- * the norm satisfies newton_tol the call returns FE2_CONVERGED without an
- * update; otherwise RVE solves and condensation, FP64 macro assembly with the
- * prescribed increment (load_factor - current) * dir_vals, FP64 banded
- * Cholesky solve, update of q and w~ (dw_b = -(x_r + X_F dF_b)).
+ * (generalized scheme: Eqs. (46)-(49); classical: Eqs. (43)-(45) with the
+ * inner RVE equilibration of fe2_equilibrate_rve first).  Steps: macro
+ * gradients, RVE integration, residual norms; if the handle's load factor
+ * already equals load_factor and the norm satisfies newton_tol the call
+ * returns FE2_CONVERGED without an update; otherwise RVE solves and
+ * condensation, FP64 macro assembly with the prescribed increment
+ * (load_factor - current) * dir_vals, FP64 banded Cholesky solve, update of
+ * q and w~ (generalized: dw_b = -(x_r + X_F dF_b); classical predictor:
+ * dw_b = -X_F dF_b).
  * norms_host (may be NULL) receives 4 doubles describing the state the call
  * started from: ||[R_macro(free); R_micro]||, ||R_macro(free)||,
  * ||R_micro||, ||F_int|| (R_micro,b = eta_b J_b / |Omega| r_b).  Waits for
  * the norms on `stream`. */
 int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* stream);
+
+/* Inner RVE equilibration of the classical scheme (Sec. 4.1, the micro
+ * Newton loop of Eqs. (43)-(44)) at the current macro displacement: every RVE
+ * iterates w~_b <- w~_b - K_ww^-1 r_b until ||r_b|| <= micro_tol *
+ * max(1, ||r_b^0||) (r_b^0 = residual at entry), at most max_micro_it
+ * updates.  RVEs already in equilibrium are skipped.  iters_host (may be
+ * NULL) receives the number of update rounds.  Waits on `stream` once per
+ * round.  Returns FE2_ENOCONV when an RVE did not reach micro_tol or an inner
+ * solve missed rve_tol; the fluctuations keep the last iterate. */
+int fe2_equilibrate_rve(fe2_handle h, int* iters_host, void* stream);
 
 /* Copy the state: u_dev [n_nodes*dim] macro displacement q - X; w_dev
  * [FE2_Q_FIELD_LEN] fluctuations (either may be NULL). */
@@ -210,7 +222,8 @@ int fe2_get_data(fe2_handle h, int which, double* dst_dev, void* stream);
 /* Integer properties of a handle. */
 enum {
   FE2_Q_NF = 0, FE2_Q_FIELD_LEN = 1, FE2_Q_NDOF = 2, FE2_Q_BANDWIDTH = 3,
-  FE2_Q_FAILED_RVES = 4, FE2_Q_N_RVE = 5, FE2_Q_FIELD_OFFSETS = 6 /* into int64 out[n_rve+1] */
+  FE2_Q_FAILED_RVES = 4, FE2_Q_N_RVE = 5, FE2_Q_FIELD_OFFSETS = 6, /* into int64 out[n_rve+1] */
+  FE2_Q_MICRO_ITERS = 7   /* update rounds of the last inner equilibration */
 };
 int fe2_query(fe2_handle h, int which, int64_t* out);
 

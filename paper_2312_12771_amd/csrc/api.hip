@@ -89,7 +89,10 @@ struct fe2_ctx {
   hipEvent_t ev[8] = {};
   double prof_ms[8] = {};   // assemble+norms, RVE solve, macro assemble+solve, update, steps, solve launches
   double* mv64 = nullptr;
-  int* flag_host = nullptr;       // pinned [2]
+  int* flag_host = nullptr;       // pinned [3]
+  double* thr2 = nullptr;         // [n_rve] inner-loop thresholds
+  int* count = nullptr;           // RVEs above their threshold
+  int last_micro_its = 0;
   int last_failed = 0;
   bool have_solution = false;     // X holds the X_F of an earlier solve (warm start)
 
@@ -141,6 +144,7 @@ struct fe2_ctx {
     a.iters = iters;
     a.mv64 = mv64;
     a.fail_count = fail_count;
+    a.thr2 = thr2;
     a.h1 = rve_size / c.n1;
     a.h2 = rve_size / c.n2;
     a.volume = volume;
@@ -176,6 +180,7 @@ struct fe2_ctx {
     a.iters = iters;
     a.mv64 = mv64;
     a.fail_count = fail_count;
+    a.thr2 = thr2;
     a.fft_tab = nullptr;
     a.volume = volume;
     a.tol = rve_tol;
@@ -196,7 +201,7 @@ void free_ctx(fe2_ctx* h) {
                   h->phase, h->params, h->foff, h->u, h->w, h->r, h->Xs, h->Cbar, h->Phat,
                   h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
-                  h->norms_dev, h->kdense, h->mv64};
+                  h->norms_dev, h->kdense, h->mv64, h->thr2, h->count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& c : h->classes) {
@@ -330,10 +335,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     return set_error("finite strain takes FE2_NEO_HOOKE (lambda, mu) or FE2_MOONEY_RIVLIN (alpha, beta, kappa)"),
            FE2_EINVAL;
   if (h->kin != FE2_SMALL_STRAIN && !finite) return set_error("unknown kinematics"), FE2_EINVAL;
-  if (h->scheme != FE2_SCHEME_GENERALIZED) {
-    set_error("only the generalized scheme is available");
-    return FE2_ENOTSUP;
-  }
+  if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL)
+    return set_error("unknown scheme"), FE2_EINVAL;
+  if (h->scheme == FE2_SCHEME_CLASSICAL && (!(h->micro_tol > 0.0) || h->max_micro_it <= 0))
+    return set_error("the classical scheme needs micro_tol > 0 and max_micro_it > 0"), FE2_EINVAL;
 
   // Per-RVE material parameters as the kernels read them: (lambda, mu) per
   // phase for small strain, (alpha, beta, kappa) of the Eq. (59) family for
@@ -453,8 +458,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if ((rc = dalloc(&h->r_true, h->ndof))) return rc;
   if ((rc = dalloc(&h->f_int, h->ndof))) return rc;
   if ((rc = dalloc(&h->norms_dev, 4))) return rc;
+  if ((rc = dalloc(&h->thr2, nr))) return rc;
+  if ((rc = dalloc(&h->count, 1))) return rc;
   if (hipHostMalloc(reinterpret_cast<void**>(&h->norms_host), 4 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 2 * sizeof(int)) != hipSuccess)
+      hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 3 * sizeof(int)) != hipSuccess)
     return set_error("pinned host allocation failed"), FE2_ENOMEM;
   if (band_cholesky_lds(h->bw) > 160 * 1024 - 64)
     return set_error("macro half bandwidth " + std::to_string(h->bw) + " exceeds the LDS panel"), FE2_ENOTSUP;
@@ -516,6 +523,46 @@ int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
     if (rc) return rc;
   }
   return FE2_OK;
+}
+
+// Classical inner loop at the current macro state (Sec. 4.1): RVE Newton
+// iterations w_b -= K_ww^-1 r_b until ||r_b|| <= micro_tol max(1, ||r_b^0||).
+int equilibrate_impl(fe2_ctx* h, hipStream_t s) {
+  int rc = assemble_impl(h, s);
+  if (rc) return rc;
+  const unsigned nb = nblk(h->n_rve, 256);
+  hipLaunchKernelGGL(k_micro_thr, dim3(nb), dim3(256), 0, s, h->n_rve, h->rnorm2, h->micro_tol, h->thr2);
+  FE2_HIP_CHECK(hipGetLastError());
+  h->last_micro_its = 0;
+  for (int it = 0;; ++it) {
+    hipLaunchKernelGGL(k_count_above, dim3(1), dim3(1024), 0, s, h->n_rve, h->rnorm2, h->thr2, h->count);
+    FE2_HIP_CHECK(hipGetLastError());
+    FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host + 2, h->count, sizeof(int), hipMemcpyDeviceToHost, s));
+    FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    FE2_HIP_CHECK(hipStreamSynchronize(s));
+    if (it > 0 && h->flag_host[0] != 0) {
+      h->last_failed = h->flag_host[0];
+      return set_error(std::to_string(h->last_failed) + " inner RVE solves missed rve_tol"), FE2_ENOCONV;
+    }
+    if (h->flag_host[2] == 0) return FE2_OK;
+    if (it >= h->max_micro_it) {
+      h->last_failed = h->flag_host[2];
+      return set_error(std::to_string(h->last_failed) + " RVEs not in equilibrium after max_micro_it"),
+             FE2_ENOCONV;
+    }
+    hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->fail_count, static_cast<size_t>(1), 0);
+    for (auto& c : h->classes) {
+      const int n = static_cast<int>(c.rves.size());
+      const int fl = RVE_SOLVE | RVE_RONLY;
+      rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, fl), n, h->precision, h->nF + 1, s)
+                                       : launch_lin2d(h->largs(c, fl), n, h->precision, h->nF + 1, s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_sub_xr, dim3(h->n_rve), dim3(256), 0, s, h->nF, h->foff, h->Xs, h->w);
+    FE2_HIP_CHECK(hipGetLastError());
+    h->last_micro_its = it + 1;
+    if ((rc = assemble_impl(h, s))) return rc;
+  }
 }
 
 // Macro residual vectors and norms of the current assembly (no solve).
@@ -638,9 +685,11 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   auto mark = [&](int i) {
     if (h->prof) (void)hipEventRecord(h->ev[i], s);
   };
-  // a2-a4 at the current state and the residual norms (a10)
+  const bool classical = h->scheme == FE2_SCHEME_CLASSICAL;
+  // a2-a4 at the current state (classical: after the inner equilibration)
+  // and the residual norms (a10)
   mark(0);
-  if ((rc = assemble_impl(h, s))) return rc;
+  if ((rc = classical ? equilibrate_impl(h, s) : assemble_impl(h, s))) return rc;
   if ((rc = residual_impl(h, load_factor, s))) return rc;
   mark(1);
   FE2_HIP_CHECK(hipMemcpyAsync(h->norms_host, h->norms_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -657,7 +706,8 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   }
   // a5-a6: RVE solves; the residual column is dropped when every RVE
   // residual is exactly zero (first iteration from the reference state)
-  const int nrhs = h->norms_host[2] == 0.0 ? h->nF : h->nF + 1;
+  // (classical: the RVEs are in equilibrium and only X_F is needed)
+  const int nrhs = (classical || h->norms_host[2] == 0.0) ? h->nF : h->nF + 1;
   mark(2);
   if ((rc = solve_impl(h, nrhs, s))) return rc;
   mark(3);
@@ -687,6 +737,15 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
            FE2_ENOCONV;
   if (h->last_failed) return set_error(std::to_string(h->last_failed) + " RVE solves missed rve_tol"), FE2_ENOCONV;
   return FE2_OK;
+}
+
+int fe2_equilibrate_rve(fe2_handle h, int* iters_host, void* stream) {
+  FE2_GUARD(h);
+  if (!(h->micro_tol > 0.0) || h->max_micro_it <= 0)
+    return set_error("inner equilibration needs micro_tol > 0 and max_micro_it > 0"), FE2_EINVAL;
+  const int rc = equilibrate_impl(h, static_cast<hipStream_t>(stream));
+  if (iters_host) *iters_host = h->last_micro_its;
+  return rc;
 }
 
 int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream) {
@@ -773,6 +832,7 @@ int fe2_query(fe2_handle h, int which, int64_t* out) {
     case FE2_Q_FAILED_RVES: *out = h->last_failed; return FE2_OK;
     case FE2_Q_N_RVE: *out = h->n_rve; return FE2_OK;
     case FE2_Q_FIELD_OFFSETS: std::memcpy(out, h->h_foff.data(), h->h_foff.size() * sizeof(int64_t)); return FE2_OK;
+    case FE2_Q_MICRO_ITERS: *out = h->last_micro_its; return FE2_OK;
     default: return set_error("unknown query"), FE2_EINVAL;
   }
 }

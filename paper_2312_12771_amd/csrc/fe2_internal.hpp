@@ -70,7 +70,9 @@ enum RveFlags : int {
   RVE_SOLVE = 2,      // PCG + refinement + condensation (a5, a6)
   RVE_WARM = 4,       // start from the solution stored in X
   RVE_RCOL = 8,       // solve the residual column (nF+1 right-hand sides)
-  RVE_FFT = 16        // homogeneous-reference (FFT) preconditioner
+  RVE_FFT = 16,       // homogeneous-reference (FFT) preconditioner
+  RVE_RONLY = 32      // solve the residual column only (x_r), no condensation;
+                      // RVEs with rnorm2 <= thr2 are skipped (x_r = 0)
 };
 
 // One launch handles the RVEs of one resolution class (same n1 x n2 and same
@@ -97,6 +99,7 @@ struct Lin2DArgs {
   double* iters;                // [n_rve] inner PCG iterations (all columns)
   double* mv64;                 // [n_rve] FP64 operator applications
   int* fail_count;              // RVEs that missed tol
+  const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
   const float* fft_tab;         // spectral preconditioner table (RVE_FFT)
   double volume;
   double tol, tol_in;
@@ -125,6 +128,7 @@ struct Fin2DArgs {
   double* iters;                // [n_rve] inner PCG iterations (all columns)
   double* mv64;                 // [n_rve] FP64 operator applications
   int* fail_count;              // RVEs that missed tol (or lost J > 0)
+  const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
   double h1, h2;                // element edge lengths
   double volume;
   double tol, tol_in;

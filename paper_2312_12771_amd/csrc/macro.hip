@@ -566,6 +566,40 @@ __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int
   }
 }
 
+// Classical inner loop (Sec. 4.1): per-RVE stopping threshold
+// thr2_b = tol^2 max(1, ||r_b^0||^2), the number of RVEs above it, and the
+// Newton update w_b -= x_r of the RVEs' residual solves.
+__global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, double tol,
+                            double* __restrict__ thr2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_rve) thr2[b] = tol * tol * fmax(1.0, rnorm2[b]);
+}
+
+__global__ void __launch_bounds__(1024) k_count_above(int n_rve, const double* __restrict__ rnorm2,
+                                                      const double* __restrict__ thr2, int* __restrict__ count) {
+  __shared__ int part[16];
+  int c = 0;
+  for (int b = threadIdx.x; b < n_rve; b += blockDim.x) c += !(rnorm2[b] <= thr2[b]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < static_cast<int>(blockDim.x + 63) / 64; ++w) t += part[w];
+    *count = t;
+  }
+}
+
+__global__ void k_sub_xr(int nF, const int64_t* __restrict__ foff, const double* __restrict__ X,
+                         double* __restrict__ w) {
+  const int b = blockIdx.x;
+  const int64_t fo = foff[b];
+  const int64_t flen = foff[b + 1] - fo;
+  const double* xr = X + fo * (nF + 1) + nF * flen;
+  for (int64_t t = threadIdx.x; t < flen; t += blockDim.x) w[fo + t] -= xr[t];
+}
+
 // Norms of the convergence test: out = [||[R_free; R_micro]||, ||R_free||,
 // ||R_micro||, ||F_int||] with R_micro,b = wdet_b / |Omega| r_b.
 __global__ void __launch_bounds__(1024) k_norms(MacroArgs m, const double* __restrict__ r_true,

@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
     double red[23];
     {
       double acc[22];
-      pass64(std::integral_constant<int, 0>(), 0, nullptr, solve, acc);
+      pass64(std::integral_constant<int, 0>(), 0, nullptr, solve && !(a.flags & RVE_RONLY), acc);
 #pragma unroll
       for (int t = 0; t < 20; ++t) red[t] = acc[t];
       red[21] = acc[20];
@@ -346,7 +346,16 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
       a.rnorm2[b] = red[20];
     }
     if (!solve) return;
-    if (tid == 0) {   // condensation accumulates into these
+    if ((a.flags & RVE_RONLY) && red[20] <= a.thr2[b]) {   // in equilibrium: x_r = 0
+#pragma unroll
+      for (int k = 0; k < NPT; ++k)
+        if (node_ok(k)) {
+          Xb[NF * flen + 2 * (tid + k * WG)] = 0.0;
+          Xb[NF * flen + 2 * (tid + k * WG) + 1] = 0.0;
+        }
+      return;
+    }
+    if (tid == 0 && !(a.flags & RVE_RONLY)) {   // condensation accumulates into these
 #pragma unroll
       for (int t = 0; t < NF * NF; ++t) a.Cbar[static_cast<size_t>(b) * NF * NF + t] = red[4 + t];
 #pragma unroll
@@ -450,8 +459,9 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
   bool all_ok = true;
   double worst = 0.0;
 
+  const bool ronly = (a.flags & RVE_RONLY) != 0;
 #pragma unroll 1
-  for (int kc = 0; kc < NRHS; ++kc) {
+  for (int kc = ronly ? NF : 0; kc < NRHS; ++kc) {
     double* xc = Xb + kc * flen;
     bool xzero = !warm || kc >= NF;
     if (xzero) {
@@ -507,6 +517,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
       }
       // inner Jacobi PCG in TI on K d = res, from d = 0
       TI ri[NPT][2], xi[NPT][2], pown[NPT][2];
+      bool indefinite = false;
       double rz, r0;
       __syncthreads();   // force buffer free before s_p is written
       {
@@ -539,7 +550,10 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
 #pragma unroll
           for (int d = 0; d < 2; ++d) pq[0] += static_cast<double>(pown[k][d]) * static_cast<double>(q[k][d]);
         wg_sum<1, NW>(pq, s_red, parity);
-        if (!(pq[0] > 0.0)) break;   // breakdown (exact solution or loss of definiteness)
+        if (!(pq[0] > 0.0)) {   // breakdown: exact solution, or negative curvature
+          indefinite = !(pq[0] == 0.0);
+          break;
+        }
         const TI alpha = static_cast<TI>(rz / pq[0]);
         double red2[2] = {0.0, 0.0};
 #pragma unroll
@@ -567,6 +581,11 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
             if (node_ok(k)) put_halo<N1, N2>(s_p + d * P::PN, n % N1, n / N1, pown[k][d]);
           }
       }
+      if (indefinite) {   // K_ww is not positive definite here: PCG cannot solve it
+        worst = __builtin_inf();
+        all_ok = false;
+        break;
+      }
 #pragma unroll
       for (int k = 0; k < NPT; ++k)
         if (node_ok(k)) {
@@ -585,6 +604,16 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
         xc[2 * (tid + k * WG)] = 0.0;
         xc[2 * (tid + k * WG) + 1] = 0.0;
       }
+  }
+
+  if (ronly) {
+    if (tid == 0) {
+      a.relres[b] = worst;
+      a.iters[b] = static_cast<double>(iters);
+      a.mv64[b] = static_cast<double>(nmv64);
+      if (!all_ok) atomicAdd(a.fail_count, 1);
+    }
+    return;
   }
 
   // ---- a6: condensation (energy form) ---------------------------------------

@@ -250,6 +250,17 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
   }
   if (!(a.flags & RVE_SOLVE)) return;
+  const bool ronly = (a.flags & RVE_RONLY) != 0;
+  if (ronly && a.rnorm2[b] <= a.thr2[b]) {   // already in equilibrium: x_r = 0
+    double* xc = Xb + NF * flen;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (exists[k]) {
+        xc[2 * node_of(k)] = 0.0;
+        xc[2 * node_of(k) + 1] = 0.0;
+      }
+    return;
+  }
 
   // ---- a5: per column, FP64 refinement around the inner PCG --------------
   TI dinv[4][2];
@@ -275,7 +286,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   double worst = 0.0;
 
 #pragma unroll 1
-  for (int kc = 0; kc < NRHS; ++kc) {
+  for (int kc = ronly ? NF : 0; kc < NRHS; ++kc) {
     double* xc = Xb + kc * flen;
     bool xzero = !warm || kc >= NF;   // warm start: previous X_F; x_r from zero
     if (xzero) {
@@ -405,6 +416,16 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         xc[2 * node_of(k)] = 0.0;
         xc[2 * node_of(k) + 1] = 0.0;
       }
+  }
+
+  if (ronly) {
+    if (tid == 0) {
+      a.relres[b] = worst;
+      a.iters[b] = static_cast<double>(iters);
+      a.mv64[b] = static_cast<double>(nmv64);
+      if (!all_ok) atomicAdd(a.fail_count, 1);
+    }
+    return;
   }
 
   // ---- a6: condensation (energy form) from a final FP64 pass -------------

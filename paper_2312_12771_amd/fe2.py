@@ -34,7 +34,7 @@ FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
  FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
  FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64) = range(13)
 (FE2_Q_NF, FE2_Q_FIELD_LEN, FE2_Q_NDOF, FE2_Q_BANDWIDTH, FE2_Q_FAILED_RVES,
- FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS) = range(7)
+ FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS, FE2_Q_MICRO_ITERS) = range(8)
 
 _KIN = {"small": FE2_SMALL_STRAIN, "finite": FE2_FINITE_STRAIN}
 _MAT = {"linear": FE2_LINEAR_ISO, "neohooke": FE2_NEO_HOOKE,
@@ -69,6 +69,7 @@ _sig = {
     "fe2_assemble_rve": (C.c_int, [_vp, _vp]),
     "fe2_condense": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fe2_newton_step": (C.c_int, [_vp, C.c_double, _dp, _vp]),
+    "fe2_equilibrate_rve": (C.c_int, [_vp, C.POINTER(C.c_int), _vp]),
     "fe2_get_state": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fe2_set_state": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp]),
     "fe2_get_data": (C.c_int, [_vp, C.c_int, _vp, _vp]),
@@ -204,6 +205,14 @@ def fe2_newton_step(h: Handle, load_factor: float, stream=None):
     return st, norms
 
 
+def fe2_equilibrate_rve(h: Handle, stream=None, allow_noconv=False):
+    """Classical inner loop at the current state; returns (status, rounds)."""
+    its = C.c_int(0)
+    st = _lib.fe2_equilibrate_rve(h.ptr, C.byref(its), _stream_ptr(stream))
+    _check(st, "fe2_equilibrate_rve", (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,))
+    return st, int(its.value)
+
+
 def fe2_get_state(h: Handle, u=None, w=None, stream=None):
     return _check(_lib.fe2_get_state(h.ptr, _dev_ptr(u), _dev_ptr(w), _stream_ptr(stream)),
                   "fe2_get_state")
@@ -254,14 +263,18 @@ def abi_version() -> int:
 # host-side driver: load stepping around fe2_newton_step
 # --------------------------------------------------------------------------
 
-def solve(h: Handle, load_factors, max_it: int = 20, stream=None, history: Optional[list] = None):
+def solve(h: Handle, load_factors, max_it: int = 20, stream=None, history: Optional[list] = None,
+          diverge_at: float = 1e10):
     """Load stepping: for every load factor call fe2_newton_step until it
-    reports convergence.  Raises RuntimeError when a step exceeds max_it."""
+    reports convergence.  Raises RuntimeError when a step exceeds max_it or
+    the macro residual norm exceeds ``diverge_at`` (or is not finite)."""
     for lam in load_factors:
         h_step = []
         for it in range(max_it + 1):
             st, norms = fe2_newton_step(h, lam, stream)
             h_step.append(norms)
+            if not np.isfinite(norms[1]) or norms[1] > diverge_at:
+                raise RuntimeError(f"diverged at load factor {lam}, iteration {it}")
             if st == FE2_CONVERGED:
                 break
         else:

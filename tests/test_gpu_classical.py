@@ -1,0 +1,170 @@
+"""GPU parity of the classical (staggered) scheme of Sec. 4.1 and of its inner
+RVE equilibration against the FP64 oracle, through the C ABI.
+
+* fe2_equilibrate_rve: every RVE's micro Newton loop at a fixed, strongly
+  nonlinear macro gradient reaches the oracle's equilibrium fluctuation.
+* One classical macro iteration (Eqs. (43)-(45)): macro increment, state and
+  norms equal the oracle's classical_step.
+* Load stepping with the classical scheme: converged state and Newton
+  iteration counts equal the oracle's; for a linear problem both schemes give
+  the same solution.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import macro as M
+from oracle import rve as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe2():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2312_12771_amd import fe2 as f
+    return f
+
+
+def dz(n):
+    return torch.zeros(int(n), dtype=torch.float64, device="cuda")
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def get(fe2, h, which, n):
+    t = dz(n)
+    fe2.fe2_get_data(h, which, t)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("name,kw", [("cfg5", dict(macro=(2, 1), rve=8)),
+                                     ("cook", dict(n_macro=1, n_rve=30))])
+def test_inner_equilibration_matches_oracle(fe2, name, kw, prec):
+    p = W.config(name, **kw)
+    rng = np.random.default_rng(21)
+    # deformations of a few per cent at which every RVE tangent is positive
+    # definite (checked below with the oracle's matrices)
+    u = (0.01 if name == "cfg5" else 3.0) * rng.standard_normal(p.n_dofs)
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-12, micro_tol=1e-13,
+                      scheme="classical")
+    fe2.fe2_set_state(h, u=torch.tensor(u, device="cuda"), load_factor=0.0)
+    st, rounds = fe2.fe2_equilibrate_rve(h)
+    assert st == fe2.FE2_OK and rounds >= 2
+    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
+    off = fe2.fe2_query(h, fe2.FE2_Q_FIELD_OFFSETS)
+    w = dz(flen)
+    fe2.fe2_get_state(h, w=w)
+    w = w.cpu().numpy()
+    res = get(fe2, h, fe2.FE2_D_RESIDUAL, flen)
+    geo = M.macro_geometry(p)
+    for b in range(p.n_rve):
+        F = M.macro_gradient(p, geo, u, b)
+        assert np.abs(F - np.eye(2).ravel()).max() > 0.01
+        s0 = R.assemble_rve(*R.rve_problem_args(p, b)[:3], p.kinematics, p.material, F, None,
+                            p.rve_size)
+        assert np.linalg.eigvalsh(s0.K_ww.toarray())[0] > 0.0
+        wo, hist = R.equilibrate_rve(p, b, F, tol=1e-13)
+        assert rel(w[off[b]:off[b + 1]], wo) < 1e-9
+        # the GPU stopped by the same rule as the oracle
+        assert np.linalg.norm(res[off[b]:off[b + 1]]) < 1e-13 * max(1.0, hist[0])
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_classical_one_macro_iteration(fe2, prec):
+    p = W.config("cfg5", macro=(3, 2), rve=8)
+    rng = np.random.default_rng(17)
+    u = 5e-3 * rng.standard_normal(p.n_dofs)
+    ws = []
+    for b in range(p.n_rve):
+        w = 1e-4 * rng.standard_normal(128)
+        w[:2] = 0.0
+        ws.append(w)
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-12, scheme="classical")
+    fe2.fe2_set_state(h, u=torch.tensor(u, device="cuda"),
+                      w=torch.tensor(np.concatenate(ws), device="cuda"), load_factor=0.2)
+    st, norms = fe2.fe2_newton_step(h, 0.3)
+    assert st == fe2.FE2_OK
+    du = get(fe2, h, fe2.FE2_D_MACRO_DU, p.n_dofs)
+    u_gpu, w_gpu = dz(p.n_dofs), dz(fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN))
+    fe2.fe2_get_state(h, u_gpu, w_gpu)
+    torch.cuda.synchronize()
+    geo = M.macro_geometry(p)
+    state = M.State(u=u.copy(), w=[w.copy() for w in ws], lam=0.2)
+    nrm, du_o, _ = M.classical_step(p, geo, state, 0.3)
+    assert rel(du, du_o) < 1e-9
+    assert rel(u_gpu.cpu().numpy(), state.u) < 1e-12
+    assert rel(w_gpu.cpu().numpy(), np.concatenate(state.w)) < 1e-9
+    # the micro part of the norm is rounding-level after equilibration
+    assert abs(norms[1] - nrm.macro) <= 1e-10 * nrm.macro
+    assert abs(norms[3] - nrm.scale) <= 1e-10 * nrm.scale
+    assert norms[2] < 1e-11 * nrm.scale and nrm.micro < 1e-11 * nrm.scale
+    h.close()
+
+
+def test_classical_load_stepping_matches_oracle(fe2):
+    p = W.config("cfg5", macro=(2, 2), rve=8)
+    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-12, newton_tol=1e-10, scheme="classical")
+    hist = []
+    fe2.solve(h, p.load_factors, history=hist)
+    u, w = dz(p.n_dofs), dz(fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN))
+    fe2.fe2_get_state(h, u, w)
+    torch.cuda.synchronize()
+    st, hist_o = M.solve(p, scheme="classical", tol=1e-10)
+    assert rel(u.cpu().numpy(), st.u) < 1e-9
+    assert rel(w.cpu().numpy(), np.concatenate(st.w)) < 1e-7
+    assert [len(x) for x in hist] == [len(x) for x in hist_o]
+    h.close()
+
+
+def test_schemes_agree_on_a_linear_problem(fe2):
+    """Small strain: the generalized step reaches the nested solution in one
+    iteration, so both schemes give the same macro displacement."""
+    p = W.config("cfg2", macro=(3, 3), rve=16)
+    us = []
+    for scheme in ("generalized", "classical"):
+        h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-12, scheme=scheme)
+        hist = []
+        fe2.solve(h, p.load_factors, history=hist)
+        assert len(hist[0]) == 2
+        u = dz(p.n_dofs)
+        fe2.fe2_get_state(h, u=u)
+        us.append(u.cpu().numpy())
+        h.close()
+    assert rel(us[1], us[0]) < 1e-10
+
+
+def test_indefinite_rve_tangent_is_reported(fe2):
+    """At about 8-15 % volumetric compression with w = 0 three RVEs of this
+    state have an RVE tangent K_ww with a negative eigenvalue (checked with
+    the oracle's matrices).  The PCG solver needs a positive definite K_ww:
+    those RVEs are reported as failed (negative curvature), the others
+    solve."""
+    p = W.config("cfg5", macro=(2, 1), rve=8)
+    rng = np.random.default_rng(21)
+    u = 0.03 * rng.standard_normal(p.n_dofs)
+    geo = M.macro_geometry(p)
+    indef = []
+    for b in range(p.n_rve):
+        F = M.macro_gradient(p, geo, u, b)
+        s0 = R.assemble_rve(*R.rve_problem_args(p, b)[:3], p.kinematics, p.material, F, None,
+                            p.rve_size)
+        indef.append(np.linalg.eigvalsh(s0.K_ww.toarray())[0] < 0.0)
+    assert sum(indef) == 3
+    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-12)
+    fe2.fe2_set_state(h, u=torch.tensor(u, device="cuda"), load_factor=0.0)
+    fe2.fe2_assemble_rve(h)
+    st = fe2.fe2_condense(h, allow_noconv=True)
+    assert st == fe2.FE2_ENOCONV
+    assert fe2.fe2_query(h, fe2.FE2_Q_FAILED_RVES) == 3
+    relres = get(fe2, h, fe2.FE2_D_RVE_RELRES, p.n_rve)
+    assert np.all(np.isinf(relres[np.array(indef)]))
+    assert np.all(relres[~np.array(indef)] < 1e-12)
+    h.close()
