@@ -239,6 +239,39 @@ int fe2_get_profile(fe2_handle h, double* out);
 /* Release all device memory of the handle (waits for its work). */
 int fe2_destroy(fe2_handle h);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network (not part of the paper): a multilayer perceptron that
+ * stands in for the equilibrated RVE response of the nested scheme
+ * (Sec. 4.1), trained on RVE solves of this library.  FP32 throughout.
+ *   y = W_L h_{L-1} + b_L,  h_l = tanh(W_l h_{l-1} + b_l),  h_0 = x,
+ * W_l of shape (sizes[l+1], sizes[l]) row-major; the flat parameter vector
+ * holds W_0, b_0, W_1, b_1, ... (fe2_mlp_n_params floats).
+ * Loss L = (1/B) sum_s sum_o w_o (y_so - t_so)^2.
+ * All *_dev pointers are caller-owned device float32 arrays, row-major
+ * [batch][width].  Calls enqueue on `stream` and return without waiting,
+ * except fe2_mlp_loss_grad with loss_host != NULL.
+ * ------------------------------------------------------------------------ */
+typedef struct fe2_mlp_ctx* fe2_mlp;
+
+/* n_layers weight layers (1..8), sizes[n_layers+1] widths (1..4096), buffers
+ * for up to max_batch samples.  Parameters and Adam moments start at zero. */
+int fe2_mlp_create(int n_layers, const int* sizes, int max_batch, void* stream, fe2_mlp* out);
+int fe2_mlp_destroy(fe2_mlp m);
+int fe2_mlp_n_params(fe2_mlp m, int64_t* out);
+int fe2_mlp_set_params(fe2_mlp m, const float* theta_dev, void* stream);
+int fe2_mlp_get_params(fe2_mlp m, float* theta_dev, void* stream);
+/* Y_dev [batch][sizes[n_layers]] = network(X_dev [batch][sizes[0]]). */
+int fe2_mlp_forward(fe2_mlp m, int batch, const float* X_dev, float* Y_dev, void* stream);
+/* Loss and its gradient with respect to the parameters (kept in the handle
+ * for fe2_mlp_adam_step; also copied to grad_dev when it is not NULL).
+ * loss_host != NULL waits for the stream and returns the loss. */
+int fe2_mlp_loss_grad(fe2_mlp m, int batch, const float* X_dev, const float* T_dev, const float* w_out_dev,
+                      float* grad_dev, double* loss_host, void* stream);
+/* One Adam step (Kingma and Ba, with bias correction) with the stored
+ * gradient; the step counter starts at 1 after create or reset. */
+int fe2_mlp_adam_step(fe2_mlp m, float lr, float beta1, float beta2, float eps, void* stream);
+int fe2_mlp_reset_optimizer(fe2_mlp m, void* stream);
+
 const char* fe2_strerror(int status);
 const char* fe2_last_error(void);
 int fe2_abi_version(void);

@@ -77,6 +77,15 @@ _sig = {
     "fe2_destroy": (C.c_int, [_vp]),
     "fe2_set_profiling": (C.c_int, [_vp, C.c_int]),
     "fe2_get_profile": (C.c_int, [_vp, _dp]),
+    "fe2_mlp_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.c_int, _vp, C.POINTER(_vp)]),
+    "fe2_mlp_destroy": (C.c_int, [_vp]),
+    "fe2_mlp_n_params": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
+    "fe2_mlp_set_params": (C.c_int, [_vp, _vp, _vp]),
+    "fe2_mlp_get_params": (C.c_int, [_vp, _vp, _vp]),
+    "fe2_mlp_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "fe2_mlp_loss_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _dp, _vp]),
+    "fe2_mlp_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "fe2_mlp_reset_optimizer": (C.c_int, [_vp, _vp]),
     "fe2_strerror": (C.c_char_p, [C.c_int]),
     "fe2_last_error": (C.c_char_p, []),
     "fe2_abi_version": (C.c_int, []),
@@ -112,6 +121,15 @@ def _dev_ptr(t):
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("device buffers must be contiguous float64 tensors on the GPU")
+    return _vp(t.data_ptr())
+
+
+def _dev_ptr32(t):
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("network buffers must be contiguous float32 tensors on the GPU")
     return _vp(t.data_ptr())
 
 
@@ -282,3 +300,68 @@ def solve(h: Handle, load_factors, max_it: int = 20, stream=None, history: Optio
         if history is not None:
             history.append(h_step)
     return h
+
+
+# --------------------------------------------------------------------------
+# surrogate network
+# --------------------------------------------------------------------------
+
+class MLP:
+    """Owns an fe2_mlp: tanh multilayer perceptron with FP32 forward,
+    loss gradient and Adam on the GPU (argument marshalling only)."""
+
+    def __init__(self, sizes, max_batch: int, stream=None):
+        arr = (C.c_int * len(sizes))(*[int(x) for x in sizes])
+        p = _vp()
+        _check(_lib.fe2_mlp_create(len(sizes) - 1, arr, int(max_batch), _stream_ptr(stream), C.byref(p)),
+               "fe2_mlp_create")
+        self._ptr = p
+        self.sizes = list(sizes)
+        self.max_batch = int(max_batch)
+        n = C.c_int64()
+        _check(_lib.fe2_mlp_n_params(self._ptr, C.byref(n)), "fe2_mlp_n_params")
+        self.n_params = int(n.value)
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("network is closed")
+        return self._ptr
+
+    def set_params(self, theta, stream=None):
+        _check(_lib.fe2_mlp_set_params(self.ptr, _dev_ptr32(theta), _stream_ptr(stream)), "fe2_mlp_set_params")
+
+    def get_params(self, out, stream=None):
+        _check(_lib.fe2_mlp_get_params(self.ptr, _dev_ptr32(out), _stream_ptr(stream)), "fe2_mlp_get_params")
+        return out
+
+    def forward(self, X, Y, stream=None):
+        _check(_lib.fe2_mlp_forward(self.ptr, int(X.shape[0]), _dev_ptr32(X), _dev_ptr32(Y),
+                                    _stream_ptr(stream)), "fe2_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T, w_out, grad=None, want_loss=True, stream=None):
+        loss = C.c_double(0.0)
+        _check(_lib.fe2_mlp_loss_grad(self.ptr, int(X.shape[0]), _dev_ptr32(X), _dev_ptr32(T),
+                                      _dev_ptr32(w_out), _dev_ptr32(grad),
+                                      C.byref(loss) if want_loss else None, _stream_ptr(stream)),
+               "fe2_mlp_loss_grad")
+        return float(loss.value) if want_loss else None
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.fe2_mlp_adam_step(self.ptr, float(lr), float(beta1), float(beta2), float(eps),
+                                      _stream_ptr(stream)), "fe2_mlp_adam_step")
+
+    def reset_optimizer(self, stream=None):
+        _check(_lib.fe2_mlp_reset_optimizer(self.ptr, _stream_ptr(stream)), "fe2_mlp_reset_optimizer")
+
+    def close(self):
+        if self._ptr is not None:
+            _lib.fe2_mlp_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,4 +19,5 @@ from .generators import (  # noqa: F401
     phases_sphere,
     phases_cross,
     subset_problem,
+    mlp_init,
 )

@@ -402,6 +402,19 @@ def cook(n_macro=20, n_rve=30, n_steps=22, traction=(-5.0, 10.0)):
                                        traction=traction))
 
 
+def mlp_init(sizes: Sequence[int], seed: int = SEED_BASE) -> np.ndarray:
+    """Initial parameters of a multilayer perceptron in the flat layout
+    W_0, b_0, W_1, b_1, ... (W_l of shape (sizes[l+1], sizes[l]), row-major):
+    weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        a = np.sqrt(6.0 / (sizes[i] + sizes[i + 1]))
+        parts.append(rng.uniform(-a, a, size=sizes[i + 1] * sizes[i]))
+        parts.append(np.zeros(sizes[i + 1]))
+    return np.concatenate(parts)
+
+
 _CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4,
             "cfg5": cfg5, "cook": cook}
 
