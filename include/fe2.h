@@ -215,7 +215,9 @@ enum {
   FE2_D_MACRO_GRAD = 0, FE2_D_RESIDUAL = 1, FE2_D_PBAR = 2, FE2_D_SOLUTION = 3,
   FE2_D_RVE_ITERS = 4, FE2_D_RVE_RELRES = 5, FE2_D_MACRO_RHS = 6,
   FE2_D_MACRO_RTRUE = 7, FE2_D_MACRO_DU = 8, FE2_D_MACRO_KDENSE = 9,
-  FE2_D_CBAR = 10, FE2_D_PHAT = 11, FE2_D_RVE_MV64 = 12
+  FE2_D_CBAR = 10, FE2_D_PHAT = 11, FE2_D_RVE_MV64 = 12,
+  FE2_D_PHASE_FRACTION = 13,   /* [n_rve] volume fraction of phase 1 */
+  FE2_D_SURR_ERR = 14          /* [n_rve] last fe2_surrogate_judge error per point */
 };
 int fe2_get_data(fe2_handle h, int which, double* dst_dev, void* stream);
 
@@ -271,6 +273,54 @@ int fe2_mlp_loss_grad(fe2_mlp m, int batch, const float* X_dev, const float* T_d
  * gradient; the step counter starts at 1 after create or reset. */
 int fe2_mlp_adam_step(fe2_mlp m, float lr, float beta1, float beta2, float eps, void* stream);
 int fe2_mlp_reset_optimizer(fe2_mlp m, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate of the equilibrated RVE response (2D finite strain).
+ * Input x = (E11, E22, E12, phi): Green-Lagrange strain of the macro
+ * gradient and the phase-1 volume fraction of the RVE; output
+ * y = (S11, S22, S12, D11, D22, D33, D12, D13, D23): second Piola-Kirchhoff
+ * stress and the symmetric Voigt matrix of dS/dE (tensor shear components,
+ * S_v = D (E11, E22, 2 E12)).  The homogenized first Piola-Kirchhoff stress
+ * and tangent follow as P = F S and A_iJkL = delta_ik S_LJ + F_iM F_kN C_MJNL.
+ * Normalisation vector `norm` (26 doubles): in_lo[4], in_hi[4] (the network
+ * sees 2 (x - lo) / (hi - lo) - 1 and the surrogate is used only inside
+ * [lo, hi]), out_mean[9], out_std[9] (y = mean + std * network output).
+ * ------------------------------------------------------------------------ */
+
+/* Equilibrated RVE response at caller-given macro gradients (the material
+ * point of the nested scheme, Sec. 4.1): F_dev [n_rve][nF]; every RVE is
+ * equilibrated from its current fluctuation (fe2_equilibrate_rve rules) and
+ * condensed.  Outputs (NULL = skip): P_dev [n_rve][nF] volume-averaged
+ * stress, C_dev [n_rve][nF][nF] homogenized tangent, ok_dev [n_rve] 1.0 where
+ * the RVE reached equilibrium and the condensation met rve_tol, else 0.0.
+ * Returns FE2_ENOCONV when some RVE failed (the others are still valid). */
+int fe2_rve_response(fe2_handle h, const double* F_dev, double* P_dev, double* C_dev, double* ok_dev,
+                     void* stream);
+/* Training pairs from RVE responses of this handle's RVE batch (FP64):
+ * X_dev [n_rve][4] inputs, T_dev [n_rve][9] outputs as defined above. */
+int fe2_surrogate_dataset(fe2_handle h, const double* F_dev, const double* P_dev, const double* C_dev,
+                          double* X_dev, double* T_dev, void* stream);
+/* Column statistics of V_dev [n][m] over the rows with ok_dev[row] != 0
+ * (ok_dev may be NULL): out_dev [4][m] = min, max, mean, standard deviation. */
+int fe2_surrogate_stats(int n, int m, const double* V_dev, const double* ok_dev, double* out_dev, void* stream);
+/* out_dev [n][m] (float) = (V - a) / b (mode 0) or 2 (V - a) / (b - a) - 1
+ * (mode 1), per column. */
+int fe2_surrogate_normalize(int n, int m, const double* V_dev, const double* a_dev, const double* b_dev, int mode,
+                            float* out_dev, void* stream);
+/* Use the network in fe2_newton_step: every Gauss point whose input lies in
+ * [in_lo, in_hi] and that the judge has not rejected takes (P, A) from the
+ * network; the others run the classical RVE path (inner equilibration and
+ * condensation).  The network must map 4 -> 9 and hold max_batch >= n_rve;
+ * the handle keeps the pointer (detach before destroying the network). */
+int fe2_surrogate_attach(fe2_handle h, fe2_mlp net, const double* norm_dev, void* stream);
+int fe2_surrogate_detach(fe2_handle h);
+/* Error judge at the current state: full RVE responses at every Gauss point
+ * (surrogate points from w~ = 0) against the network's; a point with
+ * max(|dP| / max(|P|, 1e-3 |A|), |dA| / |A|) > tol (Frobenius norms) is
+ * rejected for the rest of the handle's life and keeps its equilibrated
+ * fluctuation.  Returns the largest error and the number of points rejected
+ * by this call. */
+int fe2_surrogate_judge(fe2_handle h, double tol, double* max_err_host, int* n_rejected_host, void* stream);
 
 const char* fe2_strerror(int status);
 const char* fe2_last_error(void);

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "macro.hpp"
+#include "surrogate.hpp"
 
 namespace fe2 {
 
@@ -91,8 +92,17 @@ struct fe2_ctx {
   double* mv64 = nullptr;
   int* flag_host = nullptr;       // pinned [3]
   double* thr2 = nullptr;         // [n_rve] inner-loop thresholds
-  int* count = nullptr;           // RVEs above their threshold
+  int* count = nullptr;           // [2] RVEs above their threshold, RVEs excluded
   int last_micro_its = 0;
+  int* eq_skip = nullptr;         // [n_rve] RVEs excluded from the current inner loop
+  const int* skip = nullptr;      // RVEs the RVE kernels leave alone (null: none)
+  bool fixed_grad = false;        // macro gradients set by the caller, not from u
+  // surrogate (finite strain): network, normalisation, per-point flags
+  fe2_mlp surr_net = nullptr;
+  double *surr_norm = nullptr, *phi = nullptr, *surrP = nullptr, *surrC = nullptr, *surr_err = nullptr;
+  float *surr_X = nullptr, *surr_Y = nullptr;
+  int *accept = nullptr, *banned = nullptr;
+  double* okf = nullptr;          // [n_rve] fe2_rve_response status
   int last_failed = 0;
   bool have_solution = false;     // X holds the X_F of an earlier solve (warm start)
 
@@ -145,6 +155,7 @@ struct fe2_ctx {
     a.mv64 = mv64;
     a.fail_count = fail_count;
     a.thr2 = thr2;
+    a.skip = skip;
     a.h1 = rve_size / c.n1;
     a.h2 = rve_size / c.n2;
     a.volume = volume;
@@ -181,6 +192,7 @@ struct fe2_ctx {
     a.mv64 = mv64;
     a.fail_count = fail_count;
     a.thr2 = thr2;
+    a.skip = skip;
     a.fft_tab = nullptr;
     a.volume = volume;
     a.tol = rve_tol;
@@ -201,7 +213,8 @@ void free_ctx(fe2_ctx* h) {
                   h->phase, h->params, h->foff, h->u, h->w, h->r, h->Xs, h->Cbar, h->Phat,
                   h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
-                  h->norms_dev, h->kdense, h->mv64, h->thr2, h->count};
+                  h->norms_dev, h->kdense, h->mv64, h->thr2, h->count, h->eq_skip, h->surr_norm, h->phi,
+                  h->surrP, h->surrC, h->surr_err, h->surr_X, h->surr_Y, h->accept, h->banned, h->okf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& c : h->classes) {
@@ -459,7 +472,12 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if ((rc = dalloc(&h->f_int, h->ndof))) return rc;
   if ((rc = dalloc(&h->norms_dev, 4))) return rc;
   if ((rc = dalloc(&h->thr2, nr))) return rc;
-  if ((rc = dalloc(&h->count, 1))) return rc;
+  if ((rc = dalloc(&h->count, 2))) return rc;
+  if ((rc = dalloc(&h->eq_skip, nr))) return rc;
+  if ((rc = dalloc(&h->okf, nr))) return rc;
+  if ((rc = dalloc(&h->phi, nr))) return rc;
+  hipLaunchKernelGGL(k_phase_fraction, dim3(h->n_rve), dim3(256), 0, s, h->n_rve, h->phase_off, h->phase, h->phi);
+  FE2_HIP_CHECK(hipGetLastError());
   if (hipHostMalloc(reinterpret_cast<void**>(&h->norms_host), 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 3 * sizeof(int)) != hipSuccess)
     return set_error("pinned host allocation failed"), FE2_ENOMEM;
@@ -501,8 +519,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
 
 int assemble_impl(fe2_ctx* h, hipStream_t s) {
   MacroArgs m = h->margs();
-  hipLaunchKernelGGL(k_macro_grad, dim3(nblk(h->n_rve, 128)), dim3(128), 0, s, m, h->u, h->mgrad);
-  FE2_HIP_CHECK(hipGetLastError());
+  if (!h->fixed_grad) {
+    hipLaunchKernelGGL(k_macro_grad, dim3(nblk(h->n_rve, 128)), dim3(128), 0, s, m, h->u, h->mgrad);
+    FE2_HIP_CHECK(hipGetLastError());
+  }
   for (auto& c : h->classes) {
     const int n = static_cast<int>(c.rves.size());
     int rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, RVE_ASSEMBLE), n, h->precision, h->nF, s)
@@ -527,43 +547,91 @@ int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
 
 // Classical inner loop at the current macro state (Sec. 4.1): RVE Newton
 // iterations w_b -= K_ww^-1 r_b until ||r_b|| <= micro_tol max(1, ||r_b^0||).
+// RVEs in h->skip are left alone; an RVE whose inner solve fails is excluded
+// from further rounds (the others finish) and the call returns FE2_ENOCONV.
 int equilibrate_impl(fe2_ctx* h, hipStream_t s) {
-  int rc = assemble_impl(h, s);
-  if (rc) return rc;
   const unsigned nb = nblk(h->n_rve, 256);
-  hipLaunchKernelGGL(k_micro_thr, dim3(nb), dim3(256), 0, s, h->n_rve, h->rnorm2, h->micro_tol, h->thr2);
+  const int* outer = h->skip;
+  hipLaunchKernelGGL(k_copy_mask, dim3(nb), dim3(256), 0, s, h->n_rve, outer, h->eq_skip);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->count + 1, static_cast<size_t>(1), 0);
   FE2_HIP_CHECK(hipGetLastError());
+  h->skip = h->eq_skip;
+  int rc = assemble_impl(h, s);
+  if (!rc) {
+    hipLaunchKernelGGL(k_micro_thr, dim3(nb), dim3(256), 0, s, h->n_rve, h->rnorm2, h->micro_tol, h->thr2);
+    if (hipGetLastError() != hipSuccess) rc = (set_error("launch failed"), FE2_EHIP);
+  }
   h->last_micro_its = 0;
-  for (int it = 0;; ++it) {
-    hipLaunchKernelGGL(k_count_above, dim3(1), dim3(1024), 0, s, h->n_rve, h->rnorm2, h->thr2, h->count);
-    FE2_HIP_CHECK(hipGetLastError());
-    FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host + 2, h->count, sizeof(int), hipMemcpyDeviceToHost, s));
-    FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
-    FE2_HIP_CHECK(hipStreamSynchronize(s));
-    if (it > 0 && h->flag_host[0] != 0) {
-      h->last_failed = h->flag_host[0];
-      return set_error(std::to_string(h->last_failed) + " inner RVE solves missed rve_tol"), FE2_ENOCONV;
+  for (int it = 0; !rc; ++it) {
+    hipLaunchKernelGGL(k_count_above, dim3(1), dim3(1024), 0, s, h->n_rve, h->rnorm2, h->thr2, h->eq_skip, h->count);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h->flag_host + 1, h->count, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = (set_error("inner loop: HIP call failed"), FE2_EHIP);
+      break;
     }
-    if (h->flag_host[2] == 0) return FE2_OK;
+    const int active = h->flag_host[1], dead = h->flag_host[2];
+    if (active == 0) {
+      if (dead) {
+        h->last_failed = dead;
+        rc = (set_error(std::to_string(dead) + " inner RVE solves failed (missed rve_tol or indefinite)"),
+              FE2_ENOCONV);
+      }
+      break;
+    }
     if (it >= h->max_micro_it) {
-      h->last_failed = h->flag_host[2];
-      return set_error(std::to_string(h->last_failed) + " RVEs not in equilibrium after max_micro_it"),
-             FE2_ENOCONV;
+      h->last_failed = active + dead;
+      rc = (set_error(std::to_string(active) + " RVEs not in equilibrium after max_micro_it"), FE2_ENOCONV);
+      break;
     }
-    hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->fail_count, static_cast<size_t>(1), 0);
     for (auto& c : h->classes) {
       const int n = static_cast<int>(c.rves.size());
       const int fl = RVE_SOLVE | RVE_RONLY;
       rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, fl), n, h->precision, h->nF + 1, s)
                                        : launch_lin2d(h->largs(c, fl), n, h->precision, h->nF + 1, s);
-      if (rc) return rc;
+      if (rc) break;
     }
-    hipLaunchKernelGGL(k_sub_xr, dim3(h->n_rve), dim3(256), 0, s, h->nF, h->foff, h->Xs, h->w);
-    FE2_HIP_CHECK(hipGetLastError());
+    if (rc) break;
+    hipLaunchKernelGGL(k_mark_dead, dim3(nb), dim3(256), 0, s, h->n_rve, h->relres, h->rve_tol, h->eq_skip,
+                       h->count + 1);
+    hipLaunchKernelGGL(k_sub_xr, dim3(h->n_rve), dim3(256), 0, s, h->nF, h->foff, h->Xs, h->eq_skip, h->w);
+    if (hipGetLastError() != hipSuccess) {
+      rc = (set_error("inner loop: launch failed"), FE2_EHIP);
+      break;
+    }
     h->last_micro_its = it + 1;
-    if ((rc = assemble_impl(h, s))) return rc;
+    rc = assemble_impl(h, s);
   }
+  h->skip = outer;
+  return rc;
 }
+
+// Surrogate pass over all RVEs at the current u (a2 + network): features,
+// inference, decoding into Pbar / Phat / Cbar of the accepted points; the
+// accepted points become the skip set of the RVE kernels.
+int surrogate_eval_impl(fe2_ctx* h, hipStream_t s) {
+  MacroArgs m = h->margs();
+  const unsigned nb = nblk(h->n_rve, 256);
+  hipLaunchKernelGGL(k_macro_grad, dim3(nblk(h->n_rve, 128)), dim3(128), 0, s, m, h->u, h->mgrad);
+  hipLaunchKernelGGL(k_surr_features, dim3(nb), dim3(256), 0, s, h->n_rve, h->mgrad, h->phi, h->surr_norm,
+                     h->banned, h->surr_X, h->accept);
+  FE2_HIP_CHECK(hipGetLastError());
+  int rc = fe2_mlp_forward(h->surr_net, h->n_rve, h->surr_X, h->surr_Y, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_surr_decode, dim3(nb), dim3(256), 0, s, h->n_rve, h->surr_Y, h->surr_norm, h->mgrad,
+                     h->accept, h->Pbar, h->Phat, h->Cbar, h->rnorm2, h->surrP, h->surrC);
+  FE2_HIP_CHECK(hipGetLastError());
+  h->skip = h->accept;
+  return FE2_OK;
+}
+
+struct SkipReset {
+  fe2_ctx* h;
+  ~SkipReset() {
+    h->skip = nullptr;
+    h->fixed_grad = false;
+  }
+};
 
 // Macro residual vectors and norms of the current assembly (no solve).
 int residual_impl(fe2_ctx* h, double lam, hipStream_t s) {
@@ -606,7 +674,7 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
 int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
   MacroArgs m = h->margs();
   hipLaunchKernelGGL(k_axpy, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->ndof, h->du, h->u);
-  hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr);
+  hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr, h->skip);
   FE2_HIP_CHECK(hipGetLastError());
   return FE2_OK;
 }
@@ -685,10 +753,14 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   auto mark = [&](int i) {
     if (h->prof) (void)hipEventRecord(h->ev[i], s);
   };
-  const bool classical = h->scheme == FE2_SCHEME_CLASSICAL;
-  // a2-a4 at the current state (classical: after the inner equilibration)
-  // and the residual norms (a10)
+  SkipReset reset{h};
+  const bool surr = h->surr_net != nullptr;
+  const bool classical = surr || h->scheme == FE2_SCHEME_CLASSICAL;
+  // a2-a4 at the current state (classical: after the inner equilibration;
+  // surrogate: network at the accepted points, inner equilibration at the
+  // others) and the residual norms (a10)
   mark(0);
+  if (surr && (rc = surrogate_eval_impl(h, s))) return rc;
   if ((rc = classical ? equilibrate_impl(h, s) : assemble_impl(h, s))) return rc;
   if ((rc = residual_impl(h, load_factor, s))) return rc;
   mark(1);
@@ -748,6 +820,131 @@ int fe2_equilibrate_rve(fe2_handle h, int* iters_host, void* stream) {
   return rc;
 }
 
+int fe2_rve_response(fe2_handle h, const double* F_dev, double* P_dev, double* C_dev, double* ok_dev, void* stream) {
+  FE2_GUARD(h);
+  if (!F_dev) return set_error("null macro gradients"), FE2_EINVAL;
+  if (!(h->micro_tol > 0.0) || h->max_micro_it <= 0)
+    return set_error("the RVE response needs micro_tol > 0 and max_micro_it > 0"), FE2_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SkipReset reset{h};
+  const size_t nr = h->n_rve, nF = h->nF;
+  FE2_HIP_CHECK(hipMemcpyAsync(h->mgrad, F_dev, nr * nF * sizeof(double), hipMemcpyDeviceToDevice, s));
+  h->fixed_grad = true;
+  h->skip = nullptr;
+  const int rc = equilibrate_impl(h, s);
+  if (rc && rc != FE2_ENOCONV) return rc;
+  h->skip = h->eq_skip;   // RVEs whose inner loop failed are not condensed
+  int rc2 = solve_impl(h, h->nF, s);
+  if (rc2) return rc2;
+  hipLaunchKernelGGL(k_ok_flags, dim3(nblk(nr, 256)), dim3(256), 0, s, h->n_rve, h->rnorm2, h->thr2, h->relres,
+                     h->rve_tol, h->okf);
+  FE2_HIP_CHECK(hipGetLastError());
+  if (P_dev) FE2_HIP_CHECK(hipMemcpyAsync(P_dev, h->Pbar, nr * nF * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (C_dev) FE2_HIP_CHECK(hipMemcpyAsync(C_dev, h->Cbar, nr * nF * nF * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (ok_dev) FE2_HIP_CHECK(hipMemcpyAsync(ok_dev, h->okf, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+  FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  if (rc == FE2_OK && h->flag_host[0] != 0) {
+    h->last_failed = h->flag_host[0];
+    return set_error(std::to_string(h->last_failed) + " RVE condensations missed rve_tol"), FE2_ENOCONV;
+  }
+  return rc;
+}
+
+int fe2_surrogate_dataset(fe2_handle h, const double* F_dev, const double* P_dev, const double* C_dev,
+                          double* X_dev, double* T_dev, void* stream) {
+  FE2_GUARD(h);
+  if (h->kin != FE2_FINITE_STRAIN || h->dim != 2)
+    return set_error("the surrogate covers 2D finite strain"), FE2_ENOTSUP;
+  if (!F_dev || !P_dev || !C_dev || !X_dev || !T_dev) return set_error("null argument"), FE2_EINVAL;
+  hipLaunchKernelGGL(k_surr_targets, dim3(nblk(h->n_rve, 128)), dim3(128), 0, static_cast<hipStream_t>(stream),
+                     h->n_rve, F_dev, P_dev, C_dev, h->phi, X_dev, T_dev);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int fe2_surrogate_stats(int n, int m, const double* V_dev, const double* ok_dev, double* out_dev, void* stream) {
+  if (n < 1 || m < 1 || !V_dev || !out_dev) return set_error("invalid statistics arguments"), FE2_EINVAL;
+  hipLaunchKernelGGL(k_col_stats, dim3(m), dim3(256), 0, static_cast<hipStream_t>(stream), n, m, V_dev, ok_dev,
+                     out_dev);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int fe2_surrogate_normalize(int n, int m, const double* V_dev, const double* a_dev, const double* b_dev, int mode,
+                            float* out_dev, void* stream) {
+  if (n < 1 || m < 1 || !V_dev || !a_dev || !b_dev || !out_dev || (mode != 0 && mode != 1))
+    return set_error("invalid normalisation arguments"), FE2_EINVAL;
+  const size_t nn = static_cast<size_t>(n) * m;
+  hipLaunchKernelGGL(k_normalize, dim3(nblk(nn, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), n, m, V_dev,
+                     a_dev, b_dev, mode, out_dev);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int fe2_surrogate_attach(fe2_handle h, fe2_mlp net, const double* norm_dev, void* stream) {
+  FE2_GUARD(h);
+  if (h->kin != FE2_FINITE_STRAIN || h->dim != 2)
+    return set_error("the surrogate covers 2D finite strain"), FE2_ENOTSUP;
+  if (!net || !norm_dev) return set_error("null argument"), FE2_EINVAL;
+  if (mlp_width(net, 0) != SURR_NIN || mlp_width(net, 1) != SURR_NOUT)
+    return set_error("the surrogate network must map 4 inputs to 9 outputs"), FE2_EINVAL;
+  if (mlp_max_batch(net) < h->n_rve) return set_error("network max_batch below the number of RVEs"), FE2_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nr = h->n_rve;
+  int rc;
+  if (!h->surr_norm) {
+    if ((rc = dalloc(&h->surr_norm, SURR_NORM)) || (rc = dalloc(&h->surrP, nr * 4)) ||
+        (rc = dalloc(&h->surrC, nr * 16)) || (rc = dalloc(&h->surr_err, nr)) || (rc = dalloc(&h->surr_X, nr * 4)) ||
+        (rc = dalloc(&h->surr_Y, nr * 9)) || (rc = dalloc(&h->accept, nr)) || (rc = dalloc(&h->banned, nr)))
+      return rc;
+  }
+  FE2_HIP_CHECK(hipMemcpyAsync(h->surr_norm, norm_dev, SURR_NORM * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_fill_i, dim3(nblk(nr, 256)), dim3(256), 0, s, h->banned, nr, 0);
+  hipLaunchKernelGGL(k_fill_i, dim3(nblk(nr, 256)), dim3(256), 0, s, h->accept, nr, 0);
+  FE2_HIP_CHECK(hipGetLastError());
+  h->surr_net = net;
+  return FE2_OK;
+}
+
+int fe2_surrogate_detach(fe2_handle h) {
+  FE2_GUARD(h);
+  h->surr_net = nullptr;
+  return FE2_OK;
+}
+
+int fe2_surrogate_judge(fe2_handle h, double tol, double* max_err_host, int* n_rejected_host, void* stream) {
+  FE2_GUARD(h);
+  if (!h->surr_net) return set_error("no surrogate attached"), FE2_ESTATE;
+  if (!(tol > 0.0)) return set_error("tol must be positive"), FE2_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SkipReset reset{h};
+  int rc = surrogate_eval_impl(h, s);
+  if (rc) return rc;
+  // full RVE responses at every point; the accepted points start from w = 0
+  hipLaunchKernelGGL(k_zero_w_masked, dim3(h->n_rve), dim3(256), 0, s, h->foff, h->accept, h->w);
+  FE2_HIP_CHECK(hipGetLastError());
+  h->skip = nullptr;
+  h->fixed_grad = true;
+  const int rc_eq = equilibrate_impl(h, s);
+  if (rc_eq && rc_eq != FE2_ENOCONV) return rc_eq;
+  h->skip = h->eq_skip;
+  if ((rc = solve_impl(h, h->nF, s))) return rc;
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->count, static_cast<size_t>(1), 0);
+  hipLaunchKernelGGL(k_surr_compare, dim3(nblk(h->n_rve, 256)), dim3(256), 0, s, h->n_rve, h->accept, h->surrP,
+                     h->surrC, h->Pbar, h->Cbar, tol, h->surr_err, h->banned, h->count);
+  hipLaunchKernelGGL(k_col_stats, dim3(1), dim3(256), 0, s, h->n_rve, 1, h->surr_err,
+                     static_cast<const double*>(nullptr), h->norms_dev);
+  FE2_HIP_CHECK(hipGetLastError());
+  double st[4];
+  FE2_HIP_CHECK(hipMemcpyAsync(st, h->norms_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->count, sizeof(int), hipMemcpyDeviceToHost, s));
+  FE2_HIP_CHECK(hipStreamSynchronize(s));
+  if (max_err_host) *max_err_host = st[1];
+  if (n_rejected_host) *n_rejected_host = h->flag_host[0];
+  return rc_eq;
+}
+
 int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream) {
   FE2_GUARD(h);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -781,6 +978,8 @@ int fe2_get_data(fe2_handle h, int which, double* dst, void* stream) {
     case FE2_D_RVE_ITERS: src = h->iters; n = nr; break;
     case FE2_D_RVE_RELRES: src = h->relres; n = nr; break;
     case FE2_D_RVE_MV64: src = h->mv64; n = nr; break;
+    case FE2_D_PHASE_FRACTION: src = h->phi; n = nr; break;
+    case FE2_D_SURR_ERR: src = h->surr_err; n = nr; break;
     case FE2_D_MACRO_RHS: src = h->rhs; n = h->ndof; break;
     case FE2_D_MACRO_RTRUE: src = h->r_true; n = h->ndof; break;
     case FE2_D_MACRO_DU: src = h->du; n = h->ndof; break;

@@ -100,6 +100,7 @@ struct Lin2DArgs {
   double* mv64;                 // [n_rve] FP64 operator applications
   int* fail_count;              // RVEs that missed tol
   const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
+  const int* skip;              // [n_rve] or null: RVEs with skip[b] != 0 are left untouched
   const float* fft_tab;         // spectral preconditioner table (RVE_FFT)
   double volume;
   double tol, tol_in;
@@ -129,12 +130,17 @@ struct Fin2DArgs {
   double* mv64;                 // [n_rve] FP64 operator applications
   int* fail_count;              // RVEs that missed tol (or lost J > 0)
   const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
+  const int* skip;              // [n_rve] or null: RVEs with skip[b] != 0 are left untouched
   double h1, h2;                // element edge lengths
   double volume;
   double tol, tol_in;
   int max_it, max_ir;
   int flags;
 };
+
+// Surrogate network (mlp.hip): input (which = 0) or output width, batch cap
+int mlp_width(fe2_mlp q, int which);
+int mlp_max_batch(fe2_mlp q);
 
 // Launchers (rve_lin2d.hip, rve_fin2d.hip)
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,

@@ -541,8 +541,10 @@ __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__
 // a9: dF_b = B_b du_e; w_b -= x_r + X_F dF_b (generalized) or X_F dF_b
 // (classical predictor).  One work-group per RVE.
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
-                           const double* __restrict__ X, double* __restrict__ w, int use_xr) {
+                           const double* __restrict__ X, double* __restrict__ w, int use_xr,
+                           const int* __restrict__ skip) {
   const int b = blockIdx.x;
+  if (skip && skip[b]) return;
   __shared__ double dF[9];
   const int e = b / m.n_gp;
   const int nd = m.nen * m.dim;
@@ -576,10 +578,11 @@ __global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, double
 }
 
 __global__ void __launch_bounds__(1024) k_count_above(int n_rve, const double* __restrict__ rnorm2,
-                                                      const double* __restrict__ thr2, int* __restrict__ count) {
+                                                      const double* __restrict__ thr2, const int* __restrict__ skip,
+                                                      int* __restrict__ count) {
   __shared__ int part[16];
   int c = 0;
-  for (int b = threadIdx.x; b < n_rve; b += blockDim.x) c += !(rnorm2[b] <= thr2[b]);
+  for (int b = threadIdx.x; b < n_rve; b += blockDim.x) c += !(skip && skip[b]) && !(rnorm2[b] <= thr2[b]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
@@ -592,12 +595,30 @@ __global__ void __launch_bounds__(1024) k_count_above(int n_rve, const double* _
 }
 
 __global__ void k_sub_xr(int nF, const int64_t* __restrict__ foff, const double* __restrict__ X,
-                         double* __restrict__ w) {
+                         const int* __restrict__ skip, double* __restrict__ w) {
   const int b = blockIdx.x;
+  if (skip && skip[b]) return;
   const int64_t fo = foff[b];
   const int64_t flen = foff[b + 1] - fo;
   const double* xr = X + fo * (nF + 1) + nF * flen;
   for (int64_t t = threadIdx.x; t < flen; t += blockDim.x) w[fo + t] -= xr[t];
+}
+
+// RVEs whose last inner solve missed tol are excluded from further rounds
+// (dead[b] = 1); count = number of RVEs excluded by this call.
+__global__ void k_mark_dead(int n_rve, const double* __restrict__ relres, double tol, int* __restrict__ dead,
+                            int* __restrict__ count) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_rve || dead[b]) return;
+  if (!(relres[b] <= tol)) {
+    dead[b] = 1;
+    atomicAdd(count, 1);
+  }
+}
+
+__global__ void k_copy_mask(int n, const int* __restrict__ src, int* __restrict__ dst) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) dst[b] = src ? src[b] : 0;
 }
 
 // Norms of the convergence test: out = [||[R_free; R_micro]||, ||R_free||,

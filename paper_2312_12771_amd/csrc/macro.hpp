@@ -43,13 +43,18 @@ __global__ void k_band_cholesky(int n, int bw, double* __restrict__ band,
 size_t band_cholesky_lds(int bw);
 __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y);
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
-                           const double* __restrict__ X, double* __restrict__ w, int use_xr);
+                           const double* __restrict__ X, double* __restrict__ w, int use_xr,
+                           const int* __restrict__ skip);
 __global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, double tol,
                             double* __restrict__ thr2);
 __global__ void k_count_above(int n_rve, const double* __restrict__ rnorm2,
-                              const double* __restrict__ thr2, int* __restrict__ count);
+                              const double* __restrict__ thr2, const int* __restrict__ skip,
+                              int* __restrict__ count);
 __global__ void k_sub_xr(int nF, const int64_t* __restrict__ foff, const double* __restrict__ X,
-                         double* __restrict__ w);
+                         const int* __restrict__ skip, double* __restrict__ w);
+__global__ void k_mark_dead(int n_rve, const double* __restrict__ relres, double tol, int* __restrict__ dead,
+                            int* __restrict__ count);
+__global__ void k_copy_mask(int n, const int* __restrict__ src, int* __restrict__ dst);
 __global__ void k_norms(MacroArgs m, const double* __restrict__ r_true,
                         const double* __restrict__ f_int, const double* __restrict__ rnorm2,
                         double volume, double* __restrict__ out);

@@ -251,6 +251,11 @@ int check_batch(fe2_mlp_ctx* q, int batch) {
 
 }  // namespace
 
+namespace fe2 {
+int mlp_width(fe2_mlp q, int which) { return which == 0 ? q->sizes.front() : q->sizes.back(); }
+int mlp_max_batch(fe2_mlp q) { return q->max_batch; }
+}  // namespace fe2
+
 extern "C" {
 
 int fe2_mlp_create(int n_layers, const int* sizes, int max_batch, void* stream, fe2_mlp* out) {

@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
   constexpr int NPT = (NN + WG - 1) / WG;   // owned nodes per thread
   const int tid = threadIdx.x;
   const int b = a.rve_list[blockIdx.x];
+  if (a.skip && a.skip[b]) return;   // handled elsewhere (whole work-group)
 
   extern __shared__ __align__(16) unsigned char smem[];
   double* s_red = reinterpret_cast<double*>(smem);
@@ -353,6 +354,11 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
           Xb[NF * flen + 2 * (tid + k * WG)] = 0.0;
           Xb[NF * flen + 2 * (tid + k * WG) + 1] = 0.0;
         }
+      if (tid == 0) {
+        a.relres[b] = 0.0;
+        a.iters[b] = 0.0;
+        a.mv64[b] = 0.0;
+      }
       return;
     }
     if (tid == 0 && !(a.flags & RVE_RONLY)) {   // condensation accumulates into these

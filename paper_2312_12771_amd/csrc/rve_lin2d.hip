@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   static_assert(NB1 * NB2 <= WG, "work-group too small for the RVE");
   const int tid = threadIdx.x;
   const int b = a.rve_list[blockIdx.x];
+  if (a.skip && a.skip[b]) return;   // handled elsewhere (whole work-group)
 
   extern __shared__ __align__(16) unsigned char smem[];
   double* s_red = reinterpret_cast<double*>(smem);
@@ -259,6 +260,11 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         xc[2 * node_of(k)] = 0.0;
         xc[2 * node_of(k) + 1] = 0.0;
       }
+    if (tid == 0) {
+      a.relres[b] = 0.0;
+      a.iters[b] = 0.0;
+      a.mv64[b] = 0.0;
+    }
     return;
   }
 

@@ -32,7 +32,8 @@ FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT = 0, 1, 2
 FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
 (FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
  FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
- FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64) = range(13)
+ FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64, FE2_D_PHASE_FRACTION,
+ FE2_D_SURR_ERR) = range(15)
 (FE2_Q_NF, FE2_Q_FIELD_LEN, FE2_Q_NDOF, FE2_Q_BANDWIDTH, FE2_Q_FAILED_RVES,
  FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS, FE2_Q_MICRO_ITERS) = range(8)
 
@@ -86,6 +87,13 @@ _sig = {
     "fe2_mlp_loss_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _dp, _vp]),
     "fe2_mlp_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     "fe2_mlp_reset_optimizer": (C.c_int, [_vp, _vp]),
+    "fe2_rve_response": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "fe2_surrogate_dataset": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fe2_surrogate_stats": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
+    "fe2_surrogate_normalize": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp, C.c_int, _vp, _vp]),
+    "fe2_surrogate_attach": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "fe2_surrogate_detach": (C.c_int, [_vp]),
+    "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
     "fe2_strerror": (C.c_char_p, [C.c_int]),
     "fe2_last_error": (C.c_char_p, []),
     "fe2_abi_version": (C.c_int, []),
@@ -229,6 +237,52 @@ def fe2_equilibrate_rve(h: Handle, stream=None, allow_noconv=False):
     st = _lib.fe2_equilibrate_rve(h.ptr, C.byref(its), _stream_ptr(stream))
     _check(st, "fe2_equilibrate_rve", (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,))
     return st, int(its.value)
+
+
+def fe2_rve_response(h: Handle, F, P=None, Cm=None, ok=None, stream=None, allow_noconv=False):
+    """Equilibrated RVE response at the macro gradients F [n_rve*nF]."""
+    st = _lib.fe2_rve_response(h.ptr, _dev_ptr(F), _dev_ptr(P), _dev_ptr(Cm), _dev_ptr(ok), _stream_ptr(stream))
+    return _check(st, "fe2_rve_response", (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,))
+
+
+def fe2_surrogate_dataset(h: Handle, F, P, Cm, X, T, stream=None):
+    return _check(_lib.fe2_surrogate_dataset(h.ptr, _dev_ptr(F), _dev_ptr(P), _dev_ptr(Cm), _dev_ptr(X),
+                                             _dev_ptr(T), _stream_ptr(stream)), "fe2_surrogate_dataset")
+
+
+def fe2_surrogate_stats(V, m: int, ok=None, out=None, stream=None):
+    """Column statistics of V [n*m] -> out [4*m] (min, max, mean, std)."""
+    import torch
+    n = V.numel() // m
+    if out is None:
+        out = torch.zeros(4 * m, dtype=torch.float64, device=V.device)
+    _check(_lib.fe2_surrogate_stats(int(n), int(m), _dev_ptr(V), _dev_ptr(ok), _dev_ptr(out), _stream_ptr(stream)),
+           "fe2_surrogate_stats")
+    return out
+
+
+def fe2_surrogate_normalize(V, m: int, a, b, mode: int, out, stream=None):
+    n = V.numel() // m
+    return _check(_lib.fe2_surrogate_normalize(int(n), int(m), _dev_ptr(V), _dev_ptr(a), _dev_ptr(b), int(mode),
+                                               _dev_ptr32(out), _stream_ptr(stream)), "fe2_surrogate_normalize")
+
+
+def fe2_surrogate_attach(h: Handle, net, norm, stream=None):
+    return _check(_lib.fe2_surrogate_attach(h.ptr, net.ptr, _dev_ptr(norm), _stream_ptr(stream)),
+                  "fe2_surrogate_attach")
+
+
+def fe2_surrogate_detach(h: Handle):
+    return _check(_lib.fe2_surrogate_detach(h.ptr), "fe2_surrogate_detach")
+
+
+def fe2_surrogate_judge(h: Handle, tol: float, stream=None):
+    """Returns (status, max error, rejected points)."""
+    err = C.c_double(0.0)
+    nrej = C.c_int(0)
+    st = _lib.fe2_surrogate_judge(h.ptr, float(tol), C.byref(err), C.byref(nrej), _stream_ptr(stream))
+    _check(st, "fe2_surrogate_judge", (FE2_OK, FE2_ENOCONV))
+    return st, float(err.value), int(nrej.value)
 
 
 def fe2_get_state(h: Handle, u=None, w=None, stream=None):

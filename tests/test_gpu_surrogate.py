@@ -1,0 +1,115 @@
+"""The RVE-response surrogate on the GPU, through the C ABI.
+
+* The material-point driver (fe2_rve_response) reproduces the oracle's
+  nested response: equilibrated RVE (Sec. 4.1) and its condensed stress and
+  tangent.
+* The training pairs encode exactly that response: (S, D) mapped back through
+  P = F S and A = delta S + F F C reproduce (P, A); the features are the
+  Green-Lagrange strain and the phase-1 fraction.
+* Trained on GPU-generated RVE solves, the network drives the Neo-Hookean
+  configuration's load stepping with the RVE solve as fallback and judge:
+  same macro displacement as the full monolithic solve within the judge's
+  tolerance, at a fraction of the time (the gain the network brings).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import rve as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def libs():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2312_12771_amd import fe2, surrogate
+    return fe2, surrogate
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def test_material_point_response_matches_oracle(libs):
+    fe2, S = libs
+    p = W.cfg5_material_points(8, rve=8)
+    E, U = W.surrogate_samples(8, seed=3)
+    X, T, ok, P, A = S.rve_responses(p, U, precision="fp64", rve_tol=1e-12, micro_tol=1e-13)
+    X, T, ok = X.cpu().numpy().reshape(8, 4), T.cpu().numpy().reshape(8, 9), ok.cpu().numpy()
+    P, A = P.cpu().numpy().reshape(8, 4), A.cpu().numpy().reshape(8, 4, 4)
+    assert np.all(ok == 1.0)
+    for b in range(8):
+        w, _ = R.equilibrate_rve(p, b, U[b], tol=1e-13)
+        c = R.homogenize_rve(p, b, U[b], w)
+        assert rel(P[b], c.P_bar) < 1e-9
+        assert rel(A[b], c.C) < 1e-9
+        # features
+        ph = p.phase_id[p.rve_off[b]:p.rve_off[b + 1]]
+        assert rel(X[b, :3], E[b]) < 1e-12
+        assert abs(X[b, 3] - ph.mean()) < 1e-15
+        # targets map back to (P, A): P = F S, A_iJkL = d_ik S_LJ + F_iM F_kN C_MJNL
+        F = U[b].reshape(2, 2)
+        Sm = np.array([[T[b, 0], T[b, 2]], [T[b, 2], T[b, 1]]])
+        D = np.array([[T[b, 3], T[b, 6], T[b, 7]], [T[b, 6], T[b, 4], T[b, 8]], [T[b, 7], T[b, 8], T[b, 5]]])
+        v = [[0, 2], [2, 1]]
+        Ct = np.array([[[[D[v[M][J], v[N][L]] for L in range(2)] for N in range(2)] for J in range(2)]
+                       for M in range(2)])
+        A2 = np.einsum("ik,LJ->iJkL", np.eye(2), Sm) + np.einsum("iM,kN,MJNL->iJkL", F, F, Ct)
+        assert rel((F @ Sm).ravel(), P[b]) < 1e-10
+        assert rel(A2.reshape(4, 4), A[b]) < 1e-10
+
+
+def test_surrogate_training_and_gain_over_the_full_solve(libs):
+    fe2, S = libs
+    # training set: 4096 equilibrated 32x32 RVE responses generated on the GPU
+    pt = W.cfg5_material_points(4096, rve=32)
+    _, U = W.surrogate_samples(4096, seed=101)
+    t0 = time.perf_counter()
+    X, T, ok, _, _ = S.rve_responses(pt, U)
+    t_data = time.perf_counter() - t0
+    assert ok.sum().item() >= 4000
+    sur = S.Surrogate.train(X, T, ok, steps=3000)
+    # held-out set
+    pv = W.cfg5_material_points(512, rve=32, seed=W.generators.SEED_BASE + 51)
+    _, Uv = W.surrogate_samples(512, seed=202)
+    Xv, Tv, okv, _, _ = S.rve_responses(pv, Uv)
+    rms = sur.validation_rms(Xv, Tv, okv)
+    print(f"data {t_data:.2f}s, training {sur.train_log['seconds']:.2f}s "
+          f"loss {sur.train_log['final_loss']:.2e}, held-out rms {rms:.2e}")
+    assert rms < 2e-2
+
+    # the Neo-Hookean configuration on an 8x8 macro mesh (256 RVEs of 32x32)
+    p = W.config("cfg5", macro=(8, 8))
+    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fe2.solve(hf, p.load_factors)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    uf = torch.zeros(p.n_dofs, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_state(hf, u=uf)
+    hf.close()
+
+    # an FP32 network resolves the stress to about 1e-7 relative: the
+    # surrogate path converges the macro residual to 1e-6
+    hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6, scheme="classical")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = S.solve_with_surrogate(hs, sur, p.load_factors, judge_tol=2e-2, judge="last")
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    us = torch.zeros(p.n_dofs, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_state(hs, u=us)
+    hs.close()
+    err_u = rel(us.cpu().numpy(), uf.cpu().numpy())
+    print(f"full {t_full:.3f}s, surrogate {t_sur:.3f}s (x{t_full / t_sur:.1f}), |du|/|u| {err_u:.2e}, "
+          f"judge max err {stats['max_err']}, rejected {stats['rejected']}, newton {stats['newton']}")
+    assert stats["judge_calls"] >= 1
+    assert err_u < 1e-2
+    assert t_sur < 0.5 * t_full
+    sur.close()

@@ -20,4 +20,7 @@ from .generators import (  # noqa: F401
     phases_cross,
     subset_problem,
     mlp_init,
+    cfg5_material_points,
+    surrogate_samples,
+    SURROGATE_BOX,
 )

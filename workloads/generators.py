@@ -402,6 +402,49 @@ def cook(n_macro=20, n_rve=30, n_steps=22, traction=(-5.0, 10.0)):
                                        traction=traction))
 
 
+# Strain box of the surrogate's training set: Green-Lagrange strains met along
+# the Neo-Hookean configuration's uniaxial path to 10 % stretch (E11 up to
+# 0.105, lateral contraction, small shear) with a margin, and the phase-1
+# volume fractions of its inclusions (radius 0.15 to 0.35).
+SURROGATE_BOX = dict(E11=(-0.005, 0.115), E22=(-0.05, 0.005), E12=(-0.02, 0.02))
+
+
+def cfg5_material_points(n: int, rve: int = 32, mu=(1.0, 20.0), seed: int = SEED_BASE + 50) -> Problem:
+    """n RVEs of the Neo-Hookean configuration's kind (circle of radius
+    U[0.15, 0.35] drawn per RVE, shear moduli 1 / 20, lambda = 2 mu), hung on
+    a dummy strip of n/4 macro elements (numbered along the strip, so the
+    macro band stays narrow): the batch of a material-point
+    driver (training data of the surrogate)."""
+    if n % 4:
+        raise ValueError("n must be a multiple of 4")
+    rng = np.random.default_rng(seed)
+    X, conn = macro_q4_grid(1, n // 4, 1.0, float(n // 4))
+    radius = rng.uniform(0.15, 0.35, size=n)
+    off, ph = _pack_phases([phases_circle(rve, rve, r) for r in radius])
+    params = np.zeros((n, 2, 2))
+    params[:, 0] = (2.0 * mu[0], mu[0])
+    params[:, 1] = (2.0 * mu[1], mu[1])
+    res = np.full((n, 2), rve, dtype=np.int32)
+    return _problem("cfg5_points", 2, "finite", "neohooke", X, conn, np.zeros(0, dtype=np.int32), np.zeros(0),
+                    res, off, ph, params, seed, meta=dict(radius=radius))
+
+
+def surrogate_samples(n: int, seed: int, box=None):
+    """n Green-Lagrange strains uniform in ``box`` and the matching
+    symmetric right stretch tensors U = sqrt(I + 2E) (row-major 2x2), the
+    macro gradients at which training RVE responses are computed."""
+    box = SURROGATE_BOX if box is None else box
+    rng = np.random.default_rng(seed)
+    E = np.stack([rng.uniform(*box["E11"], n), rng.uniform(*box["E22"], n), rng.uniform(*box["E12"], n)], axis=1)
+    Cm = np.zeros((n, 2, 2))
+    Cm[:, 0, 0] = 1 + 2 * E[:, 0]
+    Cm[:, 1, 1] = 1 + 2 * E[:, 1]
+    Cm[:, 0, 1] = Cm[:, 1, 0] = 2 * E[:, 2]
+    lam, V = np.linalg.eigh(Cm)
+    U = np.einsum("nij,nj,nkj->nik", V, np.sqrt(lam), V)
+    return E, U.reshape(n, 4)
+
+
 def mlp_init(sizes: Sequence[int], seed: int = SEED_BASE) -> np.ndarray:
     """Initial parameters of a multilayer perceptron in the flat layout
     W_0, b_0, W_1, b_1, ... (W_l of shape (sizes[l+1], sizes[l]), row-major):
