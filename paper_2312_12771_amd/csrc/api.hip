@@ -177,7 +177,7 @@ struct fe2_ctx {
     a.params = params;
     a.kv64 = c.d_tab;
     a.KwF64 = c.d_tab + 10;
-    a.KFF64 = c.d_tab + 34;
+    a.KFF64 = c.d_tab + (dim == 3 ? 154 : 34);
     a.macro = mgrad;
     a.foff = foff;
     a.w = w;
@@ -341,7 +341,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
 
   // supported combinations
   const bool finite = h->kin == FE2_FINITE_STRAIN;
-  if (h->dim != 2) return set_error("this build supports 2D RVEs"), FE2_ENOTSUP;
+  if (h->dim == 3 && finite) return set_error("3D RVEs are supported for small strain only"), FE2_ENOTSUP;
   if (!finite && (h->mat != FE2_LINEAR_ISO || h->n_pp != 2))
     return set_error("small strain takes FE2_LINEAR_ISO with (lambda, mu) per phase"), FE2_EINVAL;
   if (finite && !((h->mat == FE2_NEO_HOOKE && h->n_pp == 2) || (h->mat == FE2_MOONEY_RIVLIN && h->n_pp == 3)))
@@ -385,7 +385,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   // strain (the finite-strain kernel evaluates the law per Gauss point)
   std::map<std::tuple<int, int, double>, int> key2cls;
   for (int b = 0; b < h->n_rve; ++b) {
-    const int n1 = d->rve_res[b * 2], n2 = d->rve_res[b * 2 + 1];
+    const int n1 = d->rve_res[b * h->dim], n2 = d->rve_res[b * h->dim + 1];
+    const int n3 = h->dim == 3 ? d->rve_res[b * 3 + 2] : 1;
     double rho0 = 0.0;
     if (!finite) {
       const double* p = kpar.data() + static_cast<size_t>(b) * 4;
@@ -394,9 +395,11 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       if (std::fabs(rho0 - rho1) > 1e-12 * std::fabs(rho0))
         return set_error("both phases of an RVE must share lambda/mu"), FE2_ENOTSUP;
     }
-    if (!(finite ? fin2d_supported(n1, n2) : lin2d_supported(n1, n2)))
-      return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" +
-                       std::to_string(n2)),
+    const bool ok = h->dim == 3 ? lin3d_supported(n1, n2, n3)
+                                : (finite ? fin2d_supported(n1, n2) : lin2d_supported(n1, n2));
+    if (!ok)
+      return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" + std::to_string(n2) +
+                       (h->dim == 3 ? "x" + std::to_string(n3) : std::string())),
              FE2_ENOTSUP;
     auto key = std::make_tuple(n1, n2, rho0);
     auto it = key2cls.find(key);
@@ -503,11 +506,20 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   for (auto& c : h->classes) {
     if ((rc = upload(&c.d_list, c.rves.data(), c.rves.size(), s))) return rc;
     if (finite) continue;
+    double err = 0.0;
+    if (h->dim == 3) {
+      if ((rc = dalloc(&c.d_tab, REF3_TABLE))) return rc;
+      hipLaunchKernelGGL(k_ref_tables_3d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, c.rho, c.d_tab);
+      FE2_HIP_CHECK(hipGetLastError());
+      FE2_HIP_CHECK(hipMemcpyAsync(&err, c.d_tab + REF3_TABLE - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      FE2_HIP_CHECK(hipStreamSynchronize(s));
+      if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
+      continue;
+    }
     if ((rc = dalloc(&c.d_tab, 44))) return rc;
     hipLaunchKernelGGL(k_ref_tables_2d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, h->rve_size / c.n2, c.rho,
                        c.d_tab);
     FE2_HIP_CHECK(hipGetLastError());
-    double err = 0.0;
     FE2_HIP_CHECK(hipMemcpyAsync(&err, c.d_tab + 43, sizeof(double), hipMemcpyDeviceToHost, s));
     FE2_HIP_CHECK(hipStreamSynchronize(s));
     if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
@@ -515,6 +527,13 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   FE2_HIP_CHECK(hipStreamSynchronize(s));
   h->lam = 0.0;
   return FE2_OK;
+}
+
+// one RVE class through the kernel of its kind
+int launch_class(fe2_ctx* h, const RveClass& c, int flags, int n, int nrhs, hipStream_t s) {
+  if (h->kin == FE2_FINITE_STRAIN) return launch_fin2d(h->fargs(c, flags), n, h->precision, nrhs, s);
+  if (h->dim == 3) return launch_lin3d(h->largs(c, flags), n, h->precision, nrhs, s);
+  return launch_lin2d(h->largs(c, flags), n, h->precision, nrhs, s);
 }
 
 int assemble_impl(fe2_ctx* h, hipStream_t s) {
@@ -525,8 +544,7 @@ int assemble_impl(fe2_ctx* h, hipStream_t s) {
   }
   for (auto& c : h->classes) {
     const int n = static_cast<int>(c.rves.size());
-    int rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, RVE_ASSEMBLE), n, h->precision, h->nF, s)
-                                         : launch_lin2d(h->largs(c, RVE_ASSEMBLE), n, h->precision, h->nF, s);
+    int rc = launch_class(h, c, RVE_ASSEMBLE, n, h->nF, s);
     if (rc) return rc;
   }
   return FE2_OK;
@@ -538,8 +556,7 @@ int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
   h->have_solution = true;
   for (auto& c : h->classes) {
     const int n = static_cast<int>(c.rves.size());
-    int rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, flags), n, h->precision, nrhs, s)
-                                         : launch_lin2d(h->largs(c, flags), n, h->precision, nrhs, s);
+    int rc = launch_class(h, c, flags, n, nrhs, s);
     if (rc) return rc;
   }
   return FE2_OK;
@@ -587,8 +604,7 @@ int equilibrate_impl(fe2_ctx* h, hipStream_t s) {
     for (auto& c : h->classes) {
       const int n = static_cast<int>(c.rves.size());
       const int fl = RVE_SOLVE | RVE_RONLY;
-      rc = h->kin == FE2_FINITE_STRAIN ? launch_fin2d(h->fargs(c, fl), n, h->precision, h->nF + 1, s)
-                                       : launch_lin2d(h->largs(c, fl), n, h->precision, h->nF + 1, s);
+      rc = launch_class(h, c, fl, n, h->nF + 1, s);
       if (rc) break;
     }
     if (rc) break;

@@ -149,6 +149,11 @@ size_t lin2d_lds_bytes(int n1, int n2, int nrhs);
 bool lin2d_supported(int n1, int n2);
 int launch_fin2d(const Fin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
+// 3D small strain (rve_lin3d.hip): cubes n x n x n, reuses Lin2DArgs with
+// n1 = n, KwF64 = [24][6], KFF64 = [6][6]
+int launch_lin3d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
+                 hipStream_t s);
+bool lin3d_supported(int n1, int n2, int n3);
 bool fin2d_supported(int n1, int n2);
 
 }  // namespace fe2

@@ -12,6 +12,7 @@
 //   * fluctuation update dw_b = -(x_r + X_F dF_b) (Eq. (49)) and the residual
 //     norms of the convergence test.
 #include "macro.hpp"
+#include "elem3d.hpp"
 
 namespace fe2 {
 
@@ -72,6 +73,80 @@ __global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) out[34 + 3 * i + j] = KFF[i][j];
   out[43] = err / scale;
+}
+
+// Reference tables of the hex8 box element (cube of side h, lambda = rho,
+// mu = 1) by 2x2x2 Gauss quadrature, Voigt order [11,22,33,23,13,12] with
+// engineering shear: out = kv[10] | KwF[24][6] | KFF[6][6] | consistency
+// error of K against the ten-value structure of kref3_id / kref3_sign.
+__global__ void k_ref_tables_3d(double h, double rho, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double g = 0.57735026918962576451;
+  double C[6][6] = {};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[i][j] = rho + (i == j ? 2.0 : 0.0);
+  C[3][3] = C[4][4] = C[5][5] = 1.0;
+  double K[24][24] = {};
+  double KwF[24][6] = {};
+  double KFF[6][6] = {};
+  const double wt = 0.125 * h * h * h;
+  for (int gp = 0; gp < 8; ++gp) {
+    const double xi[3] = {(gp & 1) ? g : -g, (gp & 2) ? g : -g, (gp & 4) ? g : -g};
+    double B[6][24] = {};
+    for (int a = 0; a < 8; ++a) {
+      double dN[3];
+      for (int f = 0; f < 3; ++f) {
+        double v = 0.125 * hsg(a, f) * (2.0 / h);
+        for (int k = 0; k < 3; ++k)
+          if (k != f) v *= 1.0 + hsg(a, k) * xi[k];
+        dN[f] = v;
+      }
+      B[0][3 * a] = dN[0];
+      B[1][3 * a + 1] = dN[1];
+      B[2][3 * a + 2] = dN[2];
+      B[3][3 * a + 1] = dN[2];
+      B[3][3 * a + 2] = dN[1];
+      B[4][3 * a] = dN[2];
+      B[4][3 * a + 2] = dN[0];
+      B[5][3 * a] = dN[1];
+      B[5][3 * a + 1] = dN[0];
+    }
+    for (int r = 0; r < 24; ++r) {
+      double CB[6];
+      for (int i = 0; i < 6; ++i) {
+        CB[i] = 0.0;
+        for (int k = 0; k < 6; ++k) CB[i] += C[i][k] * B[k][r];
+      }
+      for (int c = 0; c < 24; ++c) {
+        double v = 0.0;
+        for (int i = 0; i < 6; ++i) v += CB[i] * B[i][c];
+        K[r][c] += wt * v;
+      }
+      for (int j = 0; j < 6; ++j) KwF[r][j] += wt * CB[j];
+    }
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) KFF[i][j] += wt * C[i][j];
+  }
+  double kv[10] = {};
+  bool seen[10] = {};
+  double err = 0.0, scale = 0.0;
+  for (int r = 0; r < 24; ++r)
+    for (int c = 0; c < 24; ++c) {
+      const int id = kref3_id(r, c);
+      const double v = kref3_sign(r, c) * K[r][c];
+      if (!seen[id]) {
+        kv[id] = v;
+        seen[id] = true;
+      }
+      err = fmax(err, fabs(v - kv[id]));
+      scale = fmax(scale, fabs(K[r][c]));
+    }
+  for (int t = 0; t < 10; ++t) out[t] = kv[t];
+  for (int r = 0; r < 24; ++r)
+    for (int j = 0; j < 6; ++j) out[10 + 6 * r + j] = KwF[r][j];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) out[154 + 6 * i + j] = KFF[i][j];
+  out[190] = err / scale;
 }
 
 // ---------------------------------------------------------------------------

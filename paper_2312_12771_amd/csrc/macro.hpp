@@ -25,6 +25,8 @@ struct MacroArgs {
 };
 
 __global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out);
+__global__ void k_ref_tables_3d(double h, double rho, double* out);
+constexpr int REF3_TABLE = 191;   // kv[10] | KwF[24*6] | KFF[36] | error
 __global__ void k_macro_geometry(MacroArgs m);
 __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* __restrict__ out);
 __global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f);
