@@ -41,6 +41,23 @@ FLOP_PCG_ITER_DOF = 77.0
 FLOP_MV64_DOF = 66.0
 
 
+def measured_traffic():
+    """HBM bytes per launch of the RVE solve kernel from the committed
+    counter summary (FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy),
+    valid only while the kernel source is the one that was profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_lin2d_cfg2_hbm_traffic.md")
+    srcp = os.path.join(ROOT, "paper_2312_12771_amd", "csrc", "rve_lin2d.hip")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and " " not in l.split(": ")[0])
+        sha = hashlib.sha256(open(srcp, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -131,6 +148,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
@@ -146,6 +165,15 @@ def main():
     t = time.perf_counter()
     p = W.config("cfg2")
     log(f"workload built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read, 1 GiB written")
+        del src, dst
 
     forms = {}
     if "fp64" in args.forms:
@@ -166,7 +194,7 @@ def main():
                   + np.sum(head["mv64"] * head["n_dof_rve"]) * FLOP_MV64_DOF)
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_TFLOPS[head_dtype],
-                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4), traffic=None,
+                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4), traffic=measured_traffic(),
                 kernel="k_lin2d (RVE solve + condensation)", kernel_ms=round(k_ms, 4),
                 flop_per_launch=flops, pcg_iters_per_rve=float(np.mean(head["iters"])))
 

@@ -544,7 +544,7 @@ int assemble_impl(fe2_ctx* h, hipStream_t s) {
   }
   for (auto& c : h->classes) {
     const int n = static_cast<int>(c.rves.size());
-    int rc = launch_class(h, c, RVE_ASSEMBLE, n, h->nF, s);
+    int rc = launch_class(h, c, RVE_ASSEMBLE, n, 0, s);
     if (rc) return rc;
   }
   return FE2_OK;

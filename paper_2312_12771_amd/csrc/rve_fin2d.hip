@@ -378,6 +378,9 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
     }
   }
 
+  if constexpr (NRHS == 0) {   // assemble-only instantiation
+    return;
+  } else {
   // ---- Jacobi diagonal ------------------------------------------------------
   TI dinv[NPT][2];
   {
@@ -670,6 +673,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) Pb[i] *= rV;
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -694,6 +698,7 @@ static int launch_t(const Fin2DArgs& a, int n_launch, hipStream_t s) {
 
 template <int N1, int N2>
 static int launch_n(const Fin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
+  if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
   if (precision == FE2_PREC_FP64)
     return nrhs == NF ? launch_t<double, NF, N1, N2>(a, n_launch, s) : launch_t<double, NF + 1, N1, N2>(a, n_launch, s);
   return nrhs == NF ? launch_t<float, NF, N1, N2>(a, n_launch, s) : launch_t<float, NF + 1, N1, N2>(a, n_launch, s);
@@ -711,7 +716,8 @@ bool fin2d_supported(int n1, int n2) {
 
 int launch_fin2d(const Fin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (n_launch <= 0) return FE2_OK;
-  if (nrhs != NF && nrhs != NF + 1) return set_error("finite-strain solve takes 4 or 5 right-hand sides"), FE2_EINVAL;
+  if (nrhs != 0 && nrhs != NF && nrhs != NF + 1)
+    return set_error("finite-strain kernel takes 0 (assemble), 4 or 5 right-hand sides"), FE2_EINVAL;
 #define FE2_CASE(A, B) \
   if (a.n1 == A && a.n2 == B) return launch_n<A, B>(a, n_launch, precision, nrhs, s);
   FE2_FIN2D_SIZES(FE2_CASE)

@@ -250,6 +250,9 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
   }
+  if constexpr (NRHS == 0) {   // assemble-only instantiation
+    return;
+  } else {
   if (!(a.flags & RVE_SOLVE)) return;
   const bool ronly = (a.flags & RVE_RONLY) != 0;
   if (ronly && a.rnorm2[b] <= a.thr2[b]) {   // already in equilibrium: x_r = 0
@@ -494,6 +497,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       a.Phat[static_cast<size_t>(b) * NF + i] = ph_i / V;
     }
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -523,6 +527,7 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 
 template <int N1, int N2>
 static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
+  if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
   if (precision == FE2_PREC_FP64)
     return nrhs == 3 ? launch_t<double, 3, N1, N2>(a, n_launch, s) : launch_t<double, 4, N1, N2>(a, n_launch, s);
   return nrhs == 3 ? launch_t<float, 3, N1, N2>(a, n_launch, s) : launch_t<float, 4, N1, N2>(a, n_launch, s);

@@ -324,6 +324,9 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
 #pragma unroll
     for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
   }
+  if constexpr (NRHS == 0) {   // assemble-only instantiation
+    return;
+  } else {
   if (!(a.flags & RVE_SOLVE)) return;
   const bool ronly = (a.flags & RVE_RONLY) != 0;
   if (ronly && a.rnorm2[b] <= a.thr2[b]) {   // already in equilibrium: x_r = 0
@@ -557,6 +560,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
       for (int i = 0; i < NF; ++i) Pb[i] = Pint[i] / V;
     }
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -580,6 +584,7 @@ static int launch3_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 
 template <int N>
 static int launch3_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
+  if (nrhs == 0) return launch3_t<double, 0, N>(a, n_launch, s);   // assemble only (FP64)
   if (precision == FE2_PREC_FP64)
     return nrhs == NF ? launch3_t<double, NF, N>(a, n_launch, s) : launch3_t<double, NF + 1, N>(a, n_launch, s);
   return nrhs == NF ? launch3_t<float, NF, N>(a, n_launch, s) : launch3_t<float, NF + 1, N>(a, n_launch, s);
@@ -598,7 +603,8 @@ bool lin3d_supported(int n1, int n2, int n3) {
 
 int launch_lin3d(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (n_launch <= 0) return FE2_OK;
-  if (nrhs != NF && nrhs != NF + 1) return set_error("3D solve takes 6 or 7 right-hand sides"), FE2_EINVAL;
+  if (nrhs != 0 && nrhs != NF && nrhs != NF + 1)
+    return set_error("3D kernel takes 0 (assemble), 6 or 7 right-hand sides"), FE2_EINVAL;
 #define FE2_CASE(A) \
   if (a.n1 == A) return launch3_n<A>(a, n_launch, precision, nrhs, s);
   FE2_LIN3D_SIZES(FE2_CASE)
