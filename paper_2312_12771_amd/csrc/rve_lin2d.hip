@@ -89,14 +89,46 @@ __device__ __forceinline__ void mv_block(const V* __restrict__ pb, const V* __re
   }
 }
 
+// y = K v (FP64) at one owned node (di, dj) of the block, element by
+// element; used by the FP64 passes (residuals, assembly, condensation),
+// which run a few times per column.  The empty asm after each element
+// consumes its contribution and keeps the next element's loads behind it,
+// so only one element's corner values are live (the FP64 window of the
+// whole block would otherwise set the kernel's register budget).
+template <int N1, int N2>
+__device__ __forceinline__ void mv_node64(const double* __restrict__ pb, const double* __restrict__ eb,
+                                          const double (&kv)[10], int di, int dj, double (&y)[2]) {
+  using P = Pad<N1, N2>;
+  y[0] = y[1] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ea = elem_ea(di, q), ec = elem_ec(dj, q), cc = elem_cc(q);
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int o = (ec + cyo(m)) * P::PW + ea + cxo(m);
+      const double vx = pb[o], vy = pb[P::PN + o];
+      t0 = kfma(kv, 2 * cc, 2 * m, vx, t0);
+      t0 = kfma(kv, 2 * cc, 2 * m + 1, vy, t0);
+      t1 = kfma(kv, 2 * cc + 1, 2 * m, vx, t1);
+      t1 = kfma(kv, 2 * cc + 1, 2 * m + 1, vy, t1);
+    }
+    const double sc = eb[ec * P::PW + ea];
+    y[0] = fma(sc, t0, y[0]);
+    y[1] = fma(sc, t1, y[1]);
+    asm volatile("" : "+v"(y[0]), "+v"(y[1]) : : "memory");
+  }
+}
+
 template <int N1, int N2>
 __device__ __forceinline__ double elem_scale(const double* __restrict__ eb, int di, int dj, int q) {
   return eb[elem_ec(dj, q) * Pad<N1, N2>::PW + elem_ea(di, q)];
 }
 
-// Column j of K_wF at owned node (di, dj), component d.
+// Column j of K_wF at owned node (di, dj), component d; KwF is the uniform
+// [8][NF] element table in global memory (read through scalar loads).
 template <int N1, int N2>
-__device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const double (&KwF)[8 * NF],
+__device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const double* __restrict__ KwF,
                                            int di, int dj, int d, int j) {
   double s = 0.0;
 #pragma unroll
@@ -109,7 +141,7 @@ __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const 
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
 // one search direction [2][PN] in TI aliased with the FP64 staging [2][PN].
 __host__ __device__ constexpr size_t lin2d_red_doubles(int nw, int nrhs) {
-  return 2 * static_cast<size_t>(nw) * (2 * NF * nrhs > 5 ? 2 * NF * nrhs : 5);
+  return 2 * static_cast<size_t>(nw) * (2 * NF > 5 ? 2 * NF : 5) + 0 * nrhs;
 }
 __host__ __device__ constexpr size_t lin2d_vec_offset(int n1, int n2, int wg, int nrhs) {
   return ((lin2d_red_doubles(wg / 64, nrhs) * 8 + static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 12) + 15) &
@@ -147,9 +179,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     kv64[t] = a.kv64[t];
     kvI[t] = static_cast<TI>(kv64[t]);
   }
-  double KwF[8 * NF];
-#pragma unroll
-  for (int t = 0; t < 8 * NF; ++t) KwF[t] = a.KwF64[t];
+  const double* KwF = a.KwF64;   // [8][NF], uniform
 
   // ---- ownership of a 2x2 node block -------------------------------------
   const bool own = tid < NB1 * NB2;
@@ -208,7 +238,8 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     stage(a.w + fo);
     __syncthreads();
     double y[4][2];
-    mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
     double red[5] = {0.0, 0.0, 0.0, 0.0, ssum};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -314,7 +345,8 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         __syncthreads();   // earlier readers of the staging buffer are done
         stage(xc);
         __syncthreads();
-        mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+        #pragma unroll
+    for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
         ++nmv64;
       }
       TI ri[4][2];
@@ -438,10 +470,9 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   }
 
   // ---- a6: condensation (energy form) from a final FP64 pass -------------
-  //   G1[i][j] = b_i . x_j,  G2[i][j] = x_i . (b_j - K x_j)
-  double G[2 * NF * NRHS];
-#pragma unroll
-  for (int i = 0; i < 2 * NF * NRHS; ++i) G[i] = 0.0;
+  //   G1[i][j] = b_i . x_j,  G2[i][j] = x_i . (b_j - K x_j), one column j
+  //   at a time; thread 0 writes Cbar column j (or Phat for j = NF)
+  double* Cb = a.Cbar + static_cast<size_t>(b) * NF * NF;
 #pragma unroll 1
   for (int jc = 0; jc < NRHS; ++jc) {
     const double* xc = Xb + jc * flen;
@@ -449,9 +480,10 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     stage(xc);
     __syncthreads();
     double y[4][2];
-    mv_block<N1, N2, double>(s_st + base, eb, kv64, y);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
     ++nmv64;
-    double g1[NF] = {0.0, 0.0, 0.0}, g2[NF] = {0.0, 0.0, 0.0};
+    double g[2 * NF] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (!dof[k]) continue;
@@ -464,37 +496,30 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         const double res = bj - y[k][d];
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
-          g1[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj;
-          const double xi_ = (i == jc) ? xj : Xb[i * flen + 2 * node_of(k) + d];
-          g2[i] += xi_ * res;
+          g[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj;
+          g[NF + i] += Xb[i * flen + 2 * node_of(k) + d] * res;
         }
       }
     }
+    wg_sum<2 * NF, NW>(g, s_red, parity);
+    if (tid == 0) {
+      if (jc < NF) {
 #pragma unroll
-    for (int jj = 0; jj < NRHS; ++jj)
-      if (jj == jc) {
+        for (int i = 0; i < NF; ++i) Cb[i * NF + jc] = (ssum * a.KFF64[i * NF + jc] - g[i] - g[NF + i]) / V;
+      } else {
 #pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          G[i * NRHS + jj] = g1[i];
-          G[NF * NRHS + i * NRHS + jj] = g2[i];
-        }
+        for (int i = 0; i < NF; ++i) a.Phat[static_cast<size_t>(b) * NF + i] = (Pint[i] - g[i] - g[NF + i]) / V;
       }
+    }
   }
-  wg_sum<2 * NF * NRHS, NW>(G, s_red, parity);
   if (tid == 0) {
     a.relres[b] = worst;
     a.iters[b] = static_cast<double>(iters);
     a.mv64[b] = static_cast<double>(nmv64);
     if (!all_ok) atomicAdd(a.fail_count, 1);
+    if constexpr (NRHS == NF) {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
-#pragma unroll
-      for (int j = 0; j < NF; ++j)
-        a.Cbar[static_cast<size_t>(b) * NF * NF + i * NF + j] =
-            (ssum * a.KFF64[i * NF + j] - G[i * NRHS + j] - G[NF * NRHS + i * NRHS + j]) / V;
-      double ph_i = Pint[i];
-      if constexpr (NRHS > NF) ph_i -= G[i * NRHS + NF] + G[NF * NRHS + i * NRHS + NF];
-      a.Phat[static_cast<size_t>(b) * NF + i] = ph_i / V;
+      for (int i = 0; i < NF; ++i) a.Phat[static_cast<size_t>(b) * NF + i] = Pint[i] / V;
     }
   }
   }
