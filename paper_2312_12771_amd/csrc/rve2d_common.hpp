@@ -62,5 +62,49 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double* s_red, int& pari
   }
 }
 
+// Wave sum with DPP cross-lane moves (no LDS traffic): quad butterflies,
+// half-row and row mirrors give every lane its 16-lane row sum; the two row
+// broadcasts accumulate the rows upwards, so lane 63 holds the wave total.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                                               false));
+}
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += dpp_f<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);        // row_half_mirror
+  v += dpp_f<0x140>(v);        // row_mirror
+  v += dpp_f<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Work-group sum of FP32 per-lane partials: wave totals in FP32 (DPP), the
+// cross-wave sum in FP64 through LDS (one barrier, alternating buffers as
+// wg_sum).  Every thread receives the totals.
+template <int NV, int NW>
+__device__ __forceinline__ void wg_sum_f(const float (&v)[NV], double (&out)[NV], double* s_red, int& parity) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  double* buf = s_red + parity * (NW * NV);
+  parity ^= 1;
+  float w[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) w[i] = wave_sum_to_last(v[i]);
+  if (lane == 63) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = static_cast<double>(w[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += buf[k * NV + i];
+    out[i] = t;
+  }
+}
+
 }  // namespace rve2d
 }  // namespace fe2

@@ -379,66 +379,69 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         break;
       }
       // ---- inner PCG on K d = r (precision TI, Jacobi preconditioner) -----
+      // Chronopoulos-Gear form of CG: u = M^-1 r and w = K u are formed
+      // every iteration and the three inner products (r.u, w.u, r.r) go
+      // through one fused work-group reduction; p and s = K p follow by
+      // recurrence.  Two barriers per iteration (u visible, reduction).
       __syncthreads();   // staging reads finished before s_p is written
-      TI xi[4][2];
-      double rz, r0;
-      {
-        double red2[2] = {0.0, 0.0};
+      TI xi[4][2], uv[4][2], pv[4][2], sv[4][2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int d = 0; d < 2; ++d) {
-            xi[k][d] = TI(0);
-            const TI z = dinv[k][d] * ri[k][d];
-            if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), z);
-            red2[0] += static_cast<double>(ri[k][d]) * static_cast<double>(z);
-            red2[1] += static_cast<double>(ri[k][d]) * static_cast<double>(ri[k][d]);
-          }
-        wg_sum<2, NW>(red2, s_red, parity);
-        rz = red2[0];
-        r0 = red2[1];
-      }
+        for (int d = 0; d < 2; ++d) {
+          xi[k][d] = pv[k][d] = sv[k][d] = TI(0);
+          uv[k][d] = dinv[k][d] * ri[k][d];
+          if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
+        }
+      double r0 = 0.0, gam_old = 1.0, alpha_old = 1.0;
 #pragma unroll 1
       for (int it = 0; it < a.max_it; ++it) {
-        __syncthreads();   // search direction visible
+        __syncthreads();   // u visible
+        TI wv[4][2];
+        mv_block<N1, N2, TI>(s_p + base, ebI, kvI, wv);
+        TI pg = TI(0), pd = TI(0), pr = TI(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            if (!dof[k]) wv[k][d] = TI(0);
+            pg = fma(ri[k][d], uv[k][d], pg);
+            pd = fma(wv[k][d], uv[k][d], pd);
+            pr = fma(ri[k][d], ri[k][d], pr);
+          }
+        double red3[3];
+        if constexpr (sizeof(TI) == 4) {
+          const float v3[3] = {pg, pd, pr};
+          wg_sum_f<3, NW>(v3, red3, s_red, parity);
+        } else {
+          red3[0] = pg;
+          red3[1] = pd;
+          red3[2] = pr;
+          wg_sum<3, NW>(red3, s_red, parity);
+        }
+        const double gam = red3[0], del = red3[1], rr = red3[2];
+        if (it == 0) r0 = rr;
+        if (rr <= tin2 * r0 || !(gam > 0.0)) break;
+        const double beta = (it == 0) ? 0.0 : gam / gam_old;
+        const double den = (it == 0) ? del : del - beta * gam / alpha_old;
+        if (!(den > 0.0)) break;   // breakdown (exact solution or loss of definiteness)
+        const double alpha = gam / den;
         ++iters;
-        TI q[4][2];
-        mv_block<N1, N2, TI>(s_p + base, ebI, kvI, q);
-        TI pown[4][2];
-        double pq[1] = {0.0};
+        const TI aI = static_cast<TI>(alpha), bI = static_cast<TI>(beta);
+        // every read of s_p in this iteration precedes the reduction's barrier
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            pown[k][d] = s_p[d * P::PN + pidx[k]];
-            if (!dof[k]) q[k][d] = TI(0);
-            pq[0] += static_cast<double>(pown[k][d]) * static_cast<double>(q[k][d]);
+            pv[k][d] = fma(bI, pv[k][d], uv[k][d]);
+            sv[k][d] = fma(bI, sv[k][d], wv[k][d]);
+            xi[k][d] = fma(aI, pv[k][d], xi[k][d]);
+            ri[k][d] = fma(-aI, sv[k][d], ri[k][d]);
+            uv[k][d] = dinv[k][d] * ri[k][d];
+            if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
           }
-        wg_sum<1, NW>(pq, s_red, parity);
-        if (!(pq[0] > 0.0)) break;   // breakdown (exact solution or loss of definiteness)
-        const TI alpha = static_cast<TI>(rz / pq[0]);
-        double red2[2] = {0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int d = 0; d < 2; ++d) {
-            xi[k][d] = fma(alpha, pown[k][d], xi[k][d]);
-            ri[k][d] = fma(-alpha, q[k][d], ri[k][d]);
-            const double rv = static_cast<double>(ri[k][d]);
-            red2[0] += rv * static_cast<double>(dinv[k][d] * ri[k][d]);
-            red2[1] += rv * rv;
-          }
-        wg_sum<2, NW>(red2, s_red, parity);
-        if (red2[1] <= tin2 * r0 || !(red2[0] > 0.0)) break;
-        const TI beta = static_cast<TI>(red2[0] / rz);
-        rz = red2[0];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int d = 0; d < 2; ++d)
-            if (exists[k])
-              put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1),
-                               fma(beta, pown[k][d], dinv[k][d] * ri[k][d]));
+        gam_old = gam;
+        alpha_old = alpha;
       }
       // x64 += x_inner (FP64 accumulation in the output column)
 #pragma unroll
