@@ -162,7 +162,8 @@ int fe2_condense(fe2_handle h, double* Cbar_dev, double* Phat_dev, void* stream)
  * already equals load_factor and the norm satisfies newton_tol the call
  * returns FE2_CONVERGED without an update; otherwise RVE solves and
  * condensation, FP64 macro assembly with the prescribed increment
- * (load_factor - current) * dir_vals, FP64 banded Cholesky solve, update of
+ * (load_factor - current) * dir_vals, FP64 direct solve of the banded
+ * tangent (block cyclic reduction, see fe2_band_solve), update of
  * q and w~ (generalized: dw_b = -(x_r + X_F dF_b); classical predictor:
  * dw_b = -X_F dF_b).
  * norms_host (may be NULL) receives 4 doubles describing the state the call
@@ -240,6 +241,19 @@ int fe2_get_profile(fe2_handle h, double* out);
 
 /* Release all device memory of the handle (waits for its work). */
 int fe2_destroy(fe2_handle h);
+
+/* FP64 direct solve of a symmetric positive definite banded system, the
+ * macro linear solve of every Newton update (Eq. (47) for the generalized
+ * scheme, Eq. (45) for the classical one).  band_dev: lower band storage,
+ * A(i, j) for 0 <= i - j <= bw at band_dev[j * (bw + 1) + (i - j)], n * (bw + 1)
+ * doubles, read only (entries with i >= n are ignored).  rhs_dev [n]: the
+ * right-hand side on entry, the solution on return.  The matrix is cut into
+ * blocks of the bandwidth (rounded up to 16) and solved by block cyclic
+ * reduction.  Allocates and frees its own workspace (about 4 bs^2 doubles per
+ * block) and waits for `stream`.  pivot_host (may be NULL) receives 0, or a
+ * 1-based index of a non-positive pivot, in which case FE2_ENOCONV is
+ * returned and rhs_dev is undefined.  FE2_ENOTSUP when bw exceeds 1184. */
+int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream);
 
 /* ------------------------------------------------------------------------
  * Surrogate network (not part of the paper): a multilayer perceptron that

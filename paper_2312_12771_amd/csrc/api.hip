@@ -84,6 +84,8 @@ struct fe2_ctx {
   int* info = nullptr;
   double *f_true = nullptr, *f_hat = nullptr, *ke = nullptr, *band = nullptr, *rhs = nullptr;
   double *du = nullptr, *r_true = nullptr, *f_int = nullptr, *norms_dev = nullptr, *kdense = nullptr;
+  BcrPlan bcr;                 // block cyclic reduction of the banded macro tangent
+  double* bcr_ws = nullptr;
   double* norms_host = nullptr;   // pinned [4]
   // phase timing (HIP events on the caller's stream)
   bool prof = false;
@@ -214,7 +216,8 @@ void free_ctx(fe2_ctx* h) {
                   h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
                   h->norms_dev, h->kdense, h->mv64, h->thr2, h->count, h->eq_skip, h->surr_norm, h->phi,
-                  h->surrP, h->surrC, h->surr_err, h->surr_X, h->surr_Y, h->accept, h->banned, h->okf};
+                  h->surrP, h->surrC, h->surr_err, h->surr_X, h->surr_Y, h->accept, h->banned, h->okf,
+                  h->bcr_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& c : h->classes) {
@@ -484,8 +487,11 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if (hipHostMalloc(reinterpret_cast<void**>(&h->norms_host), 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), 3 * sizeof(int)) != hipSuccess)
     return set_error("pinned host allocation failed"), FE2_ENOMEM;
-  if (band_cholesky_lds(h->bw) > 160 * 1024 - 64)
-    return set_error("macro half bandwidth " + std::to_string(h->bw) + " exceeds the LDS panel"), FE2_ENOTSUP;
+  if (h->bw > bcr_max_bandwidth())
+    return set_error("macro half bandwidth " + std::to_string(h->bw) + " exceeds the block solver's limit"),
+           FE2_ENOTSUP;
+  h->bcr = bcr_plan(h->ndof, h->bw);
+  if ((rc = dalloc(&h->bcr_ws, bcr_workspace_doubles(h->bcr)))) return rc;
 
   // zero state
   hipLaunchKernelGGL(k_fill, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->u, static_cast<size_t>(h->ndof), 0.0);
@@ -678,13 +684,7 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->info, static_cast<size_t>(1), 0);
   FE2_HIP_CHECK(hipGetLastError());
   FE2_HIP_CHECK(hipMemcpyAsync(h->du, h->rhs, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, s));
-  const size_t lds = band_cholesky_lds(h->bw);
-  if (lds > 64 * 1024)
-    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_cholesky),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(k_band_cholesky, dim3(1), dim3(512), lds, s, h->ndof, h->bw, h->band, h->du, h->info);
-  FE2_HIP_CHECK(hipGetLastError());
-  return FE2_OK;
+  return bcr_solve(h->bcr, h->bcr_ws, h->band, h->du, h->info, s);
 }
 
 int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
@@ -876,6 +876,36 @@ int fe2_surrogate_dataset(fe2_handle h, const double* F_dev, const double* P_dev
   hipLaunchKernelGGL(k_surr_targets, dim3(nblk(h->n_rve, 128)), dim3(128), 0, static_cast<hipStream_t>(stream),
                      h->n_rve, F_dev, P_dev, C_dev, h->phi, X_dev, T_dev);
   FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream) {
+  if (pivot_host) *pivot_host = 0;
+  if (n < 1 || bw < 0 || !band_dev || !rhs_dev)
+    return set_error("invalid band solve arguments"), FE2_EINVAL;
+  if (bw > bcr_max_bandwidth())
+    return set_error("half bandwidth " + std::to_string(bw) + " exceeds the block solver's limit"), FE2_ENOTSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const BcrPlan plan = bcr_plan(n, bw);
+  double* ws = nullptr;
+  int* info = nullptr;
+  int rc = dalloc(&ws, bcr_workspace_doubles(plan));
+  if (rc) return rc;
+  if (hipMalloc(reinterpret_cast<void**>(&info), sizeof(int)) != hipSuccess) {
+    (void)hipFree(ws);
+    return set_error("device allocation failed"), FE2_ENOMEM;
+  }
+  int piv = 0;
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, info, static_cast<size_t>(1), 0);
+  rc = bcr_solve(plan, ws, band_dev, rhs_dev, info, s);
+  if (!rc && (hipMemcpyAsync(&piv, info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess))
+    rc = (set_error("band solve failed on the device"), FE2_EHIP);
+  (void)hipFree(ws);
+  (void)hipFree(info);
+  if (rc) return rc;
+  if (pivot_host) *pivot_host = piv;
+  if (piv) return set_error("matrix not positive definite at pivot " + std::to_string(piv)), FE2_ENOCONV;
   return FE2_OK;
 }
 

@@ -1,0 +1,526 @@
+// FP64 direct solve of the banded SPD macro system (row a8) by block cyclic
+// reduction.
+//
+// A symmetric matrix of half bandwidth bw is block tridiagonal once it is cut
+// into blocks of bs >= bw rows: block i couples only to i-1 and i+1.  Block
+// cyclic reduction eliminates the odd blocks of the active set in parallel,
+// leaving a block tridiagonal Schur complement on the even blocks, and
+// recurses; log2(nb) levels instead of the n sequential column steps of a
+// banded Cholesky factorisation.  For an SPD matrix every Schur complement is
+// SPD (the scheme is Cholesky factorisation in a nested-dissection order of
+// the blocks), so no pivoting is needed and a non-positive pivot means the
+// matrix is not SPD.
+//
+// Per level (stride h; active blocks are the multiples of h; odd ones j =
+// h, 3h, ... are eliminated, with left neighbour j-h and right neighbour j+h):
+//   potrf : D_j = L_j L_j^T (in place), inverses of its 16x16 diagonal tiles;
+//   trsm  : [G_l | G_r | g] = L_j^-1 [A_{j,j-h} | A_{j+h,j}^T | f_j];
+//   schur : for even i:  D_i -= G_r(i-h)^T G_r(i-h) + G_l(i+h)^T G_l(i+h),
+//           f_i -= G_r(i-h)^T g(i-h) + G_l(i+h)^T g(i+h),
+//           A_{i,i-2h} = -G_r(i-h)^T G_l(i-h).
+// Block 0 is left; back substitution runs the levels in reverse:
+//   x_j = L_j^-T (g_j - G_l x_{j-h} - G_r x_{j+h}).
+//
+// Storage (device, FP64): D and C [nb][bs][bs] column-major (C_i couples
+// block i to its left active neighbour), G [nb][bs][2 bs] column-major
+// ([G_l | G_r]), invL [nb][bs/16][16][16] column-major tiles, F [nb*bs] the
+// padded right-hand side, overwritten by g and then by the solution.  Rows
+// beyond n are padded with the identity.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fe2_internal.hpp"
+#include "macro.hpp"
+
+namespace fe2 {
+
+namespace {
+
+constexpr int BT = 16;   // tile size
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// -- extraction of the blocks from lower band storage ------------------------
+__global__ void k_bcr_extract(const double* __restrict__ band, int n, int bw, int bs, int nb,
+                              double* __restrict__ D, double* __restrict__ C) {
+  const size_t per = static_cast<size_t>(bs) * bs;
+  const size_t total = per * nb;
+  for (size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int b = static_cast<int>(t / per);
+    const int rem = static_cast<int>(t - b * per);
+    const int c = rem / bs, r = rem - c * bs;
+    const int i = b * bs + r, j = b * bs + c;
+    double dv;
+    if (i < n && j < n) {
+      const int lo = i > j ? i : j, hi = i > j ? j : i;
+      dv = (lo - hi <= bw) ? band[static_cast<size_t>(hi) * (bw + 1) + (lo - hi)] : 0.0;
+    } else {
+      dv = (r == c) ? 1.0 : 0.0;
+    }
+    D[t] = dv;
+    double cv = 0.0;
+    if (b > 0 && i < n) {
+      const int jj = (b - 1) * bs + c;   // i - jj = bs + r - c >= 1
+      if (i - jj <= bw) cv = band[static_cast<size_t>(jj) * (bw + 1) + (i - jj)];
+    }
+    C[t] = cv;
+  }
+}
+
+__global__ void k_bcr_copy_in(const double* __restrict__ y, int n, int np, double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) F[i] = i < n ? y[i] : 0.0;
+}
+
+__global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = F[i];
+}
+
+// -- potrf: one work-group per eliminated block -------------------------------
+// Right-looking Cholesky in 16-column panels, in place in global memory (the
+// block stays in the work-group's L2).  Wave 0 factors the diagonal tile and
+// inverts it (lane r holds row r; wave-synchronous exchange through LDS), all
+// threads form the panel below with the inverse and apply the trailing
+// update in 4x4 register tiles.
+constexpr int PO_WG = 256;
+
+__global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, double* __restrict__ invL, int bs,
+                                                     int first, int stride, int* __restrict__ info) {
+  extern __shared__ __align__(16) double s_panel[];   // [bs][BT]
+  __shared__ double s_ex[BT * (BT + 1)];
+  __shared__ double s_inv[BT * BT];                    // column-major
+  __shared__ int s_fail;
+  const int j = first + stride * static_cast<int>(blockIdx.x);
+  const int nt = bs / BT;
+  double* Dj = D + static_cast<size_t>(j) * bs * bs;
+  double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  for (int p = 0; p < nt; ++p) {
+    const int k0 = p * BT;
+    if (tid < 64) {
+      const int r = tid;
+      double a[BT];
+#pragma unroll
+      for (int c = 0; c < BT; ++c)
+        a[c] = (r < BT && c <= r) ? Dj[static_cast<size_t>(k0 + c) * bs + k0 + r] : 0.0;
+      bool bad = false;
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
+        if (r < BT) s_ex[r] = a[c];
+        wave_sync();
+        const double d = s_ex[c];
+        double col[BT];
+#pragma unroll
+        for (int cc = c + 1; cc < BT; ++cc) col[cc] = s_ex[cc];
+        wave_sync();
+        if (!(d > 0.0)) {
+          bad = true;
+          if (r == 0) {
+            s_fail = 1;
+            atomicCAS(info, 0, j * bs + k0 + c + 1);
+          }
+          break;
+        }
+        const double sd = sqrt(d);
+        const double inv_sd = 1.0 / sd;
+        const double lrc = a[c] * inv_sd;
+        a[c] = (r == c) ? sd : (r > c ? lrc : a[c]);
+#pragma unroll
+        for (int cc = c + 1; cc < BT; ++cc) {
+          const double upd = fma(-lrc, col[cc] * inv_sd, a[cc]);
+          a[cc] = (r >= cc) ? upd : a[cc];
+        }
+      }
+      if (!bad) {
+        // L of the diagonal tile to global memory and to LDS (row r)
+        if (r < BT) {
+#pragma unroll
+          for (int c = 0; c < BT; ++c) {
+            if (c <= r) Dj[static_cast<size_t>(k0 + c) * bs + k0 + r] = a[c];
+            s_ex[r * (BT + 1) + c] = (c <= r) ? a[c] : 0.0;
+          }
+        }
+        wave_sync();
+        // lane c < 16 solves L x = e_c: column c of the inverse
+        if (r < BT) {
+          double x[BT];
+#pragma unroll
+          for (int i = 0; i < BT; ++i) {
+            double acc = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc = fma(-s_ex[i * (BT + 1) + k], x[k], acc);
+            x[i] = (i >= r) ? acc / s_ex[i * (BT + 1) + i] : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < BT; ++i) {
+            s_inv[r * BT + i] = x[i];
+            Ij[p * BT * BT + r * BT + i] = x[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (s_fail) return;
+    // panel below: L_ip = A_ip invL_pp^T, row by row
+    const int rows = bs - k0 - BT;
+    for (int t = tid; t < rows; t += PO_WG) {
+      const int ri = k0 + BT + t;
+      double a[BT];
+#pragma unroll
+      for (int k = 0; k < BT; ++k) a[k] = Dj[static_cast<size_t>(k0 + k) * bs + ri];
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
+        double l = 0.0;
+#pragma unroll
+        for (int k = 0; k <= c; ++k) l = fma(a[k], s_inv[k * BT + c], l);
+        Dj[static_cast<size_t>(k0 + c) * bs + ri] = l;
+        s_panel[t * BT + c] = l;
+      }
+    }
+    __syncthreads();
+    // trailing update of the lower tiles (ti, tk), p < tk <= ti < nt
+    const int m = nt - p - 1;
+    const int items = 16 * (m * (m + 1) / 2);
+    for (int w = tid; w < items; w += PO_WG) {
+      const int q = w >> 4, mt = w & 15;
+      int ta = static_cast<int>((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+      while (ta * (ta + 1) / 2 > q) --ta;
+      while ((ta + 1) * (ta + 2) / 2 <= q) ++ta;
+      const int tb = q - ta * (ta + 1) / 2;
+      const int lr = ta * BT + (mt >> 2) * 4;   // rows of s_panel
+      const int lc = tb * BT + (mt & 3) * 4;
+      double acc[4][4] = {};
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
+        double pi[4], pj[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          pi[x] = s_panel[(lr + x) * BT + c];
+          pj[x] = s_panel[(lc + x) * BT + c];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = fma(pi[x], pj[y], acc[x][y]);
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          double* e = Dj + static_cast<size_t>(k0 + BT + lc + y) * bs + (k0 + BT + lr + x);
+          *e -= acc[x][y];
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// -- trsm: one work-group per (16-column tile, eliminated block) --------------
+// Forward substitution L_j X = R on one tile of R = [C_j | C_{j+h}^T | f_j],
+// 16 rows at a time: S = R_i - sum_{k<i} L_ik X_k, X_i = invL_ii S.
+constexpr int TR_WG = 256;
+
+__global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D, const double* __restrict__ invL,
+                                                    const double* __restrict__ C, double* __restrict__ G,
+                                                    double* __restrict__ F, int bs, int nb, int first, int stride,
+                                                    int h, int rhs_only) {
+  extern __shared__ __align__(16) double s_x[];   // [bs][BT]
+  __shared__ double s_s[BT * BT];
+  const int j = first + stride * static_cast<int>(blockIdx.y);
+  const int nt = bs / BT;
+  const int ct = rhs_only ? 2 * nt : static_cast<int>(blockIdx.x);
+  const size_t per = static_cast<size_t>(bs) * bs;
+  const double* src;
+  double* out;
+  int ld_r, ld_c, ncol;   // R(r, c) = src[r * ld_r + c * ld_c]; out(r, c) = out[c * bs + r]
+  if (ct < nt) {
+    src = C + j * per + static_cast<size_t>(ct) * BT * bs;
+    ld_r = 1;
+    ld_c = bs;
+    out = G + j * 2 * per + static_cast<size_t>(ct) * BT * bs;
+    ncol = BT;
+  } else if (ct < 2 * nt) {
+    if (j + h >= nb) return;
+    src = C + (j + h) * per + (ct - nt) * BT;
+    ld_r = bs;
+    ld_c = 1;
+    out = G + j * 2 * per + static_cast<size_t>(bs + (ct - nt) * BT) * bs;
+    ncol = BT;
+  } else {
+    src = F + static_cast<size_t>(j) * bs;
+    ld_r = 1;
+    ld_c = 0;
+    out = F + static_cast<size_t>(j) * bs;
+    ncol = 1;
+  }
+  const double* Lj = D + j * per;
+  const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
+  const int tid = threadIdx.x;
+  const int r = tid & (BT - 1), c = tid >> 4;
+  for (int i = 0; i < nt; ++i) {
+    const int row = i * BT + r;
+    double s = 0.0;
+    if (c < ncol) {
+      s = src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c];
+      double s2 = 0.0;
+      int k = 0;
+      for (; k + 1 < i * BT; k += 2) {
+        s = fma(-Lj[static_cast<size_t>(k) * bs + row], s_x[k * BT + c], s);
+        s2 = fma(-Lj[static_cast<size_t>(k + 1) * bs + row], s_x[(k + 1) * BT + c], s2);
+      }
+      for (; k < i * BT; ++k) s = fma(-Lj[static_cast<size_t>(k) * bs + row], s_x[k * BT + c], s);
+      s += s2;
+    }
+    s_s[r * BT + c] = s;
+    __syncthreads();
+    double x = 0.0;
+    if (c < ncol) {
+      const double* Ii = Ij + i * BT * BT;
+#pragma unroll
+      for (int k = 0; k < BT; ++k)
+        if (k <= r) x = fma(Ii[k * BT + r], s_s[k * BT + c], x);
+    }
+    s_x[row * BT + c] = x;
+    __syncthreads();
+  }
+  if (c < ncol)
+    for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = s_x[row * BT + c];
+}
+
+// -- schur: one work-group per (output tile, even block) ----------------------
+// Output tiles of block i: lower tiles of D_i, all tiles of the new coupling
+// C_i, and the 16-row pieces of f_i.  Each is a sum of at most two products
+// A^T B with K = bs, staged through LDS in 64-row slabs.
+constexpr int SC_WG = 256;
+constexpr int SC_KC = 64;
+
+__global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ G, double* __restrict__ D,
+                                                     double* __restrict__ C, double* __restrict__ F, int bs, int nb,
+                                                     int h) {
+  __shared__ double s_a[SC_KC * (BT + 1)];
+  __shared__ double s_b[SC_KC * (BT + 1)];
+  const int i = 2 * h * static_cast<int>(blockIdx.y);
+  const int nt = bs / BT;
+  const int ntri = nt * (nt + 1) / 2;
+  const int q = blockIdx.x;
+  const size_t per = static_cast<size_t>(bs) * bs;
+  const int jl = i - h, jr = i + h;
+  const bool has_l = i > 0, has_r = jr < nb;
+  int kind, ta, tb;
+  if (q < ntri) {
+    kind = 0;
+    ta = static_cast<int>((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+    while (ta * (ta + 1) / 2 > q) --ta;
+    while ((ta + 1) * (ta + 2) / 2 <= q) ++ta;
+    tb = q - ta * (ta + 1) / 2;
+  } else if (q < ntri + nt * nt) {
+    kind = 1;
+    ta = (q - ntri) / nt;
+    tb = (q - ntri) - ta * nt;
+    if (!has_l || i < 2 * h) return;
+  } else {
+    kind = 2;
+    ta = q - ntri - nt * nt;
+    tb = 0;
+  }
+  // contributions: (A columns, B columns or vector)
+  const double* Ap[2];
+  const double* Bp[2];
+  int ncon = 0;
+  if (has_l) {   // G_r(i-h) on the left
+    const double* Gl = G + static_cast<size_t>(jl) * 2 * per;
+    Ap[ncon] = Gl + per + static_cast<size_t>(ta) * BT * bs;
+    Bp[ncon] = kind == 0 ? Gl + per + static_cast<size_t>(tb) * BT * bs
+             : kind == 1 ? Gl + static_cast<size_t>(tb) * BT * bs
+                         : F + static_cast<size_t>(jl) * bs;
+    ++ncon;
+  }
+  if (has_r && kind != 1) {   // G_l(i+h)
+    const double* Gr = G + static_cast<size_t>(jr) * 2 * per;
+    Ap[ncon] = Gr + static_cast<size_t>(ta) * BT * bs;
+    Bp[ncon] = kind == 0 ? Gr + static_cast<size_t>(tb) * BT * bs : F + static_cast<size_t>(jr) * bs;
+    ++ncon;
+  }
+  if (ncon == 0) return;
+  const int nb_cols = kind == 2 ? 1 : BT;
+  const int tid = threadIdx.x;
+  const int r = tid & (BT - 1), c = tid >> 4;
+  double acc = 0.0;
+  for (int cn = 0; cn < ncon; ++cn) {
+    for (int k0 = 0; k0 < bs; k0 += SC_KC) {
+      const int kc = min(SC_KC, bs - k0);
+      __syncthreads();
+      for (int t = tid; t < BT * SC_KC; t += SC_WG) {
+        const int col = t / SC_KC, k = t - col * SC_KC;
+        if (k < kc) {
+          s_a[k * (BT + 1) + col] = Ap[cn][static_cast<size_t>(col) * bs + k0 + k];
+          if (col < nb_cols) s_b[k * (BT + 1) + col] = Bp[cn][static_cast<size_t>(col) * bs + k0 + k];
+        }
+      }
+      __syncthreads();
+      if (c < nb_cols) {
+        double a2 = 0.0;
+        int k = 0;
+        for (; k + 1 < kc; k += 2) {
+          acc = fma(s_a[k * (BT + 1) + r], s_b[k * (BT + 1) + c], acc);
+          a2 = fma(s_a[(k + 1) * (BT + 1) + r], s_b[(k + 1) * (BT + 1) + c], a2);
+        }
+        if (k < kc) acc = fma(s_a[k * (BT + 1) + r], s_b[k * (BT + 1) + c], acc);
+        acc += a2;
+      }
+    }
+  }
+  if (c >= nb_cols) return;
+  const int row = ta * BT + r;
+  if (kind == 0) {
+    D[i * per + static_cast<size_t>(tb * BT + c) * bs + row] -= acc;
+  } else if (kind == 1) {
+    C[i * per + static_cast<size_t>(tb * BT + c) * bs + row] = -acc;
+  } else {
+    F[static_cast<size_t>(i) * bs + row] -= acc;
+  }
+}
+
+// -- back substitution: one work-group per eliminated block -------------------
+constexpr int BK_WG = 256;
+
+__global__ void __launch_bounds__(BK_WG) k_bcr_back(const double* __restrict__ D, const double* __restrict__ invL,
+                                                    const double* __restrict__ G, double* __restrict__ F, int bs,
+                                                    int nb, int first, int stride, int h, int alone) {
+  extern __shared__ __align__(16) double s_t[];   // [bs] right side, then x
+  __shared__ double s_red[BT * BT];
+  __shared__ double s_nb[2][1024];
+  const int j = first + stride * static_cast<int>(blockIdx.x);
+  const int nt = bs / BT;
+  const size_t per = static_cast<size_t>(bs) * bs;
+  const bool has_l = !alone && j >= h, has_r = !alone && j + h < nb;
+  const double* Gj = G + j * 2 * per;
+  const double* Lj = D + j * per;
+  const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
+  double* Fj = F + static_cast<size_t>(j) * bs;
+  const int tid = threadIdx.x;
+  // neighbour solutions, staged through LDS in chunks of 1024
+  for (int r = tid; r < bs; r += BK_WG) s_t[r] = Fj[r];
+  for (int c0 = 0; c0 < bs; c0 += 1024) {
+    const int cn = min(1024, bs - c0);
+    __syncthreads();
+    for (int t = tid; t < cn; t += BK_WG) {
+      s_nb[0][t] = has_l ? F[static_cast<size_t>(j - h) * bs + c0 + t] : 0.0;
+      s_nb[1][t] = has_r ? F[static_cast<size_t>(j + h) * bs + c0 + t] : 0.0;
+    }
+    __syncthreads();
+    if (has_l || has_r)
+      for (int r = tid; r < bs; r += BK_WG) {
+        double a1 = 0.0, a2 = 0.0;
+        for (int c = 0; c < cn; ++c) {
+          if (has_l) a1 = fma(Gj[static_cast<size_t>(c0 + c) * bs + r], s_nb[0][c], a1);
+          if (has_r) a2 = fma(Gj[per + static_cast<size_t>(c0 + c) * bs + r], s_nb[1][c], a2);
+        }
+        s_t[r] -= a1 + a2;
+      }
+  }
+  __syncthreads();
+  // L^T x = t, 16 rows at a time from the bottom
+  const int r = tid & (BT - 1), sl = tid >> 4;
+  for (int i = nt - 1; i >= 0; --i) {
+    const int col = i * BT + r;   // row of L^T = column of L
+    double part = 0.0;
+    for (int k = (i + 1) * BT + sl; k < bs; k += 16) part = fma(Lj[static_cast<size_t>(col) * bs + k], s_t[k], part);
+    s_red[sl * BT + r] = part;
+    __syncthreads();
+    if (tid < BT) {
+      double u = s_t[col];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) u -= s_red[q * BT + r];
+      s_red[r] = u;   // row 0 of s_red was read above by this thread only
+    }
+    __syncthreads();
+    if (tid < BT) {
+      // x_i = invL_ii^T u: x[r] = sum_{k >= r} invL[k][r] u[k]
+      const double* Ii = Ij + i * BT * BT;
+      double x = 0.0;
+#pragma unroll
+      for (int k = 0; k < BT; ++k)
+        if (k >= r) x = fma(Ii[r * BT + k], s_red[k], x);
+      s_t[col] = x;
+    }
+    __syncthreads();
+  }
+  for (int rr = tid; rr < bs; rr += BK_WG) Fj[rr] = s_t[rr];
+}
+
+}  // namespace
+
+BcrPlan bcr_plan(int n, int bw) {
+  BcrPlan p;
+  p.n = n;
+  p.bw = bw;
+  p.bs = std::max(BT, ((bw + BT - 1) / BT) * BT);
+  p.nb = (n + p.bs - 1) / p.bs;
+  const size_t per = static_cast<size_t>(p.bs) * p.bs;
+  p.d_len = per * p.nb;
+  p.g_len = 2 * per * p.nb;
+  p.inv_len = static_cast<size_t>(p.nb) * p.bs * BT;
+  p.f_len = static_cast<size_t>(p.nb) * p.bs;
+  return p;
+}
+
+int bcr_max_bandwidth() { return 1184; }   // panel buffer + static LDS within 160 KiB
+
+size_t bcr_workspace_doubles(const BcrPlan& p) { return 2 * p.d_len + p.g_len + p.inv_len + p.f_len; }
+
+int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* info, hipStream_t s) {
+  double* D = ws;
+  double* C = D + p.d_len;
+  double* G = C + p.d_len;
+  double* IL = G + p.g_len;
+  double* F = IL + p.inv_len;
+  const int bs = p.bs, nb = p.nb, nt = bs / BT;
+  const unsigned eg = static_cast<unsigned>(std::min<size_t>(8192, (p.d_len + 255) / 256));
+  hipLaunchKernelGGL(k_bcr_extract, dim3(eg), dim3(256), 0, s, band, p.n, p.bw, bs, nb, D, C);
+  const int np = nb * bs;
+  hipLaunchKernelGGL(k_bcr_copy_in, dim3((np + 255) / 256), dim3(256), 0, s, y, p.n, np, F);
+  const size_t lds_po = static_cast<size_t>(bs) * BT * sizeof(double);
+  const size_t lds_bk = static_cast<size_t>(bs) * sizeof(double);
+  if (lds_po + 8 * 1024 > 64 * 1024) {
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bcr_potrf),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_po)));
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bcr_trsm),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_po)));
+  }
+  const int ntri = nt * (nt + 1) / 2;
+  int h = 1;
+  for (;;) {
+    const int nact = (nb - 1) / h + 1;
+    if (nact == 1) break;
+    const int nodd = nact / 2, neven = (nact + 1) / 2;
+    hipLaunchKernelGGL(k_bcr_potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, info);
+    hipLaunchKernelGGL(k_bcr_trsm, dim3(2 * nt + 1, nodd), dim3(TR_WG), lds_po, s, D, IL, C, G, F, bs, nb, h,
+                       2 * h, h, 0);
+    hipLaunchKernelGGL(k_bcr_schur, dim3(ntri + nt * nt + nt, neven), dim3(SC_WG), 0, s, G, D, C, F, bs, nb, h);
+    h *= 2;
+  }
+  const int htop = h;
+  hipLaunchKernelGGL(k_bcr_potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, info);
+  hipLaunchKernelGGL(k_bcr_trsm, dim3(1, 1), dim3(TR_WG), lds_po, s, D, IL, C, G, F, bs, nb, 0, 0, 0, 1);
+  hipLaunchKernelGGL(k_bcr_back, dim3(1), dim3(BK_WG), lds_bk, s, D, IL, G, F, bs, nb, 0, 0, 0, 1);
+  for (h = htop / 2; h >= 1; h /= 2) {
+    const int nact = (nb - 1) / h + 1;
+    const int nodd = nact / 2;
+    hipLaunchKernelGGL(k_bcr_back, dim3(nodd), dim3(BK_WG), lds_bk, s, D, IL, G, F, bs, nb, h, 2 * h, h, 0);
+  }
+  hipLaunchKernelGGL(k_bcr_copy_out, dim3((p.n + 255) / 256), dim3(256), 0, s, F, p.n, y);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+}  // namespace fe2

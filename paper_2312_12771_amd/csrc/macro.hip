@@ -374,238 +374,6 @@ __global__ void k_fill_i(int* p, size_t n, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// banded Cholesky factorisation and solve, one work-group
-// ---------------------------------------------------------------------------
-// Right-looking blocked band Cholesky, panel width NB.  Lower band storage:
-// A(i, j), 0 <= i - j <= bw, at band[j*(bw+1) + (i-j)], overwritten by L.
-// Per panel (columns k0 .. k0+kb-1, rows k0 .. k0+m-1, m <= kb + bw):
-//   1. stage the panel and the right-hand side window in LDS;
-//   2. one wave factors the kb x kb diagonal block and solves its part of
-//      the forward substitution (wave-synchronous, no barriers);
-//   3. one thread per remaining row solves L21 = A21 L11^-T and updates its
-//      right-hand side entry;
-//   4. the trailing triangle A22 -= L21 L21^T in 4x4 register tiles, read
-//      from LDS, read-modify-written in global memory (L2 resident).
-// The backward substitution L^T x = y runs over chunks of 64 columns staged
-// in LDS, one wave per chunk.
-constexpr int BC_NB = 16;
-constexpr int BC_WG = 512;
-
-__device__ __forceinline__ double rl64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
-__global__ void __launch_bounds__(BC_WG) k_band_cholesky(int n, int bw, double* __restrict__ band,
-                                                         double* __restrict__ y, int* __restrict__ info) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double rd[BC_NB];
-  __shared__ double cb_l[64];
-  __shared__ double cb_y[64];
-  __shared__ int s_fail;
-  const int W1 = bw + 1;
-  const int MP = (BC_NB + bw + 1) & ~1;   // even: 16-byte aligned column pairs
-  double* P = reinterpret_cast<double*>(smem);
-  double* yp = P + static_cast<size_t>(BC_NB) * MP;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_fail = 0;
-  for (int k0 = 0; k0 < n; k0 += BC_NB) {
-    const int kb = min(BC_NB, n - k0);
-    const int m = min(n - k0, kb + bw);
-    __syncthreads();
-    for (int t = tid; t < kb * m; t += BC_WG) {
-      const int c = t / m, r = t - c * m;
-      P[c * MP + r] = (r >= c && r - c <= bw) ? band[static_cast<size_t>(k0 + c) * W1 + (r - c)] : 0.0;
-    }
-    for (int r = tid; r < m; r += BC_WG) yp[r] = y[k0 + r];
-    __syncthreads();
-    if (tid < 64) {
-      // lane r < kb holds row r of the diagonal block
-      double a[BC_NB];
-#pragma unroll
-      for (int c = 0; c < BC_NB; ++c) a[c] = (tid < kb && c <= tid) ? P[c * MP + tid] : 0.0;
-      double yr = tid < kb ? yp[tid] : 0.0;
-      double rdr = 0.0;
-#pragma unroll
-      for (int c = 0; c < BC_NB; ++c) {
-        if (c < kb) {
-          cb_l[tid] = a[c];
-          cb_y[tid] = yr;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          const double d = cb_l[c];
-          if (!(d > 0.0)) {   // uniform: every lane read the same pivot
-            if (tid == 0) {
-              s_fail = 1;
-              *info = k0 + c + 1;
-            }
-            break;
-          }
-          double col[BC_NB];
-#pragma unroll
-          for (int cc = c + 1; cc < BC_NB; ++cc) col[cc] = cb_l[cc];
-          const double yc0 = cb_y[c];
-          const double rls = rsqrt(d);
-          const double ls = d * rls;
-          const double yc = yc0 * rls;
-          const double lrc = a[c] * rls;           // L(tid, c) for tid > c
-          const bool below = tid > c, diag = tid == c;
-          a[c] = diag ? ls : (below ? lrc : a[c]);
-          yr = diag ? yc : (below ? fma(-lrc, yc, yr) : yr);
-          rdr = diag ? rls : rdr;
-#pragma unroll
-          for (int cc = c + 1; cc < BC_NB; ++cc) {
-            const double upd = fma(-lrc, col[cc] * rls, a[cc]);
-            a[cc] = (tid >= cc) ? upd : a[cc];
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      if (tid < kb) {
-#pragma unroll
-        for (int c = 0; c < BC_NB; ++c)
-          if (c <= tid) P[c * MP + tid] = a[c];
-        yp[tid] = yr;
-        rd[tid] = rdr;
-      }
-    }
-    __syncthreads();
-    if (s_fail) return;
-    for (int r = kb + tid; r < m; r += BC_WG) {
-      double a[BC_NB];
-#pragma unroll
-      for (int c = 0; c < BC_NB; ++c) a[c] = c < kb ? P[c * MP + r] : 0.0;
-      double yr = yp[r];
-#pragma unroll
-      for (int c = 0; c < BC_NB; ++c) {
-        if (c < kb) {
-          double v = a[c];
-#pragma unroll
-          for (int cc = 0; cc < c; ++cc) v -= a[cc] * P[cc * MP + c];
-          v *= rd[c];
-          a[c] = v;
-          yr -= v * yp[c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < BC_NB; ++c)
-        if (c < kb) P[c * MP + r] = a[c];
-      yp[r] = yr;
-    }
-    __syncthreads();
-    for (int t = tid; t < kb * m; t += BC_WG) {
-      const int c = t / m, r = t - c * m;
-      if (r >= c && r - c <= bw) band[static_cast<size_t>(k0 + c) * W1 + (r - c)] = P[c * MP + r];
-    }
-    for (int r = tid; r < m; r += BC_WG) y[k0 + r] = yp[r];
-    const int T = m - kb;
-    const int nt = (T + 3) >> 2;
-    const int ntri = nt * (nt + 1) / 2;
-    const bool vec = (kb & 1) == 0;   // 16-byte aligned tile rows
-    for (int g = tid; g < ntri; g += BC_WG) {
-      // fold the lower triangle of tiles into an (nt+1)-wide rectangle
-      const int q = g / (nt + 1), rr = g - q * (nt + 1);
-      const int ti = rr <= q ? q : nt - 1 - q;
-      const int tj = rr <= q ? rr : rr - q - 1;
-      const int i0 = kb + 4 * ti, j0 = kb + 4 * tj;
-      double old[4][4];
-#pragma unroll
-      for (int z = 0; z < 4; ++z)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int i = i0 + x, j = j0 + z;
-          old[x][z] = (i < m && j < m && i >= j) ? band[static_cast<size_t>(k0 + j) * W1 + (i - j)] : 0.0;
-        }
-      double acc[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int z = 0; z < 4; ++z) acc[x][z] = 0.0;
-      if (vec) {
-#pragma unroll 4
-        for (int c = 0; c < kb; ++c) {
-          const double2* pc = reinterpret_cast<const double2*>(P + c * MP);
-          const double2 a01 = pc[i0 >> 1], a23 = pc[(i0 >> 1) + 1];
-          const double2 b01 = pc[j0 >> 1], b23 = pc[(j0 >> 1) + 1];
-          const double pi[4] = {a01.x, a01.y, a23.x, a23.y};
-          const double pj[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int z = 0; z < 4; ++z) acc[x][z] = fma(pi[x], pj[z], acc[x][z]);
-        }
-      } else {
-        for (int c = 0; c < kb; ++c) {
-          double pi[4], pj[4];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            pi[x] = P[c * MP + i0 + x];
-            pj[x] = P[c * MP + j0 + x];
-          }
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int z = 0; z < 4; ++z) acc[x][z] = fma(pi[x], pj[z], acc[x][z]);
-        }
-      }
-#pragma unroll
-      for (int z = 0; z < 4; ++z)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int i = i0 + x, j = j0 + z;
-          if (i < m && j < m && i >= j) band[static_cast<size_t>(k0 + j) * W1 + (i - j)] = old[x][z] - acc[x][z];
-        }
-    }
-  }
-  __syncthreads();
-  constexpr int CB = 64;
-  double* Lc = P;
-  double* xw = P + static_cast<size_t>(CB) * W1;
-  double* yb = xw + CB + bw;
-  for (int c0 = ((n - 1) / CB) * CB; c0 >= 0; c0 -= CB) {
-    const int cbn = min(CB, n - c0);
-    for (int t = tid; t < cbn * W1; t += BC_WG) {
-      const int c = t / W1, d = t - c * W1;
-      Lc[t] = (c0 + c + d < n) ? band[static_cast<size_t>(c0 + c) * W1 + d] : 0.0;
-    }
-    for (int t = tid; t < CB + bw; t += BC_WG) xw[t] = (c0 + t < n) ? y[c0 + t] : 0.0;
-    __syncthreads();
-    {
-      const int c = tid >> 3, sub = tid & 7;
-      double sacc = 0.0;
-      if (c < cbn)
-        for (int d = (cbn - c) + sub; d <= bw; d += 8) sacc += Lc[c * W1 + d] * xw[c + d];
-      sacc += __shfl_xor(sacc, 1, 64);
-      sacc += __shfl_xor(sacc, 2, 64);
-      sacc += __shfl_xor(sacc, 4, 64);
-      if (sub == 0 && c < cbn) yb[c] = xw[c] - sacc;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      const int l = tid;
-      double yl = l < cbn ? yb[l] : 0.0;
-      const double rdl = l < cbn ? 1.0 / Lc[l * W1] : 0.0;
-      double xl = 0.0;
-      for (int c = cbn - 1; c >= 0; --c) {
-        const double xc = rl64(yl, c) * rl64(rdl, c);
-        if (l == c) xl = xc;
-        if (l < c && c - l <= bw) yl -= Lc[l * W1 + (c - l)] * xc;
-      }
-      if (l < cbn) y[c0 + l] = xl;
-    }
-    __syncthreads();
-  }
-}
-
-size_t band_cholesky_lds(int bw) {
-  const size_t fwd = (static_cast<size_t>(BC_NB) * (BC_NB + bw + 1) + BC_NB + bw + 1) * 8;
-  const size_t bwd = (64 * static_cast<size_t>(bw + 1) + 64 + bw + 64) * 8;
-  return fwd > bwd ? fwd : bwd;
-}
-
-// ---------------------------------------------------------------------------
 // update and norms
 // ---------------------------------------------------------------------------
 __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y) {

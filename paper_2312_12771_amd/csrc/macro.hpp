@@ -1,5 +1,5 @@
 // Macro-side kernels of libfe2 (FP64): geometry, gradients, assembly,
-// banded Cholesky, update and norms.
+// band assembly, update and norms.
 #pragma once
 
 #include "elem2d.hpp"
@@ -40,9 +40,18 @@ __global__ void k_macro_rows_band(MacroArgs m, const double* __restrict__ ke, do
                                   double* __restrict__ kdense);
 __global__ void k_fill(double* p, size_t n, double v);
 __global__ void k_fill_i(int* p, size_t n, int v);
-__global__ void k_band_cholesky(int n, int bw, double* __restrict__ band,
-                                double* __restrict__ y, int* __restrict__ info);
-size_t band_cholesky_lds(int bw);
+// Block cyclic reduction solve of a banded SPD system (bcr.hip).
+struct BcrPlan {
+  int n = 0, bw = 0, bs = 0, nb = 0;
+  size_t d_len = 0, g_len = 0, inv_len = 0, f_len = 0;
+};
+BcrPlan bcr_plan(int n, int bw);
+size_t bcr_workspace_doubles(const BcrPlan& p);
+int bcr_max_bandwidth();
+// band: lower band storage [n][bw+1] (read only); y: right-hand side in,
+// solution out; info: 0 on entry, set to a 1-based pivot index when the
+// matrix is not positive definite; ws: bcr_workspace_doubles(p) doubles.
+int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* info, hipStream_t s);
 __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y);
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
                            const double* __restrict__ X, double* __restrict__ w, int use_xr,

@@ -94,6 +94,7 @@ _sig = {
     "fe2_surrogate_attach": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fe2_surrogate_detach": (C.c_int, [_vp]),
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
+    "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
     "fe2_strerror": (C.c_char_p, [C.c_int]),
     "fe2_last_error": (C.c_char_p, []),
     "fe2_abi_version": (C.c_int, []),
@@ -237,6 +238,16 @@ def fe2_equilibrate_rve(h: Handle, stream=None, allow_noconv=False):
     st = _lib.fe2_equilibrate_rve(h.ptr, C.byref(its), _stream_ptr(stream))
     _check(st, "fe2_equilibrate_rve", (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,))
     return st, int(its.value)
+
+
+def fe2_band_solve(n: int, bw: int, band, rhs, stream=None, allow_notspd=False):
+    """Solve the SPD band system (lower band storage band [n*(bw+1)]) in place
+    in rhs [n].  Returns (status, pivot): pivot is 0, or the 1-based index of
+    a non-positive pivot (status FE2_ENOCONV, raised unless allow_notspd)."""
+    piv = C.c_int(0)
+    st = _lib.fe2_band_solve(int(n), int(bw), _dev_ptr(band), _dev_ptr(rhs), C.byref(piv), _stream_ptr(stream))
+    _check(st, "fe2_band_solve", (FE2_OK, FE2_ENOCONV) if allow_notspd else (FE2_OK,))
+    return st, piv.value
 
 
 def fe2_rve_response(h: Handle, F, P=None, Cm=None, ok=None, stream=None, allow_noconv=False):
