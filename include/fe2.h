@@ -252,7 +252,7 @@ int fe2_destroy(fe2_handle h);
  * reduction.  Allocates and frees its own workspace (about 4 bs^2 doubles per
  * block) and waits for `stream`.  pivot_host (may be NULL) receives 0, or a
  * 1-based index of a non-positive pivot, in which case FE2_ENOCONV is
- * returned and rhs_dev is undefined.  FE2_ENOTSUP when bw exceeds 1184. */
+ * returned and rhs_dev is undefined.  FE2_ENOTSUP when bw exceeds 1120. */
 int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream);
 
 /* ------------------------------------------------------------------------

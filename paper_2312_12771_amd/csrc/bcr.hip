@@ -84,34 +84,45 @@ __global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __re
 }
 
 // -- potrf: one work-group per eliminated block -------------------------------
-// Right-looking Cholesky in 16-column panels, in place in global memory (the
-// block stays in the work-group's L2).  Wave 0 factors the diagonal tile and
-// inverts it (lane r holds row r; wave-synchronous exchange through LDS), all
-// threads form the panel below with the inverse and apply the trailing
-// update in 4x4 register tiles.
+// Right-looking Cholesky in 16-column panels.  When the lower triangle of the
+// block fits in LDS (tile-packed 16x16 column-major tiles) it is factored
+// there and written back once; larger blocks are factored in place in global
+// memory.  Wave 0 factors the diagonal tile and inverts it (lane r holds row
+// r; wave-synchronous exchange through LDS); all threads form the panel below
+// with the inverse and apply the trailing update in 4x4 register tiles.
 constexpr int PO_WG = 256;
 
-__global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, double* __restrict__ invL, int bs,
-                                                     int first, int stride, int* __restrict__ info) {
-  extern __shared__ __align__(16) double s_panel[];   // [bs][BT]
-  __shared__ double s_ex[BT * (BT + 1)];
-  __shared__ double s_inv[BT * BT];                    // column-major
-  __shared__ int s_fail;
-  const int j = first + stride * static_cast<int>(blockIdx.x);
-  const int nt = bs / BT;
-  double* Dj = D + static_cast<size_t>(j) * bs * bs;
-  double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
+struct GlobalTiles {
+  double* base;
+  int ld;
+  __device__ double* tile(int ti, int tk) const { return base + static_cast<size_t>(tk) * BT * ld + ti * BT; }
+};
+struct LdsTiles {
+  double* base;
+  static constexpr int ld = BT;
+  __device__ double* tile(int ti, int tk) const { return base + (ti * (ti + 1) / 2 + tk) * (BT * BT); }
+};
+
+__device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= q
+  int a = static_cast<int>((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
+  while (a * (a + 1) / 2 > q) --a;
+  while ((a + 1) * (a + 2) / 2 <= q) ++a;
+  return a;
+}
+
+// Returns false when a pivot is not positive (info set, every thread returns).
+template <class M>
+__device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0, double* s_panel, double* s_ex,
+                           double* s_inv, int* s_fail, int* __restrict__ info) {
   const int tid = threadIdx.x;
-  if (tid == 0) s_fail = 0;
-  __syncthreads();
+  const int ld = A.ld;
   for (int p = 0; p < nt; ++p) {
-    const int k0 = p * BT;
     if (tid < 64) {
       const int r = tid;
+      double* Tpp = A.tile(p, p);
       double a[BT];
 #pragma unroll
-      for (int c = 0; c < BT; ++c)
-        a[c] = (r < BT && c <= r) ? Dj[static_cast<size_t>(k0 + c) * bs + k0 + r] : 0.0;
+      for (int c = 0; c < BT; ++c) a[c] = (r < BT && c <= r) ? Tpp[c * ld + r] : 0.0;
       bool bad = false;
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
@@ -122,11 +133,11 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
 #pragma unroll
         for (int cc = c + 1; cc < BT; ++cc) col[cc] = s_ex[cc];
         wave_sync();
-        if (!(d > 0.0)) {
+        if (!(d > 0.0)) {   // uniform: every lane read the same pivot
           bad = true;
           if (r == 0) {
-            s_fail = 1;
-            atomicCAS(info, 0, j * bs + k0 + c + 1);
+            *s_fail = 1;
+            atomicCAS(info, 0, col0 + p * BT + c + 1);
           }
           break;
         }
@@ -141,16 +152,15 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
         }
       }
       if (!bad) {
-        // L of the diagonal tile to global memory and to LDS (row r)
         if (r < BT) {
 #pragma unroll
           for (int c = 0; c < BT; ++c) {
-            if (c <= r) Dj[static_cast<size_t>(k0 + c) * bs + k0 + r] = a[c];
+            if (c <= r) Tpp[c * ld + r] = a[c];
             s_ex[r * (BT + 1) + c] = (c <= r) ? a[c] : 0.0;
           }
         }
         wave_sync();
-        // lane c < 16 solves L x = e_c: column c of the inverse
+        // lane r < 16 solves L x = e_r: column r of the inverse
         if (r < BT) {
           double x[BT];
 #pragma unroll
@@ -169,20 +179,21 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
       }
     }
     __syncthreads();
-    if (s_fail) return;
-    // panel below: L_ip = A_ip invL_pp^T, row by row
-    const int rows = bs - k0 - BT;
+    if (*s_fail) return false;
+    // panel below: L_ip = A_ip invL_pp^T, one row per thread
+    const int rows = (nt - p - 1) * BT;
     for (int t = tid; t < rows; t += PO_WG) {
-      const int ri = k0 + BT + t;
+      double* Tip = A.tile(p + 1 + t / BT, p);
+      const int rr = t % BT;
       double a[BT];
 #pragma unroll
-      for (int k = 0; k < BT; ++k) a[k] = Dj[static_cast<size_t>(k0 + k) * bs + ri];
+      for (int k = 0; k < BT; ++k) a[k] = Tip[k * ld + rr];
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
         double l = 0.0;
 #pragma unroll
         for (int k = 0; k <= c; ++k) l = fma(a[k], s_inv[k * BT + c], l);
-        Dj[static_cast<size_t>(k0 + c) * bs + ri] = l;
+        Tip[c * ld + rr] = l;
         s_panel[t * BT + c] = l;
       }
     }
@@ -192,12 +203,9 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     const int items = 16 * (m * (m + 1) / 2);
     for (int w = tid; w < items; w += PO_WG) {
       const int q = w >> 4, mt = w & 15;
-      int ta = static_cast<int>((sqrtf(8.0f * q + 1.0f) - 1.0f) * 0.5f);
-      while (ta * (ta + 1) / 2 > q) --ta;
-      while ((ta + 1) * (ta + 2) / 2 <= q) ++ta;
-      const int tb = q - ta * (ta + 1) / 2;
-      const int lr = ta * BT + (mt >> 2) * 4;   // rows of s_panel
-      const int lc = tb * BT + (mt & 3) * 4;
+      const int ta = tri_row(q), tb = q - ta * (ta + 1) / 2;
+      const int mr = (mt >> 2) * 4, mc = (mt & 3) * 4;
+      const int lr = ta * BT + mr, lc = tb * BT + mc;   // rows of s_panel
       double acc[4][4] = {};
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
@@ -212,29 +220,86 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = fma(pi[x], pj[y], acc[x][y]);
       }
+      double* Tab = A.tile(p + 1 + ta, p + 1 + tb);
 #pragma unroll
       for (int y = 0; y < 4; ++y)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          double* e = Dj + static_cast<size_t>(k0 + BT + lc + y) * bs + (k0 + BT + lr + x);
-          *e -= acc[x][y];
-        }
+        for (int x = 0; x < 4; ++x) Tab[(mc + y) * ld + mr + x] -= acc[x][y];
     }
     __syncthreads();
+  }
+  return true;
+}
+
+// LDS bytes of the two variants
+__host__ __device__ constexpr size_t potrf_lds_global(int bs) { return static_cast<size_t>(bs) * BT * 8; }
+__host__ __device__ constexpr size_t potrf_lds_resident(int bs) {
+  return potrf_lds_global(bs) + static_cast<size_t>((bs / BT) * (bs / BT + 1) / 2) * BT * BT * 8;
+}
+
+template <bool RESIDENT>
+__global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, double* __restrict__ invL, int bs,
+                                                     int first, int stride, int* __restrict__ info) {
+  extern __shared__ __align__(16) double smem[];
+  __shared__ double s_ex[BT * (BT + 1)];
+  __shared__ double s_inv[BT * BT];   // column-major
+  __shared__ int s_fail;
+  const int j = first + stride * static_cast<int>(blockIdx.x);
+  const int nt = bs / BT;
+  double* Dj = D + static_cast<size_t>(j) * bs * bs;
+  double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
+  const int tid = threadIdx.x;
+  double* s_panel = smem;   // [bs][BT]
+  if (tid == 0) s_fail = 0;
+  if constexpr (RESIDENT) {
+    double* s_tiles = smem + bs * BT;
+    const int ntri = nt * (nt + 1) / 2;
+    const int c = tid >> 4, r = tid & 15;   // one element of a tile per thread
+    {
+      int ti = 0, tk = 0;
+#pragma unroll 4
+      for (int q = 0; q < ntri; ++q) {
+        s_tiles[q * BT * BT + tid] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
+        if (++tk > ti) {
+          ++ti;
+          tk = 0;
+        }
+      }
+    }
+    __syncthreads();
+    const LdsTiles A{s_tiles};
+    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, &s_fail, info)) return;
+    int ti = 0, tk = 0;
+#pragma unroll 4
+    for (int q = 0; q < ntri; ++q) {
+      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * BT * BT + tid];
+      if (++tk > ti) {
+        ++ti;
+        tk = 0;
+      }
+    }
+  } else {
+    __syncthreads();
+    const GlobalTiles A{Dj, bs};
+    potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, &s_fail, info);
   }
 }
 
 // -- trsm: one work-group per (16-column tile, eliminated block) --------------
 // Forward substitution L_j X = R on one tile of R = [C_j | C_{j+h}^T | f_j],
-// 16 rows at a time: S = R_i - sum_{k<i} L_ik X_k, X_i = invL_ii S.
+// 16 rows at a time: S = R_i - sum_{k<i} L_ik X_k (L staged through LDS in
+// slabs of TR_KC columns), X_i = invL_ii S.
 constexpr int TR_WG = 256;
+constexpr int TR_KC = 128;
 
 __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D, const double* __restrict__ invL,
                                                     const double* __restrict__ C, double* __restrict__ G,
                                                     double* __restrict__ F, int bs, int nb, int first, int stride,
                                                     int h, int rhs_only) {
-  extern __shared__ __align__(16) double s_x[];   // [bs][BT]
+  extern __shared__ __align__(16) double s_x[];   // [bs][BT]: R, overwritten by X
+  __shared__ double s_l[TR_KC * BT];              // [k][r]
   __shared__ double s_s[BT * BT];
+  __shared__ double s_iv[BT * BT];
   const int j = first + stride * static_cast<int>(blockIdx.y);
   const int nt = bs / BT;
   const int ct = rhs_only ? 2 * nt : static_cast<int>(blockIdx.x);
@@ -266,33 +331,42 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
   const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
   const int tid = threadIdx.x;
   const int r = tid & (BT - 1), c = tid >> 4;
+#pragma unroll 4
+  for (int row = r; row < bs; row += BT)
+    s_x[row * BT + c] = (c < ncol) ? src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c] : 0.0;
   for (int i = 0; i < nt; ++i) {
     const int row = i * BT + r;
-    double s = 0.0;
-    if (c < ncol) {
-      s = src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c];
-      double s2 = 0.0;
-      int k = 0;
-      for (; k + 1 < i * BT; k += 2) {
-        s = fma(-Lj[static_cast<size_t>(k) * bs + row], s_x[k * BT + c], s);
-        s2 = fma(-Lj[static_cast<size_t>(k + 1) * bs + row], s_x[(k + 1) * BT + c], s2);
+    double s = s_x[row * BT + c];   // written by this thread
+    const double iv = Ij[i * BT * BT + tid];
+    double s2 = 0.0;
+    for (int kc0 = 0; kc0 < i * BT; kc0 += TR_KC) {
+      const int kc = min(TR_KC, i * BT - kc0);
+      __syncthreads();   // earlier readers of s_l (and of s_s, s_iv, s_x) are done
+#pragma unroll
+      for (int u = 0; u < TR_KC * BT / TR_WG; ++u) {
+        const int e = tid + u * TR_WG, k = e >> 4, rr = e & 15;
+        if (k < kc) s_l[e] = Lj[static_cast<size_t>(kc0 + k) * bs + i * BT + rr];
       }
-      for (; k < i * BT; ++k) s = fma(-Lj[static_cast<size_t>(k) * bs + row], s_x[k * BT + c], s);
-      s += s2;
+      __syncthreads();
+      int k = 0;
+      for (; k + 1 < kc; k += 2) {
+        s = fma(-s_l[k * BT + r], s_x[(kc0 + k) * BT + c], s);
+        s2 = fma(-s_l[(k + 1) * BT + r], s_x[(kc0 + k + 1) * BT + c], s2);
+      }
+      if (k < kc) s = fma(-s_l[k * BT + r], s_x[(kc0 + k) * BT + c], s);
     }
-    s_s[r * BT + c] = s;
+    s_s[r * BT + c] = s + s2;
+    s_iv[tid] = iv;   // element (r, c) of invL_ii, column-major
     __syncthreads();
     double x = 0.0;
-    if (c < ncol) {
-      const double* Ii = Ij + i * BT * BT;
 #pragma unroll
-      for (int k = 0; k < BT; ++k)
-        if (k <= r) x = fma(Ii[k * BT + r], s_s[k * BT + c], x);
-    }
+    for (int k = 0; k < BT; ++k)
+      if (k <= r) x = fma(s_iv[k * BT + r], s_s[k * BT + c], x);
     s_x[row * BT + c] = x;
-    __syncthreads();
+    // the next tile's first slab barrier orders these writes before their readers
   }
   if (c < ncol)
+#pragma unroll 4
     for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = s_x[row * BT + c];
 }
 
@@ -391,14 +465,16 @@ __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ 
 }
 
 // -- back substitution: one work-group per eliminated block -------------------
+// t = g_j - G_l x_{j-h} - G_r x_{j+h}, then L_j^T x = t from the bottom tile
+// up: x_i = invL_ii^T t_i, and t_k -= L(tile i, k)^T x_i for the rows above.
 constexpr int BK_WG = 256;
+constexpr int BK_NC = 1024;
 
 __global__ void __launch_bounds__(BK_WG) k_bcr_back(const double* __restrict__ D, const double* __restrict__ invL,
                                                     const double* __restrict__ G, double* __restrict__ F, int bs,
                                                     int nb, int first, int stride, int h, int alone) {
   extern __shared__ __align__(16) double s_t[];   // [bs] right side, then x
-  __shared__ double s_red[BT * BT];
-  __shared__ double s_nb[2][1024];
+  __shared__ double s_nb[2][BK_NC];
   const int j = first + stride * static_cast<int>(blockIdx.x);
   const int nt = bs / BT;
   const size_t per = static_cast<size_t>(bs) * bs;
@@ -408,50 +484,65 @@ __global__ void __launch_bounds__(BK_WG) k_bcr_back(const double* __restrict__ D
   const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
   double* Fj = F + static_cast<size_t>(j) * bs;
   const int tid = threadIdx.x;
-  // neighbour solutions, staged through LDS in chunks of 1024
   for (int r = tid; r < bs; r += BK_WG) s_t[r] = Fj[r];
-  for (int c0 = 0; c0 < bs; c0 += 1024) {
-    const int cn = min(1024, bs - c0);
-    __syncthreads();
-    for (int t = tid; t < cn; t += BK_WG) {
-      s_nb[0][t] = has_l ? F[static_cast<size_t>(j - h) * bs + c0 + t] : 0.0;
-      s_nb[1][t] = has_r ? F[static_cast<size_t>(j + h) * bs + c0 + t] : 0.0;
-    }
-    __syncthreads();
-    if (has_l || has_r)
-      for (int r = tid; r < bs; r += BK_WG) {
-        double a1 = 0.0, a2 = 0.0;
-        for (int c = 0; c < cn; ++c) {
-          if (has_l) a1 = fma(Gj[static_cast<size_t>(c0 + c) * bs + r], s_nb[0][c], a1);
-          if (has_r) a2 = fma(Gj[per + static_cast<size_t>(c0 + c) * bs + r], s_nb[1][c], a2);
-        }
-        s_t[r] -= a1 + a2;
+  if (has_l || has_r) {
+    for (int c0 = 0; c0 < bs; c0 += BK_NC) {
+      const int cn = min(BK_NC, bs - c0);
+      __syncthreads();
+      for (int t = tid; t < cn; t += BK_WG) {
+        s_nb[0][t] = has_l ? F[static_cast<size_t>(j - h) * bs + c0 + t] : 0.0;
+        s_nb[1][t] = has_r ? F[static_cast<size_t>(j + h) * bs + c0 + t] : 0.0;
       }
+      __syncthreads();
+      for (int r = tid; r < bs; r += BK_WG) {
+        const double* gl = Gj + static_cast<size_t>(c0) * bs + r;
+        const double* gr = gl + per;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int c = 0;
+        for (; c + 3 < cn; c += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t o = static_cast<size_t>(c + u) * bs;
+            a[u] = fma(gl[o], s_nb[0][c + u], a[u]);
+            a[u] = fma(gr[o], s_nb[1][c + u], a[u]);
+          }
+        }
+        for (; c < cn; ++c) {
+          const size_t o = static_cast<size_t>(c) * bs;
+          a[0] = fma(gl[o], s_nb[0][c], a[0]);
+          a[0] = fma(gr[o], s_nb[1][c], a[0]);
+        }
+        s_t[r] -= (a[0] + a[1]) + (a[2] + a[3]);
+      }
+    }
   }
   __syncthreads();
-  // L^T x = t, 16 rows at a time from the bottom
-  const int r = tid & (BT - 1), sl = tid >> 4;
   for (int i = nt - 1; i >= 0; --i) {
-    const int col = i * BT + r;   // row of L^T = column of L
-    double part = 0.0;
-    for (int k = (i + 1) * BT + sl; k < bs; k += 16) part = fma(Lj[static_cast<size_t>(col) * bs + k], s_t[k], part);
-    s_red[sl * BT + r] = part;
-    __syncthreads();
     if (tid < BT) {
-      double u = s_t[col];
+      // x_i = invL_ii^T t_i: x[r] = sum_{k >= r} invL[k][r] t[k]
+      const double* Ii = Ij + i * BT * BT + tid * BT;
+      double v[BT];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) u -= s_red[q * BT + r];
-      s_red[r] = u;   // row 0 of s_red was read above by this thread only
-    }
-    __syncthreads();
-    if (tid < BT) {
-      // x_i = invL_ii^T u: x[r] = sum_{k >= r} invL[k][r] u[k]
-      const double* Ii = Ij + i * BT * BT;
+      for (int k = 0; k < BT; ++k) v[k] = k >= tid ? Ii[k] : 0.0;
       double x = 0.0;
 #pragma unroll
-      for (int k = 0; k < BT; ++k)
-        if (k >= r) x = fma(Ii[r * BT + k], s_red[k], x);
-      s_t[col] = x;
+      for (int k = 0; k < BT; ++k) x = fma(v[k], s_t[i * BT + k], x);
+      wave_sync();   // every lane has read t_i before it is overwritten
+      s_t[i * BT + tid] = x;
+    }
+    __syncthreads();
+    for (int k = tid; k < i * BT; k += BK_WG) {
+      const double2* lk = reinterpret_cast<const double2*>(Lj + static_cast<size_t>(k) * bs + i * BT);
+      double2 v[BT / 2];
+#pragma unroll
+      for (int m = 0; m < BT / 2; ++m) v[m] = lk[m];
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int m = 0; m < BT / 2; ++m) {
+        a0 = fma(v[m].x, s_t[i * BT + 2 * m], a0);
+        a1 = fma(v[m].y, s_t[i * BT + 2 * m + 1], a1);
+      }
+      s_t[k] -= a0 + a1;
     }
     __syncthreads();
   }
@@ -474,7 +565,7 @@ BcrPlan bcr_plan(int n, int bw) {
   return p;
 }
 
-int bcr_max_bandwidth() { return 1184; }   // panel buffer + static LDS within 160 KiB
+int bcr_max_bandwidth() { return 1120; }   // trsm right-hand sides + staging within 160 KiB of LDS
 
 size_t bcr_workspace_doubles(const BcrPlan& p) { return 2 * p.d_len + p.g_len + p.inv_len + p.f_len; }
 
@@ -489,29 +580,33 @@ int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* 
   hipLaunchKernelGGL(k_bcr_extract, dim3(eg), dim3(256), 0, s, band, p.n, p.bw, bs, nb, D, C);
   const int np = nb * bs;
   hipLaunchKernelGGL(k_bcr_copy_in, dim3((np + 255) / 256), dim3(256), 0, s, y, p.n, np, F);
-  const size_t lds_po = static_cast<size_t>(bs) * BT * sizeof(double);
+  const size_t lds_tr = static_cast<size_t>(bs) * BT * sizeof(double);
   const size_t lds_bk = static_cast<size_t>(bs) * sizeof(double);
-  if (lds_po + 8 * 1024 > 64 * 1024) {
-    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bcr_potrf),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_po)));
+  // factor in LDS when the block's lower triangle fits next to the panel
+  const bool resident = potrf_lds_resident(bs) + 8 * 1024 <= 160 * 1024;
+  const size_t lds_po = resident ? potrf_lds_resident(bs) : potrf_lds_global(bs);
+  auto potrf = resident ? k_bcr_potrf<true> : k_bcr_potrf<false>;
+  if (lds_po + 8 * 1024 > 64 * 1024)
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(potrf), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(lds_po)));
+  if (lds_tr + 12 * 1024 > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bcr_trsm),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_po)));
-  }
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_tr)));
   const int ntri = nt * (nt + 1) / 2;
   int h = 1;
   for (;;) {
     const int nact = (nb - 1) / h + 1;
     if (nact == 1) break;
     const int nodd = nact / 2, neven = (nact + 1) / 2;
-    hipLaunchKernelGGL(k_bcr_potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, info);
-    hipLaunchKernelGGL(k_bcr_trsm, dim3(2 * nt + 1, nodd), dim3(TR_WG), lds_po, s, D, IL, C, G, F, bs, nb, h,
+    hipLaunchKernelGGL(potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, info);
+    hipLaunchKernelGGL(k_bcr_trsm, dim3(2 * nt + 1, nodd), dim3(TR_WG), lds_tr, s, D, IL, C, G, F, bs, nb, h,
                        2 * h, h, 0);
     hipLaunchKernelGGL(k_bcr_schur, dim3(ntri + nt * nt + nt, neven), dim3(SC_WG), 0, s, G, D, C, F, bs, nb, h);
     h *= 2;
   }
   const int htop = h;
-  hipLaunchKernelGGL(k_bcr_potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, info);
-  hipLaunchKernelGGL(k_bcr_trsm, dim3(1, 1), dim3(TR_WG), lds_po, s, D, IL, C, G, F, bs, nb, 0, 0, 0, 1);
+  hipLaunchKernelGGL(potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, info);
+  hipLaunchKernelGGL(k_bcr_trsm, dim3(1, 1), dim3(TR_WG), lds_tr, s, D, IL, C, G, F, bs, nb, 0, 0, 0, 1);
   hipLaunchKernelGGL(k_bcr_back, dim3(1), dim3(BK_WG), lds_bk, s, D, IL, G, F, bs, nb, 0, 0, 0, 1);
   for (h = htop / 2; h >= 1; h /= 2) {
     const int nact = (nb - 1) / h + 1;
