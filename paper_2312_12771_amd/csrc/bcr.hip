@@ -14,7 +14,7 @@
 // Per level (stride h; active blocks are the multiples of h; odd ones j =
 // h, 3h, ... are eliminated, with left neighbour j-h and right neighbour j+h):
 //   potrf : D_j = L_j L_j^T (in place), inverses of its 16x16 diagonal tiles;
-//   trsm  : [G_l | G_r | g] = L_j^-1 [A_{j,j-h} | A_{j+h,j}^T | f_j];
+//   trsm  : [G_l | G_r | L_j^-1 | g] = L_j^-1 [A_{j,j-h} | A_{j+h,j}^T | I | f_j];
 //   schur : for even i:  D_i -= G_r(i-h)^T G_r(i-h) + G_l(i+h)^T G_l(i+h),
 //           f_i -= G_r(i-h)^T g(i-h) + G_l(i+h)^T g(i+h),
 //           A_{i,i-2h} = -G_r(i-h)^T G_l(i-h).
@@ -23,9 +23,10 @@
 //
 // Storage (device, FP64): D and C [nb][bs][bs] column-major (C_i couples
 // block i to its left active neighbour), G [nb][bs][2 bs] column-major
-// ([G_l | G_r]), invL [nb][bs/16][16][16] column-major tiles, F [nb*bs] the
-// padded right-hand side, overwritten by g and then by the solution.  Rows
-// beyond n are padded with the identity.
+// ([G_l | G_r]), invL [nb][bs/16][16][16] column-major inverses of the
+// diagonal tiles, Linv [nb][bs][bs] column-major L_j^-1, F [nb*bs] the padded
+// right-hand side, overwritten by g and then by the solution, T [nb*bs] the
+// back-substitution right sides.  Rows beyond n are padded with the identity.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -113,7 +114,7 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
 // Returns false when a pivot is not positive (info set, every thread returns).
 template <class M>
 __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0, double* s_panel, double* s_ex,
-                           double* s_inv, int* s_fail, int* __restrict__ info) {
+                           double* s_inv, double* s_rd, int* s_fail, int* __restrict__ info) {
   const int tid = threadIdx.x;
   const int ld = A.ld;
   for (int p = 0; p < nt; ++p) {
@@ -141,8 +142,9 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
           }
           break;
         }
-        const double sd = sqrt(d);
-        const double inv_sd = 1.0 / sd;
+        const double inv_sd = rsqrt(d);
+        const double sd = d * inv_sd;
+        if (r == c) s_rd[c] = inv_sd;
         const double lrc = a[c] * inv_sd;
         a[c] = (r == c) ? sd : (r > c ? lrc : a[c]);
 #pragma unroll
@@ -168,7 +170,7 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
             double acc = (i == r) ? 1.0 : 0.0;
 #pragma unroll
             for (int k = 0; k < i; ++k) acc = fma(-s_ex[i * (BT + 1) + k], x[k], acc);
-            x[i] = (i >= r) ? acc / s_ex[i * (BT + 1) + i] : 0.0;
+            x[i] = (i >= r) ? acc * s_rd[i] : 0.0;
           }
 #pragma unroll
           for (int i = 0; i < BT; ++i) {
@@ -243,6 +245,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   extern __shared__ __align__(16) double smem[];
   __shared__ double s_ex[BT * (BT + 1)];
   __shared__ double s_inv[BT * BT];   // column-major
+  __shared__ double s_rd[BT];         // reciprocal pivots of the diagonal tile
   __shared__ int s_fail;
   const int j = first + stride * static_cast<int>(blockIdx.x);
   const int nt = bs / BT;
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     }
     __syncthreads();
     const LdsTiles A{s_tiles};
-    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, &s_fail, info)) return;
+    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, s_rd, &s_fail, info)) return;
     int ti = 0, tk = 0;
 #pragma unroll 4
     for (int q = 0; q < ntri; ++q) {
@@ -281,45 +284,52 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   } else {
     __syncthreads();
     const GlobalTiles A{Dj, bs};
-    potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, &s_fail, info);
+    potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, s_rd, &s_fail, info);
   }
 }
 
 // -- trsm: one work-group per (16-column tile, eliminated block) --------------
-// Forward substitution L_j X = R on one tile of R = [C_j | C_{j+h}^T | f_j],
-// 16 rows at a time: S = R_i - sum_{k<i} L_ik X_k (L staged through LDS in
-// slabs of TR_KC columns), X_i = invL_ii S.
+// Forward substitution L_j X = R on one tile of R = [C_j | C_{j+h}^T | I | f_j]
+// (the identity tiles give L_j^-1 for the back substitution), 16 rows at a
+// time: S = R_i - sum_{k<i} L_ik X_k (L staged through LDS in slabs of TR_KC
+// columns), X_i = invL_ii S.  Tiles: [0, nt) left coupling, [nt, 2nt) right
+// coupling, [2nt, 3nt) identity, 3nt right-hand side; a block with no
+// neighbours (the last one left) runs only the last nt + 1.
 constexpr int TR_WG = 256;
 constexpr int TR_KC = 128;
 
 __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D, const double* __restrict__ invL,
                                                     const double* __restrict__ C, double* __restrict__ G,
-                                                    double* __restrict__ F, int bs, int nb, int first, int stride,
-                                                    int h, int rhs_only) {
+                                                    double* __restrict__ Linv, double* __restrict__ F, int bs,
+                                                    int nb, int first, int stride, int h, int alone) {
   extern __shared__ __align__(16) double s_x[];   // [bs][BT]: R, overwritten by X
   __shared__ double s_l[TR_KC * BT];              // [k][r]
   __shared__ double s_s[BT * BT];
   __shared__ double s_iv[BT * BT];
   const int j = first + stride * static_cast<int>(blockIdx.y);
   const int nt = bs / BT;
-  const int ct = rhs_only ? 2 * nt : static_cast<int>(blockIdx.x);
+  const int ct = alone ? 2 * nt + static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
   const size_t per = static_cast<size_t>(bs) * bs;
-  const double* src;
+  const double* src = nullptr;
   double* out;
-  int ld_r, ld_c, ncol;   // R(r, c) = src[r * ld_r + c * ld_c]; out(r, c) = out[c * bs + r]
+  int ld_r = 0, ld_c = 0, ncol = BT, ident = -1, i0 = 0;
+  // R(r, c) = src[r * ld_r + c * ld_c], or (r == ident + c) for identity tiles;
+  // out(r, c) = out[c * bs + r]
   if (ct < nt) {
     src = C + j * per + static_cast<size_t>(ct) * BT * bs;
     ld_r = 1;
     ld_c = bs;
     out = G + j * 2 * per + static_cast<size_t>(ct) * BT * bs;
-    ncol = BT;
   } else if (ct < 2 * nt) {
     if (j + h >= nb) return;
     src = C + (j + h) * per + (ct - nt) * BT;
     ld_r = bs;
     ld_c = 1;
     out = G + j * 2 * per + static_cast<size_t>(bs + (ct - nt) * BT) * bs;
-    ncol = BT;
+  } else if (ct < 3 * nt) {
+    i0 = ct - 2 * nt;   // rows above the tile's diagonal stay zero
+    ident = i0 * BT;
+    out = Linv + j * per + static_cast<size_t>(i0) * BT * bs;
   } else {
     src = F + static_cast<size_t>(j) * bs;
     ld_r = 1;
@@ -331,15 +341,19 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
   const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
   const int tid = threadIdx.x;
   const int r = tid & (BT - 1), c = tid >> 4;
+  if (ident >= 0) {
+    for (int row = r; row < bs; row += BT) s_x[row * BT + c] = (row == ident + c) ? 1.0 : 0.0;
+  } else {
 #pragma unroll 4
-  for (int row = r; row < bs; row += BT)
-    s_x[row * BT + c] = (c < ncol) ? src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c] : 0.0;
-  for (int i = 0; i < nt; ++i) {
+    for (int row = r; row < bs; row += BT)
+      s_x[row * BT + c] = (c < ncol) ? src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c] : 0.0;
+  }
+  for (int i = i0; i < nt; ++i) {
     const int row = i * BT + r;
     double s = s_x[row * BT + c];   // written by this thread
     const double iv = Ij[i * BT * BT + tid];
     double s2 = 0.0;
-    for (int kc0 = 0; kc0 < i * BT; kc0 += TR_KC) {
+    for (int kc0 = i0 * BT; kc0 < i * BT; kc0 += TR_KC) {
       const int kc = min(TR_KC, i * BT - kc0);
       __syncthreads();   // earlier readers of s_l (and of s_s, s_iv, s_x) are done
 #pragma unroll
@@ -367,7 +381,7 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
   }
   if (c < ncol)
 #pragma unroll 4
-    for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = s_x[row * BT + c];
+    for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = row < i0 * BT ? 0.0 : s_x[row * BT + c];
 }
 
 // -- schur: one work-group per (output tile, even block) ----------------------
@@ -464,89 +478,66 @@ __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ 
   }
 }
 
-// -- back substitution: one work-group per eliminated block -------------------
-// t = g_j - G_l x_{j-h} - G_r x_{j+h}, then L_j^T x = t from the bottom tile
-// up: x_i = invL_ii^T t_i, and t_k -= L(tile i, k)^T x_i for the rows above.
+// -- back substitution: two passes per level, one work-group per (16-row tile,
+// eliminated block) --------------------------------------------------------
+//   back_t: t_j = g_j - G_l x_{j-h} - G_r x_{j+h}   (into T)
+//   back_x: x_j = L_j^-T t_j = sum_k Linv(k, .) t_k  (into F)
+// 256 threads = 16 rows x 16 slices of the summation index, reduced in LDS.
 constexpr int BK_WG = 256;
-constexpr int BK_NC = 1024;
 
-__global__ void __launch_bounds__(BK_WG) k_bcr_back(const double* __restrict__ D, const double* __restrict__ invL,
-                                                    const double* __restrict__ G, double* __restrict__ F, int bs,
-                                                    int nb, int first, int stride, int h, int alone) {
-  extern __shared__ __align__(16) double s_t[];   // [bs] right side, then x
-  __shared__ double s_nb[2][BK_NC];
-  const int j = first + stride * static_cast<int>(blockIdx.x);
-  const int nt = bs / BT;
+__global__ void __launch_bounds__(BK_WG) k_bcr_back_t(const double* __restrict__ G, const double* __restrict__ F,
+                                                      double* __restrict__ T, int bs, int nb, int first, int stride,
+                                                      int h, int alone) {
+  __shared__ double s_red[BT][BT + 1];
+  const int j = first + stride * static_cast<int>(blockIdx.y);
+  const int rr = threadIdx.x & 15, sl = threadIdx.x >> 4;   // 16 consecutive rows per slice
+  const int row = blockIdx.x * BT + rr;
   const size_t per = static_cast<size_t>(bs) * bs;
   const bool has_l = !alone && j >= h, has_r = !alone && j + h < nb;
   const double* Gj = G + j * 2 * per;
-  const double* Lj = D + j * per;
-  const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
-  double* Fj = F + static_cast<size_t>(j) * bs;
-  const int tid = threadIdx.x;
-  for (int r = tid; r < bs; r += BK_WG) s_t[r] = Fj[r];
-  if (has_l || has_r) {
-    for (int c0 = 0; c0 < bs; c0 += BK_NC) {
-      const int cn = min(BK_NC, bs - c0);
-      __syncthreads();
-      for (int t = tid; t < cn; t += BK_WG) {
-        s_nb[0][t] = has_l ? F[static_cast<size_t>(j - h) * bs + c0 + t] : 0.0;
-        s_nb[1][t] = has_r ? F[static_cast<size_t>(j + h) * bs + c0 + t] : 0.0;
-      }
-      __syncthreads();
-      for (int r = tid; r < bs; r += BK_WG) {
-        const double* gl = Gj + static_cast<size_t>(c0) * bs + r;
-        const double* gr = gl + per;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        int c = 0;
-        for (; c + 3 < cn; c += 4) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const size_t o = static_cast<size_t>(c + u) * bs;
-            a[u] = fma(gl[o], s_nb[0][c + u], a[u]);
-            a[u] = fma(gr[o], s_nb[1][c + u], a[u]);
-          }
-        }
-        for (; c < cn; ++c) {
-          const size_t o = static_cast<size_t>(c) * bs;
-          a[0] = fma(gl[o], s_nb[0][c], a[0]);
-          a[0] = fma(gr[o], s_nb[1][c], a[0]);
-        }
-        s_t[r] -= (a[0] + a[1]) + (a[2] + a[3]);
-      }
-    }
-  }
+  const double* xl = F + static_cast<size_t>(has_l ? j - h : j) * bs;
+  const double* xr = F + static_cast<size_t>(has_r ? j + h : j) * bs;
+  double a0 = 0.0, a1 = 0.0;
+  if (has_l)
+#pragma unroll 4
+    for (int c = sl; c < bs; c += BT) a0 = fma(Gj[static_cast<size_t>(c) * bs + row], xl[c], a0);
+  if (has_r)
+#pragma unroll 4
+    for (int c = sl; c < bs; c += BT) a1 = fma(Gj[per + static_cast<size_t>(c) * bs + row], xr[c], a1);
+  s_red[rr][sl] = a0 + a1;
   __syncthreads();
-  for (int i = nt - 1; i >= 0; --i) {
-    if (tid < BT) {
-      // x_i = invL_ii^T t_i: x[r] = sum_{k >= r} invL[k][r] t[k]
-      const double* Ii = Ij + i * BT * BT + tid * BT;
-      double v[BT];
+  if (threadIdx.x < BT) {
+    double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < BT; ++k) v[k] = k >= tid ? Ii[k] : 0.0;
-      double x = 0.0;
-#pragma unroll
-      for (int k = 0; k < BT; ++k) x = fma(v[k], s_t[i * BT + k], x);
-      wave_sync();   // every lane has read t_i before it is overwritten
-      s_t[i * BT + tid] = x;
-    }
-    __syncthreads();
-    for (int k = tid; k < i * BT; k += BK_WG) {
-      const double2* lk = reinterpret_cast<const double2*>(Lj + static_cast<size_t>(k) * bs + i * BT);
-      double2 v[BT / 2];
-#pragma unroll
-      for (int m = 0; m < BT / 2; ++m) v[m] = lk[m];
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int m = 0; m < BT / 2; ++m) {
-        a0 = fma(v[m].x, s_t[i * BT + 2 * m], a0);
-        a1 = fma(v[m].y, s_t[i * BT + 2 * m + 1], a1);
-      }
-      s_t[k] -= a0 + a1;
-    }
-    __syncthreads();
+    for (int q = 0; q < BT; ++q) t += s_red[threadIdx.x][q];
+    const size_t o = static_cast<size_t>(j) * bs + blockIdx.x * BT + threadIdx.x;
+    T[o] = F[o] - t;
   }
-  for (int rr = tid; rr < bs; rr += BK_WG) Fj[rr] = s_t[rr];
+}
+
+__global__ void __launch_bounds__(BK_WG) k_bcr_back_x(const double* __restrict__ Linv, const double* __restrict__ T,
+                                                      double* __restrict__ F, int bs, int first, int stride) {
+  __shared__ double s_red[BT][BT + 1];
+  const int j = first + stride * static_cast<int>(blockIdx.y);
+  const int rr = threadIdx.x >> 4, sl = threadIdx.x & 15;
+  const int row = blockIdx.x * BT + rr;
+  const double* li = Linv + static_cast<size_t>(j) * bs * bs + static_cast<size_t>(row) * bs;   // column `row` of L^-1
+  const double* tj = T + static_cast<size_t>(j) * bs;
+  double a0 = 0.0, a1 = 0.0;
+  int k = blockIdx.x * BT + sl;   // L^-1(k, row) = 0 for k < row
+  for (; k + BT < bs; k += 2 * BT) {
+    a0 = fma(li[k], tj[k], a0);
+    a1 = fma(li[k + BT], tj[k + BT], a1);
+  }
+  if (k < bs) a0 = fma(li[k], tj[k], a0);
+  s_red[rr][sl] = a0 + a1;
+  __syncthreads();
+  if (threadIdx.x < BT) {
+    double x = 0.0;
+#pragma unroll
+    for (int q = 0; q < BT; ++q) x += s_red[threadIdx.x][q];
+    F[static_cast<size_t>(j) * bs + blockIdx.x * BT + threadIdx.x] = x;
+  }
 }
 
 }  // namespace
@@ -567,7 +558,7 @@ BcrPlan bcr_plan(int n, int bw) {
 
 int bcr_max_bandwidth() { return 1120; }   // trsm right-hand sides + staging within 160 KiB of LDS
 
-size_t bcr_workspace_doubles(const BcrPlan& p) { return 2 * p.d_len + p.g_len + p.inv_len + p.f_len; }
+size_t bcr_workspace_doubles(const BcrPlan& p) { return 3 * p.d_len + p.g_len + p.inv_len + 2 * p.f_len; }
 
 int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* info, hipStream_t s) {
   double* D = ws;
@@ -575,13 +566,14 @@ int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* 
   double* G = C + p.d_len;
   double* IL = G + p.g_len;
   double* F = IL + p.inv_len;
+  double* LI = F + p.f_len;
+  double* T = LI + p.d_len;
   const int bs = p.bs, nb = p.nb, nt = bs / BT;
   const unsigned eg = static_cast<unsigned>(std::min<size_t>(8192, (p.d_len + 255) / 256));
   hipLaunchKernelGGL(k_bcr_extract, dim3(eg), dim3(256), 0, s, band, p.n, p.bw, bs, nb, D, C);
   const int np = nb * bs;
   hipLaunchKernelGGL(k_bcr_copy_in, dim3((np + 255) / 256), dim3(256), 0, s, y, p.n, np, F);
   const size_t lds_tr = static_cast<size_t>(bs) * BT * sizeof(double);
-  const size_t lds_bk = static_cast<size_t>(bs) * sizeof(double);
   // factor in LDS when the block's lower triangle fits next to the panel
   const bool resident = potrf_lds_resident(bs) + 8 * 1024 <= 160 * 1024;
   const size_t lds_po = resident ? potrf_lds_resident(bs) : potrf_lds_global(bs);
@@ -599,19 +591,21 @@ int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* 
     if (nact == 1) break;
     const int nodd = nact / 2, neven = (nact + 1) / 2;
     hipLaunchKernelGGL(potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, info);
-    hipLaunchKernelGGL(k_bcr_trsm, dim3(2 * nt + 1, nodd), dim3(TR_WG), lds_tr, s, D, IL, C, G, F, bs, nb, h,
+    hipLaunchKernelGGL(k_bcr_trsm, dim3(3 * nt + 1, nodd), dim3(TR_WG), lds_tr, s, D, IL, C, G, LI, F, bs, nb, h,
                        2 * h, h, 0);
     hipLaunchKernelGGL(k_bcr_schur, dim3(ntri + nt * nt + nt, neven), dim3(SC_WG), 0, s, G, D, C, F, bs, nb, h);
     h *= 2;
   }
   const int htop = h;
   hipLaunchKernelGGL(potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, info);
-  hipLaunchKernelGGL(k_bcr_trsm, dim3(1, 1), dim3(TR_WG), lds_tr, s, D, IL, C, G, F, bs, nb, 0, 0, 0, 1);
-  hipLaunchKernelGGL(k_bcr_back, dim3(1), dim3(BK_WG), lds_bk, s, D, IL, G, F, bs, nb, 0, 0, 0, 1);
+  hipLaunchKernelGGL(k_bcr_trsm, dim3(nt + 1, 1), dim3(TR_WG), lds_tr, s, D, IL, C, G, LI, F, bs, nb, 0, 0, 0, 1);
+  hipLaunchKernelGGL(k_bcr_back_t, dim3(nt, 1), dim3(BK_WG), 0, s, G, F, T, bs, nb, 0, 0, 0, 1);
+  hipLaunchKernelGGL(k_bcr_back_x, dim3(nt, 1), dim3(BK_WG), 0, s, LI, T, F, bs, 0, 0);
   for (h = htop / 2; h >= 1; h /= 2) {
     const int nact = (nb - 1) / h + 1;
     const int nodd = nact / 2;
-    hipLaunchKernelGGL(k_bcr_back, dim3(nodd), dim3(BK_WG), lds_bk, s, D, IL, G, F, bs, nb, h, 2 * h, h, 0);
+    hipLaunchKernelGGL(k_bcr_back_t, dim3(nt, nodd), dim3(BK_WG), 0, s, G, F, T, bs, nb, h, 2 * h, h, 0);
+    hipLaunchKernelGGL(k_bcr_back_x, dim3(nt, nodd), dim3(BK_WG), 0, s, LI, T, F, bs, h, 2 * h);
   }
   hipLaunchKernelGGL(k_bcr_copy_out, dim3((p.n + 255) / 256), dim3(256), 0, s, F, p.n, y);
   FE2_HIP_CHECK(hipGetLastError());
