@@ -124,6 +124,8 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
       double a[BT];
 #pragma unroll
       for (int c = 0; c < BT; ++c) a[c] = (r < BT && c <= r) ? Tpp[c * ld + r] : 0.0;
+      // Entries above the diagonal (c > r) are updated too and never read:
+      // one FMA per entry and step, no per-lane selects.
       bool bad = false;
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
@@ -143,15 +145,11 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
           break;
         }
         const double inv_sd = rsqrt(d);
-        const double sd = d * inv_sd;
         if (r == c) s_rd[c] = inv_sd;
-        const double lrc = a[c] * inv_sd;
-        a[c] = (r == c) ? sd : (r > c ? lrc : a[c]);
+        const double t = a[c] * (inv_sd * inv_sd);   // A_rc / d
 #pragma unroll
-        for (int cc = c + 1; cc < BT; ++cc) {
-          const double upd = fma(-lrc, col[cc] * inv_sd, a[cc]);
-          a[cc] = (r >= cc) ? upd : a[cc];
-        }
+        for (int cc = c + 1; cc < BT; ++cc) a[cc] = fma(-t, col[cc], a[cc]);
+        a[c] = (r == c) ? d * inv_sd : a[c] * inv_sd;
       }
       if (!bad) {
         if (r < BT) {
@@ -162,26 +160,29 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
           }
         }
         wave_sync();
-        // lane r < 16 solves L x = e_r: column r of the inverse
+        // lane r < 16 solves L x = e_r (column r of the inverse), column by
+        // column so that the updates of one step are independent
         if (r < BT) {
           double x[BT];
 #pragma unroll
-          for (int i = 0; i < BT; ++i) {
-            double acc = (i == r) ? 1.0 : 0.0;
+          for (int i = 0; i < BT; ++i) x[i] = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-            for (int k = 0; k < i; ++k) acc = fma(-s_ex[i * (BT + 1) + k], x[k], acc);
-            x[i] = (i >= r) ? acc * s_rd[i] : 0.0;
+          for (int k = 0; k < BT; ++k) {
+            x[k] *= s_rd[k];
+#pragma unroll
+            for (int i = k + 1; i < BT; ++i) x[i] = fma(-s_ex[i * (BT + 1) + k], x[k], x[i]);
           }
 #pragma unroll
-          for (int i = 0; i < BT; ++i) {
-            s_inv[r * BT + i] = x[i];
-            Ij[p * BT * BT + r * BT + i] = x[i];
-          }
+          for (int i = 0; i < BT; ++i) s_inv[r * BT + i] = (i >= r) ? x[i] : 0.0;
         }
       }
     }
     __syncthreads();
     if (*s_fail) return false;
+    // the inverse tile goes out after the barrier (its stores complete
+    // during the panel phase instead of delaying wave 0)
+    static_assert(PO_WG >= BT * BT, "one inverse entry per thread");
+    if (tid < BT * BT) Ij[p * BT * BT + tid] = s_inv[tid];
     // panel below: L_ip = A_ip invL_pp^T, one row per thread
     const int rows = (nt - p - 1) * BT;
     for (int t = tid; t < rows; t += PO_WG) {
@@ -196,7 +197,7 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
 #pragma unroll
         for (int k = 0; k <= c; ++k) l = fma(a[k], s_inv[k * BT + c], l);
         Tip[c * ld + rr] = l;
-        s_panel[t * BT + c] = l;
+        s_panel[t * (BT + 1) + c] = l;
       }
     }
     __syncthreads();
@@ -214,8 +215,8 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
         double pi[4], pj[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          pi[x] = s_panel[(lr + x) * BT + c];
-          pj[x] = s_panel[(lc + x) * BT + c];
+          pi[x] = s_panel[(lr + x) * (BT + 1) + c];
+          pj[x] = s_panel[(lc + x) * (BT + 1) + c];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -234,7 +235,7 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
 }
 
 // LDS bytes of the two variants
-__host__ __device__ constexpr size_t potrf_lds_global(int bs) { return static_cast<size_t>(bs) * BT * 8; }
+__host__ __device__ constexpr size_t potrf_lds_global(int bs) { return static_cast<size_t>(bs) * (BT + 1) * 8; }
 __host__ __device__ constexpr size_t potrf_lds_resident(int bs) {
   return potrf_lds_global(bs) + static_cast<size_t>((bs / BT) * (bs / BT + 1) / 2) * BT * BT * 8;
 }
@@ -252,10 +253,10 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   double* Dj = D + static_cast<size_t>(j) * bs * bs;
   double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
   const int tid = threadIdx.x;
-  double* s_panel = smem;   // [bs][BT]
+  double* s_panel = smem;   // [bs][BT + 1] (padded rows)
   if (tid == 0) s_fail = 0;
   if constexpr (RESIDENT) {
-    double* s_tiles = smem + bs * BT;
+    double* s_tiles = smem + bs * (BT + 1);
     const int ntri = nt * (nt + 1) / 2;
     const int c = tid >> 4, r = tid & 15;   // one element of a tile per thread
     {
