@@ -40,11 +40,15 @@ __device__ __forceinline__ void put_halo(V* f, int i, int j, V v) {
 }
 
 // Work-group sum with two alternating reduction buffers (one barrier each).
-template <int NV, int NW>
+// Each buffer holds NW * MAXNV doubles at a fixed offset, so a reduction of
+// any width never overlaps the buffer that the previous one is still being
+// read from (s_red: 2 * NW * MAXNV doubles).
+template <int NV, int NW, int MAXNV>
 __device__ __forceinline__ void wg_sum(double (&v)[NV], double* s_red, int& parity) {
+  static_assert(NV <= MAXNV, "reduction wider than its buffer");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  double* buf = s_red + parity * (NW * NV);
+  double* buf = s_red + parity * (NW * MAXNV);
   parity ^= 1;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -80,26 +84,27 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
   return v;
 }
 
-// Work-group sum of FP32 per-lane partials: wave totals in FP32 (DPP), the
-// cross-wave sum in FP64 through LDS (one barrier, alternating buffers as
-// wg_sum).  Every thread receives the totals.
-template <int NV, int NW>
-__device__ __forceinline__ void wg_sum_f(const float (&v)[NV], double (&out)[NV], double* s_red, int& parity) {
+// Work-group sum of FP32 per-lane partials: wave totals by DPP, the
+// cross-wave sum in FP32 (the totals feed FP32 scalar recurrences).  Buffers
+// as wg_sum.
+template <int NV, int NW, int MAXNV>
+__device__ __forceinline__ void wg_sum_f32(const float (&v)[NV], float (&out)[NV], double* s_red, int& parity) {
+  static_assert(NV <= MAXNV, "reduction wider than its buffer");
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  double* buf = s_red + parity * (NW * NV);
+  float* buf = reinterpret_cast<float*>(s_red + parity * (NW * MAXNV));
   parity ^= 1;
   float w[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) w[i] = wave_sum_to_last(v[i]);
   if (lane == 63) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = static_cast<double>(w[i]);
+    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = w[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    double t = 0.0;
+    float t = 0.0f;
 #pragma unroll
     for (int k = 0; k < NW; ++k) t += buf[k * NV + i];
     out[i] = t;

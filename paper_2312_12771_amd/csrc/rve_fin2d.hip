@@ -130,8 +130,9 @@ struct Phase {
 // LDS layout: reduction buffers | phase ids | w in TI (padded) |
 // union { FP64 element forces [8][NN],
 //         TI element forces [8][NN] + TI search direction (padded) [2][PN] }
+constexpr int RED_NV = 23;   // widest work-group reduction
 __host__ __device__ constexpr size_t fin2d_red_doubles(int nw, int nrhs) {
-  return 2 * static_cast<size_t>(nw) * 23;
+  return 2 * static_cast<size_t>(nw) * RED_NV + 0 * nrhs;
 }
 __host__ __device__ constexpr size_t fin2d_pn(int n1, int n2) {
   return static_cast<size_t>(rve2d::pad_w(n1)) * rve2d::pad_w(n2);
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
         red[20] += rv * rv;
       }
     }
-    wg_sum<23, NW>(red, s_red, parity);
+    wg_sum<23, NW, RED_NV>(red, s_red, parity);
     rsize2 = red[22];
     if ((a.flags & RVE_ASSEMBLE) && tid == 0) {
 #pragma unroll
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
       for (int k = 0; k < NPT; ++k)
 #pragma unroll
         for (int d = 0; d < 2; ++d) red[0] += res[k][d] * res[k][d];
-      wg_sum<2, NW>(red, s_red, parity);
+      wg_sum<2, NW, RED_NV>(red, s_red, parity);
       if (bb < 0.0) {
         // Stopping test ||b - K x|| <= max(tol ||b||, 1e-14 S), S the size of
         // the element-level terms summed into b: a right-hand side that
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
           for (int k = 0; k < NPT; ++k)
 #pragma unroll
             for (int d = 0; d < 2; ++d) rb[0] += r0[k][d] * r0[k][d];
-          wg_sum<2, NW>(rb, s_red, parity);
+          wg_sum<2, NW, RED_NV>(rb, s_red, parity);
         }
         if (kc == NF) rb[1] += rsize2;
         bb = fmax(rb[0], 1e-28 / tol2 * rb[1]);
@@ -543,7 +544,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
             red2[0] += static_cast<double>(ri[k][d]) * static_cast<double>(pown[k][d]);
             red2[1] += static_cast<double>(ri[k][d]) * static_cast<double>(ri[k][d]);
           }
-        wg_sum<2, NW>(red2, s_red, parity);
+        wg_sum<2, NW, RED_NV>(red2, s_red, parity);
         rz = red2[0];
         r0 = red2[1];
       }
@@ -558,7 +559,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
         for (int k = 0; k < NPT; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) pq[0] += static_cast<double>(pown[k][d]) * static_cast<double>(q[k][d]);
-        wg_sum<1, NW>(pq, s_red, parity);
+        wg_sum<1, NW, RED_NV>(pq, s_red, parity);
         if (!(pq[0] > 0.0)) {   // breakdown: exact solution, or negative curvature
           indefinite = !(pq[0] == 0.0);
           break;
@@ -575,7 +576,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
             red2[0] += rv * static_cast<double>(dinv[k][d] * ri[k][d]);
             red2[1] += rv * rv;
           }
-        wg_sum<2, NW>(red2, s_red, parity);
+        wg_sum<2, NW, RED_NV>(red2, s_red, parity);
         if (red2[1] <= tin2 * r0 || !(red2[0] > 0.0)) break;
         const TI beta = static_cast<TI>(red2[0] / rz);
         rz = red2[0];
@@ -650,7 +651,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
       for (int i = 0; i < NF; ++i)
         g[NF + i] += Xb[i * flen + 2 * n] * res[k][0] + Xb[i * flen + 2 * n + 1] * res[k][1];
     }
-    wg_sum<2 * NF, NW>(g, s_red, parity);
+    wg_sum<2 * NF, NW, RED_NV>(g, s_red, parity);
     if (tid == 0) {
 #pragma unroll
       for (int i = 0; i < NF; ++i) {

@@ -140,8 +140,9 @@ __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const 
 
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
 // one search direction [2][PN] in TI aliased with the FP64 staging [2][PN].
+constexpr int RED_NV = 2 * NF > 5 ? 2 * NF : 5;   // widest work-group reduction
 __host__ __device__ constexpr size_t lin2d_red_doubles(int nw, int nrhs) {
-  return 2 * static_cast<size_t>(nw) * (2 * NF > 5 ? 2 * NF : 5) + 0 * nrhs;
+  return 2 * static_cast<size_t>(nw) * RED_NV + 0 * nrhs;
 }
 __host__ __device__ constexpr size_t lin2d_vec_offset(int n1, int n2, int wg, int nrhs) {
   return ((lin2d_red_doubles(wg / 64, nrhs) * 8 + static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 12) + 15) &
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         for (int j = 0; j < NF; ++j) red[1 + j] += bF_entry<N1, N2>(eb, KwF, di, dj, d, j) * wv;
       }
     }
-    wg_sum<5, NW>(red, s_red, parity);
+    wg_sum<5, NW, RED_NV>(red, s_red, parity);
     ssum = red[4];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     }
   } else {
     double red[1] = {ssum};
-    wg_sum<1, NW>(red, s_red, parity);
+    wg_sum<1, NW, RED_NV>(red, s_red, parity);
     ssum = red[0];
 #pragma unroll
     for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
           ri[k][d] = static_cast<TI>(r64);
         }
       }
-      wg_sum<2, NW>(red, s_red, parity);
+      wg_sum<2, NW, RED_NV>(red, s_red, parity);
       const double rel = red[1] > 0.0 ? sqrt(red[0] / red[1]) : 0.0;
       if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
         worst = rel > worst ? rel : worst;
@@ -380,9 +381,14 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       }
       // ---- inner PCG on K d = r (precision TI, Jacobi preconditioner) -----
       // Chronopoulos-Gear form of CG: u = M^-1 r and w = K u are formed
-      // every iteration and the three inner products (r.u, w.u, r.r) go
-      // through one fused work-group reduction; p and s = K p follow by
-      // recurrence.  Two barriers per iteration (u visible, reduction).
+      // every iteration and both inner products (r.u, w.u) go through one
+      // fused work-group reduction; p and s = K p follow by recurrence, with
+      // den_i = (w.u)_i - beta_i^2 den_{i-1} (= gamma_i / alpha_i).  Two
+      // barriers per iteration (u visible, reduction).  Scalars are kept in
+      // TI.  The pinned node has M^-1 = 0, so its u, p and x stay zero and
+      // its residual entry (which is left to drift) never enters r.u or w.u;
+      // nodes of a block beyond the grid (odd sizes) get w = 0.  Convergence
+      // is measured in the M^-1 norm, r.u <= tol_in^2 (r.u)_0.
       __syncthreads();   // staging reads finished before s_p is written
       TI xi[4][2], uv[4][2], pv[4][2], sv[4][2];
 #pragma unroll
@@ -393,55 +399,56 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
           uv[k][d] = dinv[k][d] * ri[k][d];
           if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
         }
-      double r0 = 0.0, gam_old = 1.0, alpha_old = 1.0;
+      const TI tinI = static_cast<TI>(tin2);
+      TI gam0 = TI(0), gam_old = TI(1), den_old = TI(1);
 #pragma unroll 1
       for (int it = 0; it < a.max_it; ++it) {
         __syncthreads();   // u visible
         TI wv[4][2];
         mv_block<N1, N2, TI>(s_p + base, ebI, kvI, wv);
-        TI pg = TI(0), pd = TI(0), pr = TI(0);
+        if constexpr ((N1 & 1) || (N2 & 1)) {   // blocks reaching past the grid: keep s, r finite there
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+              if (!exists[k]) wv[k][d] = TI(0);
+        }
+        TI red[2] = {TI(0), TI(0)};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            if (!dof[k]) wv[k][d] = TI(0);
-            pg = fma(ri[k][d], uv[k][d], pg);
-            pd = fma(wv[k][d], uv[k][d], pd);
-            pr = fma(ri[k][d], ri[k][d], pr);
+            red[0] = fma(ri[k][d], uv[k][d], red[0]);
+            red[1] = fma(wv[k][d], uv[k][d], red[1]);
           }
-        double red3[3];
         if constexpr (sizeof(TI) == 4) {
-          const float v3[3] = {pg, pd, pr};
-          wg_sum_f<3, NW>(v3, red3, s_red, parity);
+          const float v2[2] = {red[0], red[1]};
+          wg_sum_f32<2, NW, RED_NV>(v2, red, s_red, parity);
         } else {
-          red3[0] = pg;
-          red3[1] = pd;
-          red3[2] = pr;
-          wg_sum<3, NW>(red3, s_red, parity);
+          wg_sum<2, NW, RED_NV>(red, s_red, parity);
         }
-        const double gam = red3[0], del = red3[1], rr = red3[2];
-        if (it == 0) r0 = rr;
-        if (rr <= tin2 * r0 || !(gam > 0.0)) break;
-        const double beta = (it == 0) ? 0.0 : gam / gam_old;
-        const double den = (it == 0) ? del : del - beta * gam / alpha_old;
-        if (!(den > 0.0)) break;   // breakdown (exact solution or loss of definiteness)
-        const double alpha = gam / den;
+        const TI gam = red[0], del = red[1];
+        if (it == 0) gam0 = gam;
+        if (!(gam > tinI * gam0) || !(gam > TI(0))) break;
+        const TI beta = (it == 0) ? TI(0) : gam / gam_old;
+        const TI den = del - beta * beta * den_old;
+        if (!(den > TI(0))) break;   // breakdown (exact solution or loss of definiteness)
+        const TI alpha = gam / den;
         ++iters;
-        const TI aI = static_cast<TI>(alpha), bI = static_cast<TI>(beta);
         // every read of s_p in this iteration precedes the reduction's barrier
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            pv[k][d] = fma(bI, pv[k][d], uv[k][d]);
-            sv[k][d] = fma(bI, sv[k][d], wv[k][d]);
-            xi[k][d] = fma(aI, pv[k][d], xi[k][d]);
-            ri[k][d] = fma(-aI, sv[k][d], ri[k][d]);
+            pv[k][d] = fma(beta, pv[k][d], uv[k][d]);
+            sv[k][d] = fma(beta, sv[k][d], wv[k][d]);
+            xi[k][d] = fma(alpha, pv[k][d], xi[k][d]);
+            ri[k][d] = fma(-alpha, sv[k][d], ri[k][d]);
             uv[k][d] = dinv[k][d] * ri[k][d];
             if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
           }
         gam_old = gam;
-        alpha_old = alpha;
+        den_old = den;
       }
       // x64 += x_inner (FP64 accumulation in the output column)
 #pragma unroll
@@ -504,7 +511,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         }
       }
     }
-    wg_sum<2 * NF, NW>(g, s_red, parity);
+    wg_sum<2 * NF, NW, RED_NV>(g, s_red, parity);
     if (tid == 0) {
       if (jc < NF) {
 #pragma unroll

@@ -197,7 +197,8 @@ __device__ __forceinline__ BFNode bf_node(const uint8_t* __restrict__ eb, double
 
 // LDS layout: reduction buffers | phase ids with halo [PN] |
 // search direction [3][PN] in TI aliased with the FP64 staging [3][PN].
-__host__ __device__ constexpr size_t lin3d_red_doubles(int nw) { return 2 * static_cast<size_t>(nw) * 12; }
+constexpr int RED_NV = 12;   // widest work-group reduction
+__host__ __device__ constexpr size_t lin3d_red_doubles(int nw) { return 2 * static_cast<size_t>(nw) * RED_NV; }
 __host__ __device__ constexpr size_t lin3d_vec_offset(int n, int wg) {
   return (lin3d_red_doubles(wg / 64) * 8 + static_cast<size_t>(n + 2) * (n + 2) * (n + 2) + 15) &
          ~static_cast<size_t>(15);
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
         for (int j = 0; j < NF; ++j) red[1 + j] += bf(d, j, rho, h2q) * wv;
       }
     }
-    wg_sum<8, NW>(red, s_red, parity);
+    wg_sum<8, NW, RED_NV>(red, s_red, parity);
     ssum = red[7];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
   } else {
     double red[1] = {ssum};
     __syncthreads();   // phase halo complete
-    wg_sum<1, NW>(red, s_red, parity);
+    wg_sum<1, NW, RED_NV>(red, s_red, parity);
     ssum = red[0];
 #pragma unroll
     for (int i = 0; i < NF; ++i) Pint[i] = a.Pbar[static_cast<size_t>(b) * NF + i] * V;
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
         }
       }
       if (!xzero) ++nmv64;
-      wg_sum<2, NW>(red, s_red, parity);
+      wg_sum<2, NW, RED_NV>(red, s_red, parity);
       const double rel = red[1] > 0.0 ? sqrt(red[0] / red[1]) : 0.0;
       if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
         worst = rel > worst ? rel : worst;
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
             red2[0] += static_cast<double>(ri[kk][d]) * static_cast<double>(pown[kk][d]);
             red2[1] += static_cast<double>(ri[kk][d]) * static_cast<double>(ri[kk][d]);
           }
-        wg_sum<2, NW>(red2, s_red, parity);
+        wg_sum<2, NW, RED_NV>(red2, s_red, parity);
         rz = red2[0];
         r0 = red2[1];
       }
@@ -451,7 +452,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
         for (int kk = 0; kk < NPT; ++kk)
 #pragma unroll
           for (int d = 0; d < 3; ++d) pq[0] += static_cast<double>(pown[kk][d]) * static_cast<double>(q[kk][d]);
-        wg_sum<1, NW>(pq, s_red, parity);
+        wg_sum<1, NW, RED_NV>(pq, s_red, parity);
         if (!(pq[0] > 0.0)) break;   // breakdown (exact solution)
         const TI alpha = static_cast<TI>(rz / pq[0]);
         double red2[2] = {0.0, 0.0};
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
             red2[0] += rv * static_cast<double>(dinv[kk] * ri[kk][d]);
             red2[1] += rv * rv;
           }
-        wg_sum<2, NW>(red2, s_red, parity);
+        wg_sum<2, NW, RED_NV>(red2, s_red, parity);
         if (red2[1] <= tin2 * r0 || !(red2[0] > 0.0)) break;
         const TI beta = static_cast<TI>(red2[0] / rz);
         rz = red2[0];
@@ -539,7 +540,7 @@ __global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
         }
       }
     }
-    wg_sum<2 * NF, NW>(g, s_red, parity);
+    wg_sum<2 * NF, NW, RED_NV>(g, s_red, parity);
     if (tid == 0) {
       if (jc < NF) {
 #pragma unroll
