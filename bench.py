@@ -17,6 +17,11 @@ update), preceded by a device-to-device reset of the state.  Two forms run:
   * fp64:  the same solver in FP64 throughout, rve_tol 1e-7 (Cbar <= 1e-10).
 value = RVE solves/s of the mixed form (RVEs / GPU time of a2-a6, HIP
 events on the stream), ms_per_step = wall time of one macro Newton step.
+
+--workload selects another configuration for the same measurement (the
+default is the 2D workload above): cfg3 (uneven 16/32/48 batch on a 128x128
+macro mesh), cfg4 (3D hex8) or cfg5 (finite-strain Neo-Hooke, first Newton
+iteration of the first load increment).
 """
 from __future__ import annotations
 
@@ -34,11 +39,30 @@ sys.path.insert(0, ROOT)
 METRIC = "RVE solves/sec + macro Newton step time at 1e-6 C̄ error vs plain FP64"
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 HBM_PEAK_GBS = 8000.0
-# algorithmic cost per RVE DOF and right-hand side:
-#   one PCG iteration: 64 flop operator (32 FMA, 2D Q4) + 13 flop vector ops
-#   one FP64 operator application (refinement residual / condensation): 66
-FLOP_PCG_ITER_DOF = 77.0
-FLOP_MV64_DOF = 66.0
+# algorithmic cost per RVE DOF and right-hand side, by (dim, kinematics):
+#   one PCG iteration = operator + 13 flop of vector work; one FP64 operator
+#   application (refinement residual / condensation) = operator + 2.
+#   2D Q4 small strain: 64 flop operator (32 FMA per DOF);
+#   3D hex8 small strain: 384 flop operator (192 FMA per DOF);
+#   2D Q4 finite strain: about 260 flop per element and operator application
+#   (tangent rebuilt at 4 Gauss points) = 130 per DOF.
+FLOP_OPERATOR_DOF = {(2, "small"): 64.0, (3, "small"): 384.0, (2, "finite"): 130.0}
+
+WORKLOADS = {
+    "cfg2": dict(desc="2D plane-strain linear, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 centred circle vf 0.3, "
+                      "E ratio lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3",
+                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+    "cfg3": dict(desc="2D plane-strain linear uneven batch, macro 128x128 Q4 (65536 RVEs), RVE 16x16/32x32/48x48 Q4 "
+                      "by Voronoi region, circle radius U[0.1,0.35], E ratio U[5,50] per macro element, uniaxial 1e-3",
+                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+    "cfg4": dict(desc="3D linear, macro 8x8x8 hex8 (4096 RVEs), RVE 10x10x10 hex8 centred sphere vf 0.2, "
+                      "E ratio 10, nu 0.3, uniaxial 1e-3",
+                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+    "cfg5": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
+                      "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; first Newton iteration of the first of ten "
+                      "load increments (u_x = 0.01)",
+                 lam=0.1, tol=dict(mixed=1e-4, fp64=1e-7)),
+}
 
 
 def measured_traffic():
@@ -62,7 +86,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
+def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
     h = fe2.fe2_setup(p, precision=precision, rve_tol=rve_tol, inner_tol=1e-5)
     ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
     flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
@@ -71,7 +95,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
 
     def step():
         fe2.fe2_set_state(h, zu, zw, 0.0)
-        st, _ = fe2.fe2_newton_step(h, 1.0)
+        st, _ = fe2.fe2_newton_step(h, lam)
         assert st == fe2.FE2_OK
 
     for _ in range(warmup):
@@ -86,7 +110,8 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
     prof = fe2.fe2_get_profile(h)
     fe2.fe2_set_profiling(h, False)
     n = p.n_rve
-    cbar = torch.zeros(n * 9, dtype=torch.float64, device="cuda")
+    nF = fe2.fe2_query(h, fe2.FE2_Q_NF)
+    cbar = torch.zeros(n * nF * nF, dtype=torch.float64, device="cuda")
     fe2.fe2_get_data(h, fe2.FE2_D_CBAR, cbar)
     iters = torch.zeros(n, dtype=torch.float64, device="cuda")
     fe2.fe2_get_data(h, fe2.FE2_D_RVE_ITERS, iters)
@@ -100,7 +125,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
     torch.cuda.synchronize()
     ts = time.perf_counter()
     hist = []
-    fe2.solve(h, [1.0], history=hist)
+    fe2.solve(h, [lam], history=hist)
     torch.cuda.synchronize()
     solve_ms = (time.perf_counter() - ts) * 1e3
     u = torch.zeros(ndof, dtype=torch.float64, device="cuda")
@@ -111,10 +136,10 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup):
         gpu_ms=dict(assemble_norms=prof[0] / steps, rve_solve=prof[1] / steps,
                     macro_assemble_solve=prof[2] / steps, update=prof[3] / steps,
                     step=prof[4] / steps),
-        cbar=cbar.cpu().numpy().reshape(n, 3, 3),
+        cbar=cbar.cpu().numpy().reshape(n, nF, nF),
         iters=iters.cpu().numpy(), mv64=mv64.cpu().numpy(), relres=relres.cpu().numpy(),
         newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(),
-        n_dof_rve=2 * np.prod(p.rve_res, axis=1) - 2)
+        n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim)
     h.close()
     return out
 
@@ -125,12 +150,13 @@ def cpu_baseline(p, seconds):
     from threadpoolctl import threadpool_limits
     from oracle import rve as R
     cb = {}
+    nF = R.n_macro_components(p.dim, p.kinematics)
     with threadpool_limits(limits=1):
-        R.homogenize_rve(p, 0, np.zeros(3))   # import/JIT warm-up outside the clock
+        R.homogenize_rve(p, 0, np.zeros(nF))   # import/JIT warm-up outside the clock
         t0 = time.perf_counter()
         b = 0
         while b < p.n_rve and (time.perf_counter() - t0 < seconds or b < 8):
-            cb[b] = R.homogenize_rve(p, b, np.zeros(3)).C
+            cb[b] = R.homogenize_rve(p, b, np.zeros(nF)).C
             b += 1
         el = time.perf_counter() - t0
     return dict(value=len(cb) / el, n=len(cb), seconds=el, cbar=cb)
@@ -148,6 +174,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS),
+                    help="configuration to time (default: the 2D benchmark workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -163,8 +191,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    p = W.config("cfg2")
-    log(f"workload built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
+    wl = WORKLOADS[args.workload]
+    p = W.config(args.workload)
+    log(f"workload {args.workload} built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -177,10 +206,10 @@ def main():
 
     forms = {}
     if "fp64" in args.forms:
-        forms["fp64"] = run_form(fe2, torch, p, "fp64", 1e-7, args.steps, args.warmup)
+        forms["fp64"] = run_form(fe2, torch, p, "fp64", wl["tol"]["fp64"], args.steps, args.warmup, wl["lam"])
         log("fp64", forms["fp64"]["gpu_ms"], "wall", forms["fp64"]["wall_ms_per_step"])
     if "mixed" in args.forms:
-        forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", 1e-4, args.steps, args.warmup)
+        forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], args.steps, args.warmup, wl["lam"])
         log("mixed", forms["mixed"]["gpu_ms"], "wall", forms["mixed"]["wall_ms_per_step"])
     head = forms.get("mixed") or forms["fp64"]
     head_dtype = "f32" if "mixed" in forms else "f64"
@@ -190,12 +219,16 @@ def main():
 
     # roofline of the dominant kernel: the RVE solve launch (one per step)
     k_ms = head["gpu_ms"]["rve_solve"]
-    flops = float(np.sum(head["iters"] * head["n_dof_rve"]) * FLOP_PCG_ITER_DOF
-                  + np.sum(head["mv64"] * head["n_dof_rve"]) * FLOP_MV64_DOF)
+    op = FLOP_OPERATOR_DOF[(p.dim, p.kinematics)]
+    flops = float(np.sum(head["iters"] * head["n_dof_rve"]) * (op + 13.0)
+                  + np.sum(head["mv64"] * head["n_dof_rve"]) * (op + 2.0))
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_TFLOPS[head_dtype],
-                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4), traffic=measured_traffic(),
-                kernel="k_lin2d (RVE solve + condensation)", kernel_ms=round(k_ms, 4),
+                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4),
+                traffic=measured_traffic() if args.workload == "cfg2" else None,
+                kernel={(2, "small"): "k_lin2d", (3, "small"): "k_lin3d", (2, "finite"): "k_fin2d"}[
+                    (p.dim, p.kinematics)] + " (RVE solve + condensation, all launches of the step)",
+                kernel_ms=round(k_ms, 4),
                 flop_per_launch=flops, pcg_iters_per_rve=float(np.mean(head["iters"])))
 
     acc = {}
@@ -226,10 +259,9 @@ def main():
         "vs_baseline": None,
         "dtype": head_dtype + "+f64" if head_dtype == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "2D plane-strain linear, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 "
-                               "centred circle vf 0.3, E ratio lognormal(ln 10, 0.5) per macro element, "
-                               "nu 0.3, uniaxial 1e-3",
-                   "n_rve": p.n_rve, "rve": "32x32", "macro_dofs": p.n_dofs,
+        "config": {"workload": wl["desc"], "name": args.workload,
+                   "n_rve": p.n_rve, "rve": sorted({"x".join(map(str, r)) for r in p.rve_res.tolist()}),
+                   "macro_dofs": p.n_dofs,
                    "step": "one monolithic Newton iteration (a2-a10) from the reference state",
                    "parallelism": "single GPU"},
         "roofline": roof,
