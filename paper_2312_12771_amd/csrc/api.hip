@@ -46,7 +46,7 @@ struct RveClass {
   double rho = 0.0;
   std::vector<int> rves;
   int* d_list = nullptr;
-  double* d_tab = nullptr;   // kv[10] | KwF[24] | KFF[9] | err
+  double* d_tab = nullptr;   // 2D: kv[10] | KwF[24] | KFF[9] | err | modes[10]
 };
 
 }  // namespace
@@ -180,6 +180,7 @@ struct fe2_ctx {
     a.kv64 = c.d_tab;
     a.KwF64 = c.d_tab + 10;
     a.KFF64 = c.d_tab + (dim == 3 ? 154 : 34);
+    a.modes64 = dim == 3 ? nullptr : c.d_tab + 44;
     a.macro = mgrad;
     a.foff = foff;
     a.w = w;
@@ -522,7 +523,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
       continue;
     }
-    if ((rc = dalloc(&c.d_tab, 44))) return rc;
+    if ((rc = dalloc(&c.d_tab, REF2_TABLE))) return rc;
     hipLaunchKernelGGL(k_ref_tables_2d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, h->rve_size / c.n2, c.rho,
                        c.d_tab);
     FE2_HIP_CHECK(hipGetLastError());

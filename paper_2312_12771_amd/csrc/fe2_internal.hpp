@@ -86,6 +86,7 @@ struct Lin2DArgs {
   const double* kv64;           // [10] distinct entries of the element stiffness, mu = 1
   const double* KwF64;          // [8*3] element coupling, mu = 1
   const double* KFF64;          // [9] element integral of C, mu = 1
+  const double* modes64;        // [10] mode constants of the element stiffness, mu = 1
   const double* macro;          // [n_rve][3] macro strain
   const int64_t* foff;          // [n_rve+1] field offsets (doubles)
   const double* w;              // state fluctuation (periodic numbering)

@@ -66,13 +66,73 @@ __global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out) {
       err = fmax(err, fabs(v - kv[id]));
       scale = fmax(scale, fabs(K[r][c]));
     }
-  // layout: kv[10] | KwF[24] | KFF[9] | consistency error
+  // Mode constants: for a box element the bilinear strain energy separates
+  // into the projections of (u_x, u_y) on the corner patterns bx = (-1,1,1,-1),
+  // by = (-1,-1,1,1) and g = (1,-1,1,-1): with X1 = bx.ux, Y2 = by.uy,
+  // Sx = by.ux, Sy = bx.uy, Hx = g.ux, Hy = g.uy,
+  //   G1 = k0 X1 + k1 Y2, G2 = k2 X1 + k3 Y2, G3 = k4 Sx + k5 Sy,
+  //   G4 = k6 Sx + k7 Sy, G5 = k8 Hx, G6 = k9 Hy,
+  //   f_x = bx G1 + by G3 + g G5,  f_y = bx G4 + by G2 + g G6.
+  // Each constant is read off K applied to one pure pattern (a pattern has
+  // squared norm 4 and is orthogonal to the others).
+  const double pat[3][4] = {{-1, 1, 1, -1}, {-1, -1, 1, 1}, {1, -1, 1, -1}};   // bx, by, g
+  auto apply = [&](int comp, int p, double f[8]) {   // f = K u, u_comp = pattern p
+    for (int r = 0; r < 8; ++r) {
+      f[r] = 0.0;
+      for (int a = 0; a < 4; ++a) f[r] += K[r][2 * a + comp] * pat[p][a];
+    }
+  };
+  auto proj = [&](const double f[8], int comp, int p) {
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a) v += pat[p][a] * f[2 * a + comp];
+    return v / 16.0;
+  };
+  double km[10], f[8];
+  apply(0, 0, f);   // ux = bx: X1 = 4
+  km[0] = proj(f, 0, 0);
+  km[2] = proj(f, 1, 1);
+  apply(1, 1, f);   // uy = by: Y2 = 4
+  km[1] = proj(f, 0, 0);
+  km[3] = proj(f, 1, 1);
+  apply(0, 1, f);   // ux = by: Sx = 4
+  km[4] = proj(f, 0, 1);
+  km[6] = proj(f, 1, 0);
+  apply(1, 0, f);   // uy = bx: Sy = 4
+  km[5] = proj(f, 0, 1);
+  km[7] = proj(f, 1, 0);
+  apply(0, 2, f);   // ux = g: Hx = 4
+  km[8] = proj(f, 0, 2);
+  apply(1, 2, f);   // uy = g: Hy = 4
+  km[9] = proj(f, 1, 2);
+  // the mode form must reproduce every column of K
+  for (int c = 0; c < 8; ++c) {
+    double ux[4] = {}, uy[4] = {};
+    (c & 1 ? uy : ux)[c / 2] = 1.0;
+    double P[2][3];   // projections of ux, uy on bx, by, g
+    for (int p = 0; p < 3; ++p) {
+      P[0][p] = P[1][p] = 0.0;
+      for (int a = 0; a < 4; ++a) {
+        P[0][p] += pat[p][a] * ux[a];
+        P[1][p] += pat[p][a] * uy[a];
+      }
+    }
+    const double G1 = km[0] * P[0][0] + km[1] * P[1][1], G2 = km[2] * P[0][0] + km[3] * P[1][1];
+    const double G3 = km[4] * P[0][1] + km[5] * P[1][0], G4 = km[6] * P[0][1] + km[7] * P[1][0];
+    const double G5 = km[8] * P[0][2], G6 = km[9] * P[1][2];
+    for (int a = 0; a < 4; ++a) {
+      const double fx = pat[0][a] * G1 + pat[1][a] * G3 + pat[2][a] * G5;
+      const double fy = pat[0][a] * G4 + pat[1][a] * G2 + pat[2][a] * G6;
+      err = fmax(err, fmax(fabs(fx - K[2 * a][c]), fabs(fy - K[2 * a + 1][c])));
+    }
+  }
+  // layout: kv[10] | KwF[24] | KFF[9] | consistency error | mode constants[10]
   for (int t = 0; t < 10; ++t) out[t] = kv[t];
   for (int r = 0; r < 8; ++r)
     for (int j = 0; j < 3; ++j) out[10 + 3 * r + j] = KwF[r][j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) out[34 + 3 * i + j] = KFF[i][j];
   out[43] = err / scale;
+  for (int t = 0; t < 10; ++t) out[44 + t] = km[t];
 }
 
 // Reference tables of the hex8 box element (cube of side h, lambda = rho,

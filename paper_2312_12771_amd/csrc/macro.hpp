@@ -25,6 +25,7 @@ struct MacroArgs {
 };
 
 __global__ void k_ref_tables_2d(double h1, double h2, double rho, double* out);
+constexpr int REF2_TABLE = 54;    // kv[10] | KwF[8*3] | KFF[9] | error | mode constants[10]
 __global__ void k_ref_tables_3d(double h, double rho, double* out);
 constexpr int REF3_TABLE = 191;   // kv[10] | KwF[24*6] | KFF[36] | error
 __global__ void k_macro_geometry(MacroArgs m);

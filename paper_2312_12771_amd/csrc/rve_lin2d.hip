@@ -89,6 +89,127 @@ __device__ __forceinline__ void mv_block(const V* __restrict__ pb, const V* __re
   }
 }
 
+// Block-major vectors of the even-size operator: block (I, J) holds its
+// nodes (2I + a, 2J + c) at [4 * (J * NB1 + I) + a + 2c], one array per
+// component; periodic neighbours are plain block indices, no halo.
+template <typename V>
+__device__ __forceinline__ void ld4(const V* p, V (&o)[4]) {
+  if constexpr (sizeof(V) == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x, o[1] = t.y, o[2] = t.z, o[3] = t.w;
+  } else {
+    const double2 t0 = reinterpret_cast<const double2*>(p)[0], t1 = reinterpret_cast<const double2*>(p)[1];
+    o[0] = t0.x, o[1] = t0.y, o[2] = t1.x, o[3] = t1.y;
+  }
+}
+template <typename V>
+__device__ __forceinline__ void st4(V* p, V a0, V a1, V a2, V a3) {
+  if constexpr (sizeof(V) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
+  } else {
+    reinterpret_cast<double2*>(p)[0] = make_double2(a0, a1);
+    reinterpret_cast<double2*>(p)[1] = make_double2(a2, a3);
+  }
+}
+
+// y = K v at the four owned nodes (even sizes), element by element through
+// the mode form of the box-element stiffness: per element the projections of
+// (v_x, v_y) on the corner patterns bx, by, g (from the edge differences of
+// the patch) give six generalized forces G1..G6 (mode constants mc, element
+// scale m), which go back to the corners as f_x = bx G1 + by G3 + g G5,
+// f_y = bx G4 + by G2 + g G6.  The thread's 2x2 elements cover its 3x3 node
+// patch; the partial sums of the five patch nodes owned by the right, top
+// and diagonal neighbours pass through LDS (three lane-contiguous quad slots
+// [3][WG][4], one barrier).  vb: block-major vector (component x, y at
+// +NBT*4); es: padded scale of element (i0, j0); blk/br/bt/bd: own, right,
+// top and top-right blocks; tl, tb, td: threads owning the blocks to the
+// left, below and below-left.
+template <int N1, int N2, int WG, typename V>
+__device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V* __restrict__ es, const V (&mc)[10],
+                                         V* __restrict__ sx, int blk, int br, int bt, int bd, int tid, int tl, int tb,
+                                         int td, V (&y)[4][2]) {
+  using P = Pad<N1, N2>;
+  constexpr int NBT = (N1 / 2) * (N2 / 2);
+  V ux[3][3], uy[3][3];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    V(&u)[3][3] = d ? uy : ux;
+    const V* v = vb + d * NBT * 4;
+    V q[4], r[4], t[4];
+    ld4(v + 4 * blk, q);
+    ld4(v + 4 * br, r);
+    ld4(v + 4 * bt, t);
+    u[0][0] = q[0], u[0][1] = q[1], u[1][0] = q[2], u[1][1] = q[3];
+    u[0][2] = r[0], u[1][2] = r[2];
+    u[2][0] = t[0], u[2][1] = t[1];
+    u[2][2] = v[4 * bd];
+  }
+  V hx[3][2], hy[3][2], vx[2][3], vy[2][3];   // horizontal / vertical edge differences
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      hx[c][a] = ux[c][a + 1] - ux[c][a];
+      hy[c][a] = uy[c][a + 1] - uy[c][a];
+    }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vx[c][a] = ux[c + 1][a] - ux[c][a];
+      vy[c][a] = uy[c + 1][a] - uy[c][a];
+    }
+  V fx[3][3], fy[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fx[c][a] = fy[c][a] = V(0);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const V m = es[c * P::PW + a];
+      const V mX = m * (hx[c][a] + hx[c + 1][a]);   // m bx.ux
+      const V mY = m * (vy[c][a] + vy[c][a + 1]);   // m by.uy
+      const V mSx = m * (vx[c][a] + vx[c][a + 1]);  // m by.ux
+      const V mSy = m * (hy[c][a] + hy[c + 1][a]);  // m bx.uy
+      const V G1 = fma(mc[0], mX, mc[1] * mY);
+      const V G2 = fma(mc[2], mX, mc[3] * mY);
+      const V G3 = fma(mc[4], mSx, mc[5] * mSy);
+      const V G4 = fma(mc[6], mSx, mc[7] * mSy);
+      const V G5 = mc[8] * (m * (hx[c + 1][a] - hx[c][a]));   // g.ux
+      const V G6 = mc[9] * (m * (vy[c][a + 1] - vy[c][a]));   // g.uy
+      const V P1 = G1 + G3, Q1 = G1 - G3, P2 = G4 + G2, Q2 = G4 - G2;
+      fx[c][a] += G5 - P1;
+      fx[c][a + 1] += Q1 - G5;
+      fx[c + 1][a + 1] += P1 + G5;
+      fx[c + 1][a] -= Q1 + G5;
+      fy[c][a] += G6 - P2;
+      fy[c][a + 1] += Q2 - G6;
+      fy[c + 1][a + 1] += P2 + G6;
+      fy[c + 1][a] -= Q2 + G6;
+    }
+  // slot 0: nodes (i0+2, j0), (i0+2, j0+1) -> right neighbour's (0, 0), (0, 1)
+  // slot 1: nodes (i0, j0+2), (i0+1, j0+2) -> top neighbour's (0, 0), (1, 0)
+  // slot 2: node (i0+2, j0+2)              -> diagonal neighbour's (0, 0)
+  st4(sx + 4 * (0 * WG + tid), fx[0][2], fy[0][2], fx[1][2], fy[1][2]);
+  st4(sx + 4 * (1 * WG + tid), fx[2][0], fy[2][0], fx[2][1], fy[2][1]);
+  st4(sx + 4 * (2 * WG + tid), fx[2][2], fy[2][2], V(0), V(0));
+  __syncthreads();
+  V gl[4], gb[4], gd[4];
+  ld4(sx + 4 * (0 * WG + tl), gl);
+  ld4(sx + 4 * (1 * WG + tb), gb);
+  ld4(sx + 4 * (2 * WG + td), gd);
+  y[0][0] = fx[0][0] + gl[0] + gb[0] + gd[0];
+  y[0][1] = fy[0][0] + gl[1] + gb[1] + gd[1];
+  y[1][0] = fx[0][1] + gb[2];
+  y[1][1] = fy[0][1] + gb[3];
+  y[2][0] = fx[1][0] + gl[2];
+  y[2][1] = fy[1][0] + gl[3];
+  y[3][0] = fx[1][1];
+  y[3][1] = fy[1][1];
+}
+
 // y = K v (FP64) at one owned node (di, dj) of the block, element by
 // element; used by the FP64 passes (residuals, assembly, condensation),
 // which run a few times per column.  The empty asm after each element
@@ -148,8 +269,13 @@ __host__ __device__ constexpr size_t lin2d_vec_offset(int n1, int n2, int wg, in
   return ((lin2d_red_doubles(wg / 64, nrhs) * 8 + static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 12) + 15) &
          ~static_cast<size_t>(15);
 }
-__host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs) {
+__host__ __device__ constexpr size_t lin2d_xch_offset(int n1, int n2, int wg, int nrhs) {
   return lin2d_vec_offset(n1, n2, wg, nrhs) + 2 * static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 8;
+}
+// exchange slots of the element-wise operator: [3][wg][4] in the inner precision
+__host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes) {
+  return lin2d_xch_offset(n1, n2, wg, nrhs) +
+         (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0);
 }
 
 template <typename TI, int NRHS, int N1, int N2, int WG>
@@ -170,6 +296,8 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   unsigned char* s_vec = smem + lin2d_vec_offset(N1, N2, WG, NRHS);
   TI* s_p = reinterpret_cast<TI*>(s_vec);          // [2][PN] search direction
   double* s_st = reinterpret_cast<double*>(s_vec);  // [2][PN] FP64 staging (aliases s_p)
+  TI* s_x = reinterpret_cast<TI*>(smem + lin2d_xch_offset(N1, N2, WG, NRHS));   // [3][WG][4] (even sizes)
+  constexpr bool EVEN = ((N1 | N2) & 1) == 0;
   int parity = 0;
 
   // ---- reference element scalars (uniform: scalar registers) -------------
@@ -181,6 +309,9 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     kvI[t] = static_cast<TI>(kv64[t]);
   }
   const double* KwF = a.KwF64;   // [8][NF], uniform
+  TI mcI[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) mcI[t] = EVEN ? static_cast<TI>(a.modes64[t]) : TI(0);
 
   // ---- ownership of a 2x2 node block -------------------------------------
   const bool own = tid < NB1 * NB2;
@@ -198,6 +329,11 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   }
   const int base = P::at(i0 - 1, j0 - 1);
   auto node_of = [&](int k) { return (j0 + (k >> 1)) * N1 + i0 + (k & 1); };
+  // threads owning the blocks to the left, below and below-left (periodic)
+  const int Il = (I + NB1 - 1) % NB1, Jb = (J + NB2 - 1) % NB2;
+  const int t_l = J * NB1 + Il, t_b = Jb * NB1 + I, t_d = Jb * NB1 + Il;
+  const int Ir = (I + 1) % NB1, Jt = (J + 1) % NB2;
+  const int b_own = J * NB1 + I, b_r = J * NB1 + Ir, b_t = Jt * NB1 + I, b_d = Jt * NB1 + Ir;
 
   // ---- element scales (mu of the phase), padded --------------------------
   const double* par = a.params + static_cast<size_t>(b) * 4;
@@ -384,7 +520,8 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       // every iteration and both inner products (r.u, w.u) go through one
       // fused work-group reduction; p and s = K p follow by recurrence, with
       // den_i = (w.u)_i - beta_i^2 den_{i-1} (= gamma_i / alpha_i).  Two
-      // barriers per iteration (u visible, reduction).  Scalars are kept in
+      // barriers per iteration (u visible, reduction; even sizes add the
+      // operator's exchange barrier).  Scalars are kept in
       // TI.  The pinned node has M^-1 = 0, so its u, p and x stay zero and
       // its residual entry (which is left to drift) never enters r.u or w.u;
       // nodes of a block beyond the grid (odd sizes) get w = 0.  Convergence
@@ -397,18 +534,25 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         for (int d = 0; d < 2; ++d) {
           xi[k][d] = pv[k][d] = sv[k][d] = TI(0);
           uv[k][d] = dinv[k][d] * ri[k][d];
-          if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
+          if constexpr (!EVEN)
+            if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
         }
+      if constexpr (EVEN)
+        if (own)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, uv[0][d], uv[1][d], uv[2][d], uv[3][d]);
       const TI tinI = static_cast<TI>(tin2);
       TI gam0 = TI(0), gam_old = TI(1), den_old = TI(1);
 #pragma unroll 1
       for (int it = 0; it < a.max_it; ++it) {
         __syncthreads();   // u visible
         TI wv[4][2];
-        mv_block<N1, N2, TI>(s_p + base, ebI, kvI, wv);
-        if constexpr ((N1 & 1) || (N2 & 1)) {   // blocks reaching past the grid: keep s, r finite there
+        if constexpr (EVEN) {
+          mv_modes<N1, N2, WG, TI>(s_p, ebI + P::PW + 1, mcI, s_x, b_own, b_r, b_t, b_d, tid, t_l, t_b, t_d, wv);
+        } else {
+          mv_block<N1, N2, TI>(s_p + base, ebI, kvI, wv);
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < 4; ++k)   // blocks reaching past the grid: keep s, r finite there
 #pragma unroll
             for (int d = 0; d < 2; ++d)
               if (!exists[k]) wv[k][d] = TI(0);
@@ -445,8 +589,14 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
             xi[k][d] = fma(alpha, pv[k][d], xi[k][d]);
             ri[k][d] = fma(-alpha, sv[k][d], ri[k][d]);
             uv[k][d] = dinv[k][d] * ri[k][d];
-            if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
+            if constexpr (!EVEN)
+              if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
           }
+        if constexpr (EVEN)
+          if (own)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+              st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, uv[0][d], uv[1][d], uv[2][d], uv[3][d]);
         gam_old = gam;
         den_old = den;
       }
@@ -543,13 +693,13 @@ static constexpr int wg_for(int n1, int n2) {
 }
 
 size_t lin2d_lds_bytes(int n1, int n2, int nrhs) {
-  return lin2d_lds_bytes_t(n1, n2, wg_for(n1, n2), nrhs);
+  return lin2d_lds_bytes_t(n1, n2, wg_for(n1, n2), nrhs, 8);
 }
 
 template <typename TI, int NRHS, int N1, int N2>
 static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = wg_for(N1, N2);
-  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS);
+  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)));
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
   auto kern = &k_lin2d<TI, NRHS, N1, N2, WG>;
   if (lds > 64 * 1024)
