@@ -121,28 +121,29 @@ __device__ __forceinline__ void st4(V* p, V a0, V a1, V a2, V a3) {
 // patch; the partial sums of the five patch nodes owned by the right, top
 // and diagonal neighbours pass through LDS (three lane-contiguous quad slots
 // [3][WG][4], one barrier).  vb: block-major vector (component x, y at
-// +NBT*4); es: padded scale of element (i0, j0); blk/br/bt/bd: own, right,
+// +NBT*4); es: scales of the elements (i0 + a, j0 + c) as es[c][a];
+// blk/br/bt/bd: own, right,
 // top and top-right blocks; tl, tb, td: threads owning the blocks to the
 // left, below and below-left.
 template <int N1, int N2, int WG, typename V>
-__device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V* __restrict__ es, const V (&mc)[10],
+__device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V (&es)[2][2], const V (&mc)[10],
                                          V* __restrict__ sx, int blk, int br, int bt, int bd, int tid, int tl, int tb,
                                          int td, V (&y)[4][2]) {
-  using P = Pad<N1, N2>;
   constexpr int NBT = (N1 / 2) * (N2 / 2);
   V ux[3][3], uy[3][3];
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
     V(&u)[3][3] = d ? uy : ux;
     const V* v = vb + d * NBT * 4;
-    V q[4], r[4], t[4];
+    V q[4], r[4], t[4], g[4];   // 16-byte reads: lane-contiguous, no bank conflicts
     ld4(v + 4 * blk, q);
     ld4(v + 4 * br, r);
     ld4(v + 4 * bt, t);
+    ld4(v + 4 * bd, g);
     u[0][0] = q[0], u[0][1] = q[1], u[1][0] = q[2], u[1][1] = q[3];
     u[0][2] = r[0], u[1][2] = r[2];
     u[2][0] = t[0], u[2][1] = t[1];
-    u[2][2] = v[4 * bd];
+    u[2][2] = g[0];
   }
   V hx[3][2], hy[3][2], vx[2][3], vy[2][3];   // horizontal / vertical edge differences
 #pragma unroll
@@ -168,7 +169,7 @@ __device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V* __re
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const V m = es[c * P::PW + a];
+      const V m = es[c][a];
       const V mX = m * (hx[c][a] + hx[c + 1][a]);   // m bx.ux
       const V mY = m * (vy[c][a] + vy[c][a + 1]);   // m by.uy
       const V mSx = m * (vx[c][a] + vx[c][a + 1]);  // m by.ux
@@ -543,12 +544,17 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
           for (int d = 0; d < 2; ++d) st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, uv[0][d], uv[1][d], uv[2][d], uv[3][d]);
       const TI tinI = static_cast<TI>(tin2);
       TI gam0 = TI(0), gam_old = TI(1), den_old = TI(1);
+      TI esc[2][2];   // scales of the thread's four elements (even sizes)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) esc[c][a2] = EVEN ? ebI[(c + 1) * P::PW + a2 + 1] : TI(0);
 #pragma unroll 1
       for (int it = 0; it < a.max_it; ++it) {
         __syncthreads();   // u visible
         TI wv[4][2];
         if constexpr (EVEN) {
-          mv_modes<N1, N2, WG, TI>(s_p, ebI + P::PW + 1, mcI, s_x, b_own, b_r, b_t, b_d, tid, t_l, t_b, t_d, wv);
+          mv_modes<N1, N2, WG, TI>(s_p, esc, mcI, s_x, b_own, b_r, b_t, b_d, tid, t_l, t_b, t_d, wv);
         } else {
           mv_block<N1, N2, TI>(s_p + base, ebI, kvI, wv);
 #pragma unroll
