@@ -487,25 +487,33 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
     for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
         ++nmv64;
       }
-      TI ri[4][2];
+      double r64[4][2];
       double red[2] = {0.0, 0.0};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int di = k & 1, dj = k >> 1;
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-          double r64 = 0.0;
+          r64[k][d] = 0.0;
           if (dof[k]) {
             const double bk = (kc < NF) ? bF_entry<N1, N2>(eb, KwF, di, dj, d, kc)
                                         : a.r[fo + 2 * node_of(k) + d];
-            r64 = bk - y[k][d];
-            red[0] += r64 * r64;
+            r64[k][d] = bk - y[k][d];
+            red[0] += r64[k][d] * r64[k][d];
             red[1] += bk * bk;
           }
-          ri[k][d] = static_cast<TI>(r64);
         }
       }
       wg_sum<2, NW, RED_NV>(red, s_red, parity);
+      // the inner solve runs on r / ||r|| (no FP32 underflow for the small
+      // corrections of late sweeps); its result is scaled back in FP64
+      const double rnrm = sqrt(red[0]);
+      const double rinv = red[0] > 0.0 ? 1.0 / rnrm : 0.0;
+      TI ri[4][2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) ri[k][d] = static_cast<TI>(r64[k][d] * rinv);
       const double rel = red[1] > 0.0 ? sqrt(red[0] / red[1]) : 0.0;
       if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
         worst = rel > worst ? rel : worst;
@@ -611,7 +619,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 2; ++d)
-          if (exists[k]) xc[2 * node_of(k) + d] += static_cast<double>(xi[k][d]);
+          if (exists[k]) xc[2 * node_of(k) + d] += rnrm * static_cast<double>(xi[k][d]);
       xzero = false;
     }
   }
