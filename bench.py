@@ -13,7 +13,9 @@ One timed step = one monolithic Newton iteration from the reference state
 and condensations, FP64 macro assembly, banded Cholesky solve, fluctuation
 update), preceded by a device-to-device reset of the state.  Two forms run:
   * mixed: FP32 PCG + FP64 residual refinement, energy-form condensation,
-    rve_tol 1e-4 (the headline value; Cbar within 1e-6 of plain FP64);
+    rve_tol 5e-4 (the headline value; the C-bar error is quadratic in the
+    solve error and stays more than ten times inside the metric's 1e-6 of
+    plain FP64, which the accuracy block of the output reports);
   * fp64:  the same solver in FP64 throughout, rve_tol 1e-7 (Cbar <= 1e-10).
 value = RVE solves/s of the mixed form (RVEs / GPU time of a2-a6, HIP
 events on the stream), ms_per_step = wall time of one macro Newton step.
@@ -51,13 +53,13 @@ FLOP_OPERATOR_DOF = {(2, "small"): 64.0, (3, "small"): 384.0, (2, "finite"): 130
 WORKLOADS = {
     "cfg2": dict(desc="2D plane-strain linear, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 centred circle vf 0.3, "
                       "E ratio lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3",
-                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+                 lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
     "cfg3": dict(desc="2D plane-strain linear uneven batch, macro 128x128 Q4 (65536 RVEs), RVE 16x16/32x32/48x48 Q4 "
                       "by Voronoi region, circle radius U[0.1,0.35], E ratio U[5,50] per macro element, uniaxial 1e-3",
-                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+                 lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
     "cfg4": dict(desc="3D linear, macro 8x8x8 hex8 (4096 RVEs), RVE 10x10x10 hex8 centred sphere vf 0.2, "
                       "E ratio 10, nu 0.3, uniaxial 1e-3",
-                 lam=1.0, tol=dict(mixed=1e-4, fp64=1e-7)),
+                 lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
     "cfg5": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
                       "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; first Newton iteration of the first of ten "
                       "load increments (u_x = 0.01)",
@@ -235,6 +237,7 @@ def main():
     if "mixed" in forms and "fp64" in forms:
         errs = [rel_frob(forms["mixed"]["cbar"][b], forms["fp64"]["cbar"][b]) for b in range(p.n_rve)]
         acc["cbar_mixed_vs_fp64_max"] = max(errs)
+        acc["meets_cbar_target_1e-6"] = bool(max(errs) <= 1e-6)
         acc["u_mixed_vs_fp64"] = float(np.abs(forms["mixed"]["u"] - forms["fp64"]["u"]).max()
                                        / np.abs(forms["fp64"]["u"]).max())
     cpu = None
