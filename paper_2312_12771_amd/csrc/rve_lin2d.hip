@@ -44,6 +44,17 @@ __device__ __forceinline__ V kfma(const V (&kv)[10], int r, int c, V x, V acc) {
   return kref_sign(r, c) > 0 ? fma(kv[kref_id(r, c)], x, acc) : fma(-kv[kref_id(r, c)], x, acc);
 }
 
+// a <- b * a + c in a's own register (a loop-carried multiplicand would
+// otherwise be recomputed into c's register and copied back every iteration)
+__device__ __forceinline__ float fma_keep(float a, float b, float c) {
+  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(a) : "v"(b), "v"(c));
+  return a;
+}
+__device__ __forceinline__ double fma_keep(double a, double b, double c) {
+  asm("v_fma_f64 %0, %1, %0, %2" : "+v"(a) : "v"(b), "v"(c));
+  return a;
+}
+
 // y = K v for the four nodes of the owned block.  pb points at the padded
 // entry of node (i0-1, j0-1) of component x (component y follows at +PN);
 // eb at the padded element (i0-1, j0-1).
@@ -598,8 +609,8 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            pv[k][d] = fma(beta, pv[k][d], uv[k][d]);
-            sv[k][d] = fma(beta, sv[k][d], wv[k][d]);
+            pv[k][d] = fma_keep(pv[k][d], beta, uv[k][d]);
+            sv[k][d] = fma_keep(sv[k][d], beta, wv[k][d]);
             xi[k][d] = fma(alpha, pv[k][d], xi[k][d]);
             ri[k][d] = fma(-alpha, sv[k][d], ri[k][d]);
             uv[k][d] = dinv[k][d] * ri[k][d];
