@@ -167,6 +167,7 @@ class RVESystem:
     free: np.ndarray         # indices of the reduced DOFs in the periodic numbering
     n_full: int              # DOFs of the periodic field before the pin
     volume: float            # |Omega|
+    r_round: float = 0.0     # finite strain: size of a rounding bound of the element residual terms
 
 
 def n_macro_components(dim, kinematics):
@@ -200,6 +201,7 @@ def assemble_rve(res, phases, params, kinematics, material, macro, w_full=None,
     ke = np.zeros((ne, nd, nd))
     kwF = np.zeros((ne, nd, nF))
     re = np.zeros((ne, nd))
+    re_abs = np.zeros((ne, nd))   # finite strain: rounding bound of re
     K_FF = np.zeros((nF, nF))
     P_int = np.zeros(nF)
     energy = 0.0
@@ -226,13 +228,23 @@ def assemble_rve(res, phases, params, kinematics, material, macro, w_full=None,
                 lam, mu = params[phases, 0], params[phases, 1]
                 P, A = tensors.nh_stress_tangent(F2, lam, mu)
                 psi = tensors.nh_energy(F2, lam, mu)
+                al, be, ka = mu / 2.0, np.zeros_like(mu), lam   # the beta = 0 member of Eq. (59)
             elif material == "mooney_rivlin":
                 a, b, k = params[phases, 0], params[phases, 1], params[phases, 2]
                 P, A = tensors.mr_stress_tangent(F2, a, b, k)
                 psi = tensors.mr_energy(F2, a, b, k)
+                al, be, ka = a, b, k
             else:
                 raise ValueError(material)
             re += wt * P @ G
+            # P = 2(a+b) F + (2bJ + k(J-1) - 2(a+2b)/J) cof F: its FP64 value
+            # is the difference of terms of the size below, which bounds the
+            # rounding of the residual (relevant near F = I, where they cancel)
+            J = np.linalg.det(F2)
+            H = np.stack([F2[:, 1, 1], -F2[:, 1, 0], -F2[:, 0, 1], F2[:, 0, 0]], axis=1)
+            c1a = np.abs(2 * be * J) + np.abs(ka * (J - 1.0)) + np.abs(2 * (al + 2 * be) / J)
+            Pa = np.abs(2 * (al + be))[:, None] * np.abs(Fv) + c1a[:, None] * np.abs(H)
+            re_abs += wt * Pa @ np.abs(G)
             ke += wt * np.einsum("ai,eij,jb->eab", G.T, A, G)
             kwF += wt * np.einsum("ai,eij->eaj", G.T, A)
             K_FF += wt * A.sum(axis=0)
@@ -249,7 +261,7 @@ def assemble_rve(res, phases, params, kinematics, material, macro, w_full=None,
     K_ww = K[free][:, free].tocsr()
     return RVESystem(K_ww=K_ww, K_wF=KwF_full[free], K_FF=K_FF, r=r_full[free],
                      P_int=P_int, energy=energy, free=free, n_full=n_full,
-                     volume=L ** dim)
+                     volume=L ** dim, r_round=float(np.sqrt(np.sum(re_abs ** 2))))
 
 
 @dataclasses.dataclass
@@ -296,7 +308,9 @@ def homogenize_rve(prob, b, macro, w_full: Optional[np.ndarray] = None) -> Conde
 
 def equilibrate_rve(prob, b, macro, w_full=None, tol=1e-13, max_it=30):
     """Classical inner Newton of Sec. 4.1 at fixed macro gradient: iterate
-    w <- w - K_ww^-1 r until ||r|| < tol * max(1, ||r_0||).  Returns the
+    w <- w - K_ww^-1 r until ||r|| < tol * max(1, ||r_0||), or until ||r|| is
+    at the FP64 rounding level 1e-14 * r_round of its evaluation (finite
+    strain; the paper's tolerance can lie below that level).  Returns the
     final periodic field and the residual history."""
     res, ph, par, L = rve_problem_args(prob, b)
     w = np.zeros(int(np.prod(res)) * len(res)) if w_full is None else np.array(w_full, dtype=np.float64)
@@ -308,7 +322,7 @@ def equilibrate_rve(prob, b, macro, w_full=None, tol=1e-13, max_it=30):
         hist.append(nr)
         if r0 is None:
             r0 = nr
-        if nr < tol * max(1.0, r0):
+        if nr < tol * max(1.0, r0) or nr <= 1e-14 * s.r_round:
             break
         dw = spla.spsolve(s.K_ww.tocsc(), s.r)
         w[s.free] -= dw

@@ -79,6 +79,7 @@ struct fe2_ctx {
   double lam = 0.0;
   double *u = nullptr, *w = nullptr, *r = nullptr, *Xs = nullptr;
   double *Cbar = nullptr, *Phat = nullptr, *Pbar = nullptr, *mgrad = nullptr, *rnorm2 = nullptr;
+  double* rsize2 = nullptr;   // [n_rve] squared size of the element-level terms of r_b (finite strain)
   double *relres = nullptr, *iters = nullptr;
   int* fail_count = nullptr;
   int* info = nullptr;
@@ -152,6 +153,7 @@ struct fe2_ctx {
     a.Phat = Phat;
     a.Pbar = Pbar;
     a.rnorm2 = rnorm2;
+    a.rsize2 = rsize2;
     a.relres = relres;
     a.iters = iters;
     a.mv64 = mv64;
@@ -214,7 +216,7 @@ void free_ctx(fe2_ctx* h) {
   void* ptrs[] = {h->conn, h->is_dir, h->vec_ptr, h->vec_src, h->nz_ptr, h->nz_col, h->nzc_ptr,
                   h->nzc_src, h->X, h->dNdX, h->wdet, h->f_ext, h->dir_full, h->phase_off,
                   h->phase, h->params, h->foff, h->u, h->w, h->r, h->Xs, h->Cbar, h->Phat,
-                  h->Pbar, h->mgrad, h->rnorm2, h->relres, h->iters, h->fail_count, h->info,
+                  h->Pbar, h->mgrad, h->rnorm2, h->rsize2, h->relres, h->iters, h->fail_count, h->info,
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
                   h->norms_dev, h->kdense, h->mv64, h->thr2, h->count, h->eq_skip, h->surr_norm, h->phi,
                   h->surrP, h->surrC, h->surr_err, h->surr_X, h->surr_Y, h->accept, h->banned, h->okf,
@@ -464,6 +466,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if ((rc = dalloc(&h->Pbar, nr * nF))) return rc;
   if ((rc = dalloc(&h->mgrad, nr * nF))) return rc;
   if ((rc = dalloc(&h->rnorm2, nr))) return rc;
+  if ((rc = dalloc(&h->rsize2, nr))) return rc;
   if ((rc = dalloc(&h->relres, nr))) return rc;
   if ((rc = dalloc(&h->iters, nr))) return rc;
   if ((rc = dalloc(&h->mv64, nr))) return rc;
@@ -582,7 +585,9 @@ int equilibrate_impl(fe2_ctx* h, hipStream_t s) {
   h->skip = h->eq_skip;
   int rc = assemble_impl(h, s);
   if (!rc) {
-    hipLaunchKernelGGL(k_micro_thr, dim3(nb), dim3(256), 0, s, h->n_rve, h->rnorm2, h->micro_tol, h->thr2);
+    hipLaunchKernelGGL(k_micro_thr, dim3(nb), dim3(256), 0, s, h->n_rve, h->rnorm2,
+                       h->kin == FE2_FINITE_STRAIN ? h->rsize2 : static_cast<const double*>(nullptr), h->micro_tol,
+                       h->thr2);
     if (hipGetLastError() != hipSuccess) rc = (set_error("launch failed"), FE2_EHIP);
   }
   h->last_micro_its = 0;

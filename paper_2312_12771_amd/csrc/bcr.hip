@@ -181,7 +181,7 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
     if (*s_fail) return false;
     // the inverse tile goes out after the barrier (its stores complete
     // during the panel phase instead of delaying wave 0)
-    static_assert(PO_WG >= BT * BT, "one inverse entry per thread");
+    static_assert(PO_WG >= BT * BT && PO_WG % (BT * BT) == 0, "one inverse entry per thread");
     if (tid < BT * BT) Ij[p * BT * BT + tid] = s_inv[tid];
     // panel below: L_ip = A_ip invL_pp^T, one row per thread
     const int rows = (nt - p - 1) * BT;
@@ -258,29 +258,21 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   if constexpr (RESIDENT) {
     double* s_tiles = smem + bs * (BT + 1);
     const int ntri = nt * (nt + 1) / 2;
-    const int c = tid >> 4, r = tid & 15;   // one element of a tile per thread
-    {
-      int ti = 0, tk = 0;
-#pragma unroll 4
-      for (int q = 0; q < ntri; ++q) {
-        s_tiles[q * BT * BT + tid] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
-        if (++tk > ti) {
-          ++ti;
-          tk = 0;
-        }
-      }
+    // one element of a tile per thread, PO_WG / 256 tiles per pass
+    constexpr int TPP = PO_WG / (BT * BT);
+    const int el = tid % (BT * BT), c = el >> 4, r = el & 15;
+#pragma unroll 2
+    for (int q = tid / (BT * BT); q < ntri; q += TPP) {
+      const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
+      s_tiles[q * BT * BT + el] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
     }
     __syncthreads();
     const LdsTiles A{s_tiles};
     if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, s_rd, &s_fail, info)) return;
-    int ti = 0, tk = 0;
-#pragma unroll 4
-    for (int q = 0; q < ntri; ++q) {
-      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * BT * BT + tid];
-      if (++tk > ti) {
-        ++ti;
-        tk = 0;
-      }
+#pragma unroll 2
+    for (int q = tid / (BT * BT); q < ntri; q += TPP) {
+      const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
+      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * BT * BT + el];
     }
   } else {
     __syncthreads();

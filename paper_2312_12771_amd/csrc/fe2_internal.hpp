@@ -126,6 +126,7 @@ struct Fin2DArgs {
   double* Phat;                 // [n_rve][4]
   double* Pbar;                 // [n_rve][4]
   double* rnorm2;               // [n_rve] ||r_b||^2
+  double* rsize2;               // [n_rve] squared size of the element-level terms of r_b (or null)
   double* relres;               // [n_rve] final relative FP64 residual
   double* iters;                // [n_rve] inner PCG iterations (all columns)
   double* mv64;                 // [n_rve] FP64 operator applications

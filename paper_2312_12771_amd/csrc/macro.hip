@@ -474,10 +474,13 @@ __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int
 // Classical inner loop (Sec. 4.1): per-RVE stopping threshold
 // thr2_b = tol^2 max(1, ||r_b^0||^2), the number of RVEs above it, and the
 // Newton update w_b -= x_r of the RVEs' residual solves.
-__global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, double tol,
-                            double* __restrict__ thr2) {
+// Equilibrium threshold of the classical inner loop: ||r_b|| <= tol max(1,
+// ||r_b^0||), but never below the rounding level 1e-14 S_b of the residual
+// evaluation (S_b^2 = rsize2: summed squared element-level terms; may be null).
+__global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, const double* __restrict__ rsize2,
+                            double tol, double* __restrict__ thr2) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < n_rve) thr2[b] = tol * tol * fmax(1.0, rnorm2[b]);
+  if (b < n_rve) thr2[b] = fmax(tol * tol * fmax(1.0, rnorm2[b]), rsize2 ? 1e-28 * rsize2[b] : 0.0);
 }
 
 __global__ void __launch_bounds__(1024) k_count_above(int n_rve, const double* __restrict__ rnorm2,

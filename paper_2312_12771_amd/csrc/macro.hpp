@@ -57,7 +57,7 @@ __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
                            const double* __restrict__ X, double* __restrict__ w, int use_xr,
                            const int* __restrict__ skip);
-__global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, double tol,
+__global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, const double* __restrict__ rsize2, double tol,
                             double* __restrict__ thr2);
 __global__ void k_count_above(int n_rve, const double* __restrict__ rnorm2,
                               const double* __restrict__ thr2, const int* __restrict__ skip,

@@ -236,7 +236,10 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
 
   // ---- FP64 element passes ------------------------------------------------
   // mode 0: forces G^T P~ at the state; acc = [int P (4) | K_FF (16) | #(J<=0) |
-  //         sum of the squared element force entries]
+  //         sum of the squared entries of a rounding bound of the element
+  //         forces: G^T applied, with absolute values, to |c0 F| + (|2b J| +
+  //         |k (J - 1)| + |2(a + 2b) / J|) |H|, the terms whose cancellation
+  //         sets the FP64 rounding level of r_b]
   // mode 1: forces G^T A (e_kc - grad x) (kc < 0: -G^T A grad x) with x the
   //         global field xg (zero when xg is null); acc[0..3] = K_Fw x when
   //         want_k; acc[20] = sum of the squared element force entries
@@ -254,6 +257,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
         if (xg) elem_vals_g(xg, e, xe);
       }
       double f[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      double fa[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // mode 0: rounding bound of f
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         double F[4], Pk[4], H[4], c1, dc1, s[4];
@@ -276,6 +280,17 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
             }
           }
           add_force<double>(f, g, r2h1, r2h2, wt, Pk);
+          const double J = F[0] * F[3] - F[1] * F[2];
+          const double c1a = fabs(q.b2 * J) + fabs(q.k * (J - 1.0)) + fabs(q.a2b2 / J);
+          double Pa[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) Pa[t] = fabs(q.c0 * F[t]) + c1a * fabs(H[t]);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const double nx = fabs(dNx<double>(m, g, r2h1)), ny = fabs(dNy<double>(m, g, r2h2));
+            fa[m][0] += wt * (nx * Pa[0] + ny * Pa[1]);
+            fa[m][1] += wt * (nx * Pa[2] + ny * Pa[3]);
+          }
         } else if constexpr (mode == 1) {
           double gx[4], dd[4];
           grad_at<double>(xe, g, r2h1, r2h2, gx);
@@ -308,14 +323,14 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
         for (int d = 0; d < 2; ++d) {
           s_ef[(2 * m + d) * NN + e] = f[m][d];
           if constexpr (mode == 1) acc[20] += f[m][d] * f[m][d];
-          if constexpr (mode == 0) acc[21] += f[m][d] * f[m][d];
+          if constexpr (mode == 0) acc[21] += fa[m][d] * fa[m][d];
         }
     }
   };
 
   // ---- a3: residual, stress integral, K_FF --------------------------------
   const bool solve = (a.flags & RVE_SOLVE) != 0;
-  double rsize2;     // squared size of the element-level terms of r_b
+  double rsize2;     // squared rounding bound of the element-level terms of r_b
   __syncthreads();   // phases and state staged
   {
     double red[23];
@@ -346,6 +361,7 @@ __global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
 #pragma unroll
       for (int t = 0; t < NF; ++t) a.Pbar[static_cast<size_t>(b) * NF + t] = red[t] / a.volume;
       a.rnorm2[b] = red[20];
+      if (a.rsize2) a.rsize2[b] = rsize2;
     }
     if (!solve) return;
     if ((a.flags & RVE_RONLY) && red[20] <= a.thr2[b]) {   // in equilibrium: x_r = 0

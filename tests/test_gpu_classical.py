@@ -72,8 +72,13 @@ def test_inner_equilibration_matches_oracle(fe2, name, kw, prec):
         assert np.linalg.eigvalsh(s0.K_ww.toarray())[0] > 0.0
         wo, hist = R.equilibrate_rve(p, b, F, tol=1e-13)
         assert rel(w[off[b]:off[b + 1]], wo) < 1e-9
-        # the GPU stopped by the same rule as the oracle
-        assert np.linalg.norm(res[off[b]:off[b + 1]]) < 1e-13 * max(1.0, hist[0])
+        # the GPU stopped by the same rule as the oracle: below the tolerance
+        # or at the FP64 rounding level of the residual (bound from the oracle
+        # at the GPU's final state)
+        s1 = R.assemble_rve(*R.rve_problem_args(p, b)[:3], p.kinematics, p.material, F,
+                            w[off[b]:off[b + 1]], p.rve_size)
+        nr = np.linalg.norm(res[off[b]:off[b + 1]])
+        assert nr < 1e-13 * max(1.0, hist[0]) or nr <= 1e-14 * s1.r_round
     h.close()
 
 
