@@ -15,6 +15,11 @@ side.
   at fixed q, then the Schur complement step and the predictor
   dw_b = -X_F dF_b.
 * Full block solve of Eq. (42) for tiny meshes.
+* Piecewise-constant macro basis of the fluctuation (Sec. 3, Eqs.
+  (constSolution1)-(constSolution2)): one fluctuation field per macro element,
+  shared by the element's Gauss points; its micro residual, Hessian blocks and
+  macro residual are the Gauss sums of the RVE quantities at (F_g, w~_e), and
+  both Newton schemes condense element by element.
 
 Prescribed displacements: the whole increment (lambda_new - lambda_old) g is
 applied through the linear system in the first iteration of a load step;
@@ -71,10 +76,11 @@ def macro_geometry(prob) -> MacroGeometry:
     return MacroGeometry(dNdX=dNdX, wdet=wdet, edofs=edofs, Bs=Bs, n_gp=n_gp)
 
 
-def macro_gradient(prob, geo: MacroGeometry, u, b):
-    """eps_b (small strain) or F_b = I + grad u (finite strain), Eq. (11)."""
-    e = b // geo.n_gp
-    g = geo.Bs[b] @ u[geo.edofs[e]]
+def macro_gradient(prob, geo: MacroGeometry, u, q):
+    """eps (small strain) or F = I + grad u (finite strain), Eq. (11), at
+    macro Gauss point q = e * n_gp + g."""
+    e = q // geo.n_gp
+    g = geo.Bs[q] @ u[geo.edofs[e]]
     if prob.kinematics == "small":
         return g
     return g + np.eye(prob.dim).ravel()
@@ -97,6 +103,9 @@ def initial_state(prob) -> State:
 
 
 def linearize(prob, geo, state) -> List[R.Condensed]:
+    """Condensed RVE of every Gauss point (Dirac macro basis)."""
+    if prob.macro_basis != "dirac":
+        raise ValueError("linearize covers the Dirac macro basis")
     return [R.homogenize_rve(prob, b, macro_gradient(prob, geo, state.u, b), state.w[b])
             for b in range(prob.n_rve)]
 
@@ -224,10 +233,12 @@ def solve(prob, scheme="generalized", tol=1e-10, max_it=20, load_factors=None,
     for lam in (prob.load_factors if load_factors is None else load_factors):
         h = []
         for it in range(max_it):
+            element = prob.macro_basis == "element"
             if scheme == "generalized":
-                nrm = generalized_step(prob, geo, state, lam)[0]
+                step = element_generalized_step if element else generalized_step
             else:
-                nrm = classical_step(prob, geo, state, lam)[0]
+                step = element_classical_step if element else classical_step
+            nrm = step(prob, geo, state, lam)[0]
             h.append(nrm)
             if not np.isfinite(nrm.macro) or nrm.macro > diverge_at:
                 raise RuntimeError(f"diverged at load {lam}, iteration {it}")
@@ -243,10 +254,11 @@ def solve(prob, scheme="generalized", tol=1e-10, max_it=20, load_factors=None,
 # full block system, Eq. (42)
 # --------------------------------------------------------------------------
 
-def full_block_step(prob, state: State, lam_target: float):
-    """Assemble [K D; E L] [dq; dw] = -[R_macro; R_micro] for the whole
-    problem and solve it directly (tiny meshes only).  K, D, L follow
-    Eqs. (39)-(41) with the Dirac macro basis; E = D^T."""
+def full_block_system(prob, state: State, lam_target: float):
+    """Assemble [K D; E L] and -[R_macro; R_micro] of Eq. (42) for the whole
+    problem (Dirac macro basis; tiny meshes only).  K, D, L follow
+    Eqs. (39)-(41); E = D^T.  Returns (A, rhs, offs) with the fluctuation of
+    RVE b at rows offs[b]:offs[b+1] (reduced numbering)."""
     geo = macro_geometry(prob)
     conds = linearize(prob, geo, state)
     nd = prob.n_dofs
@@ -269,7 +281,13 @@ def full_block_step(prob, state: State, lam_target: float):
         rhs[d] -= geo.wdet[b] * B.T @ c.P_bar
         rhs[sl] = -s * c.system.r
     rhs[:nd] += lam_target * prob.f_ext
-    A = A.tocsr()
+    return A.tocsr(), rhs, offs
+
+
+def solve_full_block(prob, A, rhs, state: State, lam_target: float):
+    """Solve the assembled block system with the prescribed increment on the
+    Dirichlet DOFs (elimination)."""
+    ntot = A.shape[0]
     mask = np.ones(ntot, dtype=bool)
     mask[prob.dir_dofs] = False
     fr = np.where(mask)[0]
@@ -277,6 +295,170 @@ def full_block_step(prob, state: State, lam_target: float):
     x[prob.dir_dofs] = (lam_target - state.lam) * prob.dir_vals
     r = rhs[fr] - A[fr][:, prob.dir_dofs] @ x[prob.dir_dofs]
     x[fr] = spla.spsolve(A[fr][:, fr].tocsc(), r)
-    du = x[:nd]
+    return x
+
+
+def full_block_step(prob, state: State, lam_target: float):
+    """One Newton step on the full block system of Eq. (42) (tiny meshes)."""
+    A, rhs, offs = full_block_system(prob, state, lam_target)
+    x = solve_full_block(prob, A, rhs, state, lam_target)
+    du = x[:prob.n_dofs]
     dws = [x[offs[b]:offs[b + 1]] for b in range(prob.n_rve)]
     return du, dws
+
+
+# --------------------------------------------------------------------------
+# piecewise-constant macro basis, Eqs. (constSolution1)-(constSolution2)
+# --------------------------------------------------------------------------
+#
+# The basis function of micro DOF c of element e is the indicator of e times
+# the RVE shape function R~^c (discontinuous across macro elements, so the
+# micro-micro Hessian block stays block diagonal).  With the element's Gauss
+# rule the micro residual of element e is sum_g (wdet_g/|Omega|) r(F_g, w~_e)
+# and the macro residual sum_g wdet_g B_g^T P_bar(F_g, w~_e); the Hessian
+# blocks are the Gauss sums of the RVE blocks of Eqs. (39)-(41).
+
+@dataclasses.dataclass
+class ElementBlocks:
+    K: np.ndarray          # (nd, nd)  sum_g s_g B_g^T K_FF,g B_g
+    D: np.ndarray          # (nd, N)   sum_g s_g B_g^T K_Fw,g   (E = D^T)
+    L: sp.csr_matrix       # (N, N)    sum_g s_g K_ww,g
+    f: np.ndarray          # (nd,)     sum_g wdet_g B_g^T P_bar,g
+    r: np.ndarray          # (N,)      sum_g s_g r_g
+    r_round: float         # sum_g s_g r_round,g (rounding size of r)
+    energy: float          # sum_g wdet_g psi_bar,g
+    system: R.RVESystem    # RVE system at the first Gauss point (numbering)
+
+
+def element_blocks(prob, geo: MacroGeometry, state: State, e: int) -> ElementBlocks:
+    """Blocks of macro element e at the current (q, w~_e); s_g = wdet_g/|Omega|."""
+    if prob.macro_basis != "element":
+        raise ValueError("element blocks need the piecewise-constant macro basis")
+    res, ph, par, Lc = R.rve_problem_args(prob, e)
+    K = D = Lm = f = r = None
+    r_round = energy = 0.0
+    first = None
+    for g in range(geo.n_gp):
+        q = e * geo.n_gp + g
+        F = macro_gradient(prob, geo, state.u, q)
+        sy = R.assemble_rve(res, ph, par, prob.kinematics, prob.material, F, state.w[e], Lc)
+        s = geo.wdet[q] / sy.volume
+        B = geo.Bs[q]
+        terms = (s * B.T @ sy.K_FF @ B, s * B.T @ sy.K_wF.T, s * sy.K_ww,
+                 geo.wdet[q] * B.T @ (sy.P_int / sy.volume), s * sy.r)
+        if first is None:
+            first = sy
+            K, D, Lm, f, r = terms
+        else:
+            K, D, Lm, f, r = K + terms[0], D + terms[1], Lm + terms[2], f + terms[3], r + terms[4]
+        r_round += s * sy.r_round
+        energy += s * sy.energy
+    return ElementBlocks(K=K, D=D, L=Lm.tocsr(), f=f, r=r, r_round=r_round,
+                         energy=energy, system=first)
+
+
+@dataclasses.dataclass
+class ElementCondensed:
+    S: np.ndarray          # (nd, nd) K - D L^-1 E
+    f_hat: np.ndarray      # (nd,)    f - D L^-1 r
+    Y: np.ndarray          # (N, nd)  L^-1 E
+    y_r: np.ndarray        # (N,)     L^-1 r
+    blocks: ElementBlocks
+
+
+def element_condense(blk: ElementBlocks) -> ElementCondensed:
+    """Schur complement of the element's micro block (Eqs. (46)-(48) with the
+    element basis): sparse LU of L, then S, the condensed force, and the two
+    solves the update needs."""
+    lu = spla.splu(blk.L.tocsc())
+    sol = lu.solve(np.concatenate([blk.D.T, blk.r[:, None]], axis=1))
+    Y, y_r = sol[:, :-1], sol[:, -1]
+    return ElementCondensed(S=blk.K - blk.D @ Y, f_hat=blk.f - blk.D @ y_r,
+                            Y=Y, y_r=y_r, blocks=blk)
+
+
+def element_macro_system(prob, geo, conds: List[ElementCondensed], lam, use_fhat=True):
+    """Assembled condensed tangent, right-hand side (with f_hat, or with the
+    true internal force for the classical scheme), true residual and F_int."""
+    nd = prob.n_dofs
+    rows, cols, vals = [], [], []
+    R_hat = np.zeros(nd)
+    F_int = np.zeros(nd)
+    for e, c in enumerate(conds):
+        d = geo.edofs[e]
+        rows.append(np.repeat(d, len(d)))
+        cols.append(np.tile(d, len(d)))
+        vals.append(c.S.ravel())
+        np.add.at(R_hat, d, c.f_hat if use_fhat else c.blocks.f)
+        np.add.at(F_int, d, c.blocks.f)
+    K = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nd, nd))
+    R_hat -= lam * prob.f_ext
+    return K, R_hat, F_int - lam * prob.f_ext, F_int
+
+
+def element_norms(prob, conds: List[ElementCondensed], R_true, F_int) -> Norms:
+    fr = free_dofs(prob)
+    rm = float(np.linalg.norm(R_true[fr]))
+    mic = float(np.sqrt(sum(float(np.sum(c.blocks.r ** 2)) for c in conds)))
+    return Norms(total=float(np.hypot(rm, mic)), macro=rm, micro=mic,
+                 scale=float(np.linalg.norm(F_int)))
+
+
+def element_generalized_step(prob, geo, state: State, lam_target: float):
+    """Generalized scheme (Sec. 4.2) with the element basis: condense every
+    element at the current (q, w~), solve the macro system, then
+    dw~_e = -(L_e^-1 r_e + L_e^-1 E_e dq_e)."""
+    conds = [element_condense(element_blocks(prob, geo, state, e)) for e in range(prob.n_elems)]
+    K, R_hat, R_true, F_int = element_macro_system(prob, geo, conds, lam_target)
+    nrm = element_norms(prob, conds, R_true, F_int)
+    du_D = (lam_target - state.lam) * prob.dir_vals
+    du = solve_macro(prob, K, -R_hat, du_D)
+    dws = []
+    for e, c in enumerate(conds):
+        dw = -(c.y_r + c.Y @ du[geo.edofs[e]])
+        state.w[e] = state.w[e] + R.expand(c.blocks.system, dw)
+        dws.append(dw)
+    state.u = state.u + du
+    state.lam = lam_target
+    return nrm, du, dws, conds
+
+
+def element_classical_step(prob, geo, state: State, lam_target: float, tol_micro=1e-13,
+                           max_micro=30):
+    """Classical scheme (Sec. 4.1) with the element basis: Newton on every
+    element's micro residual at fixed q (stop as equilibrate_rve), then the
+    Schur complement step with the true residual and dw~_e = -L_e^-1 E_e dq_e."""
+    for e in range(prob.n_elems):
+        r0 = None
+        for _ in range(max_micro + 1):
+            blk = element_blocks(prob, geo, state, e)
+            nr = float(np.linalg.norm(blk.r))
+            r0 = nr if r0 is None else r0
+            if nr < tol_micro * max(1.0, r0) or nr <= 1e-14 * blk.r_round:
+                break
+            dw = spla.spsolve(blk.L.tocsc(), blk.r)
+            state.w[e] = state.w[e] - R.expand(blk.system, dw)
+    conds = [element_condense(element_blocks(prob, geo, state, e)) for e in range(prob.n_elems)]
+    K, _, R_true, F_int = element_macro_system(prob, geo, conds, lam_target, use_fhat=False)
+    nrm = element_norms(prob, conds, R_true, F_int)
+    du_D = (lam_target - state.lam) * prob.dir_vals
+    du = solve_macro(prob, K, -R_true, du_D)
+    for e, c in enumerate(conds):
+        state.w[e] = state.w[e] + R.expand(c.blocks.system, -(c.Y @ du[geo.edofs[e]]))
+    state.u = state.u + du
+    state.lam = lam_target
+    return nrm, du, conds
+
+
+def potential_energy(prob, geo: MacroGeometry, state: State) -> float:
+    """Pi = sum_q wdet_q psi_bar(F_q, w~ of the RVE at q) - lambda f_ext . u
+    (the functional whose variations are Eqs. (35) and (constSolution1/2))."""
+    tot = 0.0
+    for q in range(prob.n_qp):
+        b = q // geo.n_gp if prob.macro_basis == "element" else q
+        res, ph, par, Lc = R.rve_problem_args(prob, b)
+        sy = R.assemble_rve(res, ph, par, prob.kinematics, prob.material,
+                            macro_gradient(prob, geo, state.u, q), state.w[b], Lc)
+        tot += geo.wdet[q] * sy.energy / sy.volume
+    return tot - state.lam * float(prob.f_ext @ state.u)

@@ -19,6 +19,7 @@ from .generators import (  # noqa: F401
     phases_sphere,
     phases_cross,
     subset_problem,
+    element_basis,
     mlp_init,
     cfg5_material_points,
     surrogate_samples,

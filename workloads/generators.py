@@ -7,7 +7,9 @@ Conventions shared by every consumer of a :class:`Problem`:
 * Q4 connectivity is counter-clockwise starting at the lower-left node; hex8
   lists the bottom face counter-clockwise, then the top face.
 * One RVE per macro Gauss point: ``b = element * n_gp + g`` with the 2-point
-  Gauss points ordered xi fastest, then eta (then zeta).
+  Gauss points ordered xi fastest, then eta (then zeta).  A problem with
+  ``macro_basis == "element"`` (piecewise-constant macro basis of the
+  fluctuation) has one RVE per macro element instead: ``b = element``.
 * An RVE is a structured grid of n1 x n2 (x n3) square/cubic elements on a cube
   cell of side ``rve_size``; ``phase_id`` stores one byte per RVE element in
   lexicographic order (i fastest), RVE after RVE, starting at ``rve_off[b]``.
@@ -48,6 +50,7 @@ class Problem:
     phase_params: np.ndarray  # (n_rve, 2, n_params) float64
     rve_size: float = 1.0
     load_factors: Sequence[float] = (1.0,)
+    macro_basis: str = "dirac"  # "dirac" (RVE per Gauss point) | "element" (RVE per element)
     seed: int = 0
     meta: Dict = dataclasses.field(default_factory=dict)
 
@@ -62,6 +65,10 @@ class Problem:
     @property
     def n_gp(self) -> int:
         return 2 ** self.dim
+
+    @property
+    def n_qp(self) -> int:
+        return self.n_elems * self.n_gp
 
     @property
     def n_rve(self) -> int:
@@ -481,3 +488,23 @@ def subset_problem(p: Problem, rves: Optional[np.ndarray] = None) -> Problem:
     return dataclasses.replace(p, rve_res=p.rve_res[rves].copy(), rve_off=off,
                                phase_id=ph,
                                phase_params=p.phase_params[rves].copy())
+
+
+def element_basis(p: Problem) -> Problem:
+    """The same problem with the piecewise-constant macro basis of the
+    fluctuation: one RVE per macro element, the one the generators placed at
+    the element's Gauss points (all Gauss points of an element carry the same
+    RVE in every generator; anything else is rejected)."""
+    if p.macro_basis != "dirac":
+        raise ValueError("expected a problem with one RVE per Gauss point")
+    ng = p.n_gp
+    for e in range(p.n_elems):
+        b0 = e * ng
+        ph0 = p.phase_id[p.rve_off[b0]:p.rve_off[b0 + 1]]
+        for b in range(b0 + 1, b0 + ng):
+            if (not np.array_equal(p.rve_res[b], p.rve_res[b0])
+                    or not np.array_equal(p.phase_params[b], p.phase_params[b0])
+                    or not np.array_equal(p.phase_id[p.rve_off[b]:p.rve_off[b + 1]], ph0)):
+                raise ValueError(f"the Gauss points of element {e} carry different RVEs")
+    q = subset_problem(p, np.arange(p.n_elems) * ng)
+    return dataclasses.replace(q, macro_basis="element", name=p.name + "_element")
