@@ -27,7 +27,8 @@
  *
  * Numbering
  *   - Macro DOFs are node-major: dof = node*dim + component.
- *   - RVE b = element * 2^dim + g, Gauss points xi fastest (2 per direction).
+ *   - RVE b = element * 2^dim + g, Gauss points xi fastest (2 per direction);
+ *     with FE2_BASIS_ELEMENT, RVE b = element.
  *   - RVE fields use the periodic node numbering of an n1 x n2 (x n3) grid,
  *     node (i,j,k) -> i + n1*(j + n2*k), DOF = node*dim + component; the
  *     corner node 0 carries the pinned fluctuation (always 0 in outputs).
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define FE2_ABI_VERSION 1
+#define FE2_ABI_VERSION 2
 
 typedef enum fe2_status {
   FE2_OK = 0,
@@ -64,6 +65,12 @@ enum { FE2_LINEAR_ISO = 0, FE2_NEO_HOOKE = 1, FE2_MOONEY_RIVLIN = 2 };
 enum { FE2_PREC_FP64 = 0, FE2_PREC_FP32_IR = 1 };
 enum { FE2_SOLVER_AUTO = 0, FE2_SOLVER_PCG_JACOBI = 1, FE2_SOLVER_PCG_FFT = 2 };
 enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
+/* Macro basis of the fluctuation: FE2_BASIS_DIRAC puts one RVE at every macro
+ * Gauss point (Dirac approach, Eqs. (31)-(35)); FE2_BASIS_ELEMENT gives every
+ * macro element one fluctuation field shared by its Gauss points (the
+ * piecewise-constant approximation of Eqs. (constSolution1)-(constSolution2),
+ * discontinuous across elements). */
+enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
 
 /*
  * Problem description (Sec. 2 and Sec. 5.2 problem statement: macro body,
@@ -81,7 +88,8 @@ enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
  *  n_dir, dir_dofs, dir_vals   prescribed DOFs (strictly increasing) and their
  *                   values at load factor 1
  *  f_ext            external nodal forces at load factor 1 [n_nodes*dim] or NULL
- *  n_rve            number of RVEs = n_elems * 2^dim
+ *  n_rve            number of RVEs: n_elems * 2^dim (FE2_BASIS_DIRAC) or
+ *                   n_elems (FE2_BASIS_ELEMENT)
  *  rve_res          RVE resolutions [n_rve][dim], every entry >= 2
  *  rve_off          offsets into phase_id [n_rve+1]
  *  phase_id         phase (0 or 1) of every RVE element, lexicographic
@@ -104,6 +112,8 @@ enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
  *  micro_tol        classical scheme: inner RVE Newton stops when
  *                   ||r_b|| <= micro_tol * max(1, ||r_b at entry||)
  *  max_pcg_it, max_ir, max_micro_it   iteration caps
+ *  macro_basis      FE2_BASIS_DIRAC or FE2_BASIS_ELEMENT (small strain only:
+ *                   FE2_ENOTSUP for finite strain)
  */
 typedef struct fe2_problem_desc {
   int32_t struct_size;
@@ -126,6 +136,7 @@ typedef struct fe2_problem_desc {
   int32_t precision, solver, scheme;
   double rve_tol, inner_tol, newton_tol, micro_tol;
   int32_t max_pcg_it, max_ir, max_micro_it;
+  int32_t macro_basis;
 } fe2_problem_desc;
 
 typedef struct fe2_ctx* fe2_handle;
@@ -139,7 +150,10 @@ typedef struct fe2_ctx* fe2_handle;
 int fe2_setup(const fe2_problem_desc* desc, void* stream, fe2_handle* out);
 
 /* Macro gradient at every Gauss point (Eq. (11): F_b = I + grad u, small
- * strain eps_b = sym grad u) and RVE element integration at the current
+ * strain eps_b = sym grad u; with FE2_BASIS_ELEMENT the RVE of element e is
+ * driven by the element average sum_g wdet_g eps_g / V_e, which is exact for
+ * its micro residual because that residual is linear in eps) and RVE element
+ * integration at the current
  * (q, w~): micro residual r_b (Eq. (35)) in the periodic numbering, the
  * integral of the micro stress (Eq. (17)) and, for finite strain, the micro
  * tangents used by the next solve.  Results stay in the handle
@@ -169,7 +183,14 @@ int fe2_condense(fe2_handle h, double* Cbar_dev, double* Phat_dev, void* stream)
  * norms_host (may be NULL) receives 4 doubles describing the state the call
  * started from: ||[R_macro(free); R_micro]||, ||R_macro(free)||,
  * ||R_micro||, ||F_int|| (R_micro,b = eta_b J_b / |Omega| r_b).  Waits for
- * the norms on `stream`. */
+ * the norms on `stream`.
+ * With FE2_BASIS_ELEMENT (small strain) the Gauss-point stress of element e is
+ * sigma_g = Pbar_e + C_V (eps_g - epsbar_e), C_V the volume average of the
+ * micro elasticity (the RVE's fluctuation cannot follow the strain variation
+ * inside the element), the element tangent is
+ *   sum_g wdet_g B_g^T C_V B_g + V_e Bbar^T (Cbar_e - C_V) Bbar,
+ * Bbar = sum_g wdet_g B_g / V_e, V_e = sum_g wdet_g, the micro residual
+ * weight is V_e / |Omega|, and dw_e = -(x_r + X_F Bbar dq_e). */
 int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* stream);
 
 /* Inner RVE equilibration of the classical scheme (Sec. 4.1, the micro

@@ -59,6 +59,7 @@ struct fe2_ctx {
   int dim = 0, kin = 0, mat = 0, nF = 0, nen = 0, n_gp = 0;
   int n_nodes = 0, n_elems = 0, n_rve = 0, ndof = 0, bw = 0, nnz = 0, n_pp = 0;
   int precision = 0, solver = 0, scheme = 0;
+  int basis = FE2_BASIS_DIRAC, n_qp = 0;
   double rve_size = 1.0, volume = 1.0;
   double rve_tol = 1e-10, inner_tol = 1e-4, newton_tol = 1e-10, micro_tol = 1e-13;
   int max_pcg_it = 2000, max_ir = 8, max_micro_it = 30;
@@ -67,6 +68,7 @@ struct fe2_ctx {
   int *conn = nullptr, *is_dir = nullptr, *vec_ptr = nullptr, *vec_src = nullptr;
   int *nz_ptr = nullptr, *nz_col = nullptr, *nzc_ptr = nullptr, *nzc_src = nullptr;
   double *X = nullptr, *dNdX = nullptr, *wdet = nullptr, *f_ext = nullptr, *dir_full = nullptr;
+  double* vol = nullptr;          // [n_rve] micro residual weight (wdet or element volume)
   // RVE batch
   int64_t* phase_off = nullptr;
   uint8_t* phase = nullptr;
@@ -124,6 +126,11 @@ struct fe2_ctx {
     m.X = X;
     m.dNdX = dNdX;
     m.wdet = wdet;
+    m.basis = basis;
+    m.n_qp = n_qp;
+    m.vol = vol;
+    m.kpar = params;
+    m.phi = phi;
     m.f_ext = f_ext;
     m.is_dir = is_dir;
     m.dir_full = dir_full;
@@ -220,7 +227,7 @@ void free_ctx(fe2_ctx* h) {
                   h->f_true, h->f_hat, h->ke, h->band, h->rhs, h->du, h->r_true, h->f_int,
                   h->norms_dev, h->kdense, h->mv64, h->thr2, h->count, h->eq_skip, h->surr_norm, h->phi,
                   h->surrP, h->surrC, h->surr_err, h->surr_X, h->surr_Y, h->accept, h->banned, h->okf,
-                  h->bcr_ws};
+                  h->bcr_ws, h->vol};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& c : h->classes) {
@@ -241,8 +248,13 @@ int validate(const fe2_problem_desc* d) {
   if (d->dim != 2 && d->dim != 3) return set_error("dim must be 2 or 3"), FE2_EINVAL;
   if (d->n_nodes <= 0 || d->n_elems <= 0 || !d->X || !d->conn)
     return set_error("empty macro mesh"), FE2_EINVAL;
-  const int ngp = d->dim == 2 ? 4 : 8;
-  if (d->n_rve != d->n_elems * ngp) return set_error("n_rve must equal n_elems * 2^dim"), FE2_EINVAL;
+  if (d->macro_basis != FE2_BASIS_DIRAC && d->macro_basis != FE2_BASIS_ELEMENT)
+    return set_error("unknown macro_basis"), FE2_EINVAL;
+  const int rves_per_elem = d->macro_basis == FE2_BASIS_ELEMENT ? 1 : (d->dim == 2 ? 4 : 8);
+  if (d->n_rve != d->n_elems * rves_per_elem)
+    return set_error(d->macro_basis == FE2_BASIS_ELEMENT ? "n_rve must equal n_elems with the element basis"
+                                                         : "n_rve must equal n_elems * 2^dim"),
+           FE2_EINVAL;
   if (!d->rve_res || !d->rve_off || !d->phase_id || !d->phase_params)
     return set_error("missing RVE arrays"), FE2_EINVAL;
   if (d->n_dir < 0 || (d->n_dir > 0 && (!d->dir_dofs || !d->dir_vals)))
@@ -330,6 +342,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   h->n_nodes = d->n_nodes;
   h->n_elems = d->n_elems;
   h->n_rve = d->n_rve;
+  h->basis = d->macro_basis;
+  h->n_qp = d->n_elems * h->n_gp;
   h->ndof = d->n_nodes * d->dim;
   h->n_pp = d->n_phase_params;
   h->precision = d->precision;
@@ -348,6 +362,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   // supported combinations
   const bool finite = h->kin == FE2_FINITE_STRAIN;
   if (h->dim == 3 && finite) return set_error("3D RVEs are supported for small strain only"), FE2_ENOTSUP;
+  if (h->basis == FE2_BASIS_ELEMENT && finite)
+    return set_error("the element basis of the fluctuation is implemented for small strain"), FE2_ENOTSUP;
   if (!finite && (h->mat != FE2_LINEAR_ISO || h->n_pp != 2))
     return set_error("small strain takes FE2_LINEAR_ISO with (lambda, mu) per phase"), FE2_EINVAL;
   if (finite && !((h->mat == FE2_NEO_HOOKE && h->n_pp == 2) || (h->mat == FE2_MOONEY_RIVLIN && h->n_pp == 3)))
@@ -455,8 +471,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
 
   // device state and work buffers
   const size_t nr = h->n_rve, nF = h->nF, nd = static_cast<size_t>(h->nen) * h->dim;
-  if ((rc = dalloc(&h->dNdX, nr * h->nen * h->dim))) return rc;
-  if ((rc = dalloc(&h->wdet, nr))) return rc;
+  const size_t nq = h->n_qp;
+  if ((rc = dalloc(&h->dNdX, nq * h->nen * h->dim))) return rc;
+  if ((rc = dalloc(&h->wdet, nq))) return rc;
+  if ((rc = dalloc(&h->vol, nr))) return rc;
   if ((rc = dalloc(&h->u, h->ndof))) return rc;
   if ((rc = dalloc(&h->w, h->field_len))) return rc;
   if ((rc = dalloc(&h->r, h->field_len))) return rc;
@@ -509,7 +527,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
 
   // macro geometry
   MacroArgs m = h->margs();
-  hipLaunchKernelGGL(k_macro_geometry, dim3(nblk(nr, 128)), dim3(128), 0, s, m);
+  hipLaunchKernelGGL(k_macro_geometry, dim3(nblk(nq, 128)), dim3(128), 0, s, m);
+  hipLaunchKernelGGL(k_rve_weight, dim3(nblk(nr, 128)), dim3(128), 0, s, m);
   FE2_HIP_CHECK(hipGetLastError());
 
   // RVE classes: work lists and reference tables
@@ -666,7 +685,7 @@ int residual_impl(fe2_ctx* h, double lam, hipStream_t s) {
   MacroArgs m = h->margs();
   const int nd = h->nen * h->dim;
   hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(static_cast<size_t>(h->n_elems) * nd, 128)), dim3(128), 0, s, m,
-                     h->Pbar, h->f_true);
+                     h->Pbar, h->f_true, h->u);
   hipLaunchKernelGGL(k_macro_rows_vec, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->f_true,
                      static_cast<const double*>(nullptr), lam, h->r_true, h->f_int, static_cast<double*>(nullptr));
   hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, s, m, h->r_true, h->f_int, h->rnorm2, h->volume,
@@ -679,7 +698,7 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
   MacroArgs m = h->margs();
   const int nd = h->nen * h->dim;
   const size_t ne_rows = static_cast<size_t>(h->n_elems) * nd;
-  hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(ne_rows, 128)), dim3(128), 0, s, m, h->Phat, h->f_hat);
+  hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(ne_rows, 128)), dim3(128), 0, s, m, h->Phat, h->f_hat, h->u);
   hipLaunchKernelGGL(k_macro_elem_mat, dim3(nblk(ne_rows, 64)), dim3(64), 0, s, m, h->Cbar, h->ke);
   hipLaunchKernelGGL(k_macro_rows_vec, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->f_true, h->f_hat, lam,
                      static_cast<double*>(nullptr), static_cast<double*>(nullptr), h->rhs);

@@ -10,7 +10,11 @@
 //   * banded Cholesky factorisation and solve in one work-group (the macro
 //     system of Eq. (48));
 //   * fluctuation update dw_b = -(x_r + X_F dF_b) (Eq. (49)) and the residual
-//     norms of the convergence test.
+//     norms of the convergence test;
+//   * the piecewise-constant macro basis of the fluctuation (Eqs.
+//     (constSolution1)-(constSolution2), small strain): RVE b = element e,
+//     driven by the element-average strain, with the in-element strain
+//     variation carried by the volume-averaged elasticity C_V.
 #include "macro.hpp"
 #include "elem3d.hpp"
 
@@ -220,9 +224,10 @@ __device__ __forceinline__ void ref_node(int dim, int a, double* xa) {
   if (dim == 3) xa[2] = a >= 4 ? 1.0 : -1.0;
 }
 
+// Geometry of macro Gauss point q = e * n_gp + g: dN/dX and wdet = w_g det J.
 __global__ void k_macro_geometry(MacroArgs m) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= m.n_rve) return;
+  if (b >= m.n_qp) return;
   const int dim = m.dim, nen = m.nen, ngp = m.n_gp;
   const int e = b / ngp, g = b % ngp;
   const double gq = 0.57735026918962576451;
@@ -277,8 +282,22 @@ __global__ void k_macro_geometry(MacroArgs m) {
   m.wdet[b] = det;
 }
 
+// Weight of RVE b in the micro residual rows: wdet of its Gauss point (Dirac
+// basis) or the element volume V_e = sum_g wdet_g (element basis).
+__global__ void k_rve_weight(MacroArgs m) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= m.n_rve) return;
+  if (m.basis == FE2_BASIS_ELEMENT) {
+    double v = 0.0;
+    for (int g = 0; g < m.n_gp; ++g) v += m.wdet[b * m.n_gp + g];
+    m.vol[b] = v;
+  } else {
+    m.vol[b] = m.wdet[b];
+  }
+}
+
 // macro strain-displacement (small) or gradient (finite) operator entry
-// B[i][col] of RVE b, col = a*dim + c.
+// B[i][col] at Gauss point q (= b with the Dirac basis), col = a*dim + c.
 __device__ __forceinline__ double macro_B(const MacroArgs& m, int b, int i, int col) {
   const int dim = m.dim;
   const int a = col / dim, c = col % dim;
@@ -304,17 +323,56 @@ __device__ __forceinline__ double macro_B(const MacroArgs& m, int b, int i, int 
   }
 }
 
-// a2: macro gradient of every RVE from the displacement u = q - X.
+// Element-average operator Bbar[i][col] = sum_g wdet_g B_g[i][col] / V_e.
+__device__ __forceinline__ double macro_Bbar(const MacroArgs& m, int e, int i, int col) {
+  double v = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int q = e * m.n_gp + g;
+    v += m.wdet[q] * macro_B(m, q, i, col);
+  }
+  return v / m.vol[e];
+}
+
+// Gradient operator of RVE b: B_b (Dirac basis) or Bbar_e (element basis).
+__device__ __forceinline__ double rve_B(const MacroArgs& m, int b, int i, int col) {
+  return m.basis == FE2_BASIS_ELEMENT ? macro_Bbar(m, b, i, col) : macro_B(m, b, i, col);
+}
+
+__device__ __forceinline__ int elem_of_rve(const MacroArgs& m, int b) {
+  return m.basis == FE2_BASIS_ELEMENT ? b : b / m.n_gp;
+}
+
+// Volume average C_V of the micro elasticity of RVE b (small strain, Voigt
+// with engineering shear): (1 - phi) C(lambda_0, mu_0) + phi C(lambda_1, mu_1),
+// phi the phase-1 fraction (all RVE elements have the same volume).
+__device__ __forceinline__ void voigt_average(const MacroArgs& m, int b, double (&C)[36]) {
+  const double* p = m.kpar + static_cast<size_t>(b) * 4;
+  const double f = m.phi[b];
+  const double lam = (1.0 - f) * p[0] + f * p[2];
+  const double mu = (1.0 - f) * p[1] + f * p[3];
+  const int nF = m.nF, nn = m.dim;   // normal components come first
+  for (int i = 0; i < nF; ++i)
+    for (int j = 0; j < nF; ++j) {
+      double v = 0.0;
+      if (i < nn && j < nn) v = lam + (i == j ? 2.0 * mu : 0.0);
+      else if (i == j) v = mu;
+      C[i * nF + j] = v;
+    }
+}
+
+// a2: macro gradient of every RVE from the displacement u = q - X (element
+// basis: the element average, exact for the RVE's residual, which is linear
+// in the macro strain).
 __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* __restrict__ out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= m.n_rve) return;
-  const int e = b / m.n_gp;
+  const int e = elem_of_rve(m, b);
   const int nd = m.nen * m.dim;
   for (int i = 0; i < m.nF; ++i) {
     double v = 0.0;
     for (int col = 0; col < nd; ++col) {
       const int node = m.conn[e * m.nen + col / m.dim];
-      v += macro_B(m, b, i, col) * u[node * m.dim + col % m.dim];
+      v += rve_B(m, b, i, col) * u[node * m.dim + col % m.dim];
     }
     if (m.kin == FE2_FINITE_STRAIN && (i / m.dim) == (i % m.dim)) v += 1.0;
     out[static_cast<size_t>(b) * m.nF + i] = v;
@@ -322,25 +380,57 @@ __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* 
 }
 
 // a7 (part): element residual vectors  f = sum_g wdet B^T P  for P = Pbar
-// (true residual) and P = Phat (condensed right-hand side).  One thread per
-// (element, row).
-__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f) {
+// (true residual) and P = Phat (condensed right-hand side).  Element basis:
+// P_g = P_e + C_V (eps_g - epsbar_e) at Gauss point g, from the current
+// displacement u.  One thread per (element, row).
+__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f,
+                                 const double* __restrict__ u) {
   const int nd = m.nen * m.dim;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_elems * nd) return;
   const int e = t / nd, row = t % nd;
+  const int nF = m.nF;
   double v = 0.0;
-  for (int g = 0; g < m.n_gp; ++g) {
-    const int b = e * m.n_gp + g;
-    double s = 0.0;
-    for (int i = 0; i < m.nF; ++i) s += macro_B(m, b, i, row) * P[static_cast<size_t>(b) * m.nF + i];
-    v += m.wdet[b] * s;
+  if (m.basis == FE2_BASIS_ELEMENT) {
+    double ue[24], CV[36], eps[8][6], ebar[6];
+    for (int col = 0; col < nd; ++col) ue[col] = u[m.conn[e * m.nen + col / m.dim] * m.dim + col % m.dim];
+    voigt_average(m, e, CV);
+    for (int i = 0; i < nF; ++i) ebar[i] = 0.0;
+    for (int g = 0; g < m.n_gp; ++g) {
+      const int q = e * m.n_gp + g;
+      for (int i = 0; i < nF; ++i) {
+        double s = 0.0;
+        for (int col = 0; col < nd; ++col) s += macro_B(m, q, i, col) * ue[col];
+        eps[g][i] = s;
+        ebar[i] += m.wdet[q] * s;
+      }
+    }
+    for (int i = 0; i < nF; ++i) ebar[i] /= m.vol[e];
+    const double* Pe = P + static_cast<size_t>(e) * nF;
+    for (int g = 0; g < m.n_gp; ++g) {
+      const int q = e * m.n_gp + g;
+      double s = 0.0;
+      for (int i = 0; i < nF; ++i) {
+        double pg = Pe[i];
+        for (int j = 0; j < nF; ++j) pg += CV[i * nF + j] * (eps[g][j] - ebar[j]);
+        s += macro_B(m, q, i, row) * pg;
+      }
+      v += m.wdet[q] * s;
+    }
+  } else {
+    for (int g = 0; g < m.n_gp; ++g) {
+      const int b = e * m.n_gp + g;
+      double s = 0.0;
+      for (int i = 0; i < nF; ++i) s += macro_B(m, b, i, row) * P[static_cast<size_t>(b) * nF + i];
+      v += m.wdet[b] * s;
+    }
   }
   f[t] = v;
 }
 
-// a7 (part): element tangents  k = sum_g wdet B^T Cbar B, one thread per
-// (element, row).
+// a7 (part): element tangents  k = sum_g wdet B^T Cbar B (Dirac basis) or
+// sum_g wdet_g B_g^T C_V B_g + V_e Bbar^T (Cbar_e - C_V) Bbar (element
+// basis), one thread per (element, row).
 __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke) {
   const int nd = m.nen * m.dim;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -349,9 +439,12 @@ __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, dou
   const int nF = m.nF;
   double acc[24];
   for (int c = 0; c < nd; ++c) acc[c] = 0.0;
+  const bool element = m.basis == FE2_BASIS_ELEMENT;
+  double CV[36];
+  if (element) voigt_average(m, e, CV);
   for (int g = 0; g < m.n_gp; ++g) {
     const int b = e * m.n_gp + g;
-    const double* C = Cb + static_cast<size_t>(b) * nF * nF;
+    const double* C = element ? CV : Cb + static_cast<size_t>(b) * nF * nF;
     double tj[9];
     for (int j = 0; j < nF; ++j) {
       double s = 0.0;
@@ -361,6 +454,20 @@ __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, dou
     for (int c = 0; c < nd; ++c) {
       double s = 0.0;
       for (int j = 0; j < nF; ++j) s += tj[j] * macro_B(m, b, j, c);
+      acc[c] += s;
+    }
+  }
+  if (element) {
+    const double* C = Cb + static_cast<size_t>(e) * nF * nF;
+    double tj[6];
+    for (int j = 0; j < nF; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < nF; ++i) s += macro_Bbar(m, e, i, row) * (C[i * nF + j] - CV[i * nF + j]);
+      tj[j] = s * m.vol[e];
+    }
+    for (int c = 0; c < nd; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < nF; ++j) s += tj[j] * macro_Bbar(m, e, j, c);
       acc[c] += s;
     }
   }
@@ -441,22 +548,22 @@ __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__
   if (i < n) y[i] += x[i];
 }
 
-// a9: dF_b = B_b du_e; w_b -= x_r + X_F dF_b (generalized) or X_F dF_b
-// (classical predictor).  One work-group per RVE.
+// a9: dF_b = B_b du_e (element basis: Bbar_e du_e); w_b -= x_r + X_F dF_b
+// (generalized) or X_F dF_b (classical predictor).  One work-group per RVE.
 __global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
                            const double* __restrict__ X, double* __restrict__ w, int use_xr,
                            const int* __restrict__ skip) {
   const int b = blockIdx.x;
   if (skip && skip[b]) return;
   __shared__ double dF[9];
-  const int e = b / m.n_gp;
+  const int e = elem_of_rve(m, b);
   const int nd = m.nen * m.dim;
   if (threadIdx.x < m.nF) {
     const int i = threadIdx.x;
     double v = 0.0;
     for (int col = 0; col < nd; ++col) {
       const int node = m.conn[e * m.nen + col / m.dim];
-      v += macro_B(m, b, i, col) * du[node * m.dim + col % m.dim];
+      v += rve_B(m, b, i, col) * du[node * m.dim + col % m.dim];
     }
     dF[i] = v;
   }
@@ -528,7 +635,8 @@ __global__ void k_copy_mask(int n, const int* __restrict__ src, int* __restrict_
 }
 
 // Norms of the convergence test: out = [||[R_free; R_micro]||, ||R_free||,
-// ||R_micro||, ||F_int||] with R_micro,b = wdet_b / |Omega| r_b.
+// ||R_micro||, ||F_int||] with R_micro,b = vol_b / |Omega| r_b (vol_b: wdet of
+// the Gauss point, or the element volume with the element basis).
 __global__ void __launch_bounds__(1024) k_norms(MacroArgs m, const double* __restrict__ r_true,
                                                 const double* __restrict__ f_int,
                                                 const double* __restrict__ rnorm2, double volume,
@@ -540,7 +648,7 @@ __global__ void __launch_bounds__(1024) k_norms(MacroArgs m, const double* __res
     s[2] += f_int[i] * f_int[i];
   }
   for (int b = threadIdx.x; b < m.n_rve; b += blockDim.x) {
-    const double sc = m.wdet[b] / volume;
+    const double sc = m.vol[b] / volume;
     s[1] += sc * sc * rnorm2[b];
   }
   for (int k = 0; k < 3; ++k) s[k] = wave_sum(s[k]);

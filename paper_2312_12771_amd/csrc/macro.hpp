@@ -9,10 +9,15 @@ namespace fe2 {
 
 struct MacroArgs {
   int n_rve, dim, nen, n_gp, nF, kin, n_elems, ndof, bw;
+  int basis;              // FE2_BASIS_DIRAC or FE2_BASIS_ELEMENT
+  int n_qp;               // macro Gauss points, n_elems * n_gp
   const int* conn;        // [n_elems][nen]
   const double* X;        // [n_nodes][dim]
-  double* dNdX;           // [n_rve][nen][dim]
-  double* wdet;           // [n_rve]
+  double* dNdX;           // [n_qp][nen][dim]
+  double* wdet;           // [n_qp]
+  double* vol;            // [n_rve] weight of the RVE's micro residual rows
+  const double* kpar;     // [n_rve][2][2] (lambda, mu) per phase (small strain)
+  const double* phi;      // [n_rve] phase-1 volume fraction
   const double* f_ext;    // [ndof] or null
   const int* is_dir;      // [ndof]
   const double* dir_full; // [ndof] prescribed value at load factor 1 (0 on free DOFs)
@@ -29,8 +34,10 @@ constexpr int REF2_TABLE = 54;    // kv[10] | KwF[8*3] | KFF[9] | error | mode c
 __global__ void k_ref_tables_3d(double h, double rho, double* out);
 constexpr int REF3_TABLE = 191;   // kv[10] | KwF[24*6] | KFF[36] | error
 __global__ void k_macro_geometry(MacroArgs m);
+__global__ void k_rve_weight(MacroArgs m);
 __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* __restrict__ out);
-__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f);
+__global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f,
+                                 const double* __restrict__ u);
 __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke);
 __global__ void k_macro_rows_vec(MacroArgs m, const double* __restrict__ f_true,
                                  const double* __restrict__ f_hat, double lam,

@@ -21,6 +21,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run paper_2312_12771_amd/build.py "
                       "(or __graft_entry__.build()) first")
 _lib = C.CDLL(LIB_PATH)
+FE2_ABI_VERSION = 2
 
 # status codes and enums (include/fe2.h)
 FE2_OK, FE2_CONVERGED = 0, 1
@@ -30,6 +31,7 @@ FE2_LINEAR_ISO, FE2_NEO_HOOKE, FE2_MOONEY_RIVLIN = 0, 1, 2
 FE2_PREC_FP64, FE2_PREC_FP32_IR = 0, 1
 FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT = 0, 1, 2
 FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
+FE2_BASIS_DIRAC, FE2_BASIS_ELEMENT = 0, 1
 (FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
  FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
  FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64, FE2_D_PHASE_FRACTION,
@@ -60,6 +62,7 @@ class fe2_problem_desc(C.Structure):
         ("rve_tol", C.c_double), ("inner_tol", C.c_double),
         ("newton_tol", C.c_double), ("micro_tol", C.c_double),
         ("max_pcg_it", C.c_int32), ("max_ir", C.c_int32), ("max_micro_it", C.c_int32),
+        ("macro_basis", C.c_int32),
     ]
 
 
@@ -103,6 +106,9 @@ for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
     _f.restype = _r
     _f.argtypes = _a
+if _lib.fe2_abi_version() != FE2_ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI version {_lib.fe2_abi_version()}, this binding expects "
+                      f"{FE2_ABI_VERSION}: rebuild the library")
 
 
 class FE2Error(RuntimeError):
@@ -170,12 +176,13 @@ def _arr(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
-def fe2_setup(problem, precision: str = "fp64", solver: str = "auto",
+def make_desc(problem, precision: str = "fp64", solver: str = "auto",
               scheme: str = "generalized", rve_tol: float = 1e-10, inner_tol: float = 1e-5,
               newton_tol: float = 1e-10, micro_tol: float = 1e-13, max_pcg_it: int = 4000,
-              max_ir: int = 8, max_micro_it: int = 30, stream=None) -> Handle:
-    """Create a handle from a problem description (any object with the
-    attributes of workloads.Problem)."""
+              max_ir: int = 8, max_micro_it: int = 30):
+    """fe2_problem_desc of a problem description (any object with the
+    attributes of workloads.Problem).  Returns (desc, keep): ``keep`` holds
+    the arrays the descriptor points into and must outlive its use."""
     keep = dict(
         X=_arr(problem.X, np.float64), conn=_arr(problem.conn, np.int32),
         dd=_arr(problem.dir_dofs, np.int32), dv=_arr(problem.dir_vals, np.float64),
@@ -208,8 +215,22 @@ def fe2_setup(problem, precision: str = "fp64", solver: str = "auto",
     d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL}[scheme]
     d.rve_tol, d.inner_tol, d.newton_tol, d.micro_tol = rve_tol, inner_tol, newton_tol, micro_tol
     d.max_pcg_it, d.max_ir, d.max_micro_it = max_pcg_it, max_ir, max_micro_it
+    d.macro_basis = {"dirac": FE2_BASIS_DIRAC, "element": FE2_BASIS_ELEMENT}[
+        getattr(problem, "macro_basis", "dirac")]
+    return d, keep
+
+
+def fe2_setup(problem, precision: str = "fp64", solver: str = "auto",
+              scheme: str = "generalized", rve_tol: float = 1e-10, inner_tol: float = 1e-5,
+              newton_tol: float = 1e-10, micro_tol: float = 1e-13, max_pcg_it: int = 4000,
+              max_ir: int = 8, max_micro_it: int = 30, stream=None) -> Handle:
+    """Create a handle from a problem description (any object with the
+    attributes of workloads.Problem)."""
+    d, keep = make_desc(problem, precision, solver, scheme, rve_tol, inner_tol, newton_tol,
+                        micro_tol, max_pcg_it, max_ir, max_micro_it)
     out = _vp()
     _check(_lib.fe2_setup(C.byref(d), _stream_ptr(stream), C.byref(out)), "fe2_setup")
+    del keep
     return Handle(out)
 
 
