@@ -60,6 +60,10 @@ WORKLOADS = {
     "cfg4": dict(desc="3D linear, macro 8x8x8 hex8 (4096 RVEs), RVE 10x10x10 hex8 centred sphere vf 0.2, "
                       "E ratio 10, nu 0.3, uniaxial 1e-3",
                  lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
+    "cfg2_element": dict(desc="the 2D linear workload (macro 64x64 Q4, RVE 32x32 Q4 centred circle vf 0.3, E ratio "
+                              "lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3) with the piecewise-"
+                              "constant macro basis of the fluctuation: one RVE per macro element (4096 RVEs)",
+                         base="cfg2", element=True, lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
     "cfg5": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
                       "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; first Newton iteration of the first of ten "
                       "load increments (u_x = 0.01)",
@@ -194,7 +198,9 @@ def main():
     torch.cuda.set_device(0)
     t = time.perf_counter()
     wl = WORKLOADS[args.workload]
-    p = W.config(args.workload)
+    p = W.config(wl.get("base", args.workload))
+    if wl.get("element"):
+        p = W.element_basis(p)
     log(f"workload {args.workload} built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
 
     if args.copy_probe:
