@@ -16,6 +16,9 @@ tensors   cross product, cofactor, determinant (Sec. 2.1, Eqs. (1)-(2)) and
 rve       RVE element integration, periodic null-space reduction and static
           condensation (Sec. 3, Eqs. (34)-(35); Sec. 4, Eqs. (39)-(49)).
 macro     macro FE, the generalized (monolithic, Sec. 4.2) and classical
-          (staggered, Sec. 4.1) Newton schemes and the full block solve
-          (Eq. (42)).
+          (staggered, Sec. 4.1) Newton schemes, the full block solve
+          (Eq. (42)) and the piecewise-constant macro basis of the
+          fluctuation.
+oned      the 1+1D benchmark of Sec. 5.1: closed form, the six
+          discretisations and their L2 errors.
 """
