@@ -357,6 +357,45 @@ int fe2_surrogate_detach(fe2_handle h);
  * by this call. */
 int fe2_surrogate_judge(fe2_handle h, double tol, double* max_err_host, int* n_rejected_host, void* stream);
 
+/*
+ * 1+1-dimensional FE^2 (Sec. 5.1): macro bar (0, macro_length) with n_macro
+ * Lagrange elements of order `order` (1 or 2, equally spaced nodes), RVE
+ * (0, 1) with n_micro elements of the same order, micro energy
+ * lambda(X~) (F~^2 - 1) (so P~ = 2 lambda F~), uniform body load, prescribed
+ * phi at both macro ends and zero fluctuation at both RVE ends (condition (ii)
+ * of Eq. (15)).  The macro rule has order + 1 Gauss points per element; RVEs
+ * sit at them (basis FE2_BASIS_DIRAC, RVE b = element * (order + 1) + g) or
+ * one per macro element (FE2_BASIS_ELEMENT, RVE b = element).  The RVE is
+ * integrated with 5 Gauss-Legendre points per element; lambda_gp gives lambda
+ * at those points, [n_micro][5], points ordered from -0.906 to 0.906 on the
+ * element's reference interval (read during setup and copied).
+ * Limits: n_micro <= 4096, n_macro <= 2^20.  Errors: FE2_EINVAL.
+ */
+typedef struct fe2_1d_desc {
+  int32_t struct_size;
+  int32_t order, n_macro, n_micro, basis;
+  double macro_length, body_load, phi_left, phi_right;
+  const double* lambda_gp;
+} fe2_1d_desc;
+typedef struct fe2_1d_ctx* fe2_1d_handle;
+
+/* Set up the RVE matrices, factor the (shared) RVE stiffness once, and start
+ * from phi linear between the boundary values and w~ = 0. */
+int fe2_1d_setup(const fe2_1d_desc* desc, void* stream, fe2_1d_handle* out);
+/* One generalized Newton iteration (Eqs. (46)-(49)) with the basis of the
+ * handle: per-RVE residual and solve for x_r, condensation, FP64 macro
+ * assembly and banded solve, update.  norms_host (may be NULL) receives the
+ * norms of the state the call started from, as fe2_newton_step.  Waits on
+ * `stream`. */
+int fe2_1d_newton_step(fe2_1d_handle h, double* norms_host, void* stream);
+/* phi_dev [order * n_macro + 1] nodal macro deformation; w_dev [n_rve][n_int]
+ * fluctuation at the interior RVE nodes (n_int = order * n_micro - 1), in
+ * node order; either may be NULL. */
+int fe2_1d_get_state(fe2_1d_handle h, double* phi_dev, double* w_dev, void* stream);
+enum { FE2_1D_Q_N_PHI = 0, FE2_1D_Q_N_RVE = 1, FE2_1D_Q_N_INT = 2 };
+int fe2_1d_query(fe2_1d_handle h, int which, int64_t* out);
+int fe2_1d_destroy(fe2_1d_handle h);
+
 const char* fe2_strerror(int status);
 const char* fe2_last_error(void);
 int fe2_abi_version(void);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe2.so")
-SOURCES = ["api.hip", "macro.hip", "bcr.hip", "rve_lin2d.hip", "rve_fin2d.hip", "rve_lin3d.hip", "mlp.hip", "surrogate.hip"]
+SOURCES = ["api.hip", "macro.hip", "bcr.hip", "rve_lin2d.hip", "rve_fin2d.hip", "rve_lin3d.hip", "mlp.hip", "surrogate.hip", "oned.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

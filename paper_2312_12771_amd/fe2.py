@@ -66,6 +66,18 @@ class fe2_problem_desc(C.Structure):
     ]
 
 
+class fe2_1d_desc(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32),
+        ("order", C.c_int32), ("n_macro", C.c_int32), ("n_micro", C.c_int32), ("basis", C.c_int32),
+        ("macro_length", C.c_double), ("body_load", C.c_double),
+        ("phi_left", C.c_double), ("phi_right", C.c_double),
+        ("lambda_gp", C.POINTER(C.c_double)),
+    ]
+
+
+FE2_1D_Q_N_PHI, FE2_1D_Q_N_RVE, FE2_1D_Q_N_INT = 0, 1, 2
+
 _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
 _sig = {
@@ -98,6 +110,11 @@ _sig = {
     "fe2_surrogate_detach": (C.c_int, [_vp]),
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
     "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
+    "fe2_1d_setup": (C.c_int, [C.POINTER(fe2_1d_desc), _vp, C.POINTER(_vp)]),
+    "fe2_1d_newton_step": (C.c_int, [_vp, _dp, _vp]),
+    "fe2_1d_get_state": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "fe2_1d_query": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int64)]),
+    "fe2_1d_destroy": (C.c_int, [_vp]),
     "fe2_strerror": (C.c_char_p, [C.c_int]),
     "fe2_last_error": (C.c_char_p, []),
     "fe2_abi_version": (C.c_int, []),
@@ -451,3 +468,68 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# 1+1D problem of Sec. 5.1
+# ---------------------------------------------------------------------------
+
+class Handle1D:
+    """Owns an fe2_1d_handle."""
+
+    def __init__(self, ptr):
+        self._ptr = ptr
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("handle is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr is not None:
+            _lib.fe2_1d_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_desc_1d(problem):
+    """fe2_1d_desc of a workloads.OneDProblem; returns (desc, keep)."""
+    lam = _arr(problem.lambda_gp, np.float64)
+    d = fe2_1d_desc()
+    d.struct_size = C.sizeof(fe2_1d_desc)
+    d.order, d.n_macro, d.n_micro = int(problem.order), int(problem.n_macro), int(problem.n_micro)
+    d.basis = {"dirac": FE2_BASIS_DIRAC, "element": FE2_BASIS_ELEMENT}[problem.basis]
+    d.macro_length, d.body_load = float(problem.macro_length), float(problem.body_load)
+    d.phi_left, d.phi_right = float(problem.phi_left), float(problem.phi_right)
+    d.lambda_gp = lam.ctypes.data_as(_dp)
+    return d, lam
+
+
+def fe2_1d_setup(problem, stream=None) -> Handle1D:
+    d, keep = make_desc_1d(problem)
+    out = _vp()
+    _check(_lib.fe2_1d_setup(C.byref(d), _stream_ptr(stream), C.byref(out)), "fe2_1d_setup")
+    del keep
+    return Handle1D(out)
+
+
+def fe2_1d_newton_step(h: Handle1D, stream=None):
+    norms = np.zeros(4)
+    _check(_lib.fe2_1d_newton_step(h.ptr, norms.ctypes.data_as(_dp), _stream_ptr(stream)), "fe2_1d_newton_step")
+    return norms
+
+
+def fe2_1d_query(h: Handle1D, which: int) -> int:
+    v = C.c_int64(0)
+    _check(_lib.fe2_1d_query(h.ptr, which, C.byref(v)), "fe2_1d_query")
+    return int(v.value)
+
+
+def fe2_1d_get_state(h: Handle1D, phi=None, w=None, stream=None):
+    _check(_lib.fe2_1d_get_state(h.ptr, _dev_ptr(phi), _dev_ptr(w), _stream_ptr(stream)), "fe2_1d_get_state")

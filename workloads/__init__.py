@@ -20,6 +20,8 @@ from .generators import (  # noqa: F401
     phases_cross,
     subset_problem,
     element_basis,
+    oned_problem,
+    OneDProblem,
     mlp_init,
     cfg5_material_points,
     surrogate_samples,

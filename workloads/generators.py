@@ -508,3 +508,34 @@ def element_basis(p: Problem) -> Problem:
                 raise ValueError(f"the Gauss points of element {e} carry different RVEs")
     q = subset_problem(p, np.arange(p.n_elems) * ng)
     return dataclasses.replace(q, macro_basis="element", name=p.name + "_element")
+
+
+# ---------------------------------------------------------------------------
+# 1+1D benchmark of Sec. 5.1 (material data and boundary data only)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class OneDProblem:
+    order: int                 # Lagrange order q of both scales
+    n_macro: int
+    n_micro: int
+    basis: str                 # "dirac" | "element"
+    macro_length: float
+    body_load: float
+    phi_left: float
+    phi_right: float
+    lambda_gp: np.ndarray      # (n_micro, 5): lambda at the 5 Gauss-Legendre points of each RVE element
+
+
+def oned_problem(k: int, order: int, basis: str = "dirac") -> OneDProblem:
+    """Sec. 5.1 with 2^k macro and 2^k RVE elements: bar (0, 1000), RVE
+    (0, 1), lambda(X~) = 20 / cos(2 pi X~ / 3 - pi / 3) sampled at the RVE
+    quadrature points, B = 1, phi(0) = 0, phi(1000) = 37575 sqrt(3) / (2 pi)."""
+    n = 2 ** k
+    xg, _ = np.polynomial.legendre.leggauss(5)
+    h = 1.0 / n
+    xt = h * np.arange(n)[:, None] + (xg[None, :] + 1.0) * h / 2.0
+    lam = 20.0 / np.cos(2.0 * np.pi / 3.0 * xt - np.pi / 3.0)
+    return OneDProblem(order=order, n_macro=n, n_micro=n, basis=basis, macro_length=1000.0,
+                       body_load=1.0, phi_left=0.0, phi_right=37575.0 * np.sqrt(3.0) / (2.0 * np.pi),
+                       lambda_gp=np.ascontiguousarray(lam))
