@@ -168,6 +168,52 @@ def cpu_baseline(p, seconds):
     return dict(value=len(cb) / el, n=len(cb), seconds=el, cbar=cb)
 
 
+def run_oned(args, fe2, torch, W, k=9, q=2):
+    """The 1+1D problem of Sec. 5.1 with the Dirac basis, 2^k macro and 2^k RVE
+    elements of order q: one generalized Newton step (per-RVE residual and
+    solve, condensation, macro assembly and banded solve, update) from the
+    initial state."""
+    p = W.oned_problem(k, q, "dirac")
+    h = fe2.fe2_1d_setup(p)
+    n_rve = fe2.fe2_1d_query(h, fe2.FE2_1D_Q_N_RVE)
+    n_int = fe2.fe2_1d_query(h, fe2.FE2_1D_Q_N_INT)
+    for _ in range(args.warmup):
+        fe2.fe2_1d_newton_step(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fe2.fe2_1d_newton_step(h)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    h.close()
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle import oned as O
+        kc = 7
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.solve(kc, q, "dirac")
+            el = time.perf_counter() - t0
+        nrc = (2 ** kc) * (q + 1)
+        cpu = dict(value=round(nrc / el, 3), unit="RVE solves/s", cores=1, kind="oracle",
+                   sample=f"whole coupled system at 2^{kc} macro and RVE elements ({nrc} RVEs of "
+                          f"{q * 2 ** kc - 1} DOFs), SciPy sparse direct solve, {el:.2f}s, BLAS threads 1")
+    line = {
+        "metric": "RVE solves/sec (1+1D problem of Sec. 5.1)",
+        "value": round(n_rve / (ms * 1e-3), 1), "unit": "RVE solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"1+1D bar (0,1000) with 2^{k} quadratic macro elements, Dirac basis "
+                               f"({n_rve} RVEs of 2^{k} quadratic elements, {n_int} DOFs each)",
+                   "name": "oned", "n_rve": n_rve, "rve_dofs": n_int},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def rel_frob(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -180,7 +226,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS),
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS) + ["oned"],
                     help="configuration to time (default: the 2D benchmark workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM counter scaling)")
@@ -196,6 +242,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "oned":
+        run_oned(args, fe2, torch, W)
+        return
     t = time.perf_counter()
     wl = WORKLOADS[args.workload]
     p = W.config(wl.get("base", args.workload))

@@ -369,7 +369,8 @@ int fe2_surrogate_judge(fe2_handle h, double tol, double* max_err_host, int* n_r
  * integrated with 5 Gauss-Legendre points per element; lambda_gp gives lambda
  * at those points, [n_micro][5], points ordered from -0.906 to 0.906 on the
  * element's reference interval (read during setup and copied).
- * Limits: n_micro <= 4096, n_macro <= 2^20.  Errors: FE2_EINVAL.
+ * Limits: n_macro <= 2^20 and (order * n_micro - 1) * (order + 3) <= 8192
+ * (the shared RVE factor is staged in 64 KiB of LDS).  Errors: FE2_EINVAL.
  */
 typedef struct fe2_1d_desc {
   int32_t struct_size;

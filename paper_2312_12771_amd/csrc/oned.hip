@@ -187,56 +187,159 @@ __device__ inline int rve_B(const OneD& o, int b, double* B, double* vol) {
 // ---------------------------------------------------------------------------
 // per-RVE work: residual, solve for x_r with the shared factor, condensation
 // ---------------------------------------------------------------------------
-// Vectors are DOF-major: entry i of RVE b at [i * n_rve + b].  r_b = K_wF F_b
-// + K_ww w_b is formed inside the forward sweep; x_r overwrites xr.
-__global__ void k1d_rve(OneD o, const double* __restrict__ phi, const double* __restrict__ w,
-                        const double* __restrict__ kw, const double* __restrict__ rinv,
-                        const double* __restrict__ kfw, const double* __restrict__ scal, double* __restrict__ xr,
-                        double* __restrict__ Fb, double* __restrict__ pbar, double* __restrict__ phat,
-                        double* __restrict__ rn2) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= o.n_rve) return;
-  const int q = o.q, n = o.n_int, nr = o.n_rve, b1 = q + 1;
+// Vectors are DOF-major: entry i of RVE b at [i * n_rve + b], so a wave reads
+// 64 consecutive RVEs per DOF.
+//
+// r_b = K_wF F_b + K_ww w_b, one thread per (DOF, RVE): fully parallel.
+__global__ void k1d_resid(OneD o, const double* __restrict__ phi, const double* __restrict__ w,
+                          const double* __restrict__ kw, const double* __restrict__ kfw, double* __restrict__ r,
+                          double* __restrict__ Fb) {
+  const size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  const int nr = o.n_rve, n = o.n_int, q = o.q, b1 = q + 1;
+  if (t >= static_cast<size_t>(n) * nr) return;
+  const int i = static_cast<int>(t / nr), b = static_cast<int>(t % nr);
   double B[3], vol;
   const int e = rve_B(o, b, B, &vol);
   double F = 0.0;
   for (int a = 0; a <= q; ++a) F += B[a] * phi[q * e + a];
-  Fb[b] = F;
-  // kw holds the lower band of K_ww (kw[i*(q+1) + d] = K(i, i-d)) followed
-  // by the same band of its Cholesky factor
-  const double* Lf = kw + static_cast<size_t>(n) * b1;
-  double pint = F * scal[0];
+  if (i == 0) Fb[b] = F;
+  double ri = kfw[i] * F + kw[i * b1] * w[t];
+  for (int d = 1; d <= q; ++d) {
+    if (i - d >= 0) ri += kw[i * b1 + d] * w[t - static_cast<size_t>(d) * nr];
+    if (i + d < n) ri += kw[(i + d) * b1 + d] * w[t + static_cast<size_t>(d) * nr];
+  }
+  r[t] = ri;
+}
+
+// Forward and backward substitution with the shared Cholesky factor, one
+// lane per RVE.  The factor, its reciprocal pivots and K_Fw are staged in LDS
+// (the same for every lane); the recurrences are sequential in the DOF
+// index, so the per-RVE loads of the next PF DOFs are issued before the
+// current PF steps run (register double buffering), leaving two FMAs and a
+// multiply per DOF on the chain.  Also ||r_b||^2, the stress integral and
+// P_hat (|Omega| = 1).
+constexpr int PF = 16;
+template <int Q>
+__global__ void __launch_bounds__(64) k1d_rve(OneD o, const double* __restrict__ r, const double* __restrict__ w,
+                                              const double* __restrict__ kw, const double* __restrict__ rinv,
+                                              const double* __restrict__ kfw, const double* __restrict__ scal,
+                                              const double* __restrict__ Fb, double* __restrict__ xr,
+                                              double* __restrict__ pbar, double* __restrict__ phat,
+                                              double* __restrict__ rn2) {
+  extern __shared__ double s_fac[];
+  constexpr int B1 = Q + 1;
+  const int n = o.n_int, nr = o.n_rve;
+  // kw holds the lower band of K_ww (kw[i*(q+1) + d] = K(i, i-d), zero for
+  // i < d) followed by the same band of its Cholesky factor
+  double* Lf = s_fac;                                   // [n][Q+1]
+  double* s_ri = s_fac + static_cast<size_t>(n) * B1;   // [n]
+  double* s_kf = s_ri + n;                              // [n]
+  for (int k = threadIdx.x; k < n * B1; k += blockDim.x) Lf[k] = kw[static_cast<size_t>(n) * B1 + k];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    s_ri[k] = rinv[k];
+    s_kf[k] = kfw[k];
+  }
+  __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nr) return;
+  const double* rb = r + b;
+  const double* wb = w + b;
+  double* xb = xr + b;
+  auto at = [&](int i) { return static_cast<size_t>(i) * nr; };
+  double pint = Fb[b] * scal[0];
   double r2 = 0.0;
+  // ---- forward: L y = r.  Full chunks [0, nf) without bounds tests (the
+  // factor's entries above the first rows are zero), then the tail.
   double y1 = 0.0, y2 = 0.0;   // y_{i-1}, y_{i-2}
-  for (int i = 0; i < n; ++i) {
-    const double wi = w[static_cast<size_t>(i) * nr + b];
-    double ri = kfw[i] * F + kw[i * b1] * wi;
-    for (int d = 1; d <= q; ++d) {
-      if (i - d >= 0) ri += kw[i * b1 + d] * w[static_cast<size_t>(i - d) * nr + b];
-      if (i + d < n) ri += kw[(i + d) * b1 + d] * w[static_cast<size_t>(i + d) * nr + b];
+  const int nf = (n / PF) * PF;
+  double rc[PF], wc[PF], rn[PF], wn[PF], out[PF];
+  if (nf > 0) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      rc[j] = rb[at(j)];
+      wc[j] = wb[at(j)];
     }
+  }
+  for (int i0 = 0; i0 < nf; i0 += PF) {
+    if (i0 + PF < nf) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        rn[j] = rb[at(i0 + PF + j)];
+        wn[j] = wb[at(i0 + PF + j)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int i = i0 + j;
+      r2 += rc[j] * rc[j];
+      pint += s_kf[i] * wc[j];
+      double v = rc[j] - Lf[i * B1 + 1] * y1;
+      if constexpr (Q == 2) v -= Lf[i * B1 + 2] * y2;
+      const double yi = v * s_ri[i];
+      out[j] = yi;
+      y2 = y1;
+      y1 = yi;
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) xb[at(i0 + j)] = out[j];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      rc[j] = rn[j];
+      wc[j] = wn[j];
+    }
+  }
+  for (int i = nf; i < n; ++i) {
+    const double ri = rb[at(i)];
     r2 += ri * ri;
-    pint += kfw[i] * wi;
+    pint += s_kf[i] * wb[at(i)];
     double v = ri;
-    if (q >= 1 && i >= 1) v -= Lf[i * b1 + 1] * y1;
-    if (q >= 2 && i >= 2) v -= Lf[i * b1 + 2] * y2;
-    const double yi = v * rinv[i];
-    xr[static_cast<size_t>(i) * nr + b] = yi;
+    if (i >= 1) v -= Lf[i * B1 + 1] * y1;
+    if (Q == 2 && i >= 2) v -= Lf[i * B1 + 2] * y2;
+    const double yi = v * s_ri[i];
+    xb[at(i)] = yi;
     y2 = y1;
     y1 = yi;
   }
+  // ---- backward: L^T x = y.  Tail [m, n) with bounds tests first, then full
+  // chunks below m, where i + Q < n always holds.
+  const int m = n > Q ? ((n - Q) / PF) * PF : 0;
   double x1 = 0.0, x2 = 0.0, fx = 0.0;   // x_{i+1}, x_{i+2}
-  for (int i = n - 1; i >= 0; --i) {
-    double v = xr[static_cast<size_t>(i) * nr + b];
-    if (q >= 1 && i + 1 < n) v -= Lf[(i + 1) * b1 + 1] * x1;
-    if (q >= 2 && i + 2 < n) v -= Lf[(i + 2) * b1 + 2] * x2;
-    const double xi = v * rinv[i];
-    xr[static_cast<size_t>(i) * nr + b] = xi;
-    fx += kfw[i] * xi;
+  for (int i = n - 1; i >= m; --i) {
+    double v = xb[at(i)];
+    if (i + 1 < n) v -= Lf[(i + 1) * B1 + 1] * x1;
+    if (Q == 2 && i + 2 < n) v -= Lf[(i + 2) * B1 + 2] * x2;
+    const double xi = v * s_ri[i];
+    xb[at(i)] = xi;
+    fx += s_kf[i] * xi;
     x2 = x1;
     x1 = xi;
   }
-  pbar[b] = pint;          // |Omega| = 1
+  if (m > 0) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) rc[j] = xb[at(m - 1 - j)];
+  }
+  for (int i0 = m - 1; i0 >= 0; i0 -= PF) {
+    if (i0 - PF >= 0) {
+#pragma unroll
+      for (int j = 0; j < PF; ++j) rn[j] = xb[at(i0 - PF - j)];
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int i = i0 - j;
+      double v = rc[j] - Lf[(i + 1) * B1 + 1] * x1;
+      if constexpr (Q == 2) v -= Lf[(i + 2) * B1 + 2] * x2;
+      const double xi = v * s_ri[i];
+      out[j] = xi;
+      fx += s_kf[i] * xi;
+      x2 = x1;
+      x1 = xi;
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) xb[at(i0 - j)] = out[j];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) rc[j] = rn[j];
+  }
+  pbar[b] = pint;
   phat[b] = pint - fx;
   rn2[b] = r2;
 }
@@ -332,19 +435,18 @@ __global__ void k1d_macro_rows(OneD o, const double* __restrict__ fe_true, const
   rhs[A] = dir ? 0.0 : fext - fh;
 }
 
-// phi += dphi; w_b -= x_r + X_F dF_b
+// w_b -= x_r + X_F dF_b with dF_b from the macro increment, one thread per
+// (DOF, RVE).
 __global__ void k1d_update(OneD o, const double* __restrict__ dphi, const double* __restrict__ xr,
                            const double* __restrict__ xf, double* __restrict__ w) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= o.n_rve) return;
+  const size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (t >= static_cast<size_t>(o.n_int) * o.n_rve) return;
+  const int i = static_cast<int>(t / o.n_rve), b = static_cast<int>(t % o.n_rve);
   double B[3], vol;
   const int e = rve_B(o, b, B, &vol);
   double dF = 0.0;
   for (int a = 0; a <= o.q; ++a) dF += B[a] * dphi[o.q * e + a];
-  for (int i = 0; i < o.n_int; ++i) {
-    const size_t k = static_cast<size_t>(i) * o.n_rve + b;
-    w[k] -= xr[k] + xf[i] * dF;
-  }
+  w[t] -= xr[t] + xf[i] * dF;
 }
 
 __global__ void k1d_axpy(int n, const double* __restrict__ x, double* __restrict__ y) {
@@ -518,7 +620,10 @@ int fe2_1d_setup(const fe2_1d_desc* d, void* stream, fe2_1d_handle* out) {
   if (d->basis != FE2_BASIS_DIRAC && d->basis != FE2_BASIS_ELEMENT) return set_error("unknown basis"), FE2_EINVAL;
   if (d->n_macro < 1 || d->n_micro < 1 || d->order * d->n_micro < 2)
     return set_error("need at least one macro element and one interior RVE node"), FE2_EINVAL;
-  if (d->n_macro > (1 << 20) || d->n_micro > 4096) return set_error("mesh too large"), FE2_EINVAL;
+  if (d->n_macro > (1 << 20)) return set_error("macro mesh too large"), FE2_EINVAL;
+  // the RVE factor, pivots and K_Fw are staged in 64 KiB of LDS
+  if ((static_cast<int64_t>(d->order) * d->n_micro - 1) * (d->order + 3) > 8192)
+    return set_error("RVE too large: (order * n_micro - 1) * (order + 3) must not exceed 8192"), FE2_EINVAL;
   if (!(d->macro_length > 0.0) || !d->lambda_gp) return set_error("bad macro length or material table"), FE2_EINVAL;
   for (int k = 0; k < d->n_micro * NG_MICRO; ++k)
     if (!(d->lambda_gp[k] > 0.0)) return set_error("lambda must be positive"), FE2_EINVAL;
@@ -538,8 +643,11 @@ int fe2_1d_newton_step(fe2_1d_handle h, double* norms_host, void* stream) {
   if (!h) return set_error("null handle"), FE2_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const OneD& o = h->o;
-  hipLaunchKernelGGL(k1d_rve, dim3(nb(o.n_rve, 64)), dim3(64), 0, s, o, h->phi, h->w, h->kw, h->rinv, h->kfw,
-                     h->scal, h->xr, h->Fb, h->pbar, h->phat, h->rn2);
+  const size_t wl = static_cast<size_t>(o.n_int) * o.n_rve;
+  hipLaunchKernelGGL(k1d_resid, dim3(nb(wl, 256)), dim3(256), 0, s, o, h->phi, h->w, h->kw, h->kfw, h->wtmp, h->Fb);
+  const size_t lds = (static_cast<size_t>(o.n_int) * (o.q + 1) + 2 * o.n_int) * sizeof(double);
+  hipLaunchKernelGGL(o.q == 1 ? k1d_rve<1> : k1d_rve<2>, dim3(nb(o.n_rve, 64)), dim3(64), lds, s, o, h->wtmp, h->w, h->kw, h->rinv, h->kfw,
+                     h->scal, h->Fb, h->xr, h->pbar, h->phat, h->rn2);
   hipLaunchKernelGGL(k1d_macro_elem, dim3(nb(o.n_mac, 64)), dim3(64), 0, s, o, h->phi, h->pbar, h->phat, h->scal,
                      h->fe_t, h->fe_h, h->ke);
   hipLaunchKernelGGL(k1d_macro_rows, dim3(nb(o.n_phi, 64)), dim3(64), 0, s, o, h->fe_t, h->fe_h, h->ke, h->band,
@@ -550,7 +658,7 @@ int fe2_1d_newton_step(fe2_1d_handle h, double* norms_host, void* stream) {
   const int rc = bcr_solve(h->plan, h->ws, h->band, h->rhs, h->info, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k1d_axpy, dim3(nb(o.n_phi, 256)), dim3(256), 0, s, o.n_phi, h->rhs, h->phi);
-  hipLaunchKernelGGL(k1d_update, dim3(nb(o.n_rve, 64)), dim3(64), 0, s, o, h->rhs, h->xr, h->xf, h->w);
+  hipLaunchKernelGGL(k1d_update, dim3(nb(wl, 256)), dim3(256), 0, s, o, h->rhs, h->xr, h->xf, h->w);
   FE2_HIP_CHECK(hipGetLastError());
   int info = 0;
   FE2_HIP_CHECK(hipMemcpyAsync(h->norms_host, h->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
