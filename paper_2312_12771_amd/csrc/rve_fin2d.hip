@@ -151,8 +151,13 @@ __host__ __device__ constexpr size_t fin2d_lds_bytes_t(int n1, int n2, int wg, i
   return fin2d_off_u(n1, n2, wg, nrhs, ti) + (a > b ? a : b);
 }
 
+// Occupancy: the FP32 instances are held to two work-groups per CU (256
+// VGPRs per lane) so that the latency of the recomputed tangents overlaps
+// across waves; the FP64 instances keep their full register budget.
+template <typename T> constexpr int kFinMinBlocks = 1;
+template <> constexpr int kFinMinBlocks<float> = 2;
 template <typename TI, int NRHS, int N1, int N2, int WG>
-__global__ void __launch_bounds__(WG) k_fin2d(const Fin2DArgs a) {
+__global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs a) {
   using P = Pad<N1, N2>;
   constexpr int NW = WG / 64;
   constexpr int NN = N1 * N2;
