@@ -207,8 +207,11 @@ __host__ __device__ constexpr size_t lin3d_lds_bytes_t(int n, int wg) {
   return lin3d_vec_offset(n, wg) + 3 * static_cast<size_t>(n + 2) * (n + 2) * (n + 2) * 8;
 }
 
+// Occupancy: FP32 instances are held to three work-groups per CU.
+template <typename T> constexpr int kLin3dMinBlocks = 1;
+template <> constexpr int kLin3dMinBlocks<float> = 3;
 template <typename TI, int NRHS, int N, int WG>
-__global__ void __launch_bounds__(WG) k_lin3d(const Lin2DArgs a) {
+__global__ void __launch_bounds__(WG, kLin3dMinBlocks<TI>) k_lin3d(const Lin2DArgs a) {
   using P = Pad3<N>;
   using rve2d::wg_sum;
   constexpr int NW = WG / 64;
