@@ -92,6 +92,7 @@ __global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __re
 // r; wave-synchronous exchange through LDS); all threads form the panel below
 // with the inverse and apply the trailing update in 4x4 register tiles.
 constexpr int PO_WG = 256;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GlobalTiles {
   double* base;
@@ -183,51 +184,50 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
     // during the panel phase instead of delaying wave 0)
     static_assert(PO_WG >= BT * BT && PO_WG % (BT * BT) == 0, "one inverse entry per thread");
     if (tid < BT * BT) Ij[p * BT * BT + tid] = s_inv[tid];
-    // panel below: L_ip = A_ip invL_pp^T, one row per thread
-    const int rows = (nt - p - 1) * BT;
-    for (int t = tid; t < rows; t += PO_WG) {
-      double* Tip = A.tile(p + 1 + t / BT, p);
-      const int rr = t % BT;
-      double a[BT];
+    // panel below: L_ip = A_ip invL_pp^T, one 16x16 tile per wave at a time
+    // as four 16x16x4 FP64 MFMAs (s_inv is column-major: s_inv[k*16 + n] =
+    // (invL_pp)_nk, the (k, n) entry of invL_pp^T)
+    {
+      const int wv = tid >> 6, ln = tid & 63;
+      const int lr = ln & 15, lk = ln >> 4;
+      for (int t = wv; t < nt - p - 1; t += PO_WG / 64) {
+        double* Tip = A.tile(p + 1 + t, p);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < BT; ++k) a[k] = Tip[k * ld + rr];
+        for (int kk = 0; kk < BT; kk += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tip[(kk + lk) * ld + lr], s_inv[(kk + lk) * BT + lr], acc, 0,
+                                                     0, 0);
+        // every lane has read its operands of this tile before any lane
+        // overwrites it: the MFMAs consume them in order within the wave
 #pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        double l = 0.0;
-#pragma unroll
-        for (int k = 0; k <= c; ++k) l = fma(a[k], s_inv[k * BT + c], l);
-        Tip[c * ld + rr] = l;
-        s_panel[t * (BT + 1) + c] = l;
+        for (int j = 0; j < 4; ++j) {
+          const int row = lk + 4 * j;
+          Tip[lr * ld + row] = acc[j];
+          s_panel[(t * BT + row) * (BT + 1) + lr] = acc[j];
+        }
       }
     }
     __syncthreads();
-    // trailing update of the lower tiles (ti, tk), p < tk <= ti < nt
+    // trailing update of the lower tiles (ti, tk), p < tk <= ti < nt, one
+    // 16x16 tile per wave at a time on the FP64 matrix cores:
+    // T_ab -= P_a P_b^T as four 16x16x4 products over the panel's columns.
+    // Operand layout of the 16x16x4 FP64 MFMA: lane l supplies row l%16 and
+    // k = l/16 of both operands; result register j of lane l is entry
+    // (l/16 + 4j, l%16).
     const int m = nt - p - 1;
-    const int items = 16 * (m * (m + 1) / 2);
-    for (int w = tid; w < items; w += PO_WG) {
-      const int q = w >> 4, mt = w & 15;
+    const int ntiles = m * (m + 1) / 2;
+    const int wv = tid >> 6, ln = tid & 63;
+    const int lr = ln & 15, lk = ln >> 4;
+    for (int q = wv; q < ntiles; q += PO_WG / 64) {
       const int ta = tri_row(q), tb = q - ta * (ta + 1) / 2;
-      const int mr = (mt >> 2) * 4, mc = (mt & 3) * 4;
-      const int lr = ta * BT + mr, lc = tb * BT + mc;   // rows of s_panel
-      double acc[4][4] = {};
+      const double* pa = s_panel + (ta * BT + lr) * (BT + 1) + lk;
+      const double* pb = s_panel + (tb * BT + lr) * (BT + 1) + lk;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        double pi[4], pj[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          pi[x] = s_panel[(lr + x) * (BT + 1) + c];
-          pj[x] = s_panel[(lc + x) * (BT + 1) + c];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = fma(pi[x], pj[y], acc[x][y]);
-      }
+      for (int kk = 0; kk < BT; kk += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb[kk], acc, 0, 0, 0);
       double* Tab = A.tile(p + 1 + ta, p + 1 + tb);
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) Tab[(mc + y) * ld + mr + x] -= acc[x][y];
+      for (int j = 0; j < 4; ++j) Tab[lr * ld + lk + 4 * j] -= acc[j];
     }
     __syncthreads();
   }
@@ -261,10 +261,24 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     // one element of a tile per thread, PO_WG / 256 tiles per pass
     constexpr int TPP = PO_WG / (BT * BT);
     const int el = tid % (BT * BT), c = el >> 4, r = el & 15;
-#pragma unroll 2
-    for (int q = tid / (BT * BT); q < ntri; q += TPP) {
-      const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
-      s_tiles[q * BT * BT + el] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
+    // the loads of a batch of tiles are all issued before the first is
+    // stored, so their latencies overlap
+    constexpr int LB = 16;
+    for (int q0 = tid / (BT * BT); q0 < ntri; q0 += LB * TPP) {
+      double v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int q = q0 + u * TPP;
+        if (q < ntri) {
+          const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
+          v[u] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int q = q0 + u * TPP;
+        if (q < ntri) s_tiles[q * BT * BT + el] = v[u];
+      }
     }
     __syncthreads();
     const LdsTiles A{s_tiles};
@@ -377,18 +391,20 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
     for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = row < i0 * BT ? 0.0 : s_x[row * BT + c];
 }
 
-// -- schur: one work-group per (output tile, even block) ----------------------
+// -- schur: one wave per (output tile, even block) -----------------------------
 // Output tiles of block i: lower tiles of D_i, all tiles of the new coupling
 // C_i, and the 16-row pieces of f_i.  Each is a sum of at most two products
-// A^T B with K = bs, staged through LDS in 64-row slabs.
-constexpr int SC_WG = 256;
-constexpr int SC_KC = 64;
+// A^T B with K = bs, formed on the FP64 matrix cores as 16x16x4 MFMAs
+// (lane l supplies row l%16 and k = l/16 of both operands; result register
+// j of lane l is entry (l/16 + 4j, l%16)).  A right-hand-side piece is the
+// product with a single column: the other 15 columns of the B operand are
+// zero.
+constexpr int SC_WG = 64;
+constexpr int SC_UNROLL = 4;   // MFMAs whose operand loads are issued together
 
 __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ G, double* __restrict__ D,
                                                      double* __restrict__ C, double* __restrict__ F, int bs, int nb,
                                                      int h) {
-  __shared__ double s_a[SC_KC * (BT + 1)];
-  __shared__ double s_b[SC_KC * (BT + 1)];
   const int i = 2 * h * static_cast<int>(blockIdx.y);
   const int nt = bs / BT;
   const int ntri = nt * (nt + 1) / 2;
@@ -432,42 +448,37 @@ __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ 
     ++ncon;
   }
   if (ncon == 0) return;
-  const int nb_cols = kind == 2 ? 1 : BT;
-  const int tid = threadIdx.x;
-  const int r = tid & (BT - 1), c = tid >> 4;
-  double acc = 0.0;
+  const int ln = threadIdx.x, lr = ln & 15, lk = ln >> 4;
+  const bool vec = kind == 2;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int cn = 0; cn < ncon; ++cn) {
-    for (int k0 = 0; k0 < bs; k0 += SC_KC) {
-      const int kc = min(SC_KC, bs - k0);
-      __syncthreads();
-      for (int t = tid; t < BT * SC_KC; t += SC_WG) {
-        const int col = t / SC_KC, k = t - col * SC_KC;
-        if (k < kc) {
-          s_a[k * (BT + 1) + col] = Ap[cn][static_cast<size_t>(col) * bs + k0 + k];
-          if (col < nb_cols) s_b[k * (BT + 1) + col] = Bp[cn][static_cast<size_t>(col) * bs + k0 + k];
-        }
+    // lane (lr, lk) reads column lr of the A block and column lr of the B
+    // block (entry lk + k0 of each); a vector B is read by the lr = 0 lanes
+    const double* pa = Ap[cn] + static_cast<size_t>(lr) * bs + lk;
+    const double* pb = vec ? Bp[cn] + lk : Bp[cn] + static_cast<size_t>(lr) * bs + lk;
+    for (int k0 = 0; k0 < bs; k0 += 4 * SC_UNROLL) {
+      double xa[SC_UNROLL], xb[SC_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SC_UNROLL; ++u) {
+        const int k = k0 + 4 * u;
+        const bool in = k < bs;
+        xa[u] = in ? pa[k] : 0.0;
+        xb[u] = (in && (!vec || lr == 0)) ? pb[k] : 0.0;
       }
-      __syncthreads();
-      if (c < nb_cols) {
-        double a2 = 0.0;
-        int k = 0;
-        for (; k + 1 < kc; k += 2) {
-          acc = fma(s_a[k * (BT + 1) + r], s_b[k * (BT + 1) + c], acc);
-          a2 = fma(s_a[(k + 1) * (BT + 1) + r], s_b[(k + 1) * (BT + 1) + c], a2);
-        }
-        if (k < kc) acc = fma(s_a[k * (BT + 1) + r], s_b[k * (BT + 1) + c], acc);
-        acc += a2;
-      }
+#pragma unroll
+      for (int u = 0; u < SC_UNROLL; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
     }
   }
-  if (c >= nb_cols) return;
-  const int row = ta * BT + r;
-  if (kind == 0) {
-    D[i * per + static_cast<size_t>(tb * BT + c) * bs + row] -= acc;
-  } else if (kind == 1) {
-    C[i * per + static_cast<size_t>(tb * BT + c) * bs + row] = -acc;
-  } else {
-    F[static_cast<size_t>(i) * bs + row] -= acc;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = ta * BT + lk + 4 * j;   // entry (lk + 4j, lr) of the tile
+    if (kind == 0) {
+      D[i * per + static_cast<size_t>(tb * BT + lr) * bs + row] -= acc[j];
+    } else if (kind == 1) {
+      C[i * per + static_cast<size_t>(tb * BT + lr) * bs + row] = -acc[j];
+    } else if (lr == 0) {
+      F[static_cast<size_t>(i) * bs + row] -= acc[j];
+    }
   }
 }
 
