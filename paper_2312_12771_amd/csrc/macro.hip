@@ -379,58 +379,101 @@ __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* 
   }
 }
 
+// Element-basis residual row: P_g = P_e + C_V (eps_g - epsbar_e) at Gauss
+// point g, from the current displacement u.
+__device__ __noinline__ double elem_vec_row_element(const MacroArgs& m, const double* __restrict__ P,
+                                                    const double* __restrict__ u, int e, int row) {
+  const int nd = m.nen * m.dim, nF = m.nF;
+  double ue[24], CV[36], eps[8][6], ebar[6];
+  for (int col = 0; col < nd; ++col) ue[col] = u[m.conn[e * m.nen + col / m.dim] * m.dim + col % m.dim];
+  voigt_average(m, e, CV);
+  for (int i = 0; i < nF; ++i) ebar[i] = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int q = e * m.n_gp + g;
+    for (int i = 0; i < nF; ++i) {
+      double s = 0.0;
+      for (int col = 0; col < nd; ++col) s += macro_B(m, q, i, col) * ue[col];
+      eps[g][i] = s;
+      ebar[i] += m.wdet[q] * s;
+    }
+  }
+  for (int i = 0; i < nF; ++i) ebar[i] /= m.vol[e];
+  const double* Pe = P + static_cast<size_t>(e) * nF;
+  double v = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int q = e * m.n_gp + g;
+    double s = 0.0;
+    for (int i = 0; i < nF; ++i) {
+      double pg = Pe[i];
+      for (int j = 0; j < nF; ++j) pg += CV[i * nF + j] * (eps[g][j] - ebar[j]);
+      s += macro_B(m, q, i, row) * pg;
+    }
+    v += m.wdet[q] * s;
+  }
+  return v;
+}
+
 // a7 (part): element residual vectors  f = sum_g wdet B^T P  for P = Pbar
-// (true residual) and P = Phat (condensed right-hand side).  Element basis:
-// P_g = P_e + C_V (eps_g - epsbar_e) at Gauss point g, from the current
-// displacement u.  One thread per (element, row).
+// (true residual) and P = Phat (condensed right-hand side); the element
+// basis uses the row form above.  One thread per (element, row).
 __global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f,
                                  const double* __restrict__ u) {
   const int nd = m.nen * m.dim;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_elems * nd) return;
   const int e = t / nd, row = t % nd;
-  const int nF = m.nF;
-  double v = 0.0;
   if (m.basis == FE2_BASIS_ELEMENT) {
-    double ue[24], CV[36], eps[8][6], ebar[6];
-    for (int col = 0; col < nd; ++col) ue[col] = u[m.conn[e * m.nen + col / m.dim] * m.dim + col % m.dim];
-    voigt_average(m, e, CV);
-    for (int i = 0; i < nF; ++i) ebar[i] = 0.0;
-    for (int g = 0; g < m.n_gp; ++g) {
-      const int q = e * m.n_gp + g;
-      for (int i = 0; i < nF; ++i) {
-        double s = 0.0;
-        for (int col = 0; col < nd; ++col) s += macro_B(m, q, i, col) * ue[col];
-        eps[g][i] = s;
-        ebar[i] += m.wdet[q] * s;
-      }
-    }
-    for (int i = 0; i < nF; ++i) ebar[i] /= m.vol[e];
-    const double* Pe = P + static_cast<size_t>(e) * nF;
-    for (int g = 0; g < m.n_gp; ++g) {
-      const int q = e * m.n_gp + g;
-      double s = 0.0;
-      for (int i = 0; i < nF; ++i) {
-        double pg = Pe[i];
-        for (int j = 0; j < nF; ++j) pg += CV[i * nF + j] * (eps[g][j] - ebar[j]);
-        s += macro_B(m, q, i, row) * pg;
-      }
-      v += m.wdet[q] * s;
-    }
-  } else {
-    for (int g = 0; g < m.n_gp; ++g) {
-      const int b = e * m.n_gp + g;
-      double s = 0.0;
-      for (int i = 0; i < nF; ++i) s += macro_B(m, b, i, row) * P[static_cast<size_t>(b) * nF + i];
-      v += m.wdet[b] * s;
-    }
+    f[t] = elem_vec_row_element(m, P, u, e, row);
+    return;
+  }
+  double v = 0.0;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int b = e * m.n_gp + g;
+    double s = 0.0;
+    for (int i = 0; i < m.nF; ++i) s += macro_B(m, b, i, row) * P[static_cast<size_t>(b) * m.nF + i];
+    v += m.wdet[b] * s;
   }
   f[t] = v;
 }
 
+// Element-basis tangent row: sum_g wdet_g B_g^T C_V B_g + V_e Bbar^T
+// (Cbar_e - C_V) Bbar (its own function: the local C_V lives in private
+// memory, which the Dirac path must not pay for).
+__device__ __noinline__ void elem_mat_row_element(const MacroArgs& m, const double* __restrict__ Cb, int e, int row,
+                                                  double* acc) {
+  const int nd = m.nen * m.dim, nF = m.nF;
+  double CV[36];
+  voigt_average(m, e, CV);
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int q = e * m.n_gp + g;
+    double tj[6];
+    for (int j = 0; j < nF; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < nF; ++i) s += macro_B(m, q, i, row) * CV[i * nF + j];
+      tj[j] = s * m.wdet[q];
+    }
+    for (int c = 0; c < nd; ++c) {
+      double s = 0.0;
+      for (int j = 0; j < nF; ++j) s += tj[j] * macro_B(m, q, j, c);
+      acc[c] += s;
+    }
+  }
+  const double* C = Cb + static_cast<size_t>(e) * nF * nF;
+  double tj[6];
+  for (int j = 0; j < nF; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < nF; ++i) s += macro_Bbar(m, e, i, row) * (C[i * nF + j] - CV[i * nF + j]);
+    tj[j] = s * m.vol[e];
+  }
+  for (int c = 0; c < nd; ++c) {
+    double s = 0.0;
+    for (int j = 0; j < nF; ++j) s += tj[j] * macro_Bbar(m, e, j, c);
+    acc[c] += s;
+  }
+}
+
 // a7 (part): element tangents  k = sum_g wdet B^T Cbar B (Dirac basis) or
-// sum_g wdet_g B_g^T C_V B_g + V_e Bbar^T (Cbar_e - C_V) Bbar (element
-// basis), one thread per (element, row).
+// the element-basis form above, one thread per (element, row).
 __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke) {
   const int nd = m.nen * m.dim;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,36 +482,23 @@ __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, dou
   const int nF = m.nF;
   double acc[24];
   for (int c = 0; c < nd; ++c) acc[c] = 0.0;
-  const bool element = m.basis == FE2_BASIS_ELEMENT;
-  double CV[36];
-  if (element) voigt_average(m, e, CV);
-  for (int g = 0; g < m.n_gp; ++g) {
-    const int b = e * m.n_gp + g;
-    const double* C = element ? CV : Cb + static_cast<size_t>(b) * nF * nF;
-    double tj[9];
-    for (int j = 0; j < nF; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < nF; ++i) s += macro_B(m, b, i, row) * C[i * nF + j];
-      tj[j] = s * m.wdet[b];
-    }
-    for (int c = 0; c < nd; ++c) {
-      double s = 0.0;
-      for (int j = 0; j < nF; ++j) s += tj[j] * macro_B(m, b, j, c);
-      acc[c] += s;
-    }
-  }
-  if (element) {
-    const double* C = Cb + static_cast<size_t>(e) * nF * nF;
-    double tj[6];
-    for (int j = 0; j < nF; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < nF; ++i) s += macro_Bbar(m, e, i, row) * (C[i * nF + j] - CV[i * nF + j]);
-      tj[j] = s * m.vol[e];
-    }
-    for (int c = 0; c < nd; ++c) {
-      double s = 0.0;
-      for (int j = 0; j < nF; ++j) s += tj[j] * macro_Bbar(m, e, j, c);
-      acc[c] += s;
+  if (m.basis == FE2_BASIS_ELEMENT) {
+    elem_mat_row_element(m, Cb, e, row, acc);
+  } else {
+    for (int g = 0; g < m.n_gp; ++g) {
+      const int b = e * m.n_gp + g;
+      const double* C = Cb + static_cast<size_t>(b) * nF * nF;
+      double tj[9];
+      for (int j = 0; j < nF; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < nF; ++i) s += macro_B(m, b, i, row) * C[i * nF + j];
+        tj[j] = s * m.wdet[b];
+      }
+      for (int c = 0; c < nd; ++c) {
+        double s = 0.0;
+        for (int j = 0; j < nF; ++j) s += tj[j] * macro_B(m, b, j, c);
+        acc[c] += s;
+      }
     }
   }
   for (int c = 0; c < nd; ++c) ke[static_cast<size_t>(t) * nd + c] = acc[c];
