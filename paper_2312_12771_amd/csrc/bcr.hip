@@ -295,24 +295,24 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   }
 }
 
-// -- trsm: one work-group per (16-column tile, eliminated block) --------------
+// -- trsm: one wave per (16-column tile, eliminated block) ---------------------
 // Forward substitution L_j X = R on one tile of R = [C_j | C_{j+h}^T | I | f_j]
 // (the identity tiles give L_j^-1 for the back substitution), 16 rows at a
-// time: S = R_i - sum_{k<i} L_ik X_k (L staged through LDS in slabs of TR_KC
-// columns), X_i = invL_ii S.  Tiles: [0, nt) left coupling, [nt, 2nt) right
-// coupling, [2nt, 3nt) identity, 3nt right-hand side; a block with no
+// time: S_i = R_i - sum_{k<i} L_ik X_k, X_i = invL_ii S_i, both products as
+// 16x16x4 FP64 MFMAs (lane l supplies row l%16 and k = l/16 of both
+// operands; result register j of lane l is entry (l/16 + 4j, l%16)).  Tiles:
+// [0, nt) left coupling, [nt, 2nt) right coupling, [2nt, 3nt) identity, 3nt
+// right-hand side (one column; the other 15 stay zero); a block with no
 // neighbours (the last one left) runs only the last nt + 1.
-constexpr int TR_WG = 256;
-constexpr int TR_KC = 128;
+constexpr int TR_WG = 64;
+constexpr int TR_UNROLL = 4;   // MFMAs whose L operand loads are issued together
 
 __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D, const double* __restrict__ invL,
                                                     const double* __restrict__ C, double* __restrict__ G,
                                                     double* __restrict__ Linv, double* __restrict__ F, int bs,
                                                     int nb, int first, int stride, int h, int alone) {
-  extern __shared__ __align__(16) double s_x[];   // [bs][BT]: R, overwritten by X
-  __shared__ double s_l[TR_KC * BT];              // [k][r]
-  __shared__ double s_s[BT * BT];
-  __shared__ double s_iv[BT * BT];
+  extern __shared__ __align__(16) double s_x[];   // [bs][BT] row-major: R, overwritten by X
+  __shared__ double s_s[BT * BT];                 // [row][col]
   const int j = first + stride * static_cast<int>(blockIdx.y);
   const int nt = bs / BT;
   const int ct = alone ? 2 * nt + static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
@@ -346,49 +346,50 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
   }
   const double* Lj = D + j * per;
   const double* Ij = invL + static_cast<size_t>(j) * nt * BT * BT;
-  const int tid = threadIdx.x;
-  const int r = tid & (BT - 1), c = tid >> 4;
-  if (ident >= 0) {
-    for (int row = r; row < bs; row += BT) s_x[row * BT + c] = (row == ident + c) ? 1.0 : 0.0;
-  } else {
-#pragma unroll 4
-    for (int row = r; row < bs; row += BT)
-      s_x[row * BT + c] = (c < ncol) ? src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(c) * ld_c] : 0.0;
+  const int ln = threadIdx.x, lr = ln & 15, lk = ln >> 4;
+  // R into LDS: lane (lr, lk) covers column lr, rows lk, lk + 4, ...
+  for (int row = lk; row < bs; row += 4) {
+    double v;
+    if (ident >= 0) v = (row == ident + lr) ? 1.0 : 0.0;
+    else v = (lr < ncol) ? src[static_cast<size_t>(row) * ld_r + static_cast<size_t>(lr) * ld_c] : 0.0;
+    s_x[row * BT + lr] = v;
   }
+  wave_sync();
   for (int i = i0; i < nt; ++i) {
-    const int row = i * BT + r;
-    double s = s_x[row * BT + c];   // written by this thread
-    const double iv = Ij[i * BT * BT + tid];
-    double s2 = 0.0;
-    for (int kc0 = i0 * BT; kc0 < i * BT; kc0 += TR_KC) {
-      const int kc = min(TR_KC, i * BT - kc0);
-      __syncthreads();   // earlier readers of s_l (and of s_s, s_iv, s_x) are done
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    // sum_{k<i} L_ik X_k: L is column-major (entry (r, k) at Lj[k * bs + r])
+    const double* lcol = Lj + static_cast<size_t>(lk) * bs + i * BT + lr;
+    for (int k0 = i0 * BT; k0 < i * BT; k0 += 4 * TR_UNROLL) {
+      double xl[TR_UNROLL];
 #pragma unroll
-      for (int u = 0; u < TR_KC * BT / TR_WG; ++u) {
-        const int e = tid + u * TR_WG, k = e >> 4, rr = e & 15;
-        if (k < kc) s_l[e] = Lj[static_cast<size_t>(kc0 + k) * bs + i * BT + rr];
+      for (int u = 0; u < TR_UNROLL; ++u) {
+        const int k = k0 + 4 * u;
+        xl[u] = k < i * BT ? lcol[static_cast<size_t>(k) * bs] : 0.0;
       }
-      __syncthreads();
-      int k = 0;
-      for (; k + 1 < kc; k += 2) {
-        s = fma(-s_l[k * BT + r], s_x[(kc0 + k) * BT + c], s);
-        s2 = fma(-s_l[(k + 1) * BT + r], s_x[(kc0 + k + 1) * BT + c], s2);
+#pragma unroll
+      for (int u = 0; u < TR_UNROLL; ++u) {
+        const int k = k0 + 4 * u;
+        if (k < i * BT) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xl[u], s_x[(k + lk) * BT + lr], acc, 0, 0, 0);
       }
-      if (k < kc) s = fma(-s_l[k * BT + r], s_x[(kc0 + k) * BT + c], s);
     }
-    s_s[r * BT + c] = s + s2;
-    s_iv[tid] = iv;   // element (r, c) of invL_ii, column-major
-    __syncthreads();
-    double x = 0.0;
 #pragma unroll
-    for (int k = 0; k < BT; ++k)
-      if (k <= r) x = fma(s_iv[k * BT + r], s_s[k * BT + c], x);
-    s_x[row * BT + c] = x;
-    // the next tile's first slab barrier orders these writes before their readers
+    for (int q = 0; q < 4; ++q) {
+      const int rr = lk + 4 * q;
+      s_s[rr * BT + lr] = s_x[(i * BT + rr) * BT + lr] - acc[q];
+    }
+    wave_sync();
+    // X_i = invL_ii S_i (invL_ii column-major: entry (r, c) at Ij[i*256 + c*16 + r])
+    v4d x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < BT; kk += 4)
+      x = __builtin_amdgcn_mfma_f64_16x16x4f64(Ij[i * BT * BT + (kk + lk) * BT + lr], s_s[(kk + lk) * BT + lr], x, 0,
+                                               0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_x[(i * BT + lk + 4 * q) * BT + lr] = x[q];
+    wave_sync();
   }
-  if (c < ncol)
-#pragma unroll 4
-    for (int row = r; row < bs; row += BT) out[static_cast<size_t>(c) * bs + row] = row < i0 * BT ? 0.0 : s_x[row * BT + c];
+  if (lr < ncol)
+    for (int row = lk; row < bs; row += 4) out[static_cast<size_t>(lr) * bs + row] = row < i0 * BT ? 0.0 : s_x[row * BT + lr];
 }
 
 // -- schur: one wave per (output tile, even block) -----------------------------
