@@ -115,6 +115,17 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
     t1 = time.perf_counter()
     prof = fe2.fe2_get_profile(h)
     fe2.fe2_set_profiling(h, False)
+    # the same steps with a5-a9 replayed from a HIP graph (first step captures)
+    fe2.fe2_set_graph(h, True)
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg0) * 1e3 / steps
+    fe2.fe2_set_graph(h, False)
     n = p.n_rve
     nF = fe2.fe2_query(h, fe2.FE2_Q_NF)
     cbar = torch.zeros(n * nF * nF, dtype=torch.float64, device="cuda")
@@ -144,7 +155,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
                     step=prof[4] / steps),
         cbar=cbar.cpu().numpy().reshape(n, nF, nF),
         iters=iters.cpu().numpy(), mv64=mv64.cpu().numpy(), relres=relres.cpu().numpy(),
-        newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(),
+        newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(), graph_ms=graph_ms,
         n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim)
     h.close()
     return out
@@ -326,6 +337,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": {k: dict(rve_solves_per_s=round(rve_rate(f), 1),
                           macro_newton_step_ms=round(f["wall_ms_per_step"], 4),
+                          macro_newton_step_ms_hip_graph=round(f["graph_ms"], 4),
                           gpu_phase_ms={kk: round(v, 4) for kk, v in f["gpu_ms"].items()},
                           pcg_iters_per_rve=float(np.mean(f["iters"])),
                           worst_rve_relres=float(np.max(f["relres"])),

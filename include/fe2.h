@@ -258,6 +258,16 @@ int fe2_query(fe2_handle h, int which, int64_t* out);
  * (a5-a6), macro assembly and banded solve (a7-a8), update (a9), whole
  * steps], and the number of timed steps that solved. */
 int fe2_set_profiling(fe2_handle h, int enable);
+/* Run the RVE solves, the macro assembly and solve and the update of each
+ * generalized fe2_newton_step as one HIP graph launch (enable = 1) instead of
+ * individual launches (0, the default).  A graph is captured the first time
+ * a launch configuration occurs (right-hand sides, warm start, load factor
+ * and its increment) and replayed afterwards; at most four are kept per
+ * handle.  Results are identical to the individual launches.  With graphs on,
+ * fe2_get_profile reports the solve, macro and update phases as one (the
+ * solve entry holds their sum; the other two are zero).  The classical
+ * scheme and the surrogate always launch individually. */
+int fe2_set_graph(fe2_handle h, int enable);
 int fe2_get_profile(fe2_handle h, double* out);
 
 /* Release all device memory of the handle (waits for its work). */

@@ -110,6 +110,17 @@ struct fe2_ctx {
   double* okf = nullptr;          // [n_rve] fe2_rve_response status
   int last_failed = 0;
   bool have_solution = false;     // X holds the X_F of an earlier solve (warm start)
+  // HIP graphs of the solve / macro / update sequence of a Newton step, one
+  // per launch configuration (fe2_set_graph); captured on cap_stream
+  struct StepGraph {
+    int nrhs = 0, flags = 0;
+    double lam = 0.0, dlam = 0.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<StepGraph> graphs;
 
   MacroArgs margs() const {
     MacroArgs m{};
@@ -236,6 +247,11 @@ void free_ctx(fe2_ctx* h) {
   }
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& g : h->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->flag_host) (void)hipHostFree(h->flag_host);
   delete h;
@@ -712,6 +728,53 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
   return bcr_solve(h->bcr, h->bcr_ws, h->band, h->du, h->info, s);
 }
 
+// The RVE solves, macro assembly and solve, and update of a generalized
+// Newton step as one HIP graph launch on `s`.  Graphs are cached per launch
+// configuration (right-hand sides, warm start, load factor and increment);
+// every buffer they touch belongs to the handle, so a cached graph stays
+// valid for the handle's lifetime.  Fills use kernels (no memset nodes).
+int update_impl(fe2_ctx* h, int use_xr, hipStream_t s);
+int graph_step_impl(fe2_ctx* h, int nrhs, double lam, double dlam, hipStream_t s) {
+  const int flags = RVE_SOLVE | (h->have_solution ? RVE_WARM : 0);
+  fe2_ctx::StepGraph* hit = nullptr;
+  for (auto& g : h->graphs)
+    if (g.nrhs == nrhs && g.flags == flags && g.lam == lam && g.dlam == dlam) hit = &g;
+  if (!hit) {
+    if (!h->cap_stream) FE2_HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    constexpr size_t kMaxGraphs = 4;
+    if (h->graphs.size() >= kMaxGraphs) {   // drop the oldest
+      (void)hipGraphExecDestroy(h->graphs.front().exec);
+      (void)hipGraphDestroy(h->graphs.front().graph);
+      h->graphs.erase(h->graphs.begin());
+    }
+    fe2_ctx::StepGraph g;
+    g.nrhs = nrhs;
+    g.flags = flags;
+    g.lam = lam;
+    g.dlam = dlam;
+    FE2_HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    int rc = solve_impl(h, nrhs, h->cap_stream);
+    if (!rc) rc = macro_solve_impl(h, lam, dlam, h->cap_stream);
+    if (!rc) rc = update_impl(h, nrhs > h->nF, h->cap_stream);
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g.graph);
+    if (rc) {
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      return rc;
+    }
+    if (ec != hipSuccess) return set_error(std::string("graph capture: ") + hipGetErrorString(ec)), FE2_EHIP;
+    const hipError_t ei = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g.graph);
+      return set_error(std::string("graph instantiation: ") + hipGetErrorString(ei)), FE2_EHIP;
+    }
+    h->graphs.push_back(g);
+    hit = &h->graphs.back();
+  }
+  h->have_solution = true;   // what solve_impl records on the host
+  FE2_HIP_CHECK(hipGraphLaunch(hit->exec, s));
+  return FE2_OK;
+}
+
 int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
   MacroArgs m = h->margs();
   hipLaunchKernelGGL(k_axpy, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->ndof, h->du, h->u);
@@ -822,13 +885,20 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   // (classical: the RVEs are in equilibrium and only X_F is needed)
   const int nrhs = (classical || h->norms_host[2] == 0.0) ? h->nF : h->nF + 1;
   mark(2);
-  if ((rc = solve_impl(h, nrhs, s))) return rc;
-  mark(3);
-  // a7-a8: macro assembly and banded Cholesky solve with the increment
-  if ((rc = macro_solve_impl(h, load_factor, dlam, s))) return rc;
-  mark(4);
-  // a9: update
-  if ((rc = update_impl(h, nrhs > h->nF, s))) return rc;
+  if (h->use_graph && !classical) {
+    // a5-a9 as one graph launch (phase marks 3 and 4 are not split)
+    if ((rc = graph_step_impl(h, nrhs, load_factor, dlam, s))) return rc;
+    mark(3);
+    mark(4);
+  } else {
+    if ((rc = solve_impl(h, nrhs, s))) return rc;
+    mark(3);
+    // a7-a8: macro assembly and banded Cholesky solve with the increment
+    if ((rc = macro_solve_impl(h, load_factor, dlam, s))) return rc;
+    mark(4);
+    // a9: update
+    if ((rc = update_impl(h, nrhs > h->nF, s))) return rc;
+  }
   mark(5);
   FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));
   FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host + 1, h->info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1113,6 +1183,12 @@ int fe2_set_profiling(fe2_handle h, int enable) {
     for (auto& e : h->ev) FE2_HIP_CHECK(hipEventCreate(&e));
   h->prof = enable != 0;
   for (double& v : h->prof_ms) v = 0.0;
+  return FE2_OK;
+}
+
+int fe2_set_graph(fe2_handle h, int enable) {
+  FE2_GUARD(h);
+  h->use_graph = enable != 0;
   return FE2_OK;
 }
 

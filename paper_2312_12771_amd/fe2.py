@@ -109,6 +109,7 @@ _sig = {
     "fe2_surrogate_attach": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fe2_surrogate_detach": (C.c_int, [_vp]),
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
+    "fe2_set_graph": (C.c_int, [_vp, C.c_int]),
     "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
     "fe2_1d_setup": (C.c_int, [C.POINTER(fe2_1d_desc), _vp, C.POINTER(_vp)]),
     "fe2_1d_newton_step": (C.c_int, [_vp, _dp, _vp]),
@@ -533,3 +534,8 @@ def fe2_1d_query(h: Handle1D, which: int) -> int:
 
 def fe2_1d_get_state(h: Handle1D, phi=None, w=None, stream=None):
     _check(_lib.fe2_1d_get_state(h.ptr, _dev_ptr(phi), _dev_ptr(w), _stream_ptr(stream)), "fe2_1d_get_state")
+
+
+def fe2_set_graph(h: Handle, enable: bool):
+    """Newton steps as one HIP graph launch per configuration (see fe2.h)."""
+    return _check(_lib.fe2_set_graph(h.ptr, 1 if enable else 0), "fe2_set_graph")
