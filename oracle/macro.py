@@ -2,7 +2,9 @@
 side.
 
 * Macro discretisation (Sec. 3, Eqs. (25)-(28)): isoparametric Q4 / hex8,
-  2-point Gauss-Legendre rule per direction; one RVE per Gauss point
+  2-point Gauss-Legendre rule per direction, or biquadratic Q9 (2D) with 3
+  points per direction (the [delta, 2] setting of Sec. 5.1 carried to 2D);
+  one RVE per Gauss point
   (Dirac macro basis of the fluctuation, Eqs. (31)-(35)), b = e*n_gp + g.
 * Macro residual R = sum_b eta_b J_b G_b^T P_b - lambda f_ext (Eq. (35)),
   tangent K = sum_b eta_b J_b G_b^T C_b G_b with the condensed C_b.
@@ -53,9 +55,53 @@ class MacroGeometry:
     n_gp: int
 
 
+# Biquadratic (Q9) macro element: reference coordinates of the nodes in the
+# generators' order (corners counter-clockwise, mid-sides bottom, right, top,
+# left, centre); shape functions are products of the 1D quadratic Lagrange
+# polynomials on the nodes -1, 0, 1; 3-point Gauss-Legendre per direction.
+Q9_NODES = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1], [0, -1], [1, 0], [0, 1], [-1, 0], [0, 0]], dtype=np.float64)
+GAUSS3 = (np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]), np.array([5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0]))
+
+
+def _lagrange2(x, node):
+    """1D quadratic Lagrange polynomial of node -1, 0 or 1 and its derivative."""
+    if node < 0:
+        return 0.5 * x * (x - 1.0), x - 0.5
+    if node > 0:
+        return 0.5 * x * (x + 1.0), x + 0.5
+    return 1.0 - x * x, -2.0 * x
+
+
+def q9_shape(xi):
+    """N_a(xi, eta) and dN_a/dxi_J of the Q9 element, shapes (9,), (9, 2)."""
+    N = np.zeros(9)
+    d = np.zeros((9, 2))
+    for a, (na, nb) in enumerate(Q9_NODES):
+        lx, dlx = _lagrange2(xi[0], na)
+        ly, dly = _lagrange2(xi[1], nb)
+        N[a] = lx * ly
+        d[a] = (dlx * ly, lx * dly)
+    return N, d
+
+
+def macro_rule(prob):
+    """Gauss points, weights and the reference shape-derivative function of
+    the macro element (order 1: Q4 / hex8 with 2 points per direction, weight
+    1; order 2: Q9 with 3 points per direction, xi fastest)."""
+    if getattr(prob, "macro_order", 1) == 2:
+        if prob.dim != 2:
+            raise ValueError("quadratic macro elements are 2D")
+        x, w = GAUSS3
+        gps = np.array([[x[i], x[j]] for j in range(3) for i in range(3)])
+        wts = np.array([w[i] * w[j] for j in range(3) for i in range(3)])
+        return gps, wts, lambda xi: q9_shape(xi)[1]
+    gps = R.gauss_points(prob.dim)
+    return gps, np.ones(len(gps)), R.dshape_ref
+
+
 def macro_geometry(prob) -> MacroGeometry:
     dim = prob.dim
-    gps = R.gauss_points(dim)
+    gps, wts, dshape = macro_rule(prob)
     ne = prob.n_elems
     n_gp = len(gps)
     nen = prob.conn.shape[1]
@@ -64,10 +110,10 @@ def macro_geometry(prob) -> MacroGeometry:
     for e in range(ne):
         Xe = prob.X[prob.conn[e]]
         for g, xi in enumerate(gps):
-            dxi = R.dshape_ref(xi)
+            dxi = dshape(xi)
             J = Xe.T @ dxi
             dNdX[e * n_gp + g] = dxi @ np.linalg.inv(J)
-            wdet[e * n_gp + g] = np.linalg.det(J)
+            wdet[e * n_gp + g] = wts[g] * np.linalg.det(J)
     edofs = (prob.conn[:, :, None] * dim + np.arange(dim)).reshape(ne, -1)
     if prob.kinematics == "small":
         Bs = np.stack([R.strain_B(d) for d in dNdX])

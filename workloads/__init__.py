@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     config,
     config_names,
     macro_q4_grid,
+    macro_q9_grid,
     macro_hex8_grid,
     macro_q4_cook,
     lame_from_young,

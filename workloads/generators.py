@@ -51,6 +51,7 @@ class Problem:
     rve_size: float = 1.0
     load_factors: Sequence[float] = (1.0,)
     macro_basis: str = "dirac"  # "dirac" (RVE per Gauss point) | "element" (RVE per element)
+    macro_order: int = 1        # 1: Q4 / hex8 with 2 Gauss points per direction; 2: Q9 (2D) with 3
     seed: int = 0
     meta: Dict = dataclasses.field(default_factory=dict)
 
@@ -64,7 +65,7 @@ class Problem:
 
     @property
     def n_gp(self) -> int:
-        return 2 ** self.dim
+        return (self.macro_order + 1) ** self.dim
 
     @property
     def n_qp(self) -> int:
@@ -112,6 +113,22 @@ def macro_q4_grid(nx: int, ny: int, Lx: float = 1.0, Ly: float = 1.0):
     n0 = j * (nx + 1) + i
     conn = np.stack([n0, n0 + 1, n0 + nx + 2, n0 + nx + 1], axis=1).astype(np.int32)
     return X, conn
+
+
+def macro_q9_grid(nx: int, ny: int, Lx: float = 1.0, Ly: float = 1.0):
+    """Biquadratic 9-node elements on a (2nx+1) x (2ny+1) node lattice (x
+    fastest).  Per element: the corners counter-clockwise from the lower left,
+    the mid-side nodes (bottom, right, top, left), then the centre."""
+    mx, my = 2 * nx + 1, 2 * ny + 1
+    XX, YY = np.meshgrid(np.linspace(0.0, Lx, mx), np.linspace(0.0, Ly, my), indexing="xy")
+    X = np.stack([XX.ravel(), YY.ravel()], axis=1)
+    conn = []
+    for ey in range(ny):
+        for ex in range(nx):
+            i0, j0 = 2 * ex, 2 * ey
+            n = lambda di, dj: (j0 + dj) * mx + i0 + di
+            conn.append([n(0, 0), n(2, 0), n(2, 2), n(0, 2), n(1, 0), n(2, 1), n(1, 2), n(0, 1), n(1, 1)])
+    return X, np.array(conn, dtype=np.int32)
 
 
 def macro_hex8_grid(nx: int, ny: int, nz: int, L=(1.0, 1.0, 1.0)):
@@ -246,30 +263,33 @@ def _problem(name, dim, kin, mat, X, conn, dofs, vals, res, off, ph, params,
                    seed=int(seed), meta=dict(meta or {}))
 
 
-def cfg1(macro=(4, 4), rve=8, E=(1.0, 10.0), nu=0.3, disp=1e-3):
-    """2D plane-strain linear laminate: 4x4 Q4 macro, 8x8 RVE, E 1 / 10."""
-    X, conn = macro_q4_grid(*macro)
-    n_rve = conn.shape[0] * 4
+def cfg1(macro=(4, 4), rve=8, E=(1.0, 10.0), nu=0.3, disp=1e-3, order=1):
+    """2D plane-strain linear laminate: 4x4 Q4 macro, 8x8 RVE, E 1 / 10
+    (order=2: Q9 macro elements, 3x3 Gauss points)."""
+    X, conn = macro_q4_grid(*macro) if order == 1 else macro_q9_grid(*macro)
+    n_rve = conn.shape[0] * (order + 1) ** 2
     ph1 = phases_laminate(rve, rve)
     off, ph = _pack_phases([ph1] * n_rve)
     lam, mu = lame_from_young(np.array(E), nu)
     params = np.broadcast_to(np.stack([lam, mu], axis=1), (n_rve, 2, 2)).copy()
     dofs, vals = rollers_2d(X, 1.0, disp)
     res = np.full((n_rve, 2), rve, dtype=np.int32)
-    return _problem("cfg1", 2, "small", "linear", X, conn, dofs, vals, res, off,
-                    ph, params, SEED_BASE + 1,
-                    meta=dict(E=E, nu=nu, disp=disp, macro=macro, rve=rve))
+    return dataclasses.replace(
+        _problem("cfg1", 2, "small", "linear", X, conn, dofs, vals, res, off,
+                 ph, params, SEED_BASE + 1,
+                 meta=dict(E=E, nu=nu, disp=disp, macro=macro, rve=rve)), macro_order=order)
 
 
-def cfg2(macro=(64, 64), rve=32, vf=0.3, nu=0.3, disp=1e-3, seed=None):
+def cfg2(macro=(64, 64), rve=32, vf=0.3, nu=0.3, disp=1e-3, seed=None, order=1):
     """2D linear: 64x64 Q4 macro, 32x32 RVE with a centred circle of volume
     fraction 0.3; inclusion/matrix E ratio lognormal(ln 10, 0.5) drawn per
-    macro element."""
+    macro element (order=2: Q9 macro elements, 3x3 Gauss points)."""
     seed = SEED_BASE + 2 if seed is None else seed
     rng = np.random.default_rng(seed)
-    X, conn = macro_q4_grid(*macro)
+    X, conn = macro_q4_grid(*macro) if order == 1 else macro_q9_grid(*macro)
     ne = conn.shape[0]
-    n_rve = ne * 4
+    ngp = (order + 1) ** 2
+    n_rve = ne * ngp
     ratio = np.exp(rng.normal(np.log(10.0), 0.5, size=ne))
     r = np.sqrt(vf / np.pi)
     ph1 = phases_circle(rve, rve, r)
@@ -279,14 +299,15 @@ def cfg2(macro=(64, 64), rve=32, vf=0.3, nu=0.3, disp=1e-3, seed=None):
     params = np.zeros((n_rve, 2, 2))
     params[:, 0, 0] = lam0
     params[:, 0, 1] = mu0
-    params[:, 1, 0] = np.repeat(lam1, 4)
-    params[:, 1, 1] = np.repeat(mu1, 4)
+    params[:, 1, 0] = np.repeat(lam1, ngp)
+    params[:, 1, 1] = np.repeat(mu1, ngp)
     dofs, vals = rollers_2d(X, 1.0, disp)
     res = np.full((n_rve, 2), rve, dtype=np.int32)
-    return _problem("cfg2", 2, "small", "linear", X, conn, dofs, vals, res, off,
-                    ph, params, seed,
-                    meta=dict(nu=nu, disp=disp, macro=macro, rve=rve, radius=r,
-                              ratio=ratio))
+    return dataclasses.replace(
+        _problem("cfg2", 2, "small", "linear", X, conn, dofs, vals, res, off,
+                 ph, params, seed,
+                 meta=dict(nu=nu, disp=disp, macro=macro, rve=rve, radius=r,
+                           ratio=ratio)), macro_order=order)
 
 
 def cfg3(macro=(128, 128), resolutions=(16, 32, 48), nu=0.3, disp=1e-3,
