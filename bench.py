@@ -22,8 +22,10 @@ events on the stream), ms_per_step = wall time of one macro Newton step.
 
 --workload selects another configuration for the same measurement (the
 default is the 2D workload above): cfg3 (uneven 16/32/48 batch on a 128x128
-macro mesh), cfg4 (3D hex8) or cfg5 (finite-strain Neo-Hooke, first Newton
-iteration of the first load increment).
+macro mesh), cfg4 (3D hex8), cfg5 (finite-strain Neo-Hooke, first Newton
+iteration of the first load increment), cfg2_element (one RVE per macro
+element), cfg2_q9 (32x32 biquadratic Q9 macro elements with 3x3 Gauss
+points) or oned (the 1+1D bar of Sec. 5.1).
 """
 from __future__ import annotations
 
@@ -64,6 +66,10 @@ WORKLOADS = {
                               "lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3) with the piecewise-"
                               "constant macro basis of the fluctuation: one RVE per macro element (4096 RVEs)",
                          base="cfg2", element=True, lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
+    "cfg2_q9": dict(desc="the 2D linear workload with biquadratic Q9 macro elements: macro 32x32 Q9 (the node grid "
+                         "of 64x64 Q4, 3x3 Gauss points, 9216 RVEs), RVE 32x32 Q4 centred circle vf 0.3, E ratio "
+                         "lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3",
+                    base="cfg2", base_kw=dict(macro=(32, 32), order=2), lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
     "cfg5": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
                       "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; first Newton iteration of the first of ten "
                       "load increments (u_x = 0.01)",
@@ -258,7 +264,7 @@ def main():
         return
     t = time.perf_counter()
     wl = WORKLOADS[args.workload]
-    p = W.config(wl.get("base", args.workload))
+    p = W.config(wl.get("base", args.workload), **wl.get("base_kw", {}))
     if wl.get("element"):
         p = W.element_basis(p)
     log(f"workload {args.workload} built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define FE2_ABI_VERSION 2
+#define FE2_ABI_VERSION 3
 
 typedef enum fe2_status {
   FE2_OK = 0,
@@ -83,12 +83,16 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *  material         FE2_LINEAR_ISO (small strain), FE2_NEO_HOOKE or
  *                   FE2_MOONEY_RIVLIN (finite strain)
  *  n_nodes, X       macro node coordinates [n_nodes][dim]
- *  n_elems, conn    macro connectivity [n_elems][2^dim] (Q4 counter-clockwise;
- *                   hex8 bottom face then top face)
+ *  n_elems, conn    macro connectivity [n_elems][nen]: nen = 2^dim for
+ *                   macro_order 1 (Q4 counter-clockwise; hex8 bottom face then
+ *                   top face), nen = 9 for macro_order 2 (Q9: corners
+ *                   counter-clockwise, then the mid-side nodes of the bottom,
+ *                   right, top and left edges, then the centre node)
  *  n_dir, dir_dofs, dir_vals   prescribed DOFs (strictly increasing) and their
  *                   values at load factor 1
  *  f_ext            external nodal forces at load factor 1 [n_nodes*dim] or NULL
- *  n_rve            number of RVEs: n_elems * 2^dim (FE2_BASIS_DIRAC) or
+ *  n_rve            number of RVEs: n_elems * (macro_order + 1)^dim
+ *                   (FE2_BASIS_DIRAC, one per Gauss point, xi fastest) or
  *                   n_elems (FE2_BASIS_ELEMENT)
  *  rve_res          RVE resolutions [n_rve][dim], every entry >= 2
  *  rve_off          offsets into phase_id [n_rve+1]
@@ -114,6 +118,12 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *  max_pcg_it, max_ir, max_micro_it   iteration caps
  *  macro_basis      FE2_BASIS_DIRAC or FE2_BASIS_ELEMENT (small strain only:
  *                   FE2_ENOTSUP for finite strain)
+ *  macro_order      Lagrange order of the macro elements: 1 (Q4 / hex8 with
+ *                   2 Gauss points per direction, unit weights) or 2
+ *                   (biquadratic Q9 with 3 Gauss points per direction and
+ *                   weights 5/9, 8/9, 5/9; the order-2 setting of Sec. 5.1
+ *                   carried to 2D).  Order 2 is 2D small strain with the
+ *                   Dirac basis; other combinations give FE2_ENOTSUP.
  */
 typedef struct fe2_problem_desc {
   int32_t struct_size;
@@ -137,6 +147,7 @@ typedef struct fe2_problem_desc {
   double rve_tol, inner_tol, newton_tol, micro_tol;
   int32_t max_pcg_it, max_ir, max_micro_it;
   int32_t macro_basis;
+  int32_t macro_order;
 } fe2_problem_desc;
 
 typedef struct fe2_ctx* fe2_handle;

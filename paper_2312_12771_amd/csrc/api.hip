@@ -56,7 +56,7 @@ using namespace fe2;
 
 struct fe2_ctx {
   // description
-  int dim = 0, kin = 0, mat = 0, nF = 0, nen = 0, n_gp = 0;
+  int dim = 0, kin = 0, mat = 0, nF = 0, nen = 0, n_gp = 0, order = 1;
   int n_nodes = 0, n_elems = 0, n_rve = 0, ndof = 0, bw = 0, nnz = 0, n_pp = 0;
   int precision = 0, solver = 0, scheme = 0;
   int basis = FE2_BASIS_DIRAC, n_qp = 0;
@@ -127,6 +127,7 @@ struct fe2_ctx {
     m.n_rve = n_rve;
     m.dim = dim;
     m.nen = nen;
+    m.order = order;
     m.n_gp = n_gp;
     m.nF = nF;
     m.kin = kin;
@@ -266,10 +267,15 @@ int validate(const fe2_problem_desc* d) {
     return set_error("empty macro mesh"), FE2_EINVAL;
   if (d->macro_basis != FE2_BASIS_DIRAC && d->macro_basis != FE2_BASIS_ELEMENT)
     return set_error("unknown macro_basis"), FE2_EINVAL;
-  const int rves_per_elem = d->macro_basis == FE2_BASIS_ELEMENT ? 1 : (d->dim == 2 ? 4 : 8);
+  if (d->macro_order != 1 && d->macro_order != 2) return set_error("macro_order must be 1 or 2"), FE2_EINVAL;
+  if (d->macro_order == 2 && d->dim != 2)
+    return set_error("quadratic macro elements are implemented in 2D (Q9)"), FE2_ENOTSUP;
+  const int nen = d->macro_order == 2 ? 9 : (1 << d->dim);
+  const int ngp = d->macro_order == 2 ? 9 : (1 << d->dim);
+  const int rves_per_elem = d->macro_basis == FE2_BASIS_ELEMENT ? 1 : ngp;
   if (d->n_rve != d->n_elems * rves_per_elem)
     return set_error(d->macro_basis == FE2_BASIS_ELEMENT ? "n_rve must equal n_elems with the element basis"
-                                                         : "n_rve must equal n_elems * 2^dim"),
+                                                         : "n_rve must equal n_elems * (macro_order + 1)^dim"),
            FE2_EINVAL;
   if (!d->rve_res || !d->rve_off || !d->phase_id || !d->phase_params)
     return set_error("missing RVE arrays"), FE2_EINVAL;
@@ -280,7 +286,7 @@ int validate(const fe2_problem_desc* d) {
     return set_error("unknown precision"), FE2_EINVAL;
   if (!(d->rve_tol > 0.0) || !(d->newton_tol >= 0.0)) return set_error("tolerances must be positive"), FE2_EINVAL;
   if (d->max_pcg_it <= 0 || d->max_ir < 0) return set_error("iteration caps must be positive"), FE2_EINVAL;
-  for (int k = 0; k < d->n_elems * (1 << d->dim); ++k)
+  for (int64_t k = 0; k < static_cast<int64_t>(d->n_elems) * nen; ++k)
     if (d->conn[k] < 0 || d->conn[k] >= d->n_nodes) return set_error("connectivity out of range"), FE2_EINVAL;
   for (int k = 0; k < d->n_dir; ++k) {
     if (d->dir_dofs[k] < 0 || d->dir_dofs[k] >= d->n_nodes * d->dim)
@@ -352,8 +358,9 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   h->dim = d->dim;
   h->kin = d->kinematics;
   h->mat = d->material;
-  h->nen = 1 << d->dim;
-  h->n_gp = 1 << d->dim;
+  h->order = d->macro_order;
+  h->nen = h->order == 2 ? 9 : 1 << d->dim;
+  h->n_gp = h->order == 2 ? 9 : 1 << d->dim;
   h->nF = d->kinematics == FE2_SMALL_STRAIN ? (d->dim == 2 ? 3 : 6) : d->dim * d->dim;
   h->n_nodes = d->n_nodes;
   h->n_elems = d->n_elems;
@@ -380,6 +387,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   if (h->dim == 3 && finite) return set_error("3D RVEs are supported for small strain only"), FE2_ENOTSUP;
   if (h->basis == FE2_BASIS_ELEMENT && finite)
     return set_error("the element basis of the fluctuation is implemented for small strain"), FE2_ENOTSUP;
+  if (h->order == 2 && (finite || h->basis != FE2_BASIS_DIRAC))
+    return set_error("Q9 macro elements are implemented for small strain with the Dirac basis"), FE2_ENOTSUP;
   if (!finite && (h->mat != FE2_LINEAR_ISO || h->n_pp != 2))
     return set_error("small strain takes FE2_LINEAR_ISO with (lambda, mu) per phase"), FE2_EINVAL;
   if (finite && !((h->mat == FE2_NEO_HOOKE && h->n_pp == 2) || (h->mat == FE2_MOONEY_RIVLIN && h->n_pp == 3)))

@@ -224,19 +224,51 @@ __device__ __forceinline__ void ref_node(int dim, int a, double* xa) {
   if (dim == 3) xa[2] = a >= 4 ? 1.0 : -1.0;
 }
 
-// Geometry of macro Gauss point q = e * n_gp + g: dN/dX and wdet = w_g det J.
-__global__ void k_macro_geometry(MacroArgs m) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= m.n_qp) return;
-  const int dim = m.dim, nen = m.nen, ngp = m.n_gp;
-  const int e = b / ngp, g = b % ngp;
+// Quadratic 1D Lagrange polynomial on the nodes -1, 0, 1 (node index k = 0,
+// 1, 2 for -1, 1, 0 as in the Q9 numbering below) and its derivative.
+__device__ __forceinline__ void lagrange2(double x, int k, double* l, double* dl) {
+  if (k == 0) {
+    *l = 0.5 * x * (x - 1.0);
+    *dl = x - 0.5;
+  } else if (k == 1) {
+    *l = 0.5 * x * (x + 1.0);
+    *dl = x + 0.5;
+  } else {
+    *l = 1.0 - x * x;
+    *dl = -2.0 * x;
+  }
+}
+
+// Reference derivatives dN_a/dxi_J of the nen shape functions at xi, and the
+// Gauss weight of point g.  Order 1: Q4 / hex8 at (+-1/sqrt3)^dim, weight 1.
+// Order 2: biquadratic Q9 (tensor products of the quadratic Lagrange
+// polynomials; corners, then mid-sides of the bottom, right, top and left
+// edges, then the centre) at the 3x3 Gauss points +-sqrt(3/5), 0 with weights
+// 5/9, 8/9, 5/9, xi fastest.
+__device__ __forceinline__ double macro_ref_derivs(const MacroArgs& m, int g, double (*dxi)[3]) {
+  const int dim = m.dim;
+  if (m.order == 2) {
+    const double gx[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+    const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    const int ix = g % 3, iy = g / 3;
+    // 1D node index per Q9 node along xi and eta (0: -1, 1: +1, 2: 0)
+    const int kx[9] = {0, 1, 1, 0, 2, 1, 2, 0, 2};
+    const int ky[9] = {0, 0, 1, 1, 0, 2, 1, 2, 2};
+    for (int a = 0; a < 9; ++a) {
+      double lx, dlx, ly, dly;
+      lagrange2(gx[ix], kx[a], &lx, &dlx);
+      lagrange2(gx[iy], ky[a], &ly, &dly);
+      dxi[a][0] = dlx * ly;
+      dxi[a][1] = lx * dly;
+    }
+    return gw[ix] * gw[iy];
+  }
   const double gq = 0.57735026918962576451;
   double xi[3];
   xi[0] = (g & 1) ? gq : -gq;
   xi[1] = (g & 2) ? gq : -gq;
   xi[2] = (g & 4) ? gq : -gq;
-  double dxi[8][3];
-  for (int a = 0; a < nen; ++a) {
+  for (int a = 0; a < m.nen; ++a) {
     double na[3];
     ref_node(dim, a, na);
     for (int J = 0; J < dim; ++J) {
@@ -245,6 +277,17 @@ __global__ void k_macro_geometry(MacroArgs m) {
       dxi[a][J] = v;
     }
   }
+  return 1.0;
+}
+
+// Geometry of macro Gauss point q = e * n_gp + g: dN/dX and wdet = w_g det J.
+__global__ void k_macro_geometry(MacroArgs m) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= m.n_qp) return;
+  const int dim = m.dim, nen = m.nen, ngp = m.n_gp;
+  const int e = b / ngp, g = b % ngp;
+  double dxi[9][3];
+  const double wg = macro_ref_derivs(m, g, dxi);
   double Jm[3][3] = {};
   for (int a = 0; a < nen; ++a) {
     const int node = m.conn[e * nen + a];
@@ -279,7 +322,7 @@ __global__ void k_macro_geometry(MacroArgs m) {
       for (int K = 0; K < dim; ++K) v += dxi[a][K] * inv[K][J];
       m.dNdX[(static_cast<size_t>(b) * nen + a) * dim + J] = v;
     }
-  m.wdet[b] = det;
+  m.wdet[b] = wg * det;
 }
 
 // Weight of RVE b in the micro residual rows: wdet of its Gauss point (Dirac

@@ -10,6 +10,7 @@ namespace fe2 {
 struct MacroArgs {
   int n_rve, dim, nen, n_gp, nF, kin, n_elems, ndof, bw;
   int basis;              // FE2_BASIS_DIRAC or FE2_BASIS_ELEMENT
+  int order;              // macro element order: 1 (Q4 / hex8), 2 (Q9)
   int n_qp;               // macro Gauss points, n_elems * n_gp
   const int* conn;        // [n_elems][nen]
   const double* X;        // [n_nodes][dim]

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run paper_2312_12771_amd/build.py "
                       "(or __graft_entry__.build()) first")
 _lib = C.CDLL(LIB_PATH)
-FE2_ABI_VERSION = 2
+FE2_ABI_VERSION = 3
 
 # status codes and enums (include/fe2.h)
 FE2_OK, FE2_CONVERGED = 0, 1
@@ -63,6 +63,7 @@ class fe2_problem_desc(C.Structure):
         ("newton_tol", C.c_double), ("micro_tol", C.c_double),
         ("max_pcg_it", C.c_int32), ("max_ir", C.c_int32), ("max_micro_it", C.c_int32),
         ("macro_basis", C.c_int32),
+        ("macro_order", C.c_int32),
     ]
 
 
@@ -235,6 +236,7 @@ def make_desc(problem, precision: str = "fp64", solver: str = "auto",
     d.max_pcg_it, d.max_ir, d.max_micro_it = max_pcg_it, max_ir, max_micro_it
     d.macro_basis = {"dirac": FE2_BASIS_DIRAC, "element": FE2_BASIS_ELEMENT}[
         getattr(problem, "macro_basis", "dirac")]
+    d.macro_order = int(getattr(problem, "macro_order", 1))
     return d, keep
 
 

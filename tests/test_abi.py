@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     lib.fe2_abi_version.restype = ctypes.c_int
-    assert lib.fe2_abi_version() == 2
+    assert lib.fe2_abi_version() == 3
     lib.fe2_strerror.restype = ctypes.c_char_p
     assert lib.fe2_strerror(0) == b"ok"
 
@@ -83,7 +83,29 @@ def test_setup_validates_the_macro_basis_without_gpu_work():
     d, keep = fe2.make_desc(pe)
     d.macro_basis = fe2.FE2_BASIS_DIRAC            # 4 RVEs for 4 elements
     assert fe2._lib.fe2_setup(ctypes.byref(d), None, ctypes.byref(out)) == fe2.FE2_EINVAL
-    assert b"2^dim" in fe2._lib.fe2_last_error()
+    assert b"(macro_order + 1)^dim" in fe2._lib.fe2_last_error()
     d.macro_basis = 7
     assert fe2._lib.fe2_setup(ctypes.byref(d), None, ctypes.byref(out)) == fe2.FE2_EINVAL
     assert b"macro_basis" in fe2._lib.fe2_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfe2.so not built")
+def test_setup_validates_the_macro_order_without_gpu_work():
+    """macro_order is 1 or 2; Q9 meshes carry 9 RVEs per element with the
+    Dirac basis; quadratic hexahedra are not implemented.  All checks run
+    before any HIP call."""
+    import workloads as W
+    from paper_2312_12771_amd import fe2
+    out = ctypes.c_void_p()
+    d, keep = fe2.make_desc(W.config("cfg2", macro=(2, 2), rve=6, order=2))
+    assert d.macro_order == 2 and d.n_rve == 36
+    d.macro_order = 3
+    assert fe2._lib.fe2_setup(ctypes.byref(d), None, ctypes.byref(out)) == fe2.FE2_EINVAL
+    assert b"macro_order" in fe2._lib.fe2_last_error()
+    d.macro_order = 1                               # 36 RVEs for 4 elements of order 1
+    assert fe2._lib.fe2_setup(ctypes.byref(d), None, ctypes.byref(out)) == fe2.FE2_EINVAL
+    assert b"(macro_order + 1)^dim" in fe2._lib.fe2_last_error()
+    d3, keep3 = fe2.make_desc(W.config("cfg4", macro=(1, 1, 1), rve=4))
+    d3.macro_order = 2
+    assert fe2._lib.fe2_setup(ctypes.byref(d3), None, ctypes.byref(out)) == fe2.FE2_ENOTSUP
+    assert b"2D (Q9)" in fe2._lib.fe2_last_error()

@@ -8,7 +8,7 @@ kernels run in the same order on the same data).  Covered: the bench
 pattern (state reset, one step at the same load factor, repeated: one
 graph replayed), load stepping (the load factor changes: a new graph per
 increment, then replays for the later iterations), an uneven batch with
-three resolution classes, and the element basis.
+three resolution classes, the element basis and Q9 macro elements.
 """
 import numpy as np
 import pytest
@@ -48,6 +48,7 @@ CASES = [
     ("cfg2", dict(macro=(3, 3), rve=16), False),
     ("cfg3", dict(macro=(3, 3), resolutions=(16, 32, 48)), False),
     ("cfg2", dict(macro=(3, 3), rve=16), True),
+    ("cfg2", dict(macro=(2, 2), rve=16, order=2), False),
 ]
 
 
