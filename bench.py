@@ -143,6 +143,12 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
     relres = torch.zeros(n, dtype=torch.float64, device="cuda")
     fe2.fe2_get_data(h, fe2.FE2_D_RVE_RELRES, relres)
     torch.cuda.synchronize()
+    # RVEs whose PCG runs the spectral preconditioner: the library's rule
+    # (square 8/16/32 RVEs of a 2D small-strain problem), checked by count
+    n_spec = fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES)
+    sq = (p.rve_res[:, 0] == p.rve_res[:, -1]) & np.isin(p.rve_res[:, 0], (8, 16, 32))
+    spectral = sq if (n_spec > 0 and p.dim == 2) else np.zeros(n, bool)
+    assert int(spectral.sum()) == n_spec, (int(spectral.sum()), n_spec)
     # a full linear solve to the Newton tolerance (informational)
     fe2.fe2_set_state(h, zu, zw, 0.0)
     torch.cuda.synchronize()
@@ -162,7 +168,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
         cbar=cbar.cpu().numpy().reshape(n, nF, nF),
         iters=iters.cpu().numpy(), mv64=mv64.cpu().numpy(), relres=relres.cpu().numpy(),
         newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(), graph_ms=graph_ms,
-        n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim)
+        n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim, spectral=spectral)
     h.close()
     return out
 
@@ -294,7 +300,13 @@ def main():
     # roofline of the dominant kernel: the RVE solve launch (one per step)
     k_ms = head["gpu_ms"]["rve_solve"]
     op = FLOP_OPERATOR_DOF[(p.dim, p.kinematics)]
-    flops = float(np.sum(head["iters"] * head["n_dof_rve"]) * (op + 13.0)
+    # per inner iteration and DOF: the operator, plus 13 (Jacobi,
+    # single-reduction recurrences) or 10 + 10 log2 n + 5 (spectral: standard
+    # PCG updates, forward and inverse 2D FFT of the packed field at
+    # 5 N^2 log2 N^2 flops each over 2 N^2 DOFs, the symbol at 10 flops per
+    # complex point)
+    per_it = np.where(head["spectral"], op + 15.0 + 10.0 * np.log2(p.rve_res[:, 0]), op + 13.0)
+    flops = float(np.sum(head["iters"] * head["n_dof_rve"] * per_it)
                   + np.sum(head["mv64"] * head["n_dof_rve"]) * (op + 2.0))
     achieved = flops / (k_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_TFLOPS[head_dtype],

@@ -104,7 +104,14 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *  rve_size         side length of the cubic RVE cell (|Omega| = rve_size^dim)
  *  precision        FE2_PREC_FP64 (plain FP64 RVE solves) or FE2_PREC_FP32_IR
  *                   (FP32 PCG with FP64 residual refinement)
- *  solver           FE2_SOLVER_AUTO, _PCG_JACOBI or _PCG_FFT
+ *  solver           preconditioner of the RVE PCG (2D small strain):
+ *                   FE2_SOLVER_PCG_JACOBI (diagonal), FE2_SOLVER_PCG_FFT
+ *                   (inverse of the periodic operator of a homogeneous
+ *                   reference medium, applied by FFT in LDS; square RVEs of
+ *                   8, 16 or 32 elements only, else FE2_ENOTSUP) or
+ *                   FE2_SOLVER_AUTO (FFT for the FP32_IR form where the size
+ *                   allows it, Jacobi otherwise).  3D and finite strain use
+ *                   Jacobi; FFT there gives FE2_ENOTSUP
  *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach
@@ -258,7 +265,8 @@ int fe2_get_data(fe2_handle h, int which, double* dst_dev, void* stream);
 enum {
   FE2_Q_NF = 0, FE2_Q_FIELD_LEN = 1, FE2_Q_NDOF = 2, FE2_Q_BANDWIDTH = 3,
   FE2_Q_FAILED_RVES = 4, FE2_Q_N_RVE = 5, FE2_Q_FIELD_OFFSETS = 6, /* into int64 out[n_rve+1] */
-  FE2_Q_MICRO_ITERS = 7   /* update rounds of the last inner equilibration */
+  FE2_Q_MICRO_ITERS = 7,  /* update rounds of the last inner equilibration */
+  FE2_Q_SPECTRAL_RVES = 8 /* RVEs whose PCG uses the spectral preconditioner */
 };
 int fe2_query(fe2_handle h, int which, int64_t* out);
 

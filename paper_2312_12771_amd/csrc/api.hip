@@ -47,6 +47,9 @@ struct RveClass {
   std::vector<int> rves;
   int* d_list = nullptr;
   double* d_tab = nullptr;   // 2D: kv[10] | KwF[24] | KFF[9] | err | modes[10]
+  bool spectral = false;     // PCG with the spectral preconditioner (2D small strain)
+  double* d_fft64 = nullptr; // its table, FP64 and FP32
+  float* d_fft32 = nullptr;
 };
 
 }  // namespace
@@ -217,13 +220,14 @@ struct fe2_ctx {
     a.fail_count = fail_count;
     a.thr2 = thr2;
     a.skip = skip;
-    a.fft_tab = nullptr;
+    a.fft_tab = c.d_fft32;
+    a.fft_tab64 = c.d_fft64;
     a.volume = volume;
     a.tol = rve_tol;
     a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
-    a.flags = flags;
+    a.flags = flags | (c.spectral ? RVE_FFT : 0);
     return a;
   }
 };
@@ -245,6 +249,8 @@ void free_ctx(fe2_ctx* h) {
   for (auto& c : h->classes) {
     if (c.d_list) (void)hipFree(c.d_list);
     if (c.d_tab) (void)hipFree(c.d_tab);
+    if (c.d_fft64) (void)hipFree(c.d_fft64);
+    if (c.d_fft32) (void)hipFree(c.d_fft32);
   }
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -395,6 +401,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     return set_error("finite strain takes FE2_NEO_HOOKE (lambda, mu) or FE2_MOONEY_RIVLIN (alpha, beta, kappa)"),
            FE2_EINVAL;
   if (h->kin != FE2_SMALL_STRAIN && !finite) return set_error("unknown kinematics"), FE2_EINVAL;
+  if (h->solver != FE2_SOLVER_AUTO && h->solver != FE2_SOLVER_PCG_JACOBI && h->solver != FE2_SOLVER_PCG_FFT)
+    return set_error("unknown solver"), FE2_EINVAL;
+  if (h->solver == FE2_SOLVER_PCG_FFT && (finite || h->dim != 2))
+    return set_error("the spectral preconditioner is implemented for 2D small strain"), FE2_ENOTSUP;
   if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL)
     return set_error("unknown scheme"), FE2_EINVAL;
   if (h->scheme == FE2_SCHEME_CLASSICAL && (!(h->micro_tol > 0.0) || h->max_micro_it <= 0))
@@ -448,6 +458,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" + std::to_string(n2) +
                        (h->dim == 3 ? "x" + std::to_string(n3) : std::string())),
              FE2_ENOTSUP;
+    if (h->solver == FE2_SOLVER_PCG_FFT && !lin2d_spectral_size(n1, n2))
+      return set_error("the spectral preconditioner needs square RVEs of 8, 16 or 32 elements"), FE2_ENOTSUP;
     auto key = std::make_tuple(n1, n2, rho0);
     auto it = key2cls.find(key);
     int ci;
@@ -569,6 +581,21 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       FE2_HIP_CHECK(hipStreamSynchronize(s));
       if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
       continue;
+    }
+    // FE2_SOLVER_AUTO: the spectral preconditioner for the FP32 inner solves
+    // (FP32_IR); the FP64 form keeps Jacobi, whose kernel holds twice the
+    // occupancy of the spectral one in FP64
+    const bool want = h->solver == FE2_SOLVER_PCG_FFT ||
+                      (h->solver == FE2_SOLVER_AUTO && h->precision == FE2_PREC_FP32_IR);
+    if (want && lin2d_spectral_size(c.n1, c.n2)) {
+      const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + c.n1;
+      std::vector<double> t64(nt);
+      lin2d_spectral_table(c.n1, c.rho, t64.data());
+      std::vector<float> t32(t64.begin(), t64.end());
+      if ((rc = upload(&c.d_fft64, t64.data(), nt, s))) return rc;
+      if ((rc = upload(&c.d_fft32, t32.data(), nt, s))) return rc;
+      FE2_HIP_CHECK(hipStreamSynchronize(s));   // the host tables die here
+      c.spectral = true;
     }
     if ((rc = dalloc(&c.d_tab, REF2_TABLE))) return rc;
     hipLaunchKernelGGL(k_ref_tables_2d, dim3(1), dim3(64), 0, s, h->rve_size / c.n1, h->rve_size / c.n2, c.rho,
@@ -1178,6 +1205,13 @@ int fe2_query(fe2_handle h, int which, int64_t* out) {
     case FE2_Q_FIELD_LEN: *out = h->field_len; return FE2_OK;
     case FE2_Q_NDOF: *out = h->ndof; return FE2_OK;
     case FE2_Q_BANDWIDTH: *out = h->bw; return FE2_OK;
+    case FE2_Q_SPECTRAL_RVES: {
+      int64_t n = 0;
+      for (const auto& c : h->classes)
+        if (c.spectral) n += static_cast<int64_t>(c.rves.size());
+      *out = n;
+      return FE2_OK;
+    }
     case FE2_Q_FAILED_RVES: *out = h->last_failed; return FE2_OK;
     case FE2_Q_N_RVE: *out = h->n_rve; return FE2_OK;
     case FE2_Q_FIELD_OFFSETS: std::memcpy(out, h->h_foff.data(), h->h_foff.size() * sizeof(int64_t)); return FE2_OK;

@@ -102,7 +102,8 @@ struct Lin2DArgs {
   int* fail_count;              // RVEs that missed tol
   const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
   const int* skip;              // [n_rve] or null: RVEs with skip[b] != 0 are left untouched
-  const float* fft_tab;         // spectral preconditioner table (RVE_FFT)
+  const float* fft_tab;         // spectral preconditioner table, FP32 (RVE_FFT)
+  const double* fft_tab64;      // the same table in FP64
   double volume;
   double tol, tol_in;
   int max_it, max_ir;
@@ -145,6 +146,12 @@ int mlp_width(fe2_mlp q, int which);
 int mlp_max_batch(fe2_mlp q);
 
 // Launchers (rve_lin2d.hip, rve_fin2d.hip)
+// Square power-of-two RVEs (8, 16, 32) run the PCG with the spectral
+// preconditioner of the homogeneous reference medium when RVE_FFT is set;
+// lin2d_spectral_table writes its table (alpha, Re beta, Im beta, 0 per
+// position, then the twiddles) for lambda/mu = rho: 4 n^2 + n doubles.
+constexpr bool lin2d_spectral_size(int n1, int n2) { return n1 == n2 && (n1 == 8 || n1 == 16 || n1 == 32); }
+void lin2d_spectral_table(int n, double rho, double* out);
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
 size_t lin2d_lds_bytes(int n1, int n2, int nrhs);

@@ -29,6 +29,9 @@
 //     FP64 from the FP64 solution kept in the output buffer; the condensation
 //     uses the FP64 residual to correct the Schur product (energy form, error
 //     quadratic in the solve error).
+#include <cmath>
+#include <type_traits>
+
 #include "rve2d_common.hpp"
 
 namespace fe2 {
@@ -271,6 +274,205 @@ __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Spectral preconditioner of the homogeneous reference medium
+// ---------------------------------------------------------------------------
+// Every element of a resolution class has stiffness mu_e K_ref, so the
+// periodic operator of a uniform medium (mu = 1) is block-circulant and the
+// Fourier transform diagonalises it into a real symmetric 2x2 symbol S(k).
+// M^-1 r = R K_0^+ R^T r (R drops the pinned corner, K_0^+ the inverse on
+// the non-constant modes) is applied in three steps on one complex field
+// z = r_x + i r_y of N x N nodes in LDS:
+//   * forward DFT by vector-radix 2x2 decimation in frequency (in place,
+//     one 2x2 butterfly group per thread and stage, output in bit-reversed
+//     order along both axes);
+//   * per bit-reversed position: W(k) = alpha(k) Z(k) + beta(k) conj Z(-k),
+//     the symbol inverse [a b; b c] applied to the two real fields packed in
+//     Z (alpha = (a + c)/2, beta = (a - c)/2 + i b; alpha = beta = 0 at k = 0);
+//   * inverse DFT by vector-radix 2x2 decimation in time (bit-reversed in,
+//     natural order out, unscaled: PCG is invariant to the preconditioner's
+//     scale), whose last stage writes u_x, u_y into the block-major search
+//     direction directly.
+// Table tab (per class): [N*N][4] (alpha, Re beta, Im beta, 0) by position
+// q*N + p, then [N/2][2] twiddles (cos, -sin)(2 pi t / N).
+template <typename TI>
+struct Cx {
+  TI re, im;
+};
+template <typename TI>
+__device__ __forceinline__ Cx<TI> cadd(Cx<TI> a, Cx<TI> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename TI>
+__device__ __forceinline__ Cx<TI> csub(Cx<TI> a, Cx<TI> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename TI>
+__device__ __forceinline__ Cx<TI> cmul(Cx<TI> a, Cx<TI> w) {
+  return {a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
+}
+template <typename TI>
+__device__ __forceinline__ Cx<TI> cmulc(Cx<TI> a, Cx<TI> w) {   // a * conj(w)
+  return {a.re * w.re + a.im * w.im, a.im * w.re - a.re * w.im};
+}
+template <typename TI>
+__device__ __forceinline__ Cx<TI> zld(const TI* z, int i, int j, int n) {
+  const TI* q = z + 2 * (j * n + i);
+  return {q[0], q[1]};
+}
+template <typename TI>
+__device__ __forceinline__ void zst(TI* z, int i, int j, int n, Cx<TI> v) {
+  TI* q = z + 2 * (j * n + i);
+  q[0] = v.re;
+  q[1] = v.im;
+}
+__device__ __forceinline__ int bitrev(int x, int m) { return static_cast<int>(__brev(static_cast<unsigned>(x)) >> (32 - m)); }
+
+// Per-thread constants of the preconditioner, loaded once per RVE: the
+// twiddles of the thread's butterfly group at every stage h = N/2 .. 2
+// (stage s has h = N >> (s + 1)), the symbol coefficients of its four
+// positions and the LDS offsets of their partners -k.
+template <int N, typename TI>
+struct SpectralRegs {
+  static constexpr int M = (N == 8) ? 3 : (N == 16) ? 4 : 5;
+  static_assert((1 << M) == N, "spectral preconditioner: N must be 8, 16 or 32");
+  static constexpr int NT = sizeof(TI) == 4 ? 1 : M - 1;   // FP32: twiddles computed per stage
+  Cx<TI> wx[NT], wy[NT];
+  TI al[4], br[4], bi[4];
+};
+
+// Twiddle e^{-2 pi i t / N} of stage st for the thread's group index (I or
+// J): FP64 from the registers, FP32 by the hardware sine and cosine (their
+// argument is in revolutions, here t/N in [0, 1/2)).
+template <int N, typename TI>
+__device__ __forceinline__ Cx<TI> spectral_twiddle(const SpectralRegs<N, TI>& g, const Cx<TI> (&w)[SpectralRegs<N, TI>::NT],
+                                                   int st, int idx) {
+  if constexpr (sizeof(TI) == 4) {
+    const int h = N >> (st + 1);
+    const float rev = static_cast<float>((idx % h) * (N / (2 * h))) * (1.0f / N);
+    return {__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev)};
+  } else {
+    return w[st];
+  }
+}
+
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, bool own, int I,
+                                               int J) {
+  const TI* tw = tab + 4 * N * N;
+  if constexpr (sizeof(TI) == 8)
+#pragma unroll
+    for (int st = 0; st < SpectralRegs<N, TI>::NT; ++st) {
+      const int h = N >> (st + 1), sc = N / (2 * h);
+      const int tx = own ? (I % h) * sc : 0, ty = own ? (J % h) * sc : 0;
+      g.wx[st] = {tw[2 * tx], tw[2 * tx + 1]};
+      g.wy[st] = {tw[2 * ty], tw[2 * ty + 1]};
+    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int p = own ? 2 * I + (k & 1) : 0, q = own ? 2 * J + (k >> 1) : 0;
+    const TI* t = tab + 4 * (q * N + p);
+    g.al[k] = t[0];
+    g.br[k] = t[1];
+    g.bi[k] = t[2];
+  }
+}
+
+// u = M^-1 r for the owned 2x2 block (I, J) (tid < (N/2)^2 owns; every
+// thread of the work-group must call it: it holds barriers).  r: inner
+// residual of the owned nodes, pinned node masked by the caller; z: complex
+// LDS buffer [N*N][2]; sp: block-major search direction (x at 0, y at
+// +N*N), written with u (pinned node zero).  Ends without a barrier: the
+// caller's next barrier makes sp visible.
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ sp,
+                                                 const SpectralRegs<N, TI>& g, bool own, int I, int J) {
+  constexpr int M = SpectralRegs<N, TI>::M;
+  // I and J opaque per call: the stage addresses (integer arithmetic on
+  // them) are formed here rather than hoisted out of the PCG loop, where
+  // they would hold some forty registers across the whole solve
+  asm volatile("" : "+v"(I), "+v"(J));
+  if (own)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zst<TI>(z, 2 * I + (k & 1), 2 * J + (k >> 1), N, {r[k][0], r[k][1]});
+  __syncthreads();
+  // forward: decimation in frequency, h = N/2 .. 2 through LDS
+#pragma unroll
+  for (int st = 0; st < M - 1; ++st) {
+    const int h = N >> (st + 1);
+    if (own) {
+      const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
+      const Cx<TI> wx = spectral_twiddle<N, TI>(g, g.wx, st, I), wy = spectral_twiddle<N, TI>(g, g.wy, st, J);
+      const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + h, j, N);
+      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = zld<TI>(z, i + h, j + h, N);
+      const Cx<TI> A = cadd(a, b), B = cmul(csub(a, b), wx), C = cadd(c, d), D = cmul(csub(c, d), wx);
+      zst<TI>(z, i, j, N, cadd(A, C));
+      zst<TI>(z, i, j + h, N, cmul(csub(A, C), wy));
+      zst<TI>(z, i + h, j, N, cadd(B, D));
+      zst<TI>(z, i + h, j + h, N, cmul(csub(B, D), wy));
+    }
+    __syncthreads();
+  }
+  // h = 1 (unit twiddles) on the owned block, then the symbol
+  Cx<TI> v[4];
+  if (own) {
+    const int i = 2 * I, j = 2 * J;
+    const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + 1, j, N);
+    const Cx<TI> c = zld<TI>(z, i, j + 1, N), d = zld<TI>(z, i + 1, j + 1, N);
+    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cadd(c, d), D = csub(c, d);
+    v[0] = cadd(A, C);
+    v[2] = csub(A, C);
+    v[1] = cadd(B, D);
+    v[3] = csub(B, D);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1), j + (k >> 1), N, v[k]);
+  }
+  __syncthreads();
+  if (own)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int p = 2 * I + (k & 1), q = 2 * J + (k >> 1);
+      const int pp = bitrev((N - bitrev(p, M)) & (N - 1), M), qp = bitrev((N - bitrev(q, M)) & (N - 1), M);
+      const Cx<TI> zp = zld<TI>(z, pp, qp, N);
+      // alpha Z + beta conj(Zp)
+      v[k] = {g.al[k] * v[k].re + g.br[k] * zp.re + g.bi[k] * zp.im,
+              g.al[k] * v[k].im + g.bi[k] * zp.re - g.br[k] * zp.im};
+    }
+  __syncthreads();   // every partner read precedes the overwrites below
+  // inverse: decimation in time, h = 1 in registers, then h = 2 .. N/2
+  if (own) {
+    const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
+    const int i = 2 * I, j = 2 * J;
+    zst<TI>(z, i, j, N, cadd(A, C));
+    zst<TI>(z, i, j + 1, N, csub(A, C));
+    zst<TI>(z, i + 1, j, N, cadd(B, D));
+    zst<TI>(z, i + 1, j + 1, N, csub(B, D));
+  }
+  constexpr int NBT = (N / 2) * (N / 2);
+#pragma unroll
+  for (int st = M - 2; st >= 0; --st) {
+    const int h = N >> (st + 1);
+    __syncthreads();
+    if (own) {
+      const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
+      const Cx<TI> wx = spectral_twiddle<N, TI>(g, g.wx, st, I), wy = spectral_twiddle<N, TI>(g, g.wy, st, J);
+      const Cx<TI> a = zld<TI>(z, i, j, N), b = cmulc(zld<TI>(z, i + h, j, N), wx);
+      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = cmulc(zld<TI>(z, i + h, j + h, N), wx);
+      const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
+      const Cx<TI> o[4] = {cadd(A, C), cadd(B, D), csub(A, C), csub(B, D)};   // (i,j) (i+h,j) (i,j+h) (i+h,j+h)
+      if (st > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1) * h, j + (k >> 1) * h, N, o[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = i + (k & 1) * h, y = j + (k >> 1) * h;
+          const int at = 4 * ((y >> 1) * (N / 2) + (x >> 1)) + (x & 1) + 2 * (y & 1);
+          const bool pin = (x | y) == 0;
+          sp[at] = pin ? TI(0) : o[k].re;
+          sp[NBT * 4 + at] = pin ? TI(0) : o[k].im;
+        }
+      }
+    }
+  }
+}
+
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
 // one search direction [2][PN] in TI aliased with the FP64 staging [2][PN].
 constexpr int RED_NV = 2 * NF > 5 ? 2 * NF : 5;   // widest work-group reduction
@@ -290,8 +492,13 @@ __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, i
          (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0);
 }
 
-template <typename TI, int NRHS, int N1, int N2, int WG>
-__global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
+// The spectral FP32 form is held to three work-groups of 256 lanes per CU
+// (at most 168 VGPRs), the occupancy of the Jacobi form.
+template <typename TI, bool FFT, int WG>
+constexpr int kLin2dMinBlocks = (sizeof(TI) == 4 && FFT && WG == 256) ? 3 : 1;
+
+template <typename TI, int NRHS, int N1, int N2, int WG, bool FFT>
+__global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(const Lin2DArgs a) {
   using P = Pad<N1, N2>;
   constexpr int NW = WG / 64;
   constexpr int NN = N1 * N2;
@@ -310,6 +517,15 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   double* s_st = reinterpret_cast<double*>(s_vec);  // [2][PN] FP64 staging (aliases s_p)
   TI* s_x = reinterpret_cast<TI*>(smem + lin2d_xch_offset(N1, N2, WG, NRHS));   // [3][WG][4] (even sizes)
   constexpr bool EVEN = ((N1 | N2) & 1) == 0;
+  static_assert(!FFT || (EVEN && N1 == N2), "spectral preconditioner needs square power-of-two RVEs");
+  const TI* ftab = nullptr;
+  if constexpr (FFT) {
+    if constexpr (sizeof(TI) == 4) ftab = reinterpret_cast<const TI*>(a.fft_tab);
+    else ftab = reinterpret_cast<const TI*>(a.fft_tab64);
+  }
+  struct NoSpectral {};
+  using SpecRegs = typename std::conditional<FFT, SpectralRegs<FFT ? N1 : 8, TI>, NoSpectral>::type;
+  SpecRegs sreg;
   int parity = 0;
 
   // ---- reference element scalars (uniform: scalar registers) -------------
@@ -467,6 +683,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       dinv[k][d] = dof[k] ? static_cast<TI>(1.0 / dg) : TI(0);
     }
   }
+  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, own, I, J);
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -557,7 +774,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
           if constexpr (!EVEN)
             if (exists[k]) put_halo<N1, N2>(s_p + d * P::PN, i0 + (k & 1), j0 + (k >> 1), uv[k][d]);
         }
-      if constexpr (EVEN)
+      if constexpr (EVEN && !FFT)
         if (own)
 #pragma unroll
           for (int d = 0; d < 2; ++d) st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, uv[0][d], uv[1][d], uv[2][d], uv[3][d]);
@@ -568,6 +785,98 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int a2 = 0; a2 < 2; ++a2) esc[c][a2] = EVEN ? ebI[(c + 1) * P::PW + a2 + 1] : TI(0);
+      if constexpr (FFT) {
+        // Standard PCG with the spectral preconditioner: q = K p, two fused
+        // reductions per iteration (p.q, then r.u after u = M^-1 r).  The
+        // single-reduction recurrence for p.Kp above loses definiteness in
+        // FP32 under this strong preconditioner; p.q formed from q does not.
+        // s_p holds p for the operator and u after the preconditioner; each
+        // thread keeps its own p, r, x in registers.
+        auto wsum1 = [&](TI v) -> TI {
+          if constexpr (sizeof(TI) == 4) {
+            const float in[1] = {v};
+            float out[1];
+            wg_sum_f32<1, NW, RED_NV>(in, out, s_red, parity);
+            return out[0];
+          } else {
+            double t[1] = {v};
+            wg_sum<1, NW, RED_NV>(t, s_red, parity);
+            return t[0];
+          }
+        };
+        auto precond = [&]() {   // u = M^-1 r into uv (own nodes); ends after a barrier
+          TI rm[4][2];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) rm[k][d] = dof[k] ? ri[k][d] : TI(0);
+          spectral_precond<N1, TI>(rm, s_x, s_p, sreg, own, I, J);
+          __syncthreads();
+          if (own) {
+            TI o[4];
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+              ld4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, o);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) uv[k][d] = o[k];
+            }
+          }
+        };
+        precond();
+        TI gpart = TI(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            gpart = fma(ri[k][d], uv[k][d], gpart);
+            pv[k][d] = uv[k][d];
+          }
+        TI gam = wsum1(gpart);
+        gam0 = gam;
+        if (own)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, pv[0][d], pv[1][d], pv[2][d], pv[3][d]);
+#pragma unroll 1
+        for (int it = 0; it < a.max_it; ++it) {
+          if (!(gam > tinI * gam0) || !(gam > TI(0))) break;
+          __syncthreads();   // p visible
+          TI wv[4][2];
+          mv_modes<N1, N2, WG, TI>(s_p, esc, mcI, s_x, b_own, b_r, b_t, b_d, tid, t_l, t_b, t_d, wv);
+          TI qpart = TI(0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) qpart = fma(pv[k][d], wv[k][d], qpart);
+          const TI pq = wsum1(qpart);
+          if (!(pq > TI(0))) break;   // exact solution or loss of definiteness
+          const TI alpha = gam / pq;
+          ++iters;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+              xi[k][d] = fma(alpha, pv[k][d], xi[k][d]);
+              ri[k][d] = fma(-alpha, wv[k][d], ri[k][d]);
+            }
+          precond();   // every read of s_p (p) precedes the p.q reduction's barrier
+          gpart = TI(0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) gpart = fma(ri[k][d], uv[k][d], gpart);
+          const TI gnew = wsum1(gpart);
+          const TI beta = gnew / gam;
+          gam = gnew;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) pv[k][d] = fma_keep(pv[k][d], beta, uv[k][d]);
+          if (own)   // own block only: no other thread reads it before the next barrier
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+              st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, pv[0][d], pv[1][d], pv[2][d], pv[3][d]);
+        }
+      } else {
 #pragma unroll 1
       for (int it = 0; it < a.max_it; ++it) {
         __syncthreads();   // u visible
@@ -624,6 +933,7 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
               st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, uv[0][d], uv[1][d], uv[2][d], uv[3][d]);
         gam_old = gam;
         den_old = den;
+      }
       }
       // x64 += x_inner (FP64 accumulation in the output column)
 #pragma unroll
@@ -710,6 +1020,69 @@ __global__ void __launch_bounds__(WG) k_lin2d(const Lin2DArgs a) {
   }
 }
 
+
+// Host: the spectral table of one class (mu = 1, lambda = rho, square
+// elements; the element size cancels in 2D).  The Q4 element stiffness by
+// 2x2 Gauss quadrature, its periodic symbol S(k) = sum_ab K_e[a][b]
+// cos(k . (x_b - x_a)) (real: the stencil is centro-symmetric), the inverse
+// of S at every k != 0 and the packing coefficients of the two real fields.
+void lin2d_spectral_table(int n, double rho, double* out) {
+  int m = 0;
+  while ((1 << m) < n) ++m;
+  const double xa[4] = {-1, 1, 1, -1}, ya[4] = {-1, -1, 1, 1};
+  const int ox[4] = {0, 1, 1, 0}, oy[4] = {0, 0, 1, 1};
+  const double C[3][3] = {{rho + 2.0, rho, 0.0}, {rho, rho + 2.0, 0.0}, {0.0, 0.0, 1.0}};
+  double K[8][8] = {};
+  const double g = 1.0 / std::sqrt(3.0);
+  for (int gp = 0; gp < 4; ++gp) {
+    const double xi = (gp & 1) ? g : -g, eta = (gp & 2) ? g : -g;
+    double B[3][8] = {};
+    for (int a = 0; a < 4; ++a) {
+      const double dx = 0.5 * xa[a] * (1.0 + ya[a] * eta), dy = 0.5 * ya[a] * (1.0 + xa[a] * xi);   // x in [0, 1]
+      B[0][2 * a] = dx;
+      B[1][2 * a + 1] = dy;
+      B[2][2 * a] = dy;
+      B[2][2 * a + 1] = dx;
+    }
+    for (int r = 0; r < 8; ++r)
+      for (int c = 0; c < 8; ++c) {
+        double v = 0.0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) v += B[i][r] * C[i][j] * B[j][c];
+        K[r][c] += 0.25 * v;   // det J = 1/4, unit weights
+      }
+  }
+  auto rev = [m](int x) {
+    int y = 0;
+    for (int t = 0; t < m; ++t) y |= ((x >> t) & 1) << (m - 1 - t);
+    return y;
+  };
+  const double two_pi = 6.283185307179586476925;
+  for (int q = 0; q < n; ++q)
+    for (int p = 0; p < n; ++p) {
+      const int kx = rev(p), ky = rev(q);
+      double S[2][2] = {};
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const double cs = std::cos(two_pi * (kx * (ox[b] - ox[a]) + ky * (oy[b] - oy[a])) / n);
+          for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 2; ++e) S[c][e] += K[2 * a + c][2 * b + e] * cs;
+        }
+      double* t = out + 4 * (q * n + p);
+      t[0] = t[1] = t[2] = t[3] = 0.0;
+      if (kx == 0 && ky == 0) continue;   // translations: projected out
+      const double det = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+      const double ia = S[1][1] / det, ic = S[0][0] / det, ib = -0.5 * (S[0][1] + S[1][0]) / det;
+      t[0] = 0.5 * (ia + ic);
+      t[1] = 0.5 * (ia - ic);
+      t[2] = ib;
+    }
+  for (int k = 0; k < n / 2; ++k) {
+    out[4 * n * n + 2 * k] = std::cos(two_pi * k / n);
+    out[4 * n * n + 2 * k + 1] = -std::sin(two_pi * k / n);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launch: dispatch on the compile-time RVE size
 // ---------------------------------------------------------------------------
@@ -721,12 +1094,14 @@ size_t lin2d_lds_bytes(int n1, int n2, int nrhs) {
   return lin2d_lds_bytes_t(n1, n2, wg_for(n1, n2), nrhs, 8);
 }
 
-template <typename TI, int NRHS, int N1, int N2>
+template <typename TI, int NRHS, int N1, int N2, bool FFT = false>
 static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = wg_for(N1, N2);
   constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)));
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
-  auto kern = &k_lin2d<TI, NRHS, N1, N2, WG>;
+  // the spectral preconditioner's complex field [N*N][2] aliases the exchange slots [3][WG][4]
+  static_assert(!FFT || 2 * N1 * N2 <= 12 * WG, "exchange slots too small for the spectral field");
+  auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -738,6 +1113,17 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 template <int N1, int N2>
 static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
+  if constexpr (lin2d_spectral_size(N1, N2)) {
+    if (a.flags & RVE_FFT) {
+      if (!a.fft_tab || !a.fft_tab64) return set_error("spectral preconditioner table missing"), FE2_EINVAL;
+      if (precision == FE2_PREC_FP64)
+        return nrhs == 3 ? launch_t<double, 3, N1, N2, true>(a, n_launch, s)
+                         : launch_t<double, 4, N1, N2, true>(a, n_launch, s);
+      return nrhs == 3 ? launch_t<float, 3, N1, N2, true>(a, n_launch, s) : launch_t<float, 4, N1, N2, true>(a, n_launch, s);
+    }
+  } else {
+    if (a.flags & RVE_FFT) return set_error("no spectral preconditioner for this RVE size"), FE2_ENOTSUP;
+  }
   if (precision == FE2_PREC_FP64)
     return nrhs == 3 ? launch_t<double, 3, N1, N2>(a, n_launch, s) : launch_t<double, 4, N1, N2>(a, n_launch, s);
   return nrhs == 3 ? launch_t<float, 3, N1, N2>(a, n_launch, s) : launch_t<float, 4, N1, N2>(a, n_launch, s);

@@ -37,7 +37,7 @@ FE2_BASIS_DIRAC, FE2_BASIS_ELEMENT = 0, 1
  FE2_D_MACRO_KDENSE, FE2_D_CBAR, FE2_D_PHAT, FE2_D_RVE_MV64, FE2_D_PHASE_FRACTION,
  FE2_D_SURR_ERR) = range(15)
 (FE2_Q_NF, FE2_Q_FIELD_LEN, FE2_Q_NDOF, FE2_Q_BANDWIDTH, FE2_Q_FAILED_RVES,
- FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS, FE2_Q_MICRO_ITERS) = range(8)
+ FE2_Q_N_RVE, FE2_Q_FIELD_OFFSETS, FE2_Q_MICRO_ITERS, FE2_Q_SPECTRAL_RVES) = range(9)
 
 _KIN = {"small": FE2_SMALL_STRAIN, "finite": FE2_FINITE_STRAIN}
 _MAT = {"linear": FE2_LINEAR_ISO, "neohooke": FE2_NEO_HOOKE,
