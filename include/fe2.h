@@ -109,9 +109,9 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *                   (inverse of the periodic operator of a homogeneous
  *                   reference medium, applied by FFT in LDS; square RVEs of
  *                   8, 16 or 32 elements only, else FE2_ENOTSUP) or
- *                   FE2_SOLVER_AUTO (FFT for the FP32_IR form where the size
- *                   allows it, Jacobi otherwise).  3D and finite strain use
- *                   Jacobi; FFT there gives FE2_ENOTSUP
+ *                   FE2_SOLVER_AUTO (FFT where the size allows it, Jacobi
+ *                   otherwise).  3D and finite strain use Jacobi; FFT there
+ *                   gives FE2_ENOTSUP
  *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach

@@ -582,11 +582,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       if (!(err < 1e-12)) return set_error("reference element table inconsistent"), FE2_EHIP;
       continue;
     }
-    // FE2_SOLVER_AUTO: the spectral preconditioner for the FP32 inner solves
-    // (FP32_IR); the FP64 form keeps Jacobi, whose kernel holds twice the
-    // occupancy of the spectral one in FP64
-    const bool want = h->solver == FE2_SOLVER_PCG_FFT ||
-                      (h->solver == FE2_SOLVER_AUTO && h->precision == FE2_PREC_FP32_IR);
+    // FE2_SOLVER_AUTO: the spectral preconditioner wherever the size allows it
+    const bool want = h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_AUTO;
     if (want && lin2d_spectral_size(c.n1, c.n2)) {
       const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + c.n1;
       std::vector<double> t64(nt);

@@ -332,38 +332,27 @@ template <int N, typename TI>
 struct SpectralRegs {
   static constexpr int M = (N == 8) ? 3 : (N == 16) ? 4 : 5;
   static_assert((1 << M) == N, "spectral preconditioner: N must be 8, 16 or 32");
-  static constexpr int NT = sizeof(TI) == 4 ? 1 : M - 1;   // FP32: twiddles computed per stage
-  Cx<TI> wx[NT], wy[NT];
+  const TI* tw;   // LDS copy of the twiddles [N/2][2]
   TI al[4], br[4], bi[4];
 };
 
 // Twiddle e^{-2 pi i t / N} of stage st for the thread's group index (I or
-// J): FP64 from the registers, FP32 by the hardware sine and cosine (their
-// argument is in revolutions, here t/N in [0, 1/2)).
+// J), from the LDS table (no VALU work, no registers held across the solve).
 template <int N, typename TI>
-__device__ __forceinline__ Cx<TI> spectral_twiddle(const SpectralRegs<N, TI>& g, const Cx<TI> (&w)[SpectralRegs<N, TI>::NT],
-                                                   int st, int idx) {
-  if constexpr (sizeof(TI) == 4) {
-    const int h = N >> (st + 1);
-    const float rev = static_cast<float>((idx % h) * (N / (2 * h))) * (1.0f / N);
-    return {__builtin_amdgcn_cosf(rev), -__builtin_amdgcn_sinf(rev)};
-  } else {
-    return w[st];
-  }
+__device__ __forceinline__ Cx<TI> spectral_twiddle(const SpectralRegs<N, TI>& g, int st, int idx) {
+  const int h = N >> (st + 1);
+  const int t = (idx % h) * (N / (2 * h));
+  return {g.tw[2 * t], g.tw[2 * t + 1]};
 }
 
+// s_tw: LDS table [N/2][2], filled here (visible after the caller's next
+// barrier).
 template <int N, typename TI>
-__device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, bool own, int I,
-                                               int J) {
+__device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, TI* s_tw, bool own,
+                                               int I, int J) {
   const TI* tw = tab + 4 * N * N;
-  if constexpr (sizeof(TI) == 8)
-#pragma unroll
-    for (int st = 0; st < SpectralRegs<N, TI>::NT; ++st) {
-      const int h = N >> (st + 1), sc = N / (2 * h);
-      const int tx = own ? (I % h) * sc : 0, ty = own ? (J % h) * sc : 0;
-      g.wx[st] = {tw[2 * tx], tw[2 * tx + 1]};
-      g.wy[st] = {tw[2 * ty], tw[2 * ty + 1]};
-    }
+  if (threadIdx.x < N) s_tw[threadIdx.x] = tw[threadIdx.x];
+  g.tw = s_tw;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int p = own ? 2 * I + (k & 1) : 0, q = own ? 2 * J + (k >> 1) : 0;
@@ -398,7 +387,7 @@ __device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __rest
     const int h = N >> (st + 1);
     if (own) {
       const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
-      const Cx<TI> wx = spectral_twiddle<N, TI>(g, g.wx, st, I), wy = spectral_twiddle<N, TI>(g, g.wy, st, J);
+      const Cx<TI> wx = spectral_twiddle<N, TI>(g, st, I), wy = spectral_twiddle<N, TI>(g, st, J);
       const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + h, j, N);
       const Cx<TI> c = zld<TI>(z, i, j + h, N), d = zld<TI>(z, i + h, j + h, N);
       const Cx<TI> A = cadd(a, b), B = cmul(csub(a, b), wx), C = cadd(c, d), D = cmul(csub(c, d), wx);
@@ -451,7 +440,7 @@ __device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __rest
     __syncthreads();
     if (own) {
       const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
-      const Cx<TI> wx = spectral_twiddle<N, TI>(g, g.wx, st, I), wy = spectral_twiddle<N, TI>(g, g.wy, st, J);
+      const Cx<TI> wx = spectral_twiddle<N, TI>(g, st, I), wy = spectral_twiddle<N, TI>(g, st, J);
       const Cx<TI> a = zld<TI>(z, i, j, N), b = cmulc(zld<TI>(z, i + h, j, N), wx);
       const Cx<TI> c = zld<TI>(z, i, j + h, N), d = cmulc(zld<TI>(z, i + h, j + h, N), wx);
       const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
@@ -487,9 +476,11 @@ __host__ __device__ constexpr size_t lin2d_xch_offset(int n1, int n2, int wg, in
   return lin2d_vec_offset(n1, n2, wg, nrhs) + 2 * static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 8;
 }
 // exchange slots of the element-wise operator: [3][wg][4] in the inner precision
-__host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes) {
+__host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes,
+                                                       bool spectral = false) {
   return lin2d_xch_offset(n1, n2, wg, nrhs) +
-         (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0);
+         (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0) +
+         (spectral ? static_cast<size_t>(n1) * ti_bytes : 0);   // twiddle table [n/2][2]
 }
 
 // The spectral FP32 form is held to three work-groups of 256 lanes per CU
@@ -683,7 +674,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       dinv[k][d] = dof[k] ? static_cast<TI>(1.0 / dg) : TI(0);
     }
   }
-  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, own, I, J);
+  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, s_x + 12 * WG, own, I, J);
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -1097,7 +1088,7 @@ size_t lin2d_lds_bytes(int n1, int n2, int nrhs) {
 template <typename TI, int NRHS, int N1, int N2, bool FFT = false>
 static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = wg_for(N1, N2);
-  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)));
+  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), FFT);
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
   // the spectral preconditioner's complex field [N*N][2] aliases the exchange slots [3][WG][4]
   static_assert(!FFT || 2 * N1 * N2 <= 12 * WG, "exchange slots too small for the spectral field");

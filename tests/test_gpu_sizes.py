@@ -100,11 +100,11 @@ def test_small_strain_3d_every_size(fe2, n):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32])
-@pytest.mark.parametrize("prec,solver", [("fp32_ir", "jacobi"), ("fp64", "fft"), ("fp64", "jacobi")])
+@pytest.mark.parametrize("prec,solver", [("fp32_ir", "jacobi"), ("fp64", "auto"), ("fp64", "jacobi")])
 def test_small_strain_2d_both_preconditioners(fe2, n, prec, solver):
     """The square power-of-two sizes run the spectral preconditioner by
-    default in the mixed form; the Jacobi one and the FP64 spectral one are
-    selectable and reach the same C-bar."""
+    default; the Jacobi one is selectable in both precisions and reaches the
+    same C-bar."""
     print("2D small strain", n, prec, solver, flush=True)
     p = with_resolution(W.config("cfg2", macro=(1, 1), rve=8), n, n)
     u, ws = random_state(p, n * 101, 1e-3, 1e-3)
@@ -112,14 +112,18 @@ def test_small_strain_2d_both_preconditioners(fe2, n, prec, solver):
 
 
 def test_spectral_preconditioner_selection(fe2):
-    """FE2_SOLVER_AUTO picks the spectral preconditioner for the mixed form on
-    square 8/16/32 RVEs only; an explicit request elsewhere is rejected."""
+    """FE2_SOLVER_AUTO picks the spectral preconditioner on square 8/16/32 RVEs
+    only (both precisions); Jacobi is selectable; an explicit spectral request
+    elsewhere is rejected."""
     p = W.config("cfg3", macro=(2, 2), resolutions=(16, 32, 48))
     res = p.rve_res[:, 0]
     h = fe2.fe2_setup(p, precision="fp32_ir")
     assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32)).sum())
     h.close()
     h = fe2.fe2_setup(p, precision="fp64")
+    assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32)).sum())
+    h.close()
+    h = fe2.fe2_setup(p, precision="fp32_ir", solver="jacobi")
     assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == 0
     h.close()
     with pytest.raises(fe2.FE2Error) as ei:
