@@ -144,9 +144,9 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
     fe2.fe2_get_data(h, fe2.FE2_D_RVE_RELRES, relres)
     torch.cuda.synchronize()
     # RVEs whose PCG runs the spectral preconditioner: the library's rule
-    # (square 8/16/32 RVEs of a 2D small-strain problem), checked by count
+    # (square 8/16/32/48 RVEs of a 2D small-strain problem), checked by count
     n_spec = fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES)
-    sq = (p.rve_res[:, 0] == p.rve_res[:, -1]) & np.isin(p.rve_res[:, 0], (8, 16, 32))
+    sq = (p.rve_res[:, 0] == p.rve_res[:, -1]) & np.isin(p.rve_res[:, 0], (8, 16, 32, 48))
     spectral = sq if (n_spec > 0 and p.dim == 2) else np.zeros(n, bool)
     assert int(spectral.sum()) == n_spec, (int(spectral.sum()), n_spec)
     # a full linear solve to the Newton tolerance (informational)
@@ -304,7 +304,7 @@ def main():
     # single-reduction recurrences) or 10 + 10 log2 n + 5 (spectral: standard
     # PCG updates, forward and inverse 2D FFT of the packed field at
     # 5 N^2 log2 N^2 flops each over 2 N^2 DOFs, the symbol at 10 flops per
-    # complex point)
+    # complex point; n = 48 counted by the same 5 N log2 N convention)
     per_it = np.where(head["spectral"], op + 15.0 + 10.0 * np.log2(p.rve_res[:, 0]), op + 13.0)
     flops = float(np.sum(head["iters"] * head["n_dof_rve"] * per_it)
                   + np.sum(head["mv64"] * head["n_dof_rve"]) * (op + 2.0))

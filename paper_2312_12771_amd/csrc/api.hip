@@ -459,7 +459,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
                        (h->dim == 3 ? "x" + std::to_string(n3) : std::string())),
              FE2_ENOTSUP;
     if (h->solver == FE2_SOLVER_PCG_FFT && !lin2d_spectral_size(n1, n2))
-      return set_error("the spectral preconditioner needs square RVEs of 8, 16 or 32 elements"), FE2_ENOTSUP;
+      return set_error("the spectral preconditioner needs square RVEs of 8, 16, 32 or 48 elements"), FE2_ENOTSUP;
     auto key = std::make_tuple(n1, n2, rho0);
     auto it = key2cls.find(key);
     int ci;
@@ -585,7 +585,7 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     // FE2_SOLVER_AUTO: the spectral preconditioner wherever the size allows it
     const bool want = h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_AUTO;
     if (want && lin2d_spectral_size(c.n1, c.n2)) {
-      const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + c.n1;
+      const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + 2 * lin2d_spectral_twiddles(c.n1);
       std::vector<double> t64(nt);
       lin2d_spectral_table(c.n1, c.rho, t64.data());
       std::vector<float> t32(t64.begin(), t64.end());

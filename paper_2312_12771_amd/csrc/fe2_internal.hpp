@@ -146,15 +146,18 @@ int mlp_width(fe2_mlp q, int which);
 int mlp_max_batch(fe2_mlp q);
 
 // Launchers (rve_lin2d.hip, rve_fin2d.hip)
-// Square power-of-two RVEs (8, 16, 32) run the PCG with the spectral
+// Square RVEs of 8, 16, 32 or 48 elements run the PCG with the spectral
 // preconditioner of the homogeneous reference medium when RVE_FFT is set;
 // lin2d_spectral_table writes its table (alpha, Re beta, Im beta, 0 per
-// position, then the twiddles) for lambda/mu = rho: 4 n^2 + n doubles.
-constexpr bool lin2d_spectral_size(int n1, int n2) { return n1 == n2 && (n1 == 8 || n1 == 16 || n1 == 32); }
+// position, then the twiddles e^{-2 pi i t / n}, t < lin2d_spectral_twiddles)
+// for lambda/mu = rho: 4 n^2 + 2 lin2d_spectral_twiddles(n) doubles.
+constexpr bool lin2d_spectral_size(int n1, int n2) {
+  return n1 == n2 && (n1 == 8 || n1 == 16 || n1 == 32 || n1 == 48);
+}
+constexpr int lin2d_spectral_twiddles(int n) { return n == 48 ? 32 : n / 2; }
 void lin2d_spectral_table(int n, double rho, double* out);
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
-size_t lin2d_lds_bytes(int n1, int n2, int nrhs);
 bool lin2d_supported(int n1, int n2);
 int launch_fin2d(const Fin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);

@@ -24,6 +24,9 @@
 //   * RVE sizes are compile-time template parameters.
 //   * PCG state lives in registers and LDS; HBM is touched only for phase ids,
 //     the state w and the outputs.
+//   * Preconditioner: Jacobi, or (square 8/16/32 RVEs) the inverse of the
+//     periodic operator of a homogeneous reference medium, applied by a 2D
+//     FFT in LDS; the latter with the standard two-reduction PCG loop.
 //   * Precision: the inner PCG runs in TI (float for the FP32_IR form, double
 //     for plain FP64).  An outer refinement loop forms the true residual in
 //     FP64 from the FP64 solution kept in the output buffer; the condensation
@@ -330,10 +333,12 @@ __device__ __forceinline__ int bitrev(int x, int m) { return static_cast<int>(__
 // positions and the LDS offsets of their partners -k.
 template <int N, typename TI>
 struct SpectralRegs {
-  static constexpr int M = (N == 8) ? 3 : (N == 16) ? 4 : 5;
-  static_assert((1 << M) == N, "spectral preconditioner: N must be 8, 16 or 32");
-  const TI* tw;   // LDS copy of the twiddles [N/2][2]
-  TI al[4], br[4], bi[4];
+  static constexpr int M = (N == 8) ? 3 : (N == 16 || N == 48) ? 4 : 5;   // log2 of the radix-2 extent
+  static_assert((1 << M) == N || (N == 48 && (3 << M) == N), "spectral preconditioner: N must be 8, 16, 32 or 48");
+  static constexpr bool HOLD = N != 48;   // symbol coefficients in registers (N = 48: read at use)
+  const TI* tw;    // LDS copy of the twiddles
+  const TI* tab;   // the class table (N = 48)
+  TI al[HOLD ? 4 : 1], br[HOLD ? 4 : 1], bi[HOLD ? 4 : 1];
 };
 
 // Twiddle e^{-2 pi i t / N} of stage st for the thread's group index (I or
@@ -351,8 +356,10 @@ template <int N, typename TI>
 __device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, TI* s_tw, bool own,
                                                int I, int J) {
   const TI* tw = tab + 4 * N * N;
-  if (threadIdx.x < N) s_tw[threadIdx.x] = tw[threadIdx.x];
+  if (threadIdx.x < 2 * lin2d_spectral_twiddles(N)) s_tw[threadIdx.x] = tw[threadIdx.x];
   g.tw = s_tw;
+  g.tab = tab;
+  if constexpr (SpectralRegs<N, TI>::HOLD)
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int p = own ? 2 * I + (k & 1) : 0, q = own ? 2 * J + (k >> 1) : 0;
@@ -462,8 +469,163 @@ __device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __rest
   }
 }
 
+// N = 48 = 3 x 16: the forward transform starts with a radix-3 x 3 stage
+// (one group of nine points (x + 16a, y + 16b), x, y < 16, per lane for the
+// first 256 lanes: the 3 x 3 DFT, then the twiddles W48^(x mx) W48^(y my)),
+// which leaves the nine residue classes of the frequency mod 3 in the nine
+// 16 x 16 sub-blocks; vector-radix 2 x 2 stages inside every sub-block
+// follow (one group per lane of the 576).  Sub-block s holds frequencies
+// s + 3 k, k bit-reversed within the block.  The inverse mirrors it: radix-2
+// stages by decimation in time, then the radix-3 combination, which writes
+// the search direction.  Twiddle table: W48^t, t < 32.
+template <typename TI>
+__device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ sp,
+                                                   const SpectralRegs<48, TI>& g, bool own, int I, int J) {
+  constexpr int N = 48, NS = 16, M = 4;
+  asm volatile("" : "+v"(I), "+v"(J));
+  const int tid = threadIdx.x;
+  const TI c3 = TI(-0.5), s3 = TI(0.86602540378443864676);   // W3 = c3 - i s3
+  auto w48 = [&](int t) -> Cx<TI> { return {g.tw[2 * t], g.tw[2 * t + 1]}; };
+  // 3-point DFT of (v0, v1, v2): out_m = sum_a v_a W3^(a m)
+  auto dft3 = [&](Cx<TI> v0, Cx<TI> v1, Cx<TI> v2, Cx<TI>* o, bool inverse) {
+    const Cx<TI> sum = cadd(v1, v2), dif = csub(v1, v2);
+    const Cx<TI> base = {v0.re + c3 * sum.re, v0.im + c3 * sum.im};
+    // W3^m (v1) + W3^2m (v2): the +-i s3 (v1 - v2) part, sign by direction
+    const TI sg = inverse ? TI(-1) : TI(1);
+    const Cx<TI> rot = {sg * s3 * dif.im, -sg * s3 * dif.re};
+    o[0] = cadd(v0, sum);
+    o[1] = cadd(base, rot);
+    o[2] = csub(base, rot);
+  };
+  if (own)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zst<TI>(z, 2 * I + (k & 1), 2 * J + (k >> 1), N, {r[k][0], r[k][1]});
+  __syncthreads();
+  if (tid < NS * NS) {   // radix-3 x 3, forward: the lane's nine points, in place, one axis at a time
+    const int x = tid % NS, y = tid / NS;
+#pragma unroll 1
+    for (int b = 0; b < 3; ++b) {   // along x
+      Cx<TI> o[3];
+      dft3(zld<TI>(z, x, y + NS * b, N), zld<TI>(z, x + NS, y + NS * b, N), zld<TI>(z, x + 2 * NS, y + NS * b, N), o,
+           false);
+#pragma unroll
+      for (int mx = 0; mx < 3; ++mx) zst<TI>(z, x + NS * mx, y + NS * b, N, o[mx]);
+    }
+#pragma unroll 1
+    for (int mx = 0; mx < 3; ++mx) {   // along y, then the twiddles
+      Cx<TI> o[3];
+      dft3(zld<TI>(z, x + NS * mx, y, N), zld<TI>(z, x + NS * mx, y + NS, N), zld<TI>(z, x + NS * mx, y + 2 * NS, N), o,
+           false);
+#pragma unroll
+      for (int my = 0; my < 3; ++my) zst<TI>(z, x + NS * mx, y + NS * my, N, cmul(o[my], cmul(w48(x * mx), w48(y * my))));
+    }
+  }
+  __syncthreads();
+  const int sx = I / 8, sy = J / 8, il = I % 8, jl = J % 8;
+#pragma unroll
+  for (int st = 0; st < M - 1; ++st) {   // radix-2 x 2 DIF, h = 8, 4, 2 inside the sub-block
+    const int h = NS >> (st + 1);
+    if (own) {
+      const int i = NS * sx + (il / h) * 2 * h + il % h, j = NS * sy + (jl / h) * 2 * h + jl % h;
+      const Cx<TI> wx = w48(3 * (il % h) * (NS / (2 * h))), wy = w48(3 * (jl % h) * (NS / (2 * h)));
+      const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + h, j, N);
+      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = zld<TI>(z, i + h, j + h, N);
+      const Cx<TI> A = cadd(a, b), B = cmul(csub(a, b), wx), C = cadd(c, d), D = cmul(csub(c, d), wx);
+      zst<TI>(z, i, j, N, cadd(A, C));
+      zst<TI>(z, i, j + h, N, cmul(csub(A, C), wy));
+      zst<TI>(z, i + h, j, N, cadd(B, D));
+      zst<TI>(z, i + h, j + h, N, cmul(csub(B, D), wy));
+    }
+    __syncthreads();
+  }
+  Cx<TI> v[4];
+  if (own) {   // h = 1 on the owned block
+    const int i = 2 * I, j = 2 * J;
+    const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + 1, j, N);
+    const Cx<TI> c = zld<TI>(z, i, j + 1, N), d = zld<TI>(z, i + 1, j + 1, N);
+    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cadd(c, d), D = csub(c, d);
+    v[0] = cadd(A, C);
+    v[2] = csub(A, C);
+    v[1] = cadd(B, D);
+    v[3] = csub(B, D);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1), j + (k >> 1), N, v[k]);
+  }
+  __syncthreads();
+  if (own)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int p = 2 * I + (k & 1), q = 2 * J + (k >> 1);
+      // frequency of position p: 3 rev(p mod 16) + p / 16; its negative's position
+      const int kx = 3 * bitrev(p % NS, M) + p / NS, ky = 3 * bitrev(q % NS, M) + q / NS;
+      const int nx = (N - kx) % N, ny = (N - ky) % N;
+      const int pp = NS * (nx % 3) + bitrev(nx / 3, M), qp = NS * (ny % 3) + bitrev(ny / 3, M);
+      const Cx<TI> zp = zld<TI>(z, pp, qp, N);
+      const TI* t = g.tab + 4 * (q * N + p);
+      const TI al = t[0], br = t[1], bi = t[2];
+      v[k] = {al * v[k].re + br * zp.re + bi * zp.im, al * v[k].im + bi * zp.re - br * zp.im};
+    }
+  __syncthreads();   // every partner read precedes the overwrites below
+  if (own) {   // inverse h = 1
+    const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
+    const int i = 2 * I, j = 2 * J;
+    zst<TI>(z, i, j, N, cadd(A, C));
+    zst<TI>(z, i, j + 1, N, csub(A, C));
+    zst<TI>(z, i + 1, j, N, cadd(B, D));
+    zst<TI>(z, i + 1, j + 1, N, csub(B, D));
+  }
+#pragma unroll
+  for (int st = M - 2; st >= 0; --st) {   // radix-2 x 2 DIT, h = 2, 4, 8
+    const int h = NS >> (st + 1);
+    __syncthreads();
+    if (own) {
+      const int i = NS * sx + (il / h) * 2 * h + il % h, j = NS * sy + (jl / h) * 2 * h + jl % h;
+      const Cx<TI> wx = w48(3 * (il % h) * (NS / (2 * h))), wy = w48(3 * (jl % h) * (NS / (2 * h)));
+      const Cx<TI> a = zld<TI>(z, i, j, N), b = cmulc(zld<TI>(z, i + h, j, N), wx);
+      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = cmulc(zld<TI>(z, i + h, j + h, N), wx);
+      const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
+      zst<TI>(z, i, j, N, cadd(A, C));
+      zst<TI>(z, i + h, j, N, cadd(B, D));
+      zst<TI>(z, i, j + h, N, csub(A, C));
+      zst<TI>(z, i + h, j + h, N, csub(B, D));
+    }
+  }
+  __syncthreads();
+  constexpr int NBT = (N / 2) * (N / 2);
+  if (tid < NS * NS) {   // radix-3 x 3 combination (inverse), in place along x, then along y into sp
+    const int x = tid % NS, y = tid / NS;
+#pragma unroll 1
+    for (int my = 0; my < 3; ++my) {
+      Cx<TI> vv[3], o[3];
+#pragma unroll
+      for (int mx = 0; mx < 3; ++mx)
+        vv[mx] = cmulc(zld<TI>(z, x + NS * mx, y + NS * my, N), cmul(w48(x * mx), w48(y * my)));
+      dft3(vv[0], vv[1], vv[2], o, true);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) zst<TI>(z, x + NS * a, y + NS * my, N, o[a]);
+    }
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) {
+      Cx<TI> o[3];
+      dft3(zld<TI>(z, x + NS * a, y, N), zld<TI>(z, x + NS * a, y + NS, N), zld<TI>(z, x + NS * a, y + 2 * NS, N), o,
+           true);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int xx = x + NS * a, yy = y + NS * b;
+        const int at = 4 * ((yy >> 1) * (N / 2) + (xx >> 1)) + (xx & 1) + 2 * (yy & 1);
+        const bool pin = (xx | yy) == 0;
+        sp[at] = pin ? TI(0) : o[b].re;
+        sp[NBT * 4 + at] = pin ? TI(0) : o[b].im;
+      }
+    }
+  }
+}
+
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
-// one search direction [2][PN] in TI aliased with the FP64 staging [2][PN].
+// one search direction [2][PN] in TI aliased with the FP64 staging [2][PN] |
+// exchange slots of the element-wise operator [3][WG][4] in TI (even sizes;
+// the spectral preconditioner's complex field aliases them) | twiddle table
+// [n/2][2] in TI (spectral preconditioner).
 constexpr int RED_NV = 2 * NF > 5 ? 2 * NF : 5;   // widest work-group reduction
 __host__ __device__ constexpr size_t lin2d_red_doubles(int nw, int nrhs) {
   return 2 * static_cast<size_t>(nw) * RED_NV + 0 * nrhs;
@@ -480,7 +642,7 @@ __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, i
                                                        bool spectral = false) {
   return lin2d_xch_offset(n1, n2, wg, nrhs) +
          (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0) +
-         (spectral ? static_cast<size_t>(n1) * ti_bytes : 0);   // twiddle table [n/2][2]
+         (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes : 0);   // twiddle table
 }
 
 // The spectral FP32 form is held to three work-groups of 256 lanes per CU
@@ -801,7 +963,8 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
           for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int d = 0; d < 2; ++d) rm[k][d] = dof[k] ? ri[k][d] : TI(0);
-          spectral_precond<N1, TI>(rm, s_x, s_p, sreg, own, I, J);
+          if constexpr (N1 == 48) spectral_precond48<TI>(rm, s_x, s_p, sreg, own, I, J);
+          else spectral_precond<N1, TI>(rm, s_x, s_p, sreg, own, I, J);
           __syncthreads();
           if (own) {
             TI o[4];
@@ -1018,8 +1181,10 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 // cos(k . (x_b - x_a)) (real: the stencil is centro-symmetric), the inverse
 // of S at every k != 0 and the packing coefficients of the two real fields.
 void lin2d_spectral_table(int n, double rho, double* out) {
+  const bool r3 = n == 48;   // 3 x 16: a radix-3 stage, then radix-2 inside 16-wide sub-blocks
+  const int ns = r3 ? 16 : n;
   int m = 0;
-  while ((1 << m) < n) ++m;
+  while ((1 << m) < ns) ++m;
   const double xa[4] = {-1, 1, 1, -1}, ya[4] = {-1, -1, 1, 1};
   const int ox[4] = {0, 1, 1, 0}, oy[4] = {0, 0, 1, 1};
   const double C[3][3] = {{rho + 2.0, rho, 0.0}, {rho, rho + 2.0, 0.0}, {0.0, 0.0, 1.0}};
@@ -1048,10 +1213,13 @@ void lin2d_spectral_table(int n, double rho, double* out) {
     for (int t = 0; t < m; ++t) y |= ((x >> t) & 1) << (m - 1 - t);
     return y;
   };
+  // frequency held at position p after the forward transform: bit reversal
+  // (powers of two); sub-block s = p / 16 holds frequencies s + 3 k (n = 48)
+  auto freq = [&](int p) { return r3 ? 3 * rev(p % ns) + p / ns : rev(p); };
   const double two_pi = 6.283185307179586476925;
   for (int q = 0; q < n; ++q)
     for (int p = 0; p < n; ++p) {
-      const int kx = rev(p), ky = rev(q);
+      const int kx = freq(p), ky = freq(q);
       double S[2][2] = {};
       for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) {
@@ -1068,7 +1236,7 @@ void lin2d_spectral_table(int n, double rho, double* out) {
       t[1] = 0.5 * (ia - ic);
       t[2] = ib;
     }
-  for (int k = 0; k < n / 2; ++k) {
+  for (int k = 0; k < lin2d_spectral_twiddles(n); ++k) {
     out[4 * n * n + 2 * k] = std::cos(two_pi * k / n);
     out[4 * n * n + 2 * k + 1] = -std::sin(two_pi * k / n);
   }
@@ -1081,10 +1249,6 @@ static constexpr int wg_for(int n1, int n2) {
   return 64 * ((((n1 + 1) / 2) * ((n2 + 1) / 2) + 63) / 64);
 }
 
-size_t lin2d_lds_bytes(int n1, int n2, int nrhs) {
-  return lin2d_lds_bytes_t(n1, n2, wg_for(n1, n2), nrhs, 8);
-}
-
 template <typename TI, int NRHS, int N1, int N2, bool FFT = false>
 static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = wg_for(N1, N2);
@@ -1092,6 +1256,7 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
   // the spectral preconditioner's complex field [N*N][2] aliases the exchange slots [3][WG][4]
   static_assert(!FFT || 2 * N1 * N2 <= 12 * WG, "exchange slots too small for the spectral field");
+  static_assert(!FFT || N1 != 48 || WG >= 256, "the radix-3 stage needs 256 lanes");
   auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

@@ -2,7 +2,7 @@
 state): 2D small strain 4^2, 6x10, 8^2, 10^2, 15^2, 16^2, 17^2, 30^2, 32^2,
 48^2 (even sizes run the element-wise operator, odd and non-square sizes the
 node-centric one), 2D finite strain 4^2, 6x10, 8^2, 15^2, 16^2, 30^2, 32^2 and
-3D 4^3, 6^3, 8^3, 10^3, and the square power-of-two 2D sizes once more with
+3D 4^3, 6^3, 8^3, 10^3, and the square 2D sizes 8, 16, 32, 48 once more with
 each preconditioner (spectral, Jacobi) in each precision.  One macro element (one RVE per Gauss point) with a
 centred circular / spherical inclusion at each size, in the mixed form with
 the residual driven to 1e-13 so that C-bar and P-hat compare at 1e-10.
@@ -99,10 +99,10 @@ def test_small_strain_3d_every_size(fe2, n):
     check_a2_to_a6(fe2, p, u, ws, 1e-10)
 
 
-@pytest.mark.parametrize("n", [8, 16, 32])
+@pytest.mark.parametrize("n", [8, 16, 32, 48])
 @pytest.mark.parametrize("prec,solver", [("fp32_ir", "jacobi"), ("fp64", "auto"), ("fp64", "jacobi")])
 def test_small_strain_2d_both_preconditioners(fe2, n, prec, solver):
-    """The square power-of-two sizes run the spectral preconditioner by
+    """The square sizes 8, 16, 32 and 48 run the spectral preconditioner by
     default; the Jacobi one is selectable in both precisions and reaches the
     same C-bar."""
     print("2D small strain", n, prec, solver, flush=True)
@@ -112,22 +112,22 @@ def test_small_strain_2d_both_preconditioners(fe2, n, prec, solver):
 
 
 def test_spectral_preconditioner_selection(fe2):
-    """FE2_SOLVER_AUTO picks the spectral preconditioner on square 8/16/32 RVEs
-    only (both precisions); Jacobi is selectable; an explicit spectral request
-    elsewhere is rejected."""
+    """FE2_SOLVER_AUTO picks the spectral preconditioner on square 8/16/32/48
+    RVEs only (both precisions); Jacobi is selectable; an explicit spectral
+    request elsewhere is rejected."""
     p = W.config("cfg3", macro=(2, 2), resolutions=(16, 32, 48))
     res = p.rve_res[:, 0]
     h = fe2.fe2_setup(p, precision="fp32_ir")
-    assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32)).sum())
+    assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32, 48)).sum())
     h.close()
     h = fe2.fe2_setup(p, precision="fp64")
-    assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32)).sum())
+    assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == int(np.isin(res, (16, 32, 48)).sum())
     h.close()
     h = fe2.fe2_setup(p, precision="fp32_ir", solver="jacobi")
     assert fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES) == 0
     h.close()
     with pytest.raises(fe2.FE2Error) as ei:
-        fe2.fe2_setup(p, solver="fft")                   # 48x48 RVEs present
+        fe2.fe2_setup(with_resolution(W.config("cfg2", macro=(1, 1), rve=8), 30, 30), solver="fft")
     assert ei.value.status == fe2.FE2_ENOTSUP
     with pytest.raises(fe2.FE2Error) as ei:
         fe2.fe2_setup(W.config("cfg4", macro=(1, 1, 1), rve=4), solver="fft")
