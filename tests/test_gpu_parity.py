@@ -7,7 +7,8 @@ right-hand side and increment (a7, a8), fluctuation update (a9) and the
 residual norms (a10).  Tolerances: 1e-10 relative on Cbar, Phat and the macro
 displacement for the plain FP64 path and for the FP32 PCG with FP64
 refinement driven to a tight rve_tol; RVE solution vectors, whose error is
-bounded by cond(K_ww) * rve_tol, are compared at 1e-9 with rve_tol = 1e-13; the looser
+bounded by cond(K_ww) * rve_tol, are compared at 1e-9 with rve_tol = 1e-13 up to 32^2
+RVEs and at 1e-9 (n/32)^2 beyond (cond(K_ww) grows as n^2); the looser
 mixed form used by the benchmark (rve_tol = 1e-4, energy-form condensation)
 must stay within 1e-6 on Cbar.
 """
@@ -107,9 +108,11 @@ def test_rows_a2_to_a6_at_nonzero_state(fe2, name, kw, prec):
         assert rel(Cb[b], c.C) < 1e-10, (b, Cb[b], c.C)
         assert rel(Ph[b], c.P_hat) < 1e-10
         Xb = sol[off[b] * (nF + 1):off[b + 1] * (nF + 1)].reshape(nF + 1, fl)
+        # cond(K_ww) grows as n^2 with the RVE resolution n: 1e-9 up to 32^2
+        tol_x = 1e-9 * max(1.0, (int(p.rve_res[b].max()) / 32.0) ** 2)
         for j in range(nF):
-            assert rel(Xb[j], R.expand(s, c.X_F[:, j])) < 1e-9
-        assert rel(Xb[nF], R.expand(s, c.x_r)) < 1e-9
+            assert rel(Xb[j], R.expand(s, c.X_F[:, j])) < tol_x
+        assert rel(Xb[nF], R.expand(s, c.x_r)) < tol_x
     h.close()
 
 
