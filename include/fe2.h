@@ -305,6 +305,20 @@ int fe2_destroy(fe2_handle h);
  * returned and rhs_dev is undefined.  FE2_ENOTSUP when bw exceeds 1120. */
 int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream);
 
+/* The table of the RVE solver's spectral preconditioner (not an operation of
+ * the paper: the inverse of the periodic Q4 stiffness of a homogeneous medium,
+ * mu = 1 and lambda = rho, that preconditions the solve of Eq. (42)'s RVE
+ * blocks), for inspection and testing; host memory, no GPU work.  n: RVE
+ * elements per side, 8, 16, 32 or 48 (else FE2_ENOTSUP); rho > 0.  out_host
+ * receives 4 n^2 + 2 t doubles: per position q * n + p of the transformed
+ * field, (alpha, Re beta, Im beta, 0) with W(k) = alpha Z(k) + beta conj Z(-k)
+ * at the frequency held there (bit-reversed along each axis; for n = 48,
+ * position p holds 3 rev(p mod 16) + p / 16), then t twiddles
+ * (cos, -sin)(2 pi k / n), t = 32 for n = 48 and n / 2 otherwise.
+ * *len_out (may be NULL) receives the length; out_host may be NULL to query
+ * it. */
+int fe2_spectral_table(int n, double rho, double* out_host, int* len_out);
+
 /* ------------------------------------------------------------------------
  * Surrogate network (not part of the paper): a multilayer perceptron that
  * stands in for the equilibrated RVE response of the nested scheme

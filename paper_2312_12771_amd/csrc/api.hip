@@ -1007,6 +1007,15 @@ int fe2_surrogate_dataset(fe2_handle h, const double* F_dev, const double* P_dev
   return FE2_OK;
 }
 
+int fe2_spectral_table(int n, double rho, double* out_host, int* len_out) {
+  if (!lin2d_spectral_size(n, n)) return set_error("spectral table: n must be 8, 16, 32 or 48"), FE2_ENOTSUP;
+  if (!(rho > 0.0)) return set_error("spectral table: rho must be positive"), FE2_EINVAL;
+  const int len = 4 * n * n + 2 * lin2d_spectral_twiddles(n);
+  if (len_out) *len_out = len;
+  if (out_host) lin2d_spectral_table(n, rho, out_host);
+  return FE2_OK;
+}
+
 int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream) {
   if (pivot_host) *pivot_host = 0;
   if (n < 1 || bw < 0 || !band_dev || !rhs_dev)

@@ -112,6 +112,7 @@ _sig = {
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
     "fe2_set_graph": (C.c_int, [_vp, C.c_int]),
     "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
+    "fe2_spectral_table": (C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "fe2_1d_setup": (C.c_int, [C.POINTER(fe2_1d_desc), _vp, C.POINTER(_vp)]),
     "fe2_1d_newton_step": (C.c_int, [_vp, _dp, _vp]),
     "fe2_1d_get_state": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -279,6 +280,16 @@ def fe2_equilibrate_rve(h: Handle, stream=None, allow_noconv=False):
     st = _lib.fe2_equilibrate_rve(h.ptr, C.byref(its), _stream_ptr(stream))
     _check(st, "fe2_equilibrate_rve", (FE2_OK, FE2_ENOCONV) if allow_noconv else (FE2_OK,))
     return st, int(its.value)
+
+
+def fe2_spectral_table(n: int, rho: float) -> np.ndarray:
+    """The RVE solver's spectral preconditioner table (host, no GPU work)."""
+    ln = C.c_int()
+    _check(_lib.fe2_spectral_table(int(n), float(rho), None, C.byref(ln)), "fe2_spectral_table")
+    out = np.zeros(ln.value, dtype=np.float64)
+    _check(_lib.fe2_spectral_table(int(n), float(rho), out.ctypes.data_as(C.POINTER(C.c_double)), None),
+           "fe2_spectral_table")
+    return out
 
 
 def fe2_band_solve(n: int, bw: int, band, rhs, stream=None, allow_notspd=False):
