@@ -721,8 +721,20 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   const double mu0 = par[1], mu1 = par[3];
   const uint8_t* ph = a.phase + a.phase_off[b];
   double ssum = 0.0;
-  for (int e = tid; e < NN; e += WG) {
-    const double s = ph[e] ? mu1 : mu0;
+  // every load of the thread in flight at once, then the LDS writes (a loop
+  // that waits for each load before the next would serialise the latencies)
+  constexpr int PE = (NN + WG - 1) / WG;   // elements (and nodes) per thread
+  uint8_t phv[PE];
+#pragma unroll
+  for (int q = 0; q < PE; ++q) {
+    const int e = tid + q * WG;
+    phv[q] = e < NN ? ph[e] : uint8_t(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PE; ++q) {
+    const int e = tid + q * WG;
+    if (e >= NN) continue;
+    const double s = phv[q] ? mu1 : mu0;
     const int i = e % N1, j = e / N1;
     put_halo<N1, N2>(s_sc, i, j, s);
     put_halo<N1, N2>(s_sc32, i, j, static_cast<float>(s));
@@ -743,10 +755,31 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   for (int j = 0; j < NF; ++j) eps[j] = a.macro[static_cast<size_t>(b) * NF + j];
 
   auto stage = [&](const double* src) {   // periodic field -> padded FP64 staging
-    for (int n = tid; n < NN; n += WG) {
-      const int i = n % N1, j = n / N1;
-      put_halo<N1, N2>(s_st, i, j, src[2 * n]);
-      put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
+    if constexpr (NRHS == 0) {
+      // assembly only: one 16-byte load per node (fields start at even
+      // offsets), all in flight before the LDS writes.  The solve
+      // instantiations keep the plain loop, whose registers do not add to
+      // the PCG's.
+      double2 v[PE];
+#pragma unroll
+      for (int q = 0; q < PE; ++q) {
+        const int n = tid + q * WG;
+        if (n < NN) v[q] = reinterpret_cast<const double2*>(src)[n];
+      }
+#pragma unroll
+      for (int q = 0; q < PE; ++q) {
+        const int n = tid + q * WG;
+        if (n >= NN) continue;
+        const int i = n % N1, j = n / N1;
+        put_halo<N1, N2>(s_st, i, j, v[q].x);
+        put_halo<N1, N2>(s_st + P::PN, i, j, v[q].y);
+      }
+    } else {
+      for (int n = tid; n < NN; n += WG) {
+        const int i = n % N1, j = n / N1;
+        put_halo<N1, N2>(s_st, i, j, src[2 * n]);
+        put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
+      }
     }
   };
 
