@@ -115,6 +115,83 @@ def test_laminate_any_grid(n1, n2):
     assert np.abs(c.C - Cex).max() <= 1e-12 * np.abs(Cex).max()
 
 
+def _hooke_voigt_3d(lam, mu):
+    """Isotropic stiffness built column by column from Hooke's law in tensor
+    form, sigma = lam tr(eps) I + 2 mu eps, with the Voigt strain
+    [e11, e22, e33, g23, g13, g12] (engineering shear: eps_ij = g_ij / 2) and
+    the stress read back in the same order.  Written without the oracle's
+    Voigt matrix."""
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    C = np.zeros((6, 6))
+    for c, (i, j) in enumerate(pairs):
+        eps = np.zeros((3, 3))
+        if i == j:
+            eps[i, i] = 1.0
+        else:
+            eps[i, j] = eps[j, i] = 0.5
+        sig = lam * np.trace(eps) * np.eye(3) + 2.0 * mu * eps
+        C[:, c] = [sig[a, b] for a, b in pairs]
+    return C
+
+
+def test_voigt_3d_is_hookes_law_in_tensor_form():
+    """The oracle's 3D Voigt stiffness against the tensor form of Hooke's law
+    (a shear diagonal of 2 mu or a misplaced lambda block fails here)."""
+    for lam, mu in [(1.7, 0.9), (0.0, 2.5), (12.0, 0.3)]:
+        np.testing.assert_allclose(T.voigt_C(lam, mu, 3), _hooke_voigt_3d(lam, mu), rtol=0, atol=1e-15)
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        lam, mu = rng.uniform(0.1, 5.0, 2)
+        e = rng.standard_normal(6)
+        eps = np.array([[e[0], e[5] / 2, e[4] / 2], [e[5] / 2, e[1], e[3] / 2], [e[4] / 2, e[3] / 2, e[2]]])
+        sig = lam * np.trace(eps) * np.eye(3) + 2 * mu * eps
+        s = T.voigt_C(lam, mu, 3) @ e
+        np.testing.assert_allclose(s, [sig[0, 0], sig[1, 1], sig[2, 2], sig[1, 2], sig[0, 2], sig[0, 1]],
+                                   rtol=1e-14, atol=1e-14)
+        # strain energy density eps:sigma/2 equals the Voigt quadratic form
+        assert abs(T.linear_energy(e, lam, mu, 3) - 0.5 * np.sum(eps * sig)) < 1e-13 * (1 + abs(np.sum(eps * sig)))
+
+
+def laminate_closed_form_3d(lam, mu, frac):
+    """Exact effective stiffness of an isotropic laminate with layers normal
+    to X3 (eps11, eps22, g12 continuous; sigma33, sigma23, sigma13
+    continuous), in the Voigt order [11, 22, 33, 23, 13, 12]; written out in
+    scalars, with M = lam + 2 mu per layer."""
+    lam = np.asarray(lam, dtype=float)
+    mu = np.asarray(mu, dtype=float)
+    Mm = lam + 2 * mu
+    avg = lambda v: float(np.dot(frac, v))
+    iM = avg(1 / Mm)
+    C33 = 1 / iM
+    C13 = avg(lam / Mm) / iM
+    C11 = avg(Mm - lam ** 2 / Mm) + avg(lam / Mm) ** 2 / iM
+    C12 = avg(lam - lam ** 2 / Mm) + avg(lam / Mm) ** 2 / iM
+    C44 = 1 / avg(1 / mu)
+    C66 = avg(mu)
+    return np.array([[C11, C12, C13, 0, 0, 0],
+                     [C12, C11, C13, 0, 0, 0],
+                     [C13, C13, C33, 0, 0, 0],
+                     [0, 0, 0, C44, 0, 0],
+                     [0, 0, 0, 0, C44, 0],
+                     [0, 0, 0, 0, 0, C66]])
+
+
+@pytest.mark.parametrize("res,n_lo", [((2, 2, 4), 2), ((2, 3, 5), 2), ((3, 2, 6), 4)])
+def test_laminate_3d_matches_closed_form(res, n_lo):
+    """hex8 RVE of two isotropic layers normal to X3 (interfaces on element
+    faces, so the piecewise-linear exact fluctuation is in the trilinear
+    space): the condensed tangent equals the layered-medium closed form."""
+    n1, n2, n3 = res
+    k = np.repeat(np.arange(n3), n1 * n2)   # element layer index (x fastest, then y, then z)
+    ph = (k >= n_lo).astype(np.uint8)
+    lam, mu = W.lame_from_young(np.array([1.0, 10.0]), 0.3)
+    params = np.stack([lam, mu], axis=1)
+    c = R.condense(R.assemble_rve(res, ph, params, "small", "linear", np.zeros(6)))
+    frac = np.array([n_lo, n3 - n_lo]) / n3
+    Cex = laminate_closed_form_3d(lam, mu, frac)
+    assert np.abs(c.C - Cex).max() <= 1e-12 * np.abs(Cex).max(), (c.C, Cex)
+
+
 def _voigt_reuss(ph, params, dim):
     Cs = [T.voigt_C(params[i, 0], params[i, 1], dim) for i in range(2)]
     f1 = float(np.mean(ph))
