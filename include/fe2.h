@@ -108,7 +108,8 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *                   FE2_SOLVER_PCG_JACOBI (diagonal), FE2_SOLVER_PCG_FFT
  *                   (inverse of the periodic operator of a homogeneous
  *                   reference medium, applied by FFT in LDS; square RVEs of
- *                   8, 16 or 32 elements only, else FE2_ENOTSUP) or
+ *                   8, 16, 32 or 48 elements only, else FE2_ENOTSUP; 48 runs
+ *                   a radix-3 x 3 stage ahead of radix-2 x 2 stages) or
  *                   FE2_SOLVER_AUTO (FFT where the size allows it, Jacobi
  *                   otherwise).  3D and finite strain use Jacobi; FFT there
  *                   gives FE2_ENOTSUP

@@ -24,9 +24,10 @@
 //   * RVE sizes are compile-time template parameters.
 //   * PCG state lives in registers and LDS; HBM is touched only for phase ids,
 //     the state w and the outputs.
-//   * Preconditioner: Jacobi, or (square 8/16/32 RVEs) the inverse of the
+//   * Preconditioner: Jacobi, or (square 8/16/32/48 RVEs) the inverse of the
 //     periodic operator of a homogeneous reference medium, applied by a 2D
-//     FFT in LDS; the latter with the standard two-reduction PCG loop.
+//     FFT in LDS (48 = 3 x 16: one radix-3 x 3 stage, then radix-2 x 2
+//     stages); the latter with the standard two-reduction PCG loop.
 //   * Precision: the inner PCG runs in TI (float for the FP32_IR form, double
 //     for plain FP64).  An outer refinement loop forms the true residual in
 //     FP64 from the FP64 solution kept in the output buffer; the condensation

@@ -6,14 +6,18 @@ numbering (a4), RVE solutions (a5), condensed tangent and stress (a6), macro
 right-hand side and increment (a7, a8), fluctuation update (a9) and the
 residual norms (a10).  Tolerances: 1e-10 relative on Cbar, Phat and the macro
 displacement for the plain FP64 path and for the FP32 PCG with FP64
-refinement driven to a tight rve_tol; RVE solution vectors, whose error is
-bounded by cond(K_ww) * rve_tol, are compared at 1e-9 with rve_tol = 1e-13 up to 32^2
-RVEs and at 1e-9 (n/32)^2 beyond (cond(K_ww) grows as n^2); the looser
-mixed form used by the benchmark (rve_tol = 1e-4, energy-form condensation)
-must stay within 1e-6 on Cbar.
+refinement driven to a tight rve_tol.  RVE solution vectors are checked in
+two steps: the oracle evaluates the FP64 residual ||b - K_ww x|| of every GPU
+column, which must meet rve_tol up to the rounding of that evaluation; the
+distance to the oracle's direct solution must then stay inside the
+perturbation bound cond(K_ww) * (both relative residuals), with cond(K_ww)
+measured by the oracle (extreme eigenvalues).  The looser mixed form used by
+the benchmark (rve_tol = 1e-4, energy-form condensation) must stay within
+1e-6 on Cbar.
 """
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import macro as M
@@ -63,6 +67,31 @@ def set_state(fe2, h, u, ws, lam=0.0):
                       w=torch.tensor(np.concatenate(ws), device="cuda"), load_factor=lam)
 
 
+def kappa(K):
+    """cond_2(K) of the SPD reduced stiffness from its extreme eigenvalues."""
+    lmax = spla.eigsh(K, k=1, which="LA", return_eigenvectors=False, tol=1e-8)[0]
+    lmin = spla.eigsh(K.tocsc(), k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-10)[0]
+    return lmax / lmin
+
+
+def check_solution(K, bvec, x_gpu, x_ref, rve_tol, kap):
+    """GPU column x_gpu of K x = b against the oracle: its FP64 residual
+    (evaluated here) within rve_tol plus the rounding of the evaluation
+    (about eps * || |K| |x| ||), and its distance to the direct solution
+    inside cond(K) times the two relative residuals."""
+    nb = np.linalg.norm(bvec)
+    if nb == 0.0:
+        assert np.abs(x_gpu).max() == 0.0
+        return
+    eps = np.finfo(np.float64).eps
+    floor = 32 * eps * np.linalg.norm(abs(K) @ np.abs(x_gpu)) / nb
+    rg = np.linalg.norm(bvec - K @ x_gpu) / nb
+    ro = np.linalg.norm(bvec - K @ x_ref) / nb
+    assert rg <= 2 * rve_tol + floor, (rg, rve_tol, floor)
+    err = np.linalg.norm(x_gpu - x_ref) / np.linalg.norm(x_ref)
+    assert err <= kap * (2 * rve_tol + floor + ro), (err, kap, rg, ro)
+
+
 def small_problem(name, **kw):
     return W.config(name, **kw)
 
@@ -108,11 +137,12 @@ def test_rows_a2_to_a6_at_nonzero_state(fe2, name, kw, prec):
         assert rel(Cb[b], c.C) < 1e-10, (b, Cb[b], c.C)
         assert rel(Ph[b], c.P_hat) < 1e-10
         Xb = sol[off[b] * (nF + 1):off[b + 1] * (nF + 1)].reshape(nF + 1, fl)
-        # cond(K_ww) grows as n^2 with the RVE resolution n: 1e-9 up to 32^2
-        tol_x = 1e-9 * max(1.0, (int(p.rve_res[b].max()) / 32.0) ** 2)
-        for j in range(nF):
-            assert rel(Xb[j], R.expand(s, c.X_F[:, j])) < tol_x
-        assert rel(Xb[nF], R.expand(s, c.x_r)) < tol_x
+        kap = kappa(s.K_ww)
+        for j in range(nF + 1):
+            bvec = s.K_wF[:, j] if j < nF else s.r
+            xref = c.X_F[:, j] if j < nF else c.x_r
+            check_solution(s.K_ww, bvec, Xb[j][s.free], xref, 1e-13, kap)
+            assert np.abs(Xb[j][:p.dim]).max() == 0.0   # pinned corner
     h.close()
 
 
