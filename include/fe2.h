@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define FE2_ABI_VERSION 3
+#define FE2_ABI_VERSION 4
 
 typedef enum fe2_status {
   FE2_OK = 0,
@@ -305,6 +305,19 @@ int fe2_destroy(fe2_handle h);
  * 1-based index of a non-positive pivot, in which case FE2_ENOCONV is
  * returned and rhs_dev is undefined.  FE2_ENOTSUP when bw exceeds 1120. */
 int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream);
+
+/* fe2_band_solve without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as fe2_band_solve, and
+ * the same kernels; the workspace (about 5 bs^2 doubles per block of bs rows)
+ * and the pivot report live in a static device array of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends.  Systems whose
+ * workspace exceeds it fail with FE2_EINVAL before any device work (the 8450
+ * unknowns of the 64 x 64 Q4 macro mesh at half bandwidth 133 need 50 MB).
+ * Calls on one GPU share that array: calls that overlap on one device (two
+ * streams or two threads) race and give undefined results.  Waits for
+ * `stream`.  Nothing is allocated by the library on any path of the call. */
+int fe2_band_solve_noalloc(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream);
 
 /* The table of the RVE solver's spectral preconditioner (not an operation of
  * the paper: the inverse of the periodic Q4 stiffness of a homogeneous medium,

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -822,6 +823,39 @@ int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
     if ((h)->broken) return set_error("handle is unusable"), FE2_ESTATE; \
   } while (0)
 
+// Workspace of fe2_band_solve_noalloc: one file-scope device array per GPU
+// (bss of the code object, resident until the process ends).  Host code
+// never names the array in a kernel argument or a copy: it resolves the
+// device address once per device with hipGetSymbolAddress and uses that.
+constexpr size_t kBandScratchBytes = size_t(64) << 20;
+constexpr size_t kBandScratchHead = 256;   // pivot report, then the workspace doubles
+static __device__ __align__(256) unsigned char scratch[kBandScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first
+// call there, with that device current).
+int band_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return set_error("no usable current HIP device"), FE2_EHIP;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_error("hipGetSymbolAddress of the band-solve scratch failed"), FE2_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FE2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1041,6 +1075,39 @@ int fe2_band_solve(int n, int bw, const double* band_dev, double* rhs_dev, int* 
   (void)hipFree(ws);
   (void)hipFree(info);
   if (rc) return rc;
+  if (pivot_host) *pivot_host = piv;
+  if (piv) return set_error("matrix not positive definite at pivot " + std::to_string(piv)), FE2_ENOCONV;
+  return FE2_OK;
+}
+
+int fe2_band_solve_noalloc(int n, int bw, const double* band_dev, double* rhs_dev, int* pivot_host, void* stream) {
+  if (pivot_host) *pivot_host = 0;
+  if (n < 1 || bw < 0 || !band_dev || !rhs_dev)
+    return set_error("invalid band solve arguments"), FE2_EINVAL;
+  if (bw > bcr_max_bandwidth())
+    return set_error("half bandwidth " + std::to_string(bw) + " exceeds the block solver's limit"), FE2_ENOTSUP;
+  const BcrPlan plan = bcr_plan(n, bw);
+  const size_t need = kBandScratchHead + bcr_workspace_doubles(plan) * sizeof(double);
+  if (need > kBandScratchBytes)
+    return set_error("band solve needs " + std::to_string(need) + " bytes of workspace; the static scratch holds " +
+                     std::to_string(kBandScratchBytes)),
+           FE2_EINVAL;
+  void* base = nullptr;
+  int rc = band_scratch(&base);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* info = static_cast<int*>(base);
+  double* ws = reinterpret_cast<double*>(static_cast<unsigned char*>(base) + kBandScratchHead);
+  // the pivot report must start at zero (a fill kernel, not a memset node)
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, info, static_cast<size_t>(1), 0);
+  rc = bcr_solve(plan, ws, band_dev, rhs_dev, info, s);
+  if (rc) return rc;
+  int piv = 0;
+  if (hipMemcpyAsync(&piv, info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error("band solve failed on the device"), FE2_EHIP;
+  }
   if (pivot_host) *pivot_host = piv;
   if (piv) return set_error("matrix not positive definite at pivot " + std::to_string(piv)), FE2_ENOCONV;
   return FE2_OK;

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run paper_2312_12771_amd/build.py "
                       "(or __graft_entry__.build()) first")
 _lib = C.CDLL(LIB_PATH)
-FE2_ABI_VERSION = 3
+FE2_ABI_VERSION = 4
 
 # status codes and enums (include/fe2.h)
 FE2_OK, FE2_CONVERGED = 0, 1
@@ -112,6 +112,7 @@ _sig = {
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
     "fe2_set_graph": (C.c_int, [_vp, C.c_int]),
     "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
+    "fe2_band_solve_noalloc": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
     "fe2_spectral_table": (C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "fe2_1d_setup": (C.c_int, [C.POINTER(fe2_1d_desc), _vp, C.POINTER(_vp)]),
     "fe2_1d_newton_step": (C.c_int, [_vp, _dp, _vp]),
@@ -299,6 +300,16 @@ def fe2_band_solve(n: int, bw: int, band, rhs, stream=None, allow_notspd=False):
     piv = C.c_int(0)
     st = _lib.fe2_band_solve(int(n), int(bw), _dev_ptr(band), _dev_ptr(rhs), C.byref(piv), _stream_ptr(stream))
     _check(st, "fe2_band_solve", (FE2_OK, FE2_ENOCONV) if allow_notspd else (FE2_OK,))
+    return st, piv.value
+
+
+def fe2_band_solve_noalloc(n: int, bw: int, band, rhs, stream=None, allow_notspd=False):
+    """fe2_band_solve with its workspace in the library's static device
+    scratch (no allocation); same arguments and result."""
+    piv = C.c_int(0)
+    st = _lib.fe2_band_solve_noalloc(int(n), int(bw), _dev_ptr(band), _dev_ptr(rhs), C.byref(piv),
+                                     _stream_ptr(stream))
+    _check(st, "fe2_band_solve_noalloc", (FE2_OK, FE2_ENOCONV) if allow_notspd else (FE2_OK,))
     return st, piv.value
 
 

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     lib.fe2_abi_version.restype = ctypes.c_int
-    assert lib.fe2_abi_version() == 3
+    assert lib.fe2_abi_version() == 4
     lib.fe2_strerror.restype = ctypes.c_char_p
     assert lib.fe2_strerror(0) == b"ok"
 
