@@ -144,9 +144,9 @@ __device__ __forceinline__ void st4(V* p, V a0, V a1, V a2, V a3) {
 // top and top-right blocks; tl, tb, td: threads owning the blocks to the
 // left, below and below-left.
 template <int N1, int N2, int WG, typename V>
-__device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V (&es)[2][2], const V (&mc)[10],
-                                         V* __restrict__ sx, int blk, int br, int bt, int bd, int tid, int tl, int tb,
-                                         int td, V (&y)[4][2]) {
+__device__ __forceinline__ void mv_modes_post(const V* __restrict__ vb, const V (&es)[2][2], const V (&mc)[10],
+                                              V* __restrict__ sx, int blk, int br, int bt, int bd, int tid,
+                                              V (&own)[2][2][2]) {
   constexpr int NBT = (N1 / 2) * (N2 / 2);
   V ux[3][3], uy[3][3];
 #pragma unroll
@@ -214,19 +214,42 @@ __device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V (&es)
   st4(sx + 4 * (0 * WG + tid), fx[0][2], fy[0][2], fx[1][2], fy[1][2]);
   st4(sx + 4 * (1 * WG + tid), fx[2][0], fy[2][0], fx[2][1], fy[2][1]);
   st4(sx + 4 * (2 * WG + tid), fx[2][2], fy[2][2], V(0), V(0));
-  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      own[c][a][0] = fx[c][a];
+      own[c][a][1] = fy[c][a];
+    }
+}
+
+// Second half after the work-group barrier: add the neighbours' partial sums.
+template <int WG, typename V>
+__device__ __forceinline__ void mv_modes_gather(const V* __restrict__ sx, const V (&own)[2][2][2], int tl, int tb,
+                                                int td, V (&y)[4][2]) {
   V gl[4], gb[4], gd[4];
   ld4(sx + 4 * (0 * WG + tl), gl);
   ld4(sx + 4 * (1 * WG + tb), gb);
   ld4(sx + 4 * (2 * WG + td), gd);
-  y[0][0] = fx[0][0] + gl[0] + gb[0] + gd[0];
-  y[0][1] = fy[0][0] + gl[1] + gb[1] + gd[1];
-  y[1][0] = fx[0][1] + gb[2];
-  y[1][1] = fy[0][1] + gb[3];
-  y[2][0] = fx[1][0] + gl[2];
-  y[2][1] = fy[1][0] + gl[3];
-  y[3][0] = fx[1][1];
-  y[3][1] = fy[1][1];
+  y[0][0] = own[0][0][0] + gl[0] + gb[0] + gd[0];
+  y[0][1] = own[0][0][1] + gl[1] + gb[1] + gd[1];
+  y[1][0] = own[0][1][0] + gb[2];
+  y[1][1] = own[0][1][1] + gb[3];
+  y[2][0] = own[1][0][0] + gl[2];
+  y[2][1] = own[1][0][1] + gl[3];
+  y[3][0] = own[1][1][0];
+  y[3][1] = own[1][1][1];
+}
+
+// y = K v at the four owned nodes, exchange barrier included.
+template <int N1, int N2, int WG, typename V>
+__device__ __forceinline__ void mv_modes(const V* __restrict__ vb, const V (&es)[2][2], const V (&mc)[10],
+                                         V* __restrict__ sx, int blk, int br, int bt, int bd, int tid, int tl, int tb,
+                                         int td, V (&y)[4][2]) {
+  V own[2][2][2];
+  mv_modes_post<N1, N2, WG, V>(vb, es, mc, sx, blk, br, bt, bd, tid, own);
+  __syncthreads();
+  mv_modes_gather<WG, V>(sx, own, tl, tb, td, y);
 }
 
 // y = K v (FP64) at one owned node (di, dj) of the block, element by
@@ -328,37 +351,49 @@ __device__ __forceinline__ void zst(TI* z, int i, int j, int n, Cx<TI> v) {
 }
 __device__ __forceinline__ int bitrev(int x, int m) { return static_cast<int>(__brev(static_cast<unsigned>(x)) >> (32 - m)); }
 
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
 // Per-thread constants of the preconditioner, loaded once per RVE: the
-// twiddles of the thread's butterfly group at every stage h = N/2 .. 2
-// (stage s has h = N >> (s + 1)), the symbol coefficients of its four
-// positions and the LDS offsets of their partners -k.
+// symbol coefficients of the thread's four positions, and pointers to the
+// LDS tables (twiddles, partner positions).
 template <int N, typename TI>
 struct SpectralRegs {
   static constexpr int M = (N == 8) ? 3 : (N == 16 || N == 48) ? 4 : 5;   // log2 of the radix-2 extent
   static_assert((1 << M) == N || (N == 48 && (3 << M) == N), "spectral preconditioner: N must be 8, 16, 32 or 48");
   static constexpr bool HOLD = N != 48;   // symbol coefficients in registers (N = 48: read at use)
-  const TI* tw;    // LDS copy of the twiddles
-  const TI* tab;   // the class table (N = 48)
+  const TI* tw;              // LDS copy of the twiddles
+  const unsigned char* pm;   // LDS: position of -k along one axis, per position
+  const TI* tab;             // the class table (N = 48)
   TI al[HOLD ? 4 : 1], br[HOLD ? 4 : 1], bi[HOLD ? 4 : 1];
 };
 
-// Twiddle e^{-2 pi i t / N} of stage st for the thread's group index (I or
-// J), from the LDS table (no VALU work, no registers held across the solve).
-template <int N, typename TI>
-__device__ __forceinline__ Cx<TI> spectral_twiddle(const SpectralRegs<N, TI>& g, int st, int idx) {
-  const int h = N >> (st + 1);
-  const int t = (idx % h) * (N / (2 * h));
-  return {g.tw[2 * t], g.tw[2 * t + 1]};
+// Position that holds the frequency -k when position p holds k (along one
+// axis): bit reversal for powers of two; for N = 48, sub-block s = p / 16
+// holds the frequencies s + 3 k, k bit-reversed within the block.
+template <int N>
+__device__ __forceinline__ int spectral_partner(int p) {
+  constexpr int M = (N == 8) ? 3 : (N == 16 || N == 48) ? 4 : 5;
+  if constexpr (N == 48) {
+    const int k = 3 * bitrev(p % 16, M) + p / 16;
+    const int n = (N - k) % N;
+    return 16 * (n % 3) + bitrev(n / 3, M);
+  } else {
+    return bitrev((N - bitrev(p, M)) & (N - 1), M);
+  }
 }
 
-// s_tw: LDS table [N/2][2], filled here (visible after the caller's next
-// barrier).
+// s_tw: LDS table [t][2] of twiddles followed by the partner map [N] bytes,
+// filled here (visible after the caller's next barrier).
 template <int N, typename TI>
 __device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, TI* s_tw, bool own,
                                                int I, int J) {
+  constexpr int T = lin2d_spectral_twiddles(N);
   const TI* tw = tab + 4 * N * N;
-  if (threadIdx.x < 2 * lin2d_spectral_twiddles(N)) s_tw[threadIdx.x] = tw[threadIdx.x];
+  if (threadIdx.x < 2 * T) s_tw[threadIdx.x] = tw[threadIdx.x];
+  unsigned char* pm = reinterpret_cast<unsigned char*>(s_tw + 2 * T);
+  if (threadIdx.x < N) pm[threadIdx.x] = static_cast<unsigned char>(spectral_partner<N>(threadIdx.x));
   g.tw = s_tw;
+  g.pm = pm;
   g.tab = tab;
   if constexpr (SpectralRegs<N, TI>::HOLD)
 #pragma unroll
@@ -371,102 +406,238 @@ __device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI*
   }
 }
 
-// u = M^-1 r for the owned 2x2 block (I, J) (tid < (N/2)^2 owns; every
-// thread of the work-group must call it: it holds barriers).  r: inner
-// residual of the owned nodes, pinned node masked by the caller; z: complex
-// LDS buffer [N*N][2]; sp: block-major search direction (x at 0, y at
-// +N*N), written with u (pinned node zero).  Ends without a barrier: the
-// caller's next barrier makes sp visible.
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ sp,
-                                                 const SpectralRegs<N, TI>& g, bool own, int I, int J) {
-  constexpr int M = SpectralRegs<N, TI>::M;
-  // I and J opaque per call: the stage addresses (integer arithmetic on
-  // them) are formed here rather than hoisted out of the PCG loop, where
-  // they would hold some forty registers across the whole solve
-  asm volatile("" : "+v"(I), "+v"(J));
-  if (own)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) zst<TI>(z, 2 * I + (k & 1), 2 * J + (k >> 1), N, {r[k][0], r[k][1]});
-  __syncthreads();
-  // forward: decimation in frequency, h = N/2 .. 2 through LDS
-#pragma unroll
-  for (int st = 0; st < M - 1; ++st) {
-    const int h = N >> (st + 1);
-    if (own) {
-      const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
-      const Cx<TI> wx = spectral_twiddle<N, TI>(g, st, I), wy = spectral_twiddle<N, TI>(g, st, J);
-      const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + h, j, N);
-      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = zld<TI>(z, i + h, j + h, N);
-      const Cx<TI> A = cadd(a, b), B = cmul(csub(a, b), wx), C = cadd(c, d), D = cmul(csub(c, d), wx);
-      zst<TI>(z, i, j, N, cadd(A, C));
-      zst<TI>(z, i, j + h, N, cmul(csub(A, C), wy));
-      zst<TI>(z, i + h, j, N, cadd(B, D));
-      zst<TI>(z, i + h, j + h, N, cmul(csub(B, D), wy));
-    }
-    __syncthreads();
+// Work-group layout of the spectral instantiations: every wave owns a tile
+// of TW x TW blocks (2TW x 2TW nodes), so the transform stages whose
+// butterflies stay inside one such window (h <= TW) exchange data within a
+// wave and need no work-group barrier.  Blocks are stored in the same order
+// (storage index of block (I, J) = its owner's thread id): the four-node
+// reads of a wave are contiguous.
+template <int NB>
+struct Tiles {
+  static constexpr int TW = NB < 8 ? NB : 8;
+  static constexpr int NT = NB / TW;
+  static_assert(NB % TW == 0, "block grid not a multiple of the wave tile");
+  static __host__ __device__ constexpr int bix(int I, int J) {
+    return ((J / TW) * NT + I / TW) * (TW * TW) + (J % TW) * TW + I % TW;
   }
-  // h = 1 (unit twiddles) on the owned block, then the symbol
-  Cx<TI> v[4];
-  if (own) {
-    const int i = 2 * I, j = 2 * J;
-    const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + 1, j, N);
-    const Cx<TI> c = zld<TI>(z, i, j + 1, N), d = zld<TI>(z, i + 1, j + 1, N);
+  static __device__ __forceinline__ int I_of(int t) { return ((t / (TW * TW)) % NT) * TW + t % TW; }
+  static __device__ __forceinline__ int J_of(int t) { return ((t / (TW * TW)) / NT) * TW + (t % (TW * TW)) / TW; }
+};
+
+// LDS writes of this wave visible to its other lanes (no work-group barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Work-group sum of per-lane partials split around a barrier that the
+// caller places (so that it can share it): wsum_post writes the wave totals
+// into one of the two alternating reduction buffers, wsum_collect adds them
+// after the barrier.
+template <int NW, typename TI>
+__device__ __forceinline__ TI wsum_collect(const TI* buf) {
+  TI t = TI(0);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += buf[w];
+  return t;
+}
+
+// Radix-2 x 2 butterfly group at distance H of the thread with block
+// coordinates (I, J): points (i, j), (i + H, j), (i, j + H), (i + H, j + H)
+// with i = I + (I & ~(H - 1)) (the (I / H) * 2H + I mod H of an in-place
+// transform), j likewise; twiddle index (I mod H) * TS along x, (J mod H) *
+// TS along y.  DIF forward (INV = false) or DIT inverse with conjugate
+// twiddles (INV = true); in place.  One base address per call, the four
+// points at constant offsets.
+template <int N, int H, int TS, bool INV, typename TI>
+__device__ __forceinline__ void vr2(TI* __restrict__ z, const TI* __restrict__ tw, unsigned I, unsigned J) {
+  const unsigned i = I + (I & ~(H - 1u)), j = J + (J & ~(H - 1u));
+  TI* zb = z + 2 * (j * N + i);
+  const TI* tx = tw + 2 * ((I & (H - 1u)) * TS);
+  const TI* ty = tw + 2 * ((J & (H - 1u)) * TS);
+  const Cx<TI> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
+  constexpr int DX = 2 * H, DY = 2 * H * N;
+  const Cx<TI> a0 = {zb[0], zb[1]}, b0 = {zb[DX], zb[DX + 1]};
+  const Cx<TI> c0 = {zb[DY], zb[DY + 1]}, d0 = {zb[DX + DY], zb[DX + DY + 1]};
+  Cx<TI> o00, o10, o01, o11;
+  if constexpr (!INV) {
+    const Cx<TI> A = cadd(a0, b0), B = cmul(csub(a0, b0), wx), C = cadd(c0, d0), D = cmul(csub(c0, d0), wx);
+    o00 = cadd(A, C);
+    o01 = cmul(csub(A, C), wy);
+    o10 = cadd(B, D);
+    o11 = cmul(csub(B, D), wy);
+  } else {
+    const Cx<TI> b = cmulc(b0, wx), d = cmulc(d0, wx);
+    const Cx<TI> A = cadd(a0, b), B = csub(a0, b), C = cmulc(cadd(c0, d), wy), D = cmulc(csub(c0, d), wy);
+    o00 = cadd(A, C);
+    o10 = cadd(B, D);
+    o01 = csub(A, C);
+    o11 = csub(B, D);
+  }
+  zb[0] = o00.re, zb[1] = o00.im;
+  zb[DX] = o10.re, zb[DX + 1] = o10.im;
+  zb[DY] = o01.re, zb[DY + 1] = o01.im;
+  zb[DX + DY] = o11.re, zb[DX + DY + 1] = o11.im;
+}
+
+// Block-major position of node (x, y) in the search direction.
+template <int N>
+__host__ __device__ constexpr int sp_at(int x, int y) {
+  return 4 * Tiles<N / 2>::bix(x >> 1, y >> 1) + (x & 1) + 2 * (y & 1);
+}
+
+// The owned block's four points (2I + a, 2J + c) of a complex field: base
+// pointer (a = c = 0), the others at +2 and +2N.
+template <int N, typename TI>
+__device__ __forceinline__ TI* own_pts(TI* z, unsigned I, unsigned J) {
+  return z + 4 * (J * N + I);
+}
+
+// Last forward stage (h = 1, unit twiddles) on the owned block: v and z
+// at the owned positions.  The caller's barrier then makes z readable for
+// the symbol's partner reads (spectral_symbol).
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_fwd1(Cx<TI> (&v)[4], TI* __restrict__ z, unsigned I, unsigned J) {
+  TI* zo = own_pts<N>(z, I, J);
+  // h = 1 (unit twiddles) on the owned block
+  {
+    const Cx<TI> a = {zo[0], zo[1]}, b = {zo[2], zo[3]};
+    const Cx<TI> c = {zo[2 * N], zo[2 * N + 1]}, d = {zo[2 * N + 2], zo[2 * N + 3]};
     const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cadd(c, d), D = csub(c, d);
     v[0] = cadd(A, C);
     v[2] = csub(A, C);
     v[1] = cadd(B, D);
     v[3] = csub(B, D);
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1), j + (k >> 1), N, v[k]);
+  for (int k = 0; k < 4; ++k) zo[(k & 1) * 2 + (k >> 1) * 2 * N] = v[k].re, zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = v[k].im;
+}
+
+// The symbol at the owned positions: W = alpha Z + beta conj Z(-k).  Shared
+// by every size (the transform stages differ: radix-2 only, or radix-3
+// first for N = 48).
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_symbol(Cx<TI> (&v)[4], const TI* __restrict__ z, const SpectralRegs<N, TI>& g,
+                                                unsigned I, unsigned J) {
+  // partner positions of the owned block from the LDS map (one 16-bit read
+  // per axis: the entries of 2I and 2I + 1)
+  const unsigned px = *reinterpret_cast<const unsigned short*>(g.pm + 2 * I);
+  const unsigned py = *reinterpret_cast<const unsigned short*>(g.pm + 2 * J);
+  const unsigned ppx[2] = {px & 0xffu, px >> 8}, ppy[2] = {py & 0xffu, py >> 8};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const TI* zp = z + 2 * (ppy[k >> 1] * N + ppx[k & 1]);
+    const TI zr = zp[0], zi = zp[1];
+    TI al, br, bi;
+    if constexpr (SpectralRegs<N, TI>::HOLD) {
+      al = g.al[k], br = g.br[k], bi = g.bi[k];
+    } else {
+      const TI* t = g.tab + 4 * ((2 * J + (k >> 1)) * N + 2 * I + (k & 1));
+      al = t[0], br = t[1], bi = t[2];
+    }
+    // alpha Z + beta conj(Zp)
+    v[k] = {al * v[k].re + br * zr + bi * zi, al * v[k].im + bi * zr - br * zi};
+  }
+}
+
+// Inverse h = 1 of the owned block into z2.
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_inv1(const Cx<TI> (&v)[4], TI* __restrict__ z2, unsigned I, unsigned J) {
+  TI* zo = own_pts<N>(z2, I, J);
+  const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
+  const Cx<TI> o[4] = {cadd(A, C), cadd(B, D), csub(A, C), csub(B, D)};   // (0,0) (1,0) (0,1) (1,1)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) zo[(k & 1) * 2 + (k >> 1) * 2 * N] = o[k].re, zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = o[k].im;
+}
+
+template <int N, typename TI, int S>
+__device__ __forceinline__ void fwd_stages(TI* z, const TI* tw, bool own, unsigned I, unsigned J) {
+  // forward radix-2 stages h = N/2 .. 2 (S = stage index), powers of two
+  constexpr int M = ilog2c(N);
+  if constexpr (S < M - 1) {
+    constexpr int H = N >> (S + 1);
+    constexpr int TW = Tiles<N / 2>::TW;
+    if (own) vr2<N, H, N / (2 * H), false, TI>(z, tw, I, J);
+    if constexpr (H > TW) __syncthreads();
+    else wave_sync();
+    fwd_stages<N, TI, S + 1>(z, tw, own, I, J);
+  }
+}
+template <int N, typename TI, int S>
+__device__ __forceinline__ void inv_stages(TI* z2, const TI* tw, bool own, unsigned I, unsigned J) {
+  // inverse radix-2 stages h = 2 .. N/4 (the last, h = N/2, writes the
+  // search direction and is done by the caller); S counts down
+  constexpr int TW = Tiles<N / 2>::TW;
+  if constexpr (S >= 1) {
+    constexpr int H = N >> (S + 1);
+    if constexpr (H > TW) __syncthreads();
+    else wave_sync();
+    if (own) vr2<N, H, N / (2 * H), true, TI>(z2, tw, I, J);
+    inv_stages<N, TI, S - 1>(z2, tw, own, I, J);
+  }
+}
+
+// u = M^-1 r for the owned 2x2 block (I, J) (every thread of the work-group
+// must call it: it holds barriers; all threads own a block for N >= 16,
+// the first 16 for N = 8).  r: inner residual of the owned nodes, pinned
+// node masked by the caller; z, z2: two complex LDS buffers [N*N][2]
+// (forward transform in z, inverse in z2, so the symbol's partner reads
+// need no barrier behind them); sp: block-major search direction (x at 0,
+// y at +N*N), written with u (pinned node zero).  Ends without a barrier:
+// the caller's next barrier makes sp visible.
+template <int N, typename TI>
+__device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ z2,
+                                                 TI* __restrict__ sp, const SpectralRegs<N, TI>& g, bool own, int Ii,
+                                                 int Ji) {
+  constexpr int M = SpectralRegs<N, TI>::M;
+  constexpr int H = N / 2;   // last inverse stage
+  constexpr int TW = Tiles<N / 2>::TW;
+  // I and J opaque per call: the stage addresses (integer arithmetic on
+  // them) are formed here rather than hoisted out of the PCG loop, where
+  // they would hold some forty registers across the whole solve
+  asm volatile("" : "+v"(Ii), "+v"(Ji));
+  const unsigned I = static_cast<unsigned>(Ii), J = static_cast<unsigned>(Ji);
+  if (own) {
+    TI* zo = own_pts<N>(z, I, J);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      zo[(k & 1) * 2 + (k >> 1) * 2 * N] = r[k][0], zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = r[k][1];
   }
   __syncthreads();
-  if (own)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int p = 2 * I + (k & 1), q = 2 * J + (k >> 1);
-      const int pp = bitrev((N - bitrev(p, M)) & (N - 1), M), qp = bitrev((N - bitrev(q, M)) & (N - 1), M);
-      const Cx<TI> zp = zld<TI>(z, pp, qp, N);
-      // alpha Z + beta conj(Zp)
-      v[k] = {g.al[k] * v[k].re + g.br[k] * zp.re + g.bi[k] * zp.im,
-              g.al[k] * v[k].im + g.bi[k] * zp.re - g.br[k] * zp.im};
-    }
-  __syncthreads();   // every partner read precedes the overwrites below
-  // inverse: decimation in time, h = 1 in registers, then h = 2 .. N/2
+  // forward: decimation in frequency; a stage that combines points of
+  // different wave windows (h > TW) is followed by a work-group barrier, the
+  // others by a wave sync
+  fwd_stages<N, TI, 0>(z, g.tw, own, I, J);
+  Cx<TI> v[4];
+  if (own) spectral_fwd1<N, TI>(v, z, I, J);
+  __syncthreads();
   if (own) {
-    const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
-    const int i = 2 * I, j = 2 * J;
-    zst<TI>(z, i, j, N, cadd(A, C));
-    zst<TI>(z, i, j + 1, N, csub(A, C));
-    zst<TI>(z, i + 1, j, N, cadd(B, D));
-    zst<TI>(z, i + 1, j + 1, N, csub(B, D));
+    spectral_symbol<N, TI>(v, z, g, I, J);
+    spectral_inv1<N, TI>(v, z2, I, J);
   }
-  constexpr int NBT = (N / 2) * (N / 2);
-#pragma unroll
-  for (int st = M - 2; st >= 0; --st) {
-    const int h = N >> (st + 1);
-    __syncthreads();
-    if (own) {
-      const int i = (I / h) * 2 * h + I % h, j = (J / h) * 2 * h + J % h;
-      const Cx<TI> wx = spectral_twiddle<N, TI>(g, st, I), wy = spectral_twiddle<N, TI>(g, st, J);
-      const Cx<TI> a = zld<TI>(z, i, j, N), b = cmulc(zld<TI>(z, i + h, j, N), wx);
-      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = cmulc(zld<TI>(z, i + h, j + h, N), wx);
-      const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
-      const Cx<TI> o[4] = {cadd(A, C), cadd(B, D), csub(A, C), csub(B, D)};   // (i,j) (i+h,j) (i,j+h) (i+h,j+h)
-      if (st > 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1) * h, j + (k >> 1) * h, N, o[k]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = i + (k & 1) * h, y = j + (k >> 1) * h;
-          const int at = 4 * ((y >> 1) * (N / 2) + (x >> 1)) + (x & 1) + 2 * (y & 1);
-          const bool pin = (x | y) == 0;
-          sp[at] = pin ? TI(0) : o[k].re;
-          sp[NBT * 4 + at] = pin ? TI(0) : o[k].im;
-        }
-      }
-    }
+  inv_stages<N, TI, M - 2>(z2, g.tw, own, I, J);
+  if constexpr (H > TW) __syncthreads();
+  else wave_sync();
+  if (own) {   // last inverse stage, h = N/2: i = I, j = J, output into the search direction
+    TI* zb = z2 + 2 * (J * N + I);
+    const TI* tx = g.tw + 2 * I;
+    const TI* ty = g.tw + 2 * J;
+    const Cx<TI> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
+    constexpr int DX = 2 * H, DY = 2 * H * N;
+    const Cx<TI> a = {zb[0], zb[1]}, b = cmulc(Cx<TI>{zb[DX], zb[DX + 1]}, wx);
+    const Cx<TI> c = {zb[DY], zb[DY + 1]}, d = cmulc(Cx<TI>{zb[DX + DY], zb[DX + DY + 1]}, wx);
+    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
+    const Cx<TI> o00 = cadd(A, C), o10 = cadd(B, D), o01 = csub(A, C), o11 = csub(B, D);
+    // node (x, y) -> block-major slot; +H along x or y is a constant offset
+    TI* sb = sp + 4 * Tiles<N / 2>::bix(I >> 1, J >> 1) + (I & 1) + 2 * (J & 1);
+    constexpr int OX = sp_at<N>(H, 0) - sp_at<N>(0, 0), OY = sp_at<N>(0, H) - sp_at<N>(0, 0);
+    const bool pin = (I | J) == 0;
+    sb[0] = pin ? TI(0) : o00.re;
+    sb[N * N] = pin ? TI(0) : o00.im;
+    sb[OX] = o10.re, sb[N * N + OX] = o10.im;
+    sb[OY] = o01.re, sb[N * N + OY] = o01.im;
+    sb[OX + OY] = o11.re, sb[N * N + OX + OY] = o11.im;
   }
 }
 
@@ -475,15 +646,18 @@ __device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __rest
 // first 256 lanes: the 3 x 3 DFT, then the twiddles W48^(x mx) W48^(y my)),
 // which leaves the nine residue classes of the frequency mod 3 in the nine
 // 16 x 16 sub-blocks; vector-radix 2 x 2 stages inside every sub-block
-// follow (one group per lane of the 576).  Sub-block s holds frequencies
-// s + 3 k, k bit-reversed within the block.  The inverse mirrors it: radix-2
-// stages by decimation in time, then the radix-3 combination, which writes
-// the search direction.  Twiddle table: W48^t, t < 32.
+// follow, each sub-block on the wave that owns its 8 x 8 blocks (no
+// work-group barriers).  Sub-block s holds frequencies s + 3 k, k
+// bit-reversed within the block.  The inverse mirrors it: radix-2 stages by
+// decimation in time (in z2), then the radix-3 combination, which writes the
+// search direction.  Twiddle table: W48^t, t < 32.
 template <typename TI>
-__device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ sp,
-                                                   const SpectralRegs<48, TI>& g, bool own, int I, int J) {
-  constexpr int N = 48, NS = 16, M = 4;
-  asm volatile("" : "+v"(I), "+v"(J));
+__device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ z2,
+                                                   TI* __restrict__ sp, const SpectralRegs<48, TI>& g, bool own,
+                                                   int Ii, int Ji) {
+  constexpr int N = 48, NS = 16;
+  asm volatile("" : "+v"(Ii), "+v"(Ji));
+  const unsigned I = static_cast<unsigned>(Ii), J = static_cast<unsigned>(Ji);
   const int tid = threadIdx.x;
   const TI c3 = TI(-0.5), s3 = TI(0.86602540378443864676);   // W3 = c3 - i s3
   auto w48 = [&](int t) -> Cx<TI> { return {g.tw[2 * t], g.tw[2 * t + 1]}; };
@@ -498,9 +672,13 @@ __device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __re
     o[1] = cadd(base, rot);
     o[2] = csub(base, rot);
   };
-  if (own)
+  (void)own;
+  {
+    TI* zo = own_pts<N>(z, I, J);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) zst<TI>(z, 2 * I + (k & 1), 2 * J + (k >> 1), N, {r[k][0], r[k][1]});
+    for (int k = 0; k < 4; ++k)
+      zo[(k & 1) * 2 + (k >> 1) * 2 * N] = r[k][0], zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = r[k][1];
+  }
   __syncthreads();
   if (tid < NS * NS) {   // radix-3 x 3, forward: the lane's nine points, in place, one axis at a time
     const int x = tid % NS, y = tid / NS;
@@ -522,77 +700,27 @@ __device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __re
     }
   }
   __syncthreads();
-  const int sx = I / 8, sy = J / 8, il = I % 8, jl = J % 8;
-#pragma unroll
-  for (int st = 0; st < M - 1; ++st) {   // radix-2 x 2 DIF, h = 8, 4, 2 inside the sub-block
-    const int h = NS >> (st + 1);
-    if (own) {
-      const int i = NS * sx + (il / h) * 2 * h + il % h, j = NS * sy + (jl / h) * 2 * h + jl % h;
-      const Cx<TI> wx = w48(3 * (il % h) * (NS / (2 * h))), wy = w48(3 * (jl % h) * (NS / (2 * h)));
-      const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + h, j, N);
-      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = zld<TI>(z, i + h, j + h, N);
-      const Cx<TI> A = cadd(a, b), B = cmul(csub(a, b), wx), C = cadd(c, d), D = cmul(csub(c, d), wx);
-      zst<TI>(z, i, j, N, cadd(A, C));
-      zst<TI>(z, i, j + h, N, cmul(csub(A, C), wy));
-      zst<TI>(z, i + h, j, N, cadd(B, D));
-      zst<TI>(z, i + h, j + h, N, cmul(csub(B, D), wy));
-    }
-    __syncthreads();
-  }
+  // radix-2 x 2 DIF, h = 8, 4, 2 inside the sub-block (one wave); twiddle
+  // W16^(t) = W48^(3t): index step 3 * 16 / (2h)
+  // (every lane owns a block: 24 x 24 blocks on 576 lanes)
+  vr2<N, 8, 3, false, TI>(z, g.tw, I, J);
+  wave_sync();
+  vr2<N, 4, 6, false, TI>(z, g.tw, I, J);
+  wave_sync();
+  vr2<N, 2, 12, false, TI>(z, g.tw, I, J);
+  wave_sync();
   Cx<TI> v[4];
-  if (own) {   // h = 1 on the owned block
-    const int i = 2 * I, j = 2 * J;
-    const Cx<TI> a = zld<TI>(z, i, j, N), b = zld<TI>(z, i + 1, j, N);
-    const Cx<TI> c = zld<TI>(z, i, j + 1, N), d = zld<TI>(z, i + 1, j + 1, N);
-    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cadd(c, d), D = csub(c, d);
-    v[0] = cadd(A, C);
-    v[2] = csub(A, C);
-    v[1] = cadd(B, D);
-    v[3] = csub(B, D);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) zst<TI>(z, i + (k & 1), j + (k >> 1), N, v[k]);
-  }
+  spectral_fwd1<N, TI>(v, z, I, J);
   __syncthreads();
-  if (own)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int p = 2 * I + (k & 1), q = 2 * J + (k >> 1);
-      // frequency of position p: 3 rev(p mod 16) + p / 16; its negative's position
-      const int kx = 3 * bitrev(p % NS, M) + p / NS, ky = 3 * bitrev(q % NS, M) + q / NS;
-      const int nx = (N - kx) % N, ny = (N - ky) % N;
-      const int pp = NS * (nx % 3) + bitrev(nx / 3, M), qp = NS * (ny % 3) + bitrev(ny / 3, M);
-      const Cx<TI> zp = zld<TI>(z, pp, qp, N);
-      const TI* t = g.tab + 4 * (q * N + p);
-      const TI al = t[0], br = t[1], bi = t[2];
-      v[k] = {al * v[k].re + br * zp.re + bi * zp.im, al * v[k].im + bi * zp.re - br * zp.im};
-    }
-  __syncthreads();   // every partner read precedes the overwrites below
-  if (own) {   // inverse h = 1
-    const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
-    const int i = 2 * I, j = 2 * J;
-    zst<TI>(z, i, j, N, cadd(A, C));
-    zst<TI>(z, i, j + 1, N, csub(A, C));
-    zst<TI>(z, i + 1, j, N, cadd(B, D));
-    zst<TI>(z, i + 1, j + 1, N, csub(B, D));
-  }
-#pragma unroll
-  for (int st = M - 2; st >= 0; --st) {   // radix-2 x 2 DIT, h = 2, 4, 8
-    const int h = NS >> (st + 1);
-    __syncthreads();
-    if (own) {
-      const int i = NS * sx + (il / h) * 2 * h + il % h, j = NS * sy + (jl / h) * 2 * h + jl % h;
-      const Cx<TI> wx = w48(3 * (il % h) * (NS / (2 * h))), wy = w48(3 * (jl % h) * (NS / (2 * h)));
-      const Cx<TI> a = zld<TI>(z, i, j, N), b = cmulc(zld<TI>(z, i + h, j, N), wx);
-      const Cx<TI> c = zld<TI>(z, i, j + h, N), d = cmulc(zld<TI>(z, i + h, j + h, N), wx);
-      const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
-      zst<TI>(z, i, j, N, cadd(A, C));
-      zst<TI>(z, i + h, j, N, cadd(B, D));
-      zst<TI>(z, i, j + h, N, csub(A, C));
-      zst<TI>(z, i + h, j + h, N, csub(B, D));
-    }
-  }
+  spectral_symbol<N, TI>(v, z, g, I, J);
+  spectral_inv1<N, TI>(v, z2, I, J);
+  wave_sync();
+  vr2<N, 2, 12, true, TI>(z2, g.tw, I, J);
+  wave_sync();
+  vr2<N, 4, 6, true, TI>(z2, g.tw, I, J);
+  wave_sync();
+  vr2<N, 8, 3, true, TI>(z2, g.tw, I, J);
   __syncthreads();
-  constexpr int NBT = (N / 2) * (N / 2);
   if (tid < NS * NS) {   // radix-3 x 3 combination (inverse), in place along x, then along y into sp
     const int x = tid % NS, y = tid / NS;
 #pragma unroll 1
@@ -600,23 +728,23 @@ __device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __re
       Cx<TI> vv[3], o[3];
 #pragma unroll
       for (int mx = 0; mx < 3; ++mx)
-        vv[mx] = cmulc(zld<TI>(z, x + NS * mx, y + NS * my, N), cmul(w48(x * mx), w48(y * my)));
+        vv[mx] = cmulc(zld<TI>(z2, x + NS * mx, y + NS * my, N), cmul(w48(x * mx), w48(y * my)));
       dft3(vv[0], vv[1], vv[2], o, true);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) zst<TI>(z, x + NS * a, y + NS * my, N, o[a]);
+      for (int a = 0; a < 3; ++a) zst<TI>(z2, x + NS * a, y + NS * my, N, o[a]);
     }
 #pragma unroll 1
     for (int a = 0; a < 3; ++a) {
       Cx<TI> o[3];
-      dft3(zld<TI>(z, x + NS * a, y, N), zld<TI>(z, x + NS * a, y + NS, N), zld<TI>(z, x + NS * a, y + 2 * NS, N), o,
-           true);
+      dft3(zld<TI>(z2, x + NS * a, y, N), zld<TI>(z2, x + NS * a, y + NS, N), zld<TI>(z2, x + NS * a, y + 2 * NS, N),
+           o, true);
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         const int xx = x + NS * a, yy = y + NS * b;
-        const int at = 4 * ((yy >> 1) * (N / 2) + (xx >> 1)) + (xx & 1) + 2 * (yy & 1);
+        const int at = sp_at<N>(xx, yy);
         const bool pin = (xx | yy) == 0;
         sp[at] = pin ? TI(0) : o[b].re;
-        sp[NBT * 4 + at] = pin ? TI(0) : o[b].im;
+        sp[N * N + at] = pin ? TI(0) : o[b].im;
       }
     }
   }
@@ -625,9 +753,23 @@ __device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __re
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
 // one search direction [2][PN] in TI aliased with the FP64 staging [2][PN] |
 // exchange slots of the element-wise operator [3][WG][4] in TI (even sizes;
-// the spectral preconditioner's complex field aliases them) | twiddle table
-// [n/2][2] in TI (spectral preconditioner).
+// the spectral preconditioner's two complex fields [2][N*N][2] alias them,
+// the region growing to hold both) | twiddle table [n/2][2] in TI (spectral
+// preconditioner).
 constexpr int RED_NV = 2 * NF > 5 ? 2 * NF : 5;   // widest work-group reduction
+template <int NW, typename TI>
+__device__ __forceinline__ const TI* wsum_post(TI v, double* s_red, int& parity) {
+  TI* buf = reinterpret_cast<TI*>(s_red + parity * (NW * RED_NV));
+  parity ^= 1;
+  if constexpr (sizeof(TI) == 4) {
+    const float w = wave_sum_to_last(v);
+    if ((threadIdx.x & 63) == 63) buf[threadIdx.x >> 6] = w;
+  } else {
+    const double w = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = w;
+  }
+  return buf;
+}
 __host__ __device__ constexpr size_t lin2d_red_doubles(int nw, int nrhs) {
   return 2 * static_cast<size_t>(nw) * RED_NV + 0 * nrhs;
 }
@@ -638,18 +780,22 @@ __host__ __device__ constexpr size_t lin2d_vec_offset(int n1, int n2, int wg, in
 __host__ __device__ constexpr size_t lin2d_xch_offset(int n1, int n2, int wg, int nrhs) {
   return lin2d_vec_offset(n1, n2, wg, nrhs) + 2 * static_cast<size_t>(pad_w(n1)) * pad_w(n2) * 8;
 }
-// exchange slots of the element-wise operator: [3][wg][4] in the inner precision
+// exchange region in elements of the inner precision
+__host__ __device__ constexpr size_t lin2d_xch_len(int n1, int n2, int wg, bool spectral) {
+  return spectral && 4 * static_cast<size_t>(n1) * n2 > 12 * static_cast<size_t>(wg) ? 4 * static_cast<size_t>(n1) * n2
+                                                                                     : 12 * static_cast<size_t>(wg);
+}
 __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes,
                                                        bool spectral = false) {
   return lin2d_xch_offset(n1, n2, wg, nrhs) +
-         (((n1 | n2) & 1) == 0 && nrhs > 0 ? 12 * static_cast<size_t>(wg) * ti_bytes : 0) +
-         (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes : 0);   // twiddle table
+         (((n1 | n2) & 1) == 0 && nrhs > 0 ? lin2d_xch_len(n1, n2, wg, spectral) * ti_bytes : 0) +
+         (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes + n1 + 2 : 0);   // twiddles, partner map
 }
 
 // The spectral FP32 form is held to three work-groups of 256 lanes per CU
 // (at most 168 VGPRs), the occupancy of the Jacobi form.
 template <typename TI, bool FFT, int WG>
-constexpr int kLin2dMinBlocks = (sizeof(TI) == 4 && FFT && WG == 256) ? 3 : 1;
+constexpr int kLin2dMinBlocks = (sizeof(TI) == 4 && FFT && WG == 256) ? 3 : (FFT && WG == 256) ? 2 : 1;
 
 template <typename TI, int NRHS, int N1, int N2, int WG, bool FFT>
 __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(const Lin2DArgs a) {
@@ -696,9 +842,22 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   for (int t = 0; t < 10; ++t) mcI[t] = EVEN ? static_cast<TI>(a.modes64[t]) : TI(0);
 
   // ---- ownership of a 2x2 node block -------------------------------------
+  // (spectral form: wave tiles of blocks, see Tiles; else row by row)
   const bool own = tid < NB1 * NB2;
-  const int I = own ? tid % NB1 : 0;
-  const int J = own ? tid / NB1 : 0;
+  auto bix = [](int I_, int J_) {
+    if constexpr (FFT) return Tiles<NB1>::bix(I_, J_);
+    else return J_ * NB1 + I_;
+  };
+  int I = 0, J = 0;
+  if (own) {
+    if constexpr (FFT) {
+      I = Tiles<NB1>::I_of(tid);
+      J = Tiles<NB1>::J_of(tid);
+    } else {
+      I = tid % NB1;
+      J = tid / NB1;
+    }
+  }
   const int i0 = 2 * I, j0 = 2 * J;
   bool exists[4], dof[4];
   int pidx[4];   // padded index of each owned node
@@ -713,9 +872,9 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   auto node_of = [&](int k) { return (j0 + (k >> 1)) * N1 + i0 + (k & 1); };
   // threads owning the blocks to the left, below and below-left (periodic)
   const int Il = (I + NB1 - 1) % NB1, Jb = (J + NB2 - 1) % NB2;
-  const int t_l = J * NB1 + Il, t_b = Jb * NB1 + I, t_d = Jb * NB1 + Il;
+  const int t_l = bix(Il, J), t_b = bix(I, Jb), t_d = bix(Il, Jb);
   const int Ir = (I + 1) % NB1, Jt = (J + 1) % NB2;
-  const int b_own = J * NB1 + I, b_r = J * NB1 + Ir, b_t = Jt * NB1 + I, b_d = Jt * NB1 + Ir;
+  const int b_own = bix(I, J), b_r = bix(Ir, J), b_t = bix(I, Jt), b_d = bix(Ir, Jt);
 
   // ---- element scales (mu of the phase), padded --------------------------
   const double* par = a.params + static_cast<size_t>(b) * 4;
@@ -870,7 +1029,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       dinv[k][d] = dof[k] ? static_cast<TI>(1.0 / dg) : TI(0);
     }
   }
-  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, s_x + 12 * WG, own, I, J);
+  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, s_x + lin2d_xch_len(N1, N2, WG, true), own, I, J);
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -973,69 +1132,74 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 #pragma unroll
         for (int a2 = 0; a2 < 2; ++a2) esc[c][a2] = EVEN ? ebI[(c + 1) * P::PW + a2 + 1] : TI(0);
       if constexpr (FFT) {
-        // Standard PCG with the spectral preconditioner: q = K p, two fused
-        // reductions per iteration (p.q, then r.u after u = M^-1 r).  The
-        // single-reduction recurrence for p.Kp above loses definiteness in
-        // FP32 under this strong preconditioner; p.q formed from q does not.
-        // s_p holds p for the operator and u after the preconditioner; each
-        // thread keeps its own p, r, x in registers.
-        auto wsum1 = [&](TI v) -> TI {
-          if constexpr (sizeof(TI) == 4) {
-            const float in[1] = {v};
-            float out[1];
-            wg_sum_f32<1, NW, RED_NV>(in, out, s_red, parity);
-            return out[0];
-          } else {
-            double t[1] = {v};
-            wg_sum<1, NW, RED_NV>(t, s_red, parity);
-            return t[0];
-          }
-        };
-        auto precond = [&]() {   // u = M^-1 r into uv (own nodes); ends after a barrier
+        // Standard PCG with the spectral preconditioner, ordered so that the
+        // operator acts on u = M^-1 r as soon as the preconditioner has
+        // written it to LDS, and q = K p follows by q = K u + beta q.  Per
+        // iteration: one preconditioner application, one operator
+        // application, the reduction of r.u (it shares the operator's
+        // exchange barrier) and that of p.q.  The single-reduction
+        // recurrence for p.Kp used by the Jacobi form loses definiteness in
+        // FP32 under this strong preconditioner; p.q formed from p and q
+        // does not.  Each thread keeps its own x, r, p, q in registers; only
+        // u passes through LDS.
+        TI qv[4][2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) qv[k][d] = TI(0);
+#pragma unroll 1
+        for (int it = 0;; ++it) {
           TI rm[4][2];
 #pragma unroll
           for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int d = 0; d < 2; ++d) rm[k][d] = dof[k] ? ri[k][d] : TI(0);
-          if constexpr (N1 == 48) spectral_precond48<TI>(rm, s_x, s_p, sreg, own, I, J);
-          else spectral_precond<N1, TI>(rm, s_x, s_p, sreg, own, I, J);
-          __syncthreads();
-          if (own) {
-            TI o[4];
+          if constexpr (N1 == 48) spectral_precond48<TI>(rm, s_x, s_x + 2 * N1 * N2, s_p, sreg, own, I, J);
+          else spectral_precond<N1, TI>(rm, s_x, s_x + 2 * N1 * N2, s_p, sreg, own, I, J);
+          __syncthreads();   // u visible (and every read of the transform buffers done)
+          // u of the owned block is read from LDS where it is used (it stays
+          // there until the next preconditioner application) rather than
+          // held across the operator
+          auto load_u = [&]() {
+            if (own) {
+              TI o[4];
 #pragma unroll
-            for (int d = 0; d < 2; ++d) {
-              ld4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, o);
+              for (int d = 0; d < 2; ++d) {
+                ld4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, o);
 #pragma unroll
-              for (int k = 0; k < 4; ++k) uv[k][d] = o[k];
+                for (int k = 0; k < 4; ++k) uv[k][d] = o[k];
+              }
             }
-          }
-        };
-        precond();
-        TI gpart = TI(0);
+          };
+          load_u();
+          TI gpart = TI(0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int d = 0; d < 2; ++d) {
-            gpart = fma(ri[k][d], uv[k][d], gpart);
-            pv[k][d] = uv[k][d];
-          }
-        TI gam = wsum1(gpart);
-        gam0 = gam;
-        if (own)
-#pragma unroll
-          for (int d = 0; d < 2; ++d) st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, pv[0][d], pv[1][d], pv[2][d], pv[3][d]);
-#pragma unroll 1
-        for (int it = 0; it < a.max_it; ++it) {
-          if (!(gam > tinI * gam0) || !(gam > TI(0))) break;
-          __syncthreads();   // p visible
+            for (int d = 0; d < 2; ++d) gpart = fma(ri[k][d], uv[k][d], gpart);
+          TI fo[2][2][2];
+          mv_modes_post<N1, N2, WG, TI>(s_p, esc, mcI, s_x, b_own, b_r, b_t, b_d, tid, fo);
+          const TI* rb = wsum_post<NW, TI>(gpart, s_red, parity);
+          __syncthreads();   // exchange slots and the r.u wave totals visible
           TI wv[4][2];
-          mv_modes<N1, N2, WG, TI>(s_p, esc, mcI, s_x, b_own, b_r, b_t, b_d, tid, t_l, t_b, t_d, wv);
+          mv_modes_gather<WG, TI>(s_x, fo, t_l, t_b, t_d, wv);
+          const TI gam = wsum_collect<NW, TI>(rb);
+          if (it == 0) gam0 = gam;
+          if (it >= a.max_it || !(gam > tinI * gam0) || !(gam > TI(0))) break;
+          const TI beta = (it == 0) ? TI(0) : gam / gam_old;
+          load_u();
           TI qpart = TI(0);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int d = 0; d < 2; ++d) qpart = fma(pv[k][d], wv[k][d], qpart);
-          const TI pq = wsum1(qpart);
+            for (int d = 0; d < 2; ++d) {
+              pv[k][d] = fma_keep(pv[k][d], beta, uv[k][d]);
+              qv[k][d] = fma_keep(qv[k][d], beta, wv[k][d]);
+              qpart = fma(pv[k][d], qv[k][d], qpart);
+            }
+          const TI* qb = wsum_post<NW, TI>(qpart, s_red, parity);
+          __syncthreads();
+          const TI pq = wsum_collect<NW, TI>(qb);
           if (!(pq > TI(0))) break;   // exact solution or loss of definiteness
           const TI alpha = gam / pq;
           ++iters;
@@ -1044,25 +1208,9 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
               xi[k][d] = fma(alpha, pv[k][d], xi[k][d]);
-              ri[k][d] = fma(-alpha, wv[k][d], ri[k][d]);
+              ri[k][d] = fma(-alpha, qv[k][d], ri[k][d]);
             }
-          precond();   // every read of s_p (p) precedes the p.q reduction's barrier
-          gpart = TI(0);
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int d = 0; d < 2; ++d) gpart = fma(ri[k][d], uv[k][d], gpart);
-          const TI gnew = wsum1(gpart);
-          const TI beta = gnew / gam;
-          gam = gnew;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int d = 0; d < 2; ++d) pv[k][d] = fma_keep(pv[k][d], beta, uv[k][d]);
-          if (own)   // own block only: no other thread reads it before the next barrier
-#pragma unroll
-            for (int d = 0; d < 2; ++d)
-              st4(s_p + d * NB1 * NB2 * 4 + 4 * b_own, pv[0][d], pv[1][d], pv[2][d], pv[3][d]);
+          gam_old = gam;
         }
       } else {
 #pragma unroll 1
@@ -1290,7 +1438,7 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
   // the spectral preconditioner's complex field [N*N][2] aliases the exchange slots [3][WG][4]
   static_assert(!FFT || 2 * N1 * N2 <= 12 * WG, "exchange slots too small for the spectral field");
-  static_assert(!FFT || N1 != 48 || WG >= 256, "the radix-3 stage needs 256 lanes");
+  static_assert(!FFT || N1 != 48 || WG == 576, "the 48-element transform assumes one block per lane");
   auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

@@ -153,7 +153,10 @@ def test_rows_a7_to_a10_one_newton_step(fe2, prec):
     the norms of the linearisation state against the oracle step."""
     p = small_problem("cfg2", macro=(3, 2), rve=16)
     u, ws = random_state(p, 11, amp=2e-4)
-    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    # the updated fluctuations carry the RVE solutions' error, about
+    # cond(K_ww) * rve_tol: drive the residual to 1e-13 so that it stays far
+    # inside the 1e-9 compared below
+    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-13)
     set_state(fe2, h, u, ws, lam=0.25)
     st, norms = fe2.fe2_newton_step(h, 0.5)
     assert st == fe2.FE2_OK
