@@ -63,7 +63,7 @@ typedef enum fe2_status {
 enum { FE2_SMALL_STRAIN = 0, FE2_FINITE_STRAIN = 1 };
 enum { FE2_LINEAR_ISO = 0, FE2_NEO_HOOKE = 1, FE2_MOONEY_RIVLIN = 2 };
 enum { FE2_PREC_FP64 = 0, FE2_PREC_FP32_IR = 1 };
-enum { FE2_SOLVER_AUTO = 0, FE2_SOLVER_PCG_JACOBI = 1, FE2_SOLVER_PCG_FFT = 2 };
+enum { FE2_SOLVER_AUTO = 0, FE2_SOLVER_PCG_JACOBI = 1, FE2_SOLVER_PCG_FFT = 2, FE2_SOLVER_PCG_FFT_MC = 4 };
 enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
 /* Macro basis of the fluctuation: FE2_BASIS_DIRAC puts one RVE at every macro
  * Gauss point (Dirac approach, Eqs. (31)-(35)); FE2_BASIS_ELEMENT gives every
@@ -111,8 +111,12 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *                   8, 16, 32 or 48 elements only, else FE2_ENOTSUP; 48 runs
  *                   a radix-3 x 3 stage ahead of radix-2 x 2 stages) or
  *                   FE2_SOLVER_AUTO (FFT where the size allows it, Jacobi
- *                   otherwise).  3D and finite strain use Jacobi; FFT there
- *                   gives FE2_ENOTSUP
+ *                   otherwise), FFT and AUTO solving the columns one after
+ *                   another; FE2_SOLVER_PCG_FFT_MC is the same preconditioner
+ *                   with the three columns of X_F in one PCG loop (FP32_IR,
+ *                   16 x 16 and 32 x 32 RVEs, three right-hand sides; other
+ *                   cases fall back to one column at a time).  3D and finite
+ *                   strain use Jacobi; FFT there gives FE2_ENOTSUP
  *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach

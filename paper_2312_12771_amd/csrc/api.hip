@@ -190,7 +190,9 @@ struct fe2_ctx {
     a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
-    a.flags = flags;
+    a.fft_tab = c.d_fft32;
+    a.fft_tab64 = c.d_fft64;
+    a.flags = flags | (c.spectral ? RVE_FFT : 0);
     return a;
   }
 
@@ -228,7 +230,7 @@ struct fe2_ctx {
     a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
-    a.flags = flags | (c.spectral ? RVE_FFT : 0);
+    a.flags = flags | (c.spectral ? RVE_FFT : 0) | (c.spectral && solver == FE2_SOLVER_PCG_FFT_MC ? RVE_MC : 0);
     return a;
   }
 };
@@ -402,10 +404,11 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     return set_error("finite strain takes FE2_NEO_HOOKE (lambda, mu) or FE2_MOONEY_RIVLIN (alpha, beta, kappa)"),
            FE2_EINVAL;
   if (h->kin != FE2_SMALL_STRAIN && !finite) return set_error("unknown kinematics"), FE2_EINVAL;
-  if (h->solver != FE2_SOLVER_AUTO && h->solver != FE2_SOLVER_PCG_JACOBI && h->solver != FE2_SOLVER_PCG_FFT)
+  if (h->solver != FE2_SOLVER_AUTO && h->solver != FE2_SOLVER_PCG_JACOBI && h->solver != FE2_SOLVER_PCG_FFT &&
+      h->solver != FE2_SOLVER_PCG_FFT_MC)
     return set_error("unknown solver"), FE2_EINVAL;
-  if (h->solver == FE2_SOLVER_PCG_FFT && (finite || h->dim != 2))
-    return set_error("the spectral preconditioner is implemented for 2D small strain"), FE2_ENOTSUP;
+  if ((h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC) && h->dim != 2)
+    return set_error("the spectral preconditioner is implemented for 2D RVEs"), FE2_ENOTSUP;
   if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL)
     return set_error("unknown scheme"), FE2_EINVAL;
   if (h->scheme == FE2_SCHEME_CLASSICAL && (!(h->micro_tol > 0.0) || h->max_micro_it <= 0))
@@ -459,8 +462,11 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" + std::to_string(n2) +
                        (h->dim == 3 ? "x" + std::to_string(n3) : std::string())),
              FE2_ENOTSUP;
-    if (h->solver == FE2_SOLVER_PCG_FFT && !lin2d_spectral_size(n1, n2))
-      return set_error("the spectral preconditioner needs square RVEs of 8, 16, 32 or 48 elements"), FE2_ENOTSUP;
+    if ((h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC) &&
+        !(finite ? fin2d_spectral_size(n1, n2) : lin2d_spectral_size(n1, n2)))
+      return set_error(finite ? "the finite-strain spectral preconditioner needs square RVEs of 8, 16 or 32 elements"
+                              : "the spectral preconditioner needs square RVEs of 8, 16, 32 or 48 elements"),
+             FE2_ENOTSUP;
     auto key = std::make_tuple(n1, n2, rho0);
     auto it = key2cls.find(key);
     int ci;
@@ -471,6 +477,16 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       c.n1 = n1;
       c.n2 = n2;
       c.rho = rho0;
+      if (finite) {
+        // reference medium of the spectral preconditioner: lambda/mu of the
+        // small-strain limit (mu = 2 (alpha + beta), lambda = kappa + 4 beta)
+        // of the stiffer phase of the class's first RVE; any positive value
+        // gives an SPD preconditioner, this one the closest reference
+        const double* q = kpar.data() + static_cast<size_t>(b) * 6;
+        const double mu0 = 2.0 * (q[0] + q[1]), mu1 = 2.0 * (q[3] + q[4]);
+        const double* qs = mu1 > mu0 ? q + 3 : q;
+        c.rho = (qs[2] + 4.0 * qs[1]) / (2.0 * (qs[0] + qs[1]));
+      }
       h->classes.push_back(c);
     } else {
       ci = it->second;
@@ -572,7 +588,21 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
   // RVE classes: work lists and reference tables
   for (auto& c : h->classes) {
     if ((rc = upload(&c.d_list, c.rves.data(), c.rves.size(), s))) return rc;
-    if (finite) continue;
+    const bool want_fft =
+        h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC || h->solver == FE2_SOLVER_AUTO;
+    if (finite) {   // FE2_SOLVER_AUTO: the spectral preconditioner wherever the size allows it
+      if (want_fft && fin2d_spectral_size(c.n1, c.n2) && c.rho > 0.0) {
+        const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + 2 * lin2d_spectral_twiddles(c.n1);
+        std::vector<double> t64(nt);
+        lin2d_spectral_table(c.n1, c.rho, t64.data());
+        std::vector<float> t32(t64.begin(), t64.end());
+        if ((rc = upload(&c.d_fft64, t64.data(), nt, s))) return rc;
+        if ((rc = upload(&c.d_fft32, t32.data(), nt, s))) return rc;
+        FE2_HIP_CHECK(hipStreamSynchronize(s));   // the host tables die here
+        c.spectral = true;
+      }
+      continue;
+    }
     double err = 0.0;
     if (h->dim == 3) {
       if ((rc = dalloc(&c.d_tab, REF3_TABLE))) return rc;
@@ -584,7 +614,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       continue;
     }
     // FE2_SOLVER_AUTO: the spectral preconditioner wherever the size allows it
-    const bool want = h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_AUTO;
+    const bool want =
+        h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC || h->solver == FE2_SOLVER_AUTO;
     if (want && lin2d_spectral_size(c.n1, c.n2)) {
       const size_t nt = 4 * static_cast<size_t>(c.n1) * c.n1 + 2 * lin2d_spectral_twiddles(c.n1);
       std::vector<double> t64(nt);

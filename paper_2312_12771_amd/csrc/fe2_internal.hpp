@@ -71,8 +71,10 @@ enum RveFlags : int {
   RVE_WARM = 4,       // start from the solution stored in X
   RVE_RCOL = 8,       // solve the residual column (nF+1 right-hand sides)
   RVE_FFT = 16,       // homogeneous-reference (FFT) preconditioner
-  RVE_RONLY = 32      // solve the residual column only (x_r), no condensation;
+  RVE_RONLY = 32,     // solve the residual column only (x_r), no condensation;
                       // RVEs with rnorm2 <= thr2 are skipped (x_r = 0)
+  RVE_MC = 64         // spectral: the columns of X_F in one PCG loop where a
+                      // kernel for the size exists (else one after another)
 };
 
 // One launch handles the RVEs of one resolution class (same n1 x n2 and same
@@ -134,6 +136,8 @@ struct Fin2DArgs {
   int* fail_count;              // RVEs that missed tol (or lost J > 0)
   const double* thr2;           // [n_rve] RVE_RONLY: skip RVEs with rnorm2 <= thr2
   const int* skip;              // [n_rve] or null: RVEs with skip[b] != 0 are left untouched
+  const float* fft_tab;         // spectral preconditioner table, FP32 (RVE_FFT)
+  const double* fft_tab64;      // the same table in FP64
   double h1, h2;                // element edge lengths
   double volume;
   double tol, tol_in;
@@ -146,8 +150,9 @@ int mlp_width(fe2_mlp q, int which);
 int mlp_max_batch(fe2_mlp q);
 
 // Launchers (rve_lin2d.hip, rve_fin2d.hip)
-// Square RVEs of 8, 16, 32 or 48 elements run the PCG with the spectral
-// preconditioner of the homogeneous reference medium when RVE_FFT is set;
+// Square RVEs of 8, 16, 32 or 48 elements (finite strain: 8, 16, 32) run the
+// PCG with the spectral preconditioner of a homogeneous reference medium
+// when RVE_FFT is set;
 // lin2d_spectral_table writes its table (alpha, Re beta, Im beta, 0 per
 // position, then the twiddles e^{-2 pi i t / n}, t < lin2d_spectral_twiddles)
 // for lambda/mu = rho: 4 n^2 + 2 lin2d_spectral_twiddles(n) doubles.
@@ -156,6 +161,7 @@ constexpr bool lin2d_spectral_size(int n1, int n2) {
 }
 constexpr int lin2d_spectral_twiddles(int n) { return n == 48 ? 32 : n / 2; }
 void lin2d_spectral_table(int n, double rho, double* out);
+constexpr bool fin2d_spectral_size(int n1, int n2) { return n1 == n2 && (n1 == 8 || n1 == 16 || n1 == 32); }
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
 bool lin2d_supported(int n1, int n2);

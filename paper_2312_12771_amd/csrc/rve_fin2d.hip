@@ -27,11 +27,17 @@
 //     memory (they run a few times per column only).
 //   * K_wF columns are applied implicitly: the refinement residual of column
 //     j is G^T A (e_j - grad x) per element, and K_Fw x = sum eta A grad x.
-//   * Precision as in the small-strain kernel: inner Jacobi PCG in TI, FP64
+//   * Precision as in the small-strain kernel: inner PCG in TI, FP64
 //     residual refinement, energy-form condensation.
+//   * Preconditioner: Jacobi, or (square 8/16/32 RVEs) the inverse of the
+//     periodic operator of a homogeneous small-strain reference medium
+//     (spectral2d.hpp).  The tangent of a uniformly elliptic state is
+//     spectrally equivalent to it, with constants set by the spread of the
+//     tangent moduli, not by the mesh.
 #include <type_traits>
 
 #include "rve2d_common.hpp"
+#include "spectral2d.hpp"
 
 namespace fe2 {
 
@@ -144,11 +150,21 @@ __host__ __device__ constexpr size_t fin2d_off_w(int n1, int n2, int wg, int nrh
 __host__ __device__ constexpr size_t fin2d_off_u(int n1, int n2, int wg, int nrhs, size_t ti) {
   return (fin2d_off_w(n1, n2, wg, nrhs) + 2 * fin2d_pn(n1, n2) * ti + 15) & ~static_cast<size_t>(15);
 }
-__host__ __device__ constexpr size_t fin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, size_t ti) {
-  const size_t nn = static_cast<size_t>(n1) * n2;
-  const size_t a = 8 * nn * 8;
-  const size_t b = 8 * nn * ti + 2 * fin2d_pn(n1, n2) * ti;
-  return fin2d_off_u(n1, n2, wg, nrhs, ti) + (a > b ? a : b);
+// The force region holds the FP64 element forces [8][NN] during the FP64
+// passes, and the inner forces [8][NN] plus the search direction [2][PN]
+// (and, spectral, the two transform fields [2][N*pitch][2]) during the
+// inner solve; the spectral twiddles and partner map follow it.
+__host__ __device__ constexpr size_t fin2d_off_z(int n1, int n2, size_t ti) {
+  return (8 * static_cast<size_t>(n1) * n2 * ti + 2 * fin2d_pn(n1, n2) * ti + 15) & ~static_cast<size_t>(15);
+}
+__host__ __device__ constexpr size_t fin2d_region(int n1, int n2, size_t ti, bool fft) {
+  const size_t a = 8 * static_cast<size_t>(n1) * n2 * 8;
+  const size_t b = fin2d_off_z(n1, n2, ti) + (fft ? 4 * static_cast<size_t>(n1) * spectral_pitch(n1) * ti : 0);
+  return (a > b ? a : b + 15) & ~static_cast<size_t>(15);
+}
+__host__ __device__ constexpr size_t fin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, size_t ti, bool fft = false) {
+  return fin2d_off_u(n1, n2, wg, nrhs, ti) + fin2d_region(n1, n2, ti, fft) +
+         (fft ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti + n1 + 2 : 0);
 }
 
 // Occupancy: the FP32 instances are held to two work-groups per CU (256
@@ -156,7 +172,7 @@ __host__ __device__ constexpr size_t fin2d_lds_bytes_t(int n1, int n2, int wg, i
 // across waves; the FP64 instances keep their full register budget.
 template <typename T> constexpr int kFinMinBlocks = 1;
 template <> constexpr int kFinMinBlocks<float> = 2;
-template <typename TI, int NRHS, int N1, int N2, int WG>
+template <typename TI, int NRHS, int N1, int N2, int WG, bool FFT>
 __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs a) {
   using P = Pad<N1, N2>;
   constexpr int NW = WG / 64;
@@ -174,7 +190,25 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
   double* s_ef = reinterpret_cast<double*>(s_u);   // [8][NN] FP64 element forces
   TI* s_efI = reinterpret_cast<TI*>(s_u);          // [8][NN] TI element forces
   TI* s_p = s_efI + 8 * NN;                        // [2][PN] TI search direction
+  TI* s_z = reinterpret_cast<TI*>(s_u + fin2d_off_z(N1, N2, sizeof(TI)));   // spectral: [2][N*pitch][2]
+  TI* s_tw = reinterpret_cast<TI*>(s_u + fin2d_region(N1, N2, sizeof(TI), FFT));   // spectral: twiddles, map
   int parity = 0;
+  static_assert(!FFT || (N1 == N2 && (N1 == 8 || N1 == 16 || N1 == 32)), "spectral sizes: 8, 16, 32");
+  // spectral preconditioner: the transform works on 2x2 node blocks, one
+  // per thread in wave tiles (the nodes the thread owns for the operator
+  // are another set; the residual passes through LDS in natural order)
+  constexpr int NB = FFT ? N1 / 2 : 8;
+  const bool sown = FFT && tid < NB * NB;
+  const int sI = sown ? Tiles<NB>::I_of(tid) : 0, sJ = sown ? Tiles<NB>::J_of(tid) : 0;
+  struct NoSpectral {};
+  using SpecRegs = typename std::conditional<FFT, SpectralRegs<FFT ? N1 : 8, TI>, NoSpectral>::type;
+  SpecRegs sreg;
+  if constexpr (FFT) {
+    const TI* ftab;
+    if constexpr (sizeof(TI) == 4) ftab = reinterpret_cast<const TI*>(a.fft_tab);
+    else ftab = reinterpret_cast<const TI*>(a.fft_tab64);
+    spectral_setup<N1, TI>(sreg, ftab, s_tw, sown, sI, sJ);   // visible after the next barrier
+  }
 
   // ---- material, geometry, state ---------------------------------------
   const double* par = a.params + static_cast<size_t>(b) * 6;
@@ -405,7 +439,10 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
   } else {
   // ---- Jacobi diagonal ------------------------------------------------------
   TI dinv[NPT][2];
-  {
+  if constexpr (FFT) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) dinv[k][0] = dinv[k][1] = TI(0);
+  } else {
     double acc[22];
     pass64(std::integral_constant<int, 2>(), 0, nullptr, false, acc);   // the gathers above precede the last barrier
     __syncthreads();
@@ -455,6 +492,38 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
     for (int k = 0; k < NPT; ++k)
 #pragma unroll
       for (int d = 0; d < 2; ++d) qv[k][d] = (node_ok(k) && tid + k * WG != 0) ? gather(s_efI, k, d) : TI(0);
+  };
+
+  // u = M^-1 r at the owned nodes (pinned node zero): Jacobi, or the
+  // spectral preconditioner (residual into the natural-order transform
+  // field, transform, u read back from it; every thread calls it)
+  auto precond = [&](const TI (&rr)[NPT][2], TI (&u)[NPT][2]) {
+    if constexpr (FFT) {
+      constexpr int ZP = spectral_pitch(N1);
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (!node_ok(k)) continue;
+        const int n = tid + k * WG;
+        TI* q = s_z + 2 * ((n / N1) * ZP + n % N1);
+        q[0] = n != 0 ? rr[k][0] : TI(0);
+        q[1] = n != 0 ? rr[k][1] : TI(0);
+      }
+      const TI none[4][2] = {};
+      spectral_precond<N1, TI, true, true>(none, s_z, s_z + 2 * N1 * ZP, s_z, sreg, sown, sI, sJ);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int n = tid + k * WG;
+        const TI* q = s_z + 2 * ((n / N1) * ZP + n % N1);
+        u[k][0] = node_ok(k) ? q[0] : TI(0);
+        u[k][1] = node_ok(k) ? q[1] : TI(0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NPT; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) u[k][d] = dinv[k][d] * rr[k][d];
+    }
   };
 
   // FP64 residual b - K x of column kc (x = 0 when xzero), and K_Fw x
@@ -546,20 +615,23 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
         all_ok = false;
         break;
       }
-      // inner Jacobi PCG in TI on K d = res, from d = 0
+      // inner PCG in TI on K d = res, from d = 0
       TI ri[NPT][2], xi[NPT][2], pown[NPT][2];
       bool indefinite = false;
       double rz, r0;
-      __syncthreads();   // force buffer free before s_p is written
+      __syncthreads();   // force buffer free before s_p (and the transform fields) are written
       {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) ri[k][d] = static_cast<TI>(res[k][d]);
+        precond(ri, pown);
         double red2[2] = {0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            ri[k][d] = static_cast<TI>(res[k][d]);
             xi[k][d] = TI(0);
-            pown[k][d] = dinv[k][d] * ri[k][d];
             const int n = tid + k * WG;
             if (node_ok(k)) put_halo<N1, N2>(s_p + d * P::PN, n % N1, n / N1, pown[k][d]);
             red2[0] += static_cast<double>(ri[k][d]) * static_cast<double>(pown[k][d]);
@@ -586,15 +658,22 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
           break;
         }
         const TI alpha = static_cast<TI>(rz / pq[0]);
-        double red2[2] = {0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
             xi[k][d] = fma(alpha, pown[k][d], xi[k][d]);
             ri[k][d] = fma(-alpha, q[k][d], ri[k][d]);
+          }
+        TI uz[NPT][2];
+        precond(ri, uz);   // (its first barrier follows every read of s_p in this iteration)
+        double red2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
             const double rv = static_cast<double>(ri[k][d]);
-            red2[0] += rv * static_cast<double>(dinv[k][d] * ri[k][d]);
+            red2[0] += rv * static_cast<double>(uz[k][d]);
             red2[1] += rv * rv;
           }
         wg_sum<2, NW, RED_NV>(red2, s_red, parity);
@@ -607,7 +686,7 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
         for (int k = 0; k < NPT; ++k)
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            pown[k][d] = fma(beta, pown[k][d], dinv[k][d] * ri[k][d]);
+            pown[k][d] = fma(beta, pown[k][d], uz[k][d]);
             const int n = tid + k * WG;
             if (node_ok(k)) put_halo<N1, N2>(s_p + d * P::PN, n % N1, n / N1, pown[k][d]);
           }
@@ -704,12 +783,13 @@ static constexpr int fin_wg(int n1, int n2) {
   return n1 * n2 >= 1024 ? 256 : 64 * ((n1 * n2 / 4 + 63) / 64 > 0 ? (n1 * n2 / 4 + 63) / 64 : 1);
 }
 
-template <typename TI, int NRHS, int N1, int N2>
+template <typename TI, int NRHS, int N1, int N2, bool FFT = false>
 static int launch_t(const Fin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = fin_wg(N1, N2);
-  constexpr size_t lds = fin2d_lds_bytes_t(N1, N2, WG, NRHS, sizeof(TI));
+  constexpr size_t lds = fin2d_lds_bytes_t(N1, N2, WG, NRHS, sizeof(TI), FFT);
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident finite-strain solver");
-  auto kern = &k_fin2d<TI, NRHS, N1, N2, WG>;
+  static_assert(!FFT || (N1 / 2) * (N2 / 2) <= WG, "one transform block per thread");
+  auto kern = &k_fin2d<TI, NRHS, N1, N2, WG, FFT>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -721,6 +801,18 @@ static int launch_t(const Fin2DArgs& a, int n_launch, hipStream_t s) {
 template <int N1, int N2>
 static int launch_n(const Fin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
+  if constexpr (fin2d_spectral_size(N1, N2)) {
+    if (a.flags & RVE_FFT) {
+      if (!a.fft_tab || !a.fft_tab64) return set_error("spectral preconditioner table missing"), FE2_EINVAL;
+      if (precision == FE2_PREC_FP64)
+        return nrhs == NF ? launch_t<double, NF, N1, N2, true>(a, n_launch, s)
+                          : launch_t<double, NF + 1, N1, N2, true>(a, n_launch, s);
+      return nrhs == NF ? launch_t<float, NF, N1, N2, true>(a, n_launch, s)
+                        : launch_t<float, NF + 1, N1, N2, true>(a, n_launch, s);
+    }
+  } else {
+    if (a.flags & RVE_FFT) return set_error("no spectral preconditioner for this RVE size"), FE2_ENOTSUP;
+  }
   if (precision == FE2_PREC_FP64)
     return nrhs == NF ? launch_t<double, NF, N1, N2>(a, n_launch, s) : launch_t<double, NF + 1, N1, N2>(a, n_launch, s);
   return nrhs == NF ? launch_t<float, NF, N1, N2>(a, n_launch, s) : launch_t<float, NF + 1, N1, N2>(a, n_launch, s);

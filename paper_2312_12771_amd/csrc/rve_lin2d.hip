@@ -37,6 +37,7 @@
 #include <type_traits>
 
 #include "rve2d_common.hpp"
+#include "spectral2d.hpp"
 
 namespace fe2 {
 
@@ -211,9 +212,11 @@ __device__ __forceinline__ void mv_modes_post(const V* __restrict__ vb, const V 
   // slot 0: nodes (i0+2, j0), (i0+2, j0+1) -> right neighbour's (0, 0), (0, 1)
   // slot 1: nodes (i0, j0+2), (i0+1, j0+2) -> top neighbour's (0, 0), (1, 0)
   // slot 2: node (i0+2, j0+2)              -> diagonal neighbour's (0, 0)
+  //         (two values per thread, [WG][2] after the two four-value slots)
   st4(sx + 4 * (0 * WG + tid), fx[0][2], fy[0][2], fx[1][2], fy[1][2]);
   st4(sx + 4 * (1 * WG + tid), fx[2][0], fy[2][0], fx[2][1], fy[2][1]);
-  st4(sx + 4 * (2 * WG + tid), fx[2][2], fy[2][2], V(0), V(0));
+  sx[8 * WG + 2 * tid] = fx[2][2];
+  sx[8 * WG + 2 * tid + 1] = fy[2][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -227,10 +230,11 @@ __device__ __forceinline__ void mv_modes_post(const V* __restrict__ vb, const V 
 template <int WG, typename V>
 __device__ __forceinline__ void mv_modes_gather(const V* __restrict__ sx, const V (&own)[2][2][2], int tl, int tb,
                                                 int td, V (&y)[4][2]) {
-  V gl[4], gb[4], gd[4];
+  V gl[4], gb[4], gd[2];
   ld4(sx + 4 * (0 * WG + tl), gl);
   ld4(sx + 4 * (1 * WG + tb), gb);
-  ld4(sx + 4 * (2 * WG + td), gd);
+  gd[0] = sx[8 * WG + 2 * td];
+  gd[1] = sx[8 * WG + 2 * td + 1];
   y[0][0] = own[0][0][0] + gl[0] + gb[0] + gd[0];
   y[0][1] = own[0][0][1] + gl[1] + gb[1] + gd[1];
   y[1][0] = own[0][1][0] + gb[2];
@@ -301,455 +305,6 @@ __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const 
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Spectral preconditioner of the homogeneous reference medium
-// ---------------------------------------------------------------------------
-// Every element of a resolution class has stiffness mu_e K_ref, so the
-// periodic operator of a uniform medium (mu = 1) is block-circulant and the
-// Fourier transform diagonalises it into a real symmetric 2x2 symbol S(k).
-// M^-1 r = R K_0^+ R^T r (R drops the pinned corner, K_0^+ the inverse on
-// the non-constant modes) is applied in three steps on one complex field
-// z = r_x + i r_y of N x N nodes in LDS:
-//   * forward DFT by vector-radix 2x2 decimation in frequency (in place,
-//     one 2x2 butterfly group per thread and stage, output in bit-reversed
-//     order along both axes);
-//   * per bit-reversed position: W(k) = alpha(k) Z(k) + beta(k) conj Z(-k),
-//     the symbol inverse [a b; b c] applied to the two real fields packed in
-//     Z (alpha = (a + c)/2, beta = (a - c)/2 + i b; alpha = beta = 0 at k = 0);
-//   * inverse DFT by vector-radix 2x2 decimation in time (bit-reversed in,
-//     natural order out, unscaled: PCG is invariant to the preconditioner's
-//     scale), whose last stage writes u_x, u_y into the block-major search
-//     direction directly.
-// Table tab (per class): [N*N][4] (alpha, Re beta, Im beta, 0) by position
-// q*N + p, then [N/2][2] twiddles (cos, -sin)(2 pi t / N).
-template <typename TI>
-struct Cx {
-  TI re, im;
-};
-template <typename TI>
-__device__ __forceinline__ Cx<TI> cadd(Cx<TI> a, Cx<TI> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename TI>
-__device__ __forceinline__ Cx<TI> csub(Cx<TI> a, Cx<TI> b) { return {a.re - b.re, a.im - b.im}; }
-template <typename TI>
-__device__ __forceinline__ Cx<TI> cmul(Cx<TI> a, Cx<TI> w) {
-  return {a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
-}
-template <typename TI>
-__device__ __forceinline__ Cx<TI> cmulc(Cx<TI> a, Cx<TI> w) {   // a * conj(w)
-  return {a.re * w.re + a.im * w.im, a.im * w.re - a.re * w.im};
-}
-template <typename TI>
-__device__ __forceinline__ Cx<TI> zld(const TI* z, int i, int j, int n) {
-  const TI* q = z + 2 * (j * n + i);
-  return {q[0], q[1]};
-}
-template <typename TI>
-__device__ __forceinline__ void zst(TI* z, int i, int j, int n, Cx<TI> v) {
-  TI* q = z + 2 * (j * n + i);
-  q[0] = v.re;
-  q[1] = v.im;
-}
-__device__ __forceinline__ int bitrev(int x, int m) { return static_cast<int>(__brev(static_cast<unsigned>(x)) >> (32 - m)); }
-
-constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
-
-// Per-thread constants of the preconditioner, loaded once per RVE: the
-// symbol coefficients of the thread's four positions, and pointers to the
-// LDS tables (twiddles, partner positions).
-template <int N, typename TI>
-struct SpectralRegs {
-  static constexpr int M = (N == 8) ? 3 : (N == 16 || N == 48) ? 4 : 5;   // log2 of the radix-2 extent
-  static_assert((1 << M) == N || (N == 48 && (3 << M) == N), "spectral preconditioner: N must be 8, 16, 32 or 48");
-  static constexpr bool HOLD = N != 48;   // symbol coefficients in registers (N = 48: read at use)
-  const TI* tw;              // LDS copy of the twiddles
-  const unsigned char* pm;   // LDS: position of -k along one axis, per position
-  const TI* tab;             // the class table (N = 48)
-  TI al[HOLD ? 4 : 1], br[HOLD ? 4 : 1], bi[HOLD ? 4 : 1];
-};
-
-// Position that holds the frequency -k when position p holds k (along one
-// axis): bit reversal for powers of two; for N = 48, sub-block s = p / 16
-// holds the frequencies s + 3 k, k bit-reversed within the block.
-template <int N>
-__device__ __forceinline__ int spectral_partner(int p) {
-  constexpr int M = (N == 8) ? 3 : (N == 16 || N == 48) ? 4 : 5;
-  if constexpr (N == 48) {
-    const int k = 3 * bitrev(p % 16, M) + p / 16;
-    const int n = (N - k) % N;
-    return 16 * (n % 3) + bitrev(n / 3, M);
-  } else {
-    return bitrev((N - bitrev(p, M)) & (N - 1), M);
-  }
-}
-
-// s_tw: LDS table [t][2] of twiddles followed by the partner map [N] bytes,
-// filled here (visible after the caller's next barrier).
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_setup(SpectralRegs<N, TI>& g, const TI* __restrict__ tab, TI* s_tw, bool own,
-                                               int I, int J) {
-  constexpr int T = lin2d_spectral_twiddles(N);
-  const TI* tw = tab + 4 * N * N;
-  if (threadIdx.x < 2 * T) s_tw[threadIdx.x] = tw[threadIdx.x];
-  unsigned char* pm = reinterpret_cast<unsigned char*>(s_tw + 2 * T);
-  if (threadIdx.x < N) pm[threadIdx.x] = static_cast<unsigned char>(spectral_partner<N>(threadIdx.x));
-  g.tw = s_tw;
-  g.pm = pm;
-  g.tab = tab;
-  if constexpr (SpectralRegs<N, TI>::HOLD)
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int p = own ? 2 * I + (k & 1) : 0, q = own ? 2 * J + (k >> 1) : 0;
-    const TI* t = tab + 4 * (q * N + p);
-    g.al[k] = t[0];
-    g.br[k] = t[1];
-    g.bi[k] = t[2];
-  }
-}
-
-// Work-group layout of the spectral instantiations: every wave owns a tile
-// of TW x TW blocks (2TW x 2TW nodes), so the transform stages whose
-// butterflies stay inside one such window (h <= TW) exchange data within a
-// wave and need no work-group barrier.  Blocks are stored in the same order
-// (storage index of block (I, J) = its owner's thread id): the four-node
-// reads of a wave are contiguous.
-template <int NB>
-struct Tiles {
-  static constexpr int TW = NB < 8 ? NB : 8;
-  static constexpr int NT = NB / TW;
-  static_assert(NB % TW == 0, "block grid not a multiple of the wave tile");
-  static __host__ __device__ constexpr int bix(int I, int J) {
-    return ((J / TW) * NT + I / TW) * (TW * TW) + (J % TW) * TW + I % TW;
-  }
-  static __device__ __forceinline__ int I_of(int t) { return ((t / (TW * TW)) % NT) * TW + t % TW; }
-  static __device__ __forceinline__ int J_of(int t) { return ((t / (TW * TW)) / NT) * TW + (t % (TW * TW)) / TW; }
-};
-
-// LDS writes of this wave visible to its other lanes (no work-group barrier)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Work-group sum of per-lane partials split around a barrier that the
-// caller places (so that it can share it): wsum_post writes the wave totals
-// into one of the two alternating reduction buffers, wsum_collect adds them
-// after the barrier.
-template <int NW, typename TI>
-__device__ __forceinline__ TI wsum_collect(const TI* buf) {
-  TI t = TI(0);
-#pragma unroll
-  for (int w = 0; w < NW; ++w) t += buf[w];
-  return t;
-}
-
-// Radix-2 x 2 butterfly group at distance H of the thread with block
-// coordinates (I, J): points (i, j), (i + H, j), (i, j + H), (i + H, j + H)
-// with i = I + (I & ~(H - 1)) (the (I / H) * 2H + I mod H of an in-place
-// transform), j likewise; twiddle index (I mod H) * TS along x, (J mod H) *
-// TS along y.  DIF forward (INV = false) or DIT inverse with conjugate
-// twiddles (INV = true); in place.  One base address per call, the four
-// points at constant offsets.
-template <int N, int H, int TS, bool INV, typename TI>
-__device__ __forceinline__ void vr2(TI* __restrict__ z, const TI* __restrict__ tw, unsigned I, unsigned J) {
-  const unsigned i = I + (I & ~(H - 1u)), j = J + (J & ~(H - 1u));
-  TI* zb = z + 2 * (j * N + i);
-  const TI* tx = tw + 2 * ((I & (H - 1u)) * TS);
-  const TI* ty = tw + 2 * ((J & (H - 1u)) * TS);
-  const Cx<TI> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
-  constexpr int DX = 2 * H, DY = 2 * H * N;
-  const Cx<TI> a0 = {zb[0], zb[1]}, b0 = {zb[DX], zb[DX + 1]};
-  const Cx<TI> c0 = {zb[DY], zb[DY + 1]}, d0 = {zb[DX + DY], zb[DX + DY + 1]};
-  Cx<TI> o00, o10, o01, o11;
-  if constexpr (!INV) {
-    const Cx<TI> A = cadd(a0, b0), B = cmul(csub(a0, b0), wx), C = cadd(c0, d0), D = cmul(csub(c0, d0), wx);
-    o00 = cadd(A, C);
-    o01 = cmul(csub(A, C), wy);
-    o10 = cadd(B, D);
-    o11 = cmul(csub(B, D), wy);
-  } else {
-    const Cx<TI> b = cmulc(b0, wx), d = cmulc(d0, wx);
-    const Cx<TI> A = cadd(a0, b), B = csub(a0, b), C = cmulc(cadd(c0, d), wy), D = cmulc(csub(c0, d), wy);
-    o00 = cadd(A, C);
-    o10 = cadd(B, D);
-    o01 = csub(A, C);
-    o11 = csub(B, D);
-  }
-  zb[0] = o00.re, zb[1] = o00.im;
-  zb[DX] = o10.re, zb[DX + 1] = o10.im;
-  zb[DY] = o01.re, zb[DY + 1] = o01.im;
-  zb[DX + DY] = o11.re, zb[DX + DY + 1] = o11.im;
-}
-
-// Block-major position of node (x, y) in the search direction.
-template <int N>
-__host__ __device__ constexpr int sp_at(int x, int y) {
-  return 4 * Tiles<N / 2>::bix(x >> 1, y >> 1) + (x & 1) + 2 * (y & 1);
-}
-
-// The owned block's four points (2I + a, 2J + c) of a complex field: base
-// pointer (a = c = 0), the others at +2 and +2N.
-template <int N, typename TI>
-__device__ __forceinline__ TI* own_pts(TI* z, unsigned I, unsigned J) {
-  return z + 4 * (J * N + I);
-}
-
-// Last forward stage (h = 1, unit twiddles) on the owned block: v and z
-// at the owned positions.  The caller's barrier then makes z readable for
-// the symbol's partner reads (spectral_symbol).
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_fwd1(Cx<TI> (&v)[4], TI* __restrict__ z, unsigned I, unsigned J) {
-  TI* zo = own_pts<N>(z, I, J);
-  // h = 1 (unit twiddles) on the owned block
-  {
-    const Cx<TI> a = {zo[0], zo[1]}, b = {zo[2], zo[3]};
-    const Cx<TI> c = {zo[2 * N], zo[2 * N + 1]}, d = {zo[2 * N + 2], zo[2 * N + 3]};
-    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cadd(c, d), D = csub(c, d);
-    v[0] = cadd(A, C);
-    v[2] = csub(A, C);
-    v[1] = cadd(B, D);
-    v[3] = csub(B, D);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) zo[(k & 1) * 2 + (k >> 1) * 2 * N] = v[k].re, zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = v[k].im;
-}
-
-// The symbol at the owned positions: W = alpha Z + beta conj Z(-k).  Shared
-// by every size (the transform stages differ: radix-2 only, or radix-3
-// first for N = 48).
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_symbol(Cx<TI> (&v)[4], const TI* __restrict__ z, const SpectralRegs<N, TI>& g,
-                                                unsigned I, unsigned J) {
-  // partner positions of the owned block from the LDS map (one 16-bit read
-  // per axis: the entries of 2I and 2I + 1)
-  const unsigned px = *reinterpret_cast<const unsigned short*>(g.pm + 2 * I);
-  const unsigned py = *reinterpret_cast<const unsigned short*>(g.pm + 2 * J);
-  const unsigned ppx[2] = {px & 0xffu, px >> 8}, ppy[2] = {py & 0xffu, py >> 8};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const TI* zp = z + 2 * (ppy[k >> 1] * N + ppx[k & 1]);
-    const TI zr = zp[0], zi = zp[1];
-    TI al, br, bi;
-    if constexpr (SpectralRegs<N, TI>::HOLD) {
-      al = g.al[k], br = g.br[k], bi = g.bi[k];
-    } else {
-      const TI* t = g.tab + 4 * ((2 * J + (k >> 1)) * N + 2 * I + (k & 1));
-      al = t[0], br = t[1], bi = t[2];
-    }
-    // alpha Z + beta conj(Zp)
-    v[k] = {al * v[k].re + br * zr + bi * zi, al * v[k].im + bi * zr - br * zi};
-  }
-}
-
-// Inverse h = 1 of the owned block into z2.
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_inv1(const Cx<TI> (&v)[4], TI* __restrict__ z2, unsigned I, unsigned J) {
-  TI* zo = own_pts<N>(z2, I, J);
-  const Cx<TI> A = cadd(v[0], v[1]), B = csub(v[0], v[1]), C = cadd(v[2], v[3]), D = csub(v[2], v[3]);
-  const Cx<TI> o[4] = {cadd(A, C), cadd(B, D), csub(A, C), csub(B, D)};   // (0,0) (1,0) (0,1) (1,1)
-#pragma unroll
-  for (int k = 0; k < 4; ++k) zo[(k & 1) * 2 + (k >> 1) * 2 * N] = o[k].re, zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = o[k].im;
-}
-
-template <int N, typename TI, int S>
-__device__ __forceinline__ void fwd_stages(TI* z, const TI* tw, bool own, unsigned I, unsigned J) {
-  // forward radix-2 stages h = N/2 .. 2 (S = stage index), powers of two
-  constexpr int M = ilog2c(N);
-  if constexpr (S < M - 1) {
-    constexpr int H = N >> (S + 1);
-    constexpr int TW = Tiles<N / 2>::TW;
-    if (own) vr2<N, H, N / (2 * H), false, TI>(z, tw, I, J);
-    if constexpr (H > TW) __syncthreads();
-    else wave_sync();
-    fwd_stages<N, TI, S + 1>(z, tw, own, I, J);
-  }
-}
-template <int N, typename TI, int S>
-__device__ __forceinline__ void inv_stages(TI* z2, const TI* tw, bool own, unsigned I, unsigned J) {
-  // inverse radix-2 stages h = 2 .. N/4 (the last, h = N/2, writes the
-  // search direction and is done by the caller); S counts down
-  constexpr int TW = Tiles<N / 2>::TW;
-  if constexpr (S >= 1) {
-    constexpr int H = N >> (S + 1);
-    if constexpr (H > TW) __syncthreads();
-    else wave_sync();
-    if (own) vr2<N, H, N / (2 * H), true, TI>(z2, tw, I, J);
-    inv_stages<N, TI, S - 1>(z2, tw, own, I, J);
-  }
-}
-
-// u = M^-1 r for the owned 2x2 block (I, J) (every thread of the work-group
-// must call it: it holds barriers; all threads own a block for N >= 16,
-// the first 16 for N = 8).  r: inner residual of the owned nodes, pinned
-// node masked by the caller; z, z2: two complex LDS buffers [N*N][2]
-// (forward transform in z, inverse in z2, so the symbol's partner reads
-// need no barrier behind them); sp: block-major search direction (x at 0,
-// y at +N*N), written with u (pinned node zero).  Ends without a barrier:
-// the caller's next barrier makes sp visible.
-template <int N, typename TI>
-__device__ __forceinline__ void spectral_precond(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ z2,
-                                                 TI* __restrict__ sp, const SpectralRegs<N, TI>& g, bool own, int Ii,
-                                                 int Ji) {
-  constexpr int M = SpectralRegs<N, TI>::M;
-  constexpr int H = N / 2;   // last inverse stage
-  constexpr int TW = Tiles<N / 2>::TW;
-  // I and J opaque per call: the stage addresses (integer arithmetic on
-  // them) are formed here rather than hoisted out of the PCG loop, where
-  // they would hold some forty registers across the whole solve
-  asm volatile("" : "+v"(Ii), "+v"(Ji));
-  const unsigned I = static_cast<unsigned>(Ii), J = static_cast<unsigned>(Ji);
-  if (own) {
-    TI* zo = own_pts<N>(z, I, J);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      zo[(k & 1) * 2 + (k >> 1) * 2 * N] = r[k][0], zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = r[k][1];
-  }
-  __syncthreads();
-  // forward: decimation in frequency; a stage that combines points of
-  // different wave windows (h > TW) is followed by a work-group barrier, the
-  // others by a wave sync
-  fwd_stages<N, TI, 0>(z, g.tw, own, I, J);
-  Cx<TI> v[4];
-  if (own) spectral_fwd1<N, TI>(v, z, I, J);
-  __syncthreads();
-  if (own) {
-    spectral_symbol<N, TI>(v, z, g, I, J);
-    spectral_inv1<N, TI>(v, z2, I, J);
-  }
-  inv_stages<N, TI, M - 2>(z2, g.tw, own, I, J);
-  if constexpr (H > TW) __syncthreads();
-  else wave_sync();
-  if (own) {   // last inverse stage, h = N/2: i = I, j = J, output into the search direction
-    TI* zb = z2 + 2 * (J * N + I);
-    const TI* tx = g.tw + 2 * I;
-    const TI* ty = g.tw + 2 * J;
-    const Cx<TI> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
-    constexpr int DX = 2 * H, DY = 2 * H * N;
-    const Cx<TI> a = {zb[0], zb[1]}, b = cmulc(Cx<TI>{zb[DX], zb[DX + 1]}, wx);
-    const Cx<TI> c = {zb[DY], zb[DY + 1]}, d = cmulc(Cx<TI>{zb[DX + DY], zb[DX + DY + 1]}, wx);
-    const Cx<TI> A = cadd(a, b), B = csub(a, b), C = cmulc(cadd(c, d), wy), D = cmulc(csub(c, d), wy);
-    const Cx<TI> o00 = cadd(A, C), o10 = cadd(B, D), o01 = csub(A, C), o11 = csub(B, D);
-    // node (x, y) -> block-major slot; +H along x or y is a constant offset
-    TI* sb = sp + 4 * Tiles<N / 2>::bix(I >> 1, J >> 1) + (I & 1) + 2 * (J & 1);
-    constexpr int OX = sp_at<N>(H, 0) - sp_at<N>(0, 0), OY = sp_at<N>(0, H) - sp_at<N>(0, 0);
-    const bool pin = (I | J) == 0;
-    sb[0] = pin ? TI(0) : o00.re;
-    sb[N * N] = pin ? TI(0) : o00.im;
-    sb[OX] = o10.re, sb[N * N + OX] = o10.im;
-    sb[OY] = o01.re, sb[N * N + OY] = o01.im;
-    sb[OX + OY] = o11.re, sb[N * N + OX + OY] = o11.im;
-  }
-}
-
-// N = 48 = 3 x 16: the forward transform starts with a radix-3 x 3 stage
-// (one group of nine points (x + 16a, y + 16b), x, y < 16, per lane for the
-// first 256 lanes: the 3 x 3 DFT, then the twiddles W48^(x mx) W48^(y my)),
-// which leaves the nine residue classes of the frequency mod 3 in the nine
-// 16 x 16 sub-blocks; vector-radix 2 x 2 stages inside every sub-block
-// follow, each sub-block on the wave that owns its 8 x 8 blocks (no
-// work-group barriers).  Sub-block s holds frequencies s + 3 k, k
-// bit-reversed within the block.  The inverse mirrors it: radix-2 stages by
-// decimation in time (in z2), then the radix-3 combination, which writes the
-// search direction.  Twiddle table: W48^t, t < 32.
-template <typename TI>
-__device__ __forceinline__ void spectral_precond48(const TI (&r)[4][2], TI* __restrict__ z, TI* __restrict__ z2,
-                                                   TI* __restrict__ sp, const SpectralRegs<48, TI>& g, bool own,
-                                                   int Ii, int Ji) {
-  constexpr int N = 48, NS = 16;
-  asm volatile("" : "+v"(Ii), "+v"(Ji));
-  const unsigned I = static_cast<unsigned>(Ii), J = static_cast<unsigned>(Ji);
-  const int tid = threadIdx.x;
-  const TI c3 = TI(-0.5), s3 = TI(0.86602540378443864676);   // W3 = c3 - i s3
-  auto w48 = [&](int t) -> Cx<TI> { return {g.tw[2 * t], g.tw[2 * t + 1]}; };
-  // 3-point DFT of (v0, v1, v2): out_m = sum_a v_a W3^(a m)
-  auto dft3 = [&](Cx<TI> v0, Cx<TI> v1, Cx<TI> v2, Cx<TI>* o, bool inverse) {
-    const Cx<TI> sum = cadd(v1, v2), dif = csub(v1, v2);
-    const Cx<TI> base = {v0.re + c3 * sum.re, v0.im + c3 * sum.im};
-    // W3^m (v1) + W3^2m (v2): the +-i s3 (v1 - v2) part, sign by direction
-    const TI sg = inverse ? TI(-1) : TI(1);
-    const Cx<TI> rot = {sg * s3 * dif.im, -sg * s3 * dif.re};
-    o[0] = cadd(v0, sum);
-    o[1] = cadd(base, rot);
-    o[2] = csub(base, rot);
-  };
-  (void)own;
-  {
-    TI* zo = own_pts<N>(z, I, J);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      zo[(k & 1) * 2 + (k >> 1) * 2 * N] = r[k][0], zo[(k & 1) * 2 + (k >> 1) * 2 * N + 1] = r[k][1];
-  }
-  __syncthreads();
-  if (tid < NS * NS) {   // radix-3 x 3, forward: the lane's nine points, in place, one axis at a time
-    const int x = tid % NS, y = tid / NS;
-#pragma unroll 1
-    for (int b = 0; b < 3; ++b) {   // along x
-      Cx<TI> o[3];
-      dft3(zld<TI>(z, x, y + NS * b, N), zld<TI>(z, x + NS, y + NS * b, N), zld<TI>(z, x + 2 * NS, y + NS * b, N), o,
-           false);
-#pragma unroll
-      for (int mx = 0; mx < 3; ++mx) zst<TI>(z, x + NS * mx, y + NS * b, N, o[mx]);
-    }
-#pragma unroll 1
-    for (int mx = 0; mx < 3; ++mx) {   // along y, then the twiddles
-      Cx<TI> o[3];
-      dft3(zld<TI>(z, x + NS * mx, y, N), zld<TI>(z, x + NS * mx, y + NS, N), zld<TI>(z, x + NS * mx, y + 2 * NS, N), o,
-           false);
-#pragma unroll
-      for (int my = 0; my < 3; ++my) zst<TI>(z, x + NS * mx, y + NS * my, N, cmul(o[my], cmul(w48(x * mx), w48(y * my))));
-    }
-  }
-  __syncthreads();
-  // radix-2 x 2 DIF, h = 8, 4, 2 inside the sub-block (one wave); twiddle
-  // W16^(t) = W48^(3t): index step 3 * 16 / (2h)
-  // (every lane owns a block: 24 x 24 blocks on 576 lanes)
-  vr2<N, 8, 3, false, TI>(z, g.tw, I, J);
-  wave_sync();
-  vr2<N, 4, 6, false, TI>(z, g.tw, I, J);
-  wave_sync();
-  vr2<N, 2, 12, false, TI>(z, g.tw, I, J);
-  wave_sync();
-  Cx<TI> v[4];
-  spectral_fwd1<N, TI>(v, z, I, J);
-  __syncthreads();
-  spectral_symbol<N, TI>(v, z, g, I, J);
-  spectral_inv1<N, TI>(v, z2, I, J);
-  wave_sync();
-  vr2<N, 2, 12, true, TI>(z2, g.tw, I, J);
-  wave_sync();
-  vr2<N, 4, 6, true, TI>(z2, g.tw, I, J);
-  wave_sync();
-  vr2<N, 8, 3, true, TI>(z2, g.tw, I, J);
-  __syncthreads();
-  if (tid < NS * NS) {   // radix-3 x 3 combination (inverse), in place along x, then along y into sp
-    const int x = tid % NS, y = tid / NS;
-#pragma unroll 1
-    for (int my = 0; my < 3; ++my) {
-      Cx<TI> vv[3], o[3];
-#pragma unroll
-      for (int mx = 0; mx < 3; ++mx)
-        vv[mx] = cmulc(zld<TI>(z2, x + NS * mx, y + NS * my, N), cmul(w48(x * mx), w48(y * my)));
-      dft3(vv[0], vv[1], vv[2], o, true);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) zst<TI>(z2, x + NS * a, y + NS * my, N, o[a]);
-    }
-#pragma unroll 1
-    for (int a = 0; a < 3; ++a) {
-      Cx<TI> o[3];
-      dft3(zld<TI>(z2, x + NS * a, y, N), zld<TI>(z2, x + NS * a, y + NS, N), zld<TI>(z2, x + NS * a, y + 2 * NS, N),
-           o, true);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int xx = x + NS * a, yy = y + NS * b;
-        const int at = sp_at<N>(xx, yy);
-        const bool pin = (xx | yy) == 0;
-        sp[at] = pin ? TI(0) : o[b].re;
-        sp[N * N + at] = pin ? TI(0) : o[b].im;
-      }
-    }
-  }
-}
-
 // LDS layout: reduction buffers | element scales FP64 [PN] | FP32 [PN] |
 // one search direction [2][PN] in TI aliased with the FP64 staging [2][PN] |
 // exchange slots of the element-wise operator [3][WG][4] in TI (even sizes;
@@ -782,13 +337,16 @@ __host__ __device__ constexpr size_t lin2d_xch_offset(int n1, int n2, int wg, in
 }
 // exchange region in elements of the inner precision
 __host__ __device__ constexpr size_t lin2d_xch_len(int n1, int n2, int wg, bool spectral) {
-  return spectral && 4 * static_cast<size_t>(n1) * n2 > 12 * static_cast<size_t>(wg) ? 4 * static_cast<size_t>(n1) * n2
-                                                                                     : 12 * static_cast<size_t>(wg);
+  return spectral && 4 * static_cast<size_t>(n1) * spectral_pitch(n1) > 12 * static_cast<size_t>(wg)
+             ? 4 * static_cast<size_t>(n1) * spectral_pitch(n1)
+             : 12 * static_cast<size_t>(wg);
+}
+__host__ __device__ constexpr size_t lin2d_xch_bytes(int n1, int n2, int wg, int nrhs, int ti_bytes, bool spectral) {
+  return ((n1 | n2) & 1) == 0 && nrhs > 0 ? lin2d_xch_len(n1, n2, wg, spectral) * ti_bytes : 0;
 }
 __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes,
                                                        bool spectral = false) {
-  return lin2d_xch_offset(n1, n2, wg, nrhs) +
-         (((n1 | n2) & 1) == 0 && nrhs > 0 ? lin2d_xch_len(n1, n2, wg, spectral) * ti_bytes : 0) +
+  return lin2d_xch_offset(n1, n2, wg, nrhs) + lin2d_xch_bytes(n1, n2, wg, nrhs, ti_bytes, spectral) +
          (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes + n1 + 2 : 0);   // twiddles, partner map
 }
 
@@ -1029,7 +587,9 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       dinv[k][d] = dof[k] ? static_cast<TI>(1.0 / dg) : TI(0);
     }
   }
-  if constexpr (FFT) spectral_setup<N1, TI>(sreg, ftab, s_x + lin2d_xch_len(N1, N2, WG, true), own, I, J);
+  if constexpr (FFT)
+    spectral_setup<N1, TI>(sreg, ftab, s_x + lin2d_xch_bytes(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), true) / sizeof(TI),
+                           own, I, J);
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -1057,8 +617,8 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
         __syncthreads();   // earlier readers of the staging buffer are done
         stage(xc);
         __syncthreads();
-        #pragma unroll
-    for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
         ++nmv64;
       }
       double r64[4][2];
@@ -1154,8 +714,8 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
           for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int d = 0; d < 2; ++d) rm[k][d] = dof[k] ? ri[k][d] : TI(0);
-          if constexpr (N1 == 48) spectral_precond48<TI>(rm, s_x, s_x + 2 * N1 * N2, s_p, sreg, own, I, J);
-          else spectral_precond<N1, TI>(rm, s_x, s_x + 2 * N1 * N2, s_p, sreg, own, I, J);
+          if constexpr (N1 == 48) spectral_precond48<TI>(rm, s_x, s_x + 2 * N1 * spectral_pitch(N1), s_p, sreg, own, I, J);
+          else spectral_precond<N1, TI>(rm, s_x, s_x + 2 * N1 * spectral_pitch(N1), s_p, sreg, own, I, J);
           __syncthreads();   // u visible (and every read of the transform buffers done)
           // u of the owned block is read from LDS where it is used (it stays
           // there until the next preconditioner application) rather than
@@ -1357,6 +917,548 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 }
 
 
+// ---------------------------------------------------------------------------
+// Multi-column solve: the n_F = 3 columns of X_F in one PCG loop
+// ---------------------------------------------------------------------------
+// Square 16 x 16 and 32 x 32 RVEs, FP32 inner precision, spectral
+// preconditioner, three right-hand sides (the RVE residual column x_r is
+// zero).  The three columns run as independent CGs in lock step: one
+// preconditioner application per iteration transforms the three fields
+// stage by stage (the stage addresses, twiddles and barriers are shared),
+// one pass of the element-wise operator serves the three search directions,
+// and the reductions carry one value per column.  A column that has
+// converged drops out of the work (uniform branches), the others go on.
+// The FP64 refinement treats the three columns together as well: every
+// sweep forms the three FP64 residuals, and the accepted sweep's residuals
+// give the condensation in the energy form for every entry,
+// E[i][j] = b_i . x_j + x_i . (b_j - K x_j), without a further pass.
+//
+// LDS (byte offsets): reduction buffers [2][NW][MR_NV] doubles | element
+// scales FP64 [PN] | FP32 [PN] | search directions u [3][2][N*N] FP32 |
+// exchange slots [3][3][WG][4] FP32, aliased by the three transform fields
+// [3][N*N][2] | twiddles, partner map.  The FP64 column of the refinement
+// passes ([2][PN] doubles, padded periodic layout) aliases the u and
+// exchange regions, which are free outside the inner solve.
+__host__ __device__ constexpr size_t al16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
+constexpr int MR_C = 3;
+constexpr int MR_NV = 2 * MR_C + MR_C * MR_C;   // FP64 sweep reduction: norms and energy-form products
+template <int N, int WG>
+struct MrLds {
+  static constexpr size_t PN = static_cast<size_t>(pad_w(N)) * pad_w(N);
+  static constexpr size_t red = 0;
+  static constexpr size_t sc = al16(2 * static_cast<size_t>(WG / 64) * MR_NV * 8);
+  static constexpr size_t sc32 = al16(sc + PN * 8);
+  static constexpr size_t u = al16(sc32 + PN * 4);
+  static constexpr size_t ulen = static_cast<size_t>(MR_C) * 2 * N * N * 4;
+  static constexpr size_t x = al16(u + ulen);
+  static constexpr size_t zlen = static_cast<size_t>(MR_C) * 2 * N * spectral_pitch(N);
+  static constexpr size_t xlen = (static_cast<size_t>(MR_C) * 12 * WG > zlen ? static_cast<size_t>(MR_C) * 12 * WG : zlen) * 4;
+  static constexpr size_t tw = x + xlen;
+  static constexpr size_t total = tw + 2 * static_cast<size_t>(lin2d_spectral_twiddles(N)) * 4 + N + 2;
+  static_assert(ulen + xlen >= 2 * PN * 8, "FP64 column does not fit the aliased region");
+};
+
+// u = M^-1 r for the three columns (see spectral_precond; every thread of
+// the work-group calls it).  z: the columns' transform fields at stride
+// 2 N^2; sp: the columns' block-major search directions at stride 2 N^2.
+// All three columns are transformed (a converged column carries zeros):
+// the stage addresses and twiddles are formed once per stage and the three
+// columns' loads and butterflies interleave.  Without a second transform
+// buffer, a barrier separates the symbol's partner reads from the
+// inverse's first writes.
+template <int N, int H, int TS, bool INV>
+__device__ __forceinline__ void vr2_mc(float* __restrict__ z, const float* __restrict__ tw, unsigned I, unsigned J) {
+  constexpr int ZS = 2 * N * spectral_pitch(N), ZP = spectral_pitch(N);
+  const unsigned i = I + (I & ~(H - 1u)), j = J + (J & ~(H - 1u));
+  float* zb = z + 2 * (j * ZP + i);
+  const float* tx = tw + 2 * ((I & (H - 1u)) * TS);
+  const float* ty = tw + 2 * ((J & (H - 1u)) * TS);
+  const Cx<float> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
+  constexpr int DX = 2 * H, DY = 2 * H * ZP;
+#pragma unroll
+  for (int c = 0; c < MR_C; ++c) {
+    float* q = zb + c * ZS;
+    const Cx<float> a0 = {q[0], q[1]}, b0 = {q[DX], q[DX + 1]};
+    const Cx<float> c0 = {q[DY], q[DY + 1]}, d0 = {q[DX + DY], q[DX + DY + 1]};
+    Cx<float> o00, o10, o01, o11;
+    if constexpr (!INV) {
+      const Cx<float> A = cadd(a0, b0), B = cmul(csub(a0, b0), wx), C = cadd(c0, d0), D = cmul(csub(c0, d0), wx);
+      o00 = cadd(A, C);
+      o01 = cmul(csub(A, C), wy);
+      o10 = cadd(B, D);
+      o11 = cmul(csub(B, D), wy);
+    } else {
+      const Cx<float> bb = cmulc(b0, wx), dd = cmulc(d0, wx);
+      const Cx<float> A = cadd(a0, bb), B = csub(a0, bb), C = cmulc(cadd(c0, dd), wy), D = cmulc(csub(c0, dd), wy);
+      o00 = cadd(A, C);
+      o10 = cadd(B, D);
+      o01 = csub(A, C);
+      o11 = csub(B, D);
+    }
+    q[0] = o00.re, q[1] = o00.im;
+    q[DX] = o10.re, q[DX + 1] = o10.im;
+    q[DY] = o01.re, q[DY + 1] = o01.im;
+    q[DX + DY] = o11.re, q[DX + DY + 1] = o11.im;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void spectral_precond_mc(const float (&r)[MR_C][4][2], float* __restrict__ z,
+                                                    float* __restrict__ sp, const SpectralRegs<N, float>& g, bool own,
+                                                    int Ii, int Ji) {
+  constexpr int M = SpectralRegs<N, float>::M;
+  constexpr int H = N / 2;   // last inverse stage
+  constexpr int TW = Tiles<N / 2>::TW;
+  constexpr int ZS = 2 * N * spectral_pitch(N), ZP = spectral_pitch(N);
+  asm volatile("" : "+v"(Ii), "+v"(Ji));
+  const unsigned I = static_cast<unsigned>(Ii), J = static_cast<unsigned>(Ji);
+  if (own) {
+    float* zo = own_pts<N>(z, I, J);
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        zo[c * ZS + (k & 1) * 2 + (k >> 1) * 2 * ZP] = r[c][k][0],
+                                                    zo[c * ZS + (k & 1) * 2 + (k >> 1) * 2 * ZP + 1] = r[c][k][1];
+  }
+  __syncthreads();
+  // forward stages h = N/2 .. 2
+  auto fwd = [&](auto hc) {
+    constexpr int HH = decltype(hc)::value;
+    if (own) vr2_mc<N, HH, N / (2 * HH), false>(z, g.tw, I, J);
+    if constexpr (HH > TW) __syncthreads();
+    else wave_sync();
+  };
+  fwd(std::integral_constant<int, N / 2>{});
+  fwd(std::integral_constant<int, N / 4>{});
+  fwd(std::integral_constant<int, N / 8>{});
+  if constexpr (M >= 5) fwd(std::integral_constant<int, N / 16>{});
+  Cx<float> v[MR_C][4];
+  if (own)
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) spectral_fwd1<N, float>(v[c], z + c * ZS, I, J);
+  __syncthreads();
+  if (own)
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) spectral_symbol<N, float>(v[c], z + c * ZS, g, I, J);
+  __syncthreads();   // every partner read precedes the overwrites below
+  if (own)
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) spectral_inv1<N, float>(v[c], z + c * ZS, I, J);
+  // inverse stages h = 2 .. N/4, in place
+  auto inv = [&](auto hc) {
+    constexpr int HH = decltype(hc)::value;
+    if constexpr (HH > TW) __syncthreads();
+    else wave_sync();
+    if (own) vr2_mc<N, HH, N / (2 * HH), true>(z, g.tw, I, J);
+  };
+  inv(std::integral_constant<int, 2>{});
+  inv(std::integral_constant<int, 4>{});
+  if constexpr (M >= 5) inv(std::integral_constant<int, 8>{});
+  if constexpr (H > TW) __syncthreads();
+  else wave_sync();
+  if (own) {   // last inverse stage, h = N/2, into the search directions
+    const float* tx = g.tw + 2 * I;
+    const float* ty = g.tw + 2 * J;
+    const Cx<float> wx = {tx[0], tx[1]}, wy = {ty[0], ty[1]};
+    constexpr int DX = 2 * H, DY = 2 * H * ZP;
+    constexpr int OX = sp_at<N>(H, 0) - sp_at<N>(0, 0), OY = sp_at<N>(0, H) - sp_at<N>(0, 0);
+    const int so = 4 * Tiles<N / 2>::bix(I >> 1, J >> 1) + (I & 1) + 2 * (J & 1);
+    const bool pin = (I | J) == 0;
+    const float* zb0 = z + 2 * (J * ZP + I);
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) {
+      const float* zb = zb0 + c * ZS;
+      const Cx<float> a0 = {zb[0], zb[1]}, b0 = cmulc(Cx<float>{zb[DX], zb[DX + 1]}, wx);
+      const Cx<float> c0 = {zb[DY], zb[DY + 1]}, d0 = cmulc(Cx<float>{zb[DX + DY], zb[DX + DY + 1]}, wx);
+      const Cx<float> A = cadd(a0, b0), B = csub(a0, b0), C = cmulc(cadd(c0, d0), wy), D = cmulc(csub(c0, d0), wy);
+      const Cx<float> o00 = cadd(A, C), o10 = cadd(B, D), o01 = csub(A, C), o11 = csub(B, D);
+      float* sb = sp + c * (2 * N * N) + so;
+      sb[0] = pin ? 0.0f : o00.re;
+      sb[N * N] = pin ? 0.0f : o00.im;
+      sb[OX] = o10.re, sb[N * N + OX] = o10.im;
+      sb[OY] = o01.re, sb[N * N + OY] = o01.im;
+      sb[OX + OY] = o11.re, sb[N * N + OX + OY] = o11.im;
+    }
+  }
+}
+
+// Wave-uniform values pinned to scalar registers.
+__device__ __forceinline__ float uni(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long t = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(t));
+  const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(t >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Work-group sums of MR_C per-lane partials around a caller's barrier.
+template <int NW>
+__device__ __forceinline__ const float* wsum_post_mc(const float (&v)[MR_C], double* s_red, int& parity) {
+  float* buf = reinterpret_cast<float*>(s_red + parity * (NW * MR_NV));
+  parity ^= 1;
+  float w[MR_C];
+#pragma unroll
+  for (int c = 0; c < MR_C; ++c) w[c] = wave_sum_to_last(v[c]);
+  if ((threadIdx.x & 63) == 63)
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) buf[(threadIdx.x >> 6) * MR_C + c] = w[c];
+  return buf;
+}
+template <int NW>
+__device__ __forceinline__ void wsum_collect_mc(const float* buf, float (&out)[MR_C]) {
+#pragma unroll
+  for (int c = 0; c < MR_C; ++c) {
+    float t = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += buf[w * MR_C + c];
+    out[c] = t;
+  }
+}
+
+template <int N, int WG>
+__global__ void __launch_bounds__(WG, 2) k_lin2d_mr(const Lin2DArgs a) {
+  using P = Pad<N, N>;
+  using L = MrLds<N, WG>;
+  constexpr int NW = WG / 64;
+  constexpr int NN = N * N;
+  constexpr int NB = N / 2;
+  constexpr int ZS = 2 * N * N;
+  static_assert(NB * NB == WG || (N == 8 && WG == 64), "one 2x2 block per lane");
+  const int tid = threadIdx.x;
+  const int b = a.rve_list[blockIdx.x];
+  if (a.skip && a.skip[b]) return;   // handled elsewhere (whole work-group)
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* s_red = reinterpret_cast<double*>(smem + L::red);
+  double* s_sc = reinterpret_cast<double*>(smem + L::sc);    // [PN] FP64 element scales
+  float* s_sc32 = reinterpret_cast<float*>(smem + L::sc32);  // [PN] FP32 element scales
+  float* s_u = reinterpret_cast<float*>(smem + L::u);        // [3][2][N*N] search directions
+  float* s_x = reinterpret_cast<float*>(smem + L::x);        // exchange slots / transform fields
+  double* s_st = reinterpret_cast<double*>(smem + L::u);     // [2][PN] FP64 column (refinement passes only)
+  int parity = 0;
+
+  double kv64[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) kv64[t] = a.kv64[t];
+  const double* KwF = a.KwF64;   // [8][NF], uniform
+  float mcI[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) mcI[t] = static_cast<float>(a.modes64[t]);
+
+  // ---- ownership: wave tiles of 2x2 node blocks ---------------------------
+  const bool own = tid < NB * NB;
+  const int I = own ? Tiles<NB>::I_of(tid) : 0;
+  const int J = own ? Tiles<NB>::J_of(tid) : 0;
+  const int i0 = 2 * I, j0 = 2 * J;
+  bool exists[4], dof[4];
+  int pidx[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = i0 + (k & 1), j = j0 + (k >> 1);
+    exists[k] = own;
+    dof[k] = own && (i | j) != 0;   // corner node 0 is pinned
+    pidx[k] = P::at(i, j);
+  }
+  const int base = P::at(i0 - 1, j0 - 1);
+  auto node_of = [&](int k) { return (j0 + (k >> 1)) * N + i0 + (k & 1); };
+  const int Il = (I + NB - 1) % NB, Jb = (J + NB - 1) % NB, Ir = (I + 1) % NB, Jt = (J + 1) % NB;
+  const int t_l = Tiles<NB>::bix(Il, J), t_b = Tiles<NB>::bix(I, Jb), t_d = Tiles<NB>::bix(Il, Jb);
+  const int b_own = Tiles<NB>::bix(I, J), b_r = Tiles<NB>::bix(Ir, J), b_t = Tiles<NB>::bix(I, Jt),
+            b_d = Tiles<NB>::bix(Ir, Jt);
+
+  // ---- element scales (mu of the phase), padded ---------------------------
+  const double* par = a.params + static_cast<size_t>(b) * 4;
+  const double mu0 = par[1], mu1 = par[3];
+  const uint8_t* ph = a.phase + a.phase_off[b];
+  double ssum = 0.0;
+  constexpr int PE = (NN + WG - 1) / WG;
+  uint8_t phv[PE];
+#pragma unroll
+  for (int q = 0; q < PE; ++q) {
+    const int e = tid + q * WG;
+    phv[q] = e < NN ? ph[e] : uint8_t(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PE; ++q) {
+    const int e = tid + q * WG;
+    if (e >= NN) continue;
+    const double s = phv[q] ? mu1 : mu0;
+    put_halo<N, N>(s_sc, e % N, e / N, s);
+    put_halo<N, N>(s_sc32, e % N, e / N, static_cast<float>(s));
+    ssum += s;
+  }
+  SpectralRegs<N, float> sreg;
+  spectral_setup<N, float>(sreg, a.fft_tab, s_x + L::xlen / 4, own, I, J);
+  {
+    double red[1] = {ssum};
+    wg_sum<1, NW, MR_NV>(red, s_red, parity);   // (its barrier also publishes the scales and tables)
+    ssum = uni(red[0]);
+  }
+  const double* eb = s_sc + base;
+  float esc[2][2];   // scales of the thread's four elements
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2) esc[c][a2] = s_sc32[base + (c + 1) * P::PW + a2 + 1];
+
+  const int64_t fo = a.foff[b];
+  constexpr int64_t flen = 2 * NN;
+  double* Xb = a.X + fo * (NF + 1);
+  const double V = a.volume;
+
+  // own nodes of a column in HBM (16-byte accesses: fields start at even offsets)
+  auto ld_own = [&](const double* src, double (&v)[4][2]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double2 t = make_double2(0.0, 0.0);
+      if (exists[k]) t = reinterpret_cast<const double2*>(src)[node_of(k)];
+      v[k][0] = t.x;
+      v[k][1] = t.y;
+    }
+  };
+  auto st_own = [&](double* dst, const double (&v)[4][2]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (exists[k]) reinterpret_cast<double2*>(dst)[node_of(k)] = make_double2(v[k][0], v[k][1]);
+  };
+  // cold start: the columns start from zero (and so does x_r, not solved here)
+  if (!(a.flags & RVE_WARM)) {
+    const double z0[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) st_own(Xb + c * flen, z0);
+  }
+  {
+    const double z0[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    st_own(Xb + NF * flen, z0);
+  }
+  bool xzero = !(a.flags & RVE_WARM);   // every column zero (no FP64 operator needed)
+
+  const float tinI = static_cast<float>(a.tol_in * a.tol_in);
+  const double tol2 = a.tol * a.tol;
+  int iters = 0, nmv64 = 0;
+  bool all_ok = true;
+  double worst = 0.0;
+  bool act[MR_C];   // columns that still need an inner solve (uniform)
+
+#pragma unroll 1
+  for (int sweep = 0;; ++sweep) {
+    // ---- FP64 residuals of the three columns, norms and energy products ----
+    // E[i][c] = b_i . x_c + x_i . r_c: the x . r term is a correction of
+    // relative size rve_tol, so it takes r in FP32 (the copy kept for the
+    // inner solve) in a second pass over the columns.
+    double red[MR_NV];
+#pragma unroll
+    for (int t = 0; t < MR_NV; ++t) red[t] = 0.0;
+    float rf[MR_C][4][2];   // r_c (FP32) for the inner solve
+#pragma unroll 1
+    for (int c = 0; c < MR_C; ++c) {
+      double y[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+      if (!xzero) {
+        double xc[4][2];
+        ld_own(Xb + c * flen, xc);
+        __syncthreads();   // earlier readers of the FP64 column (and of u) done
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          put_halo<N, N>(s_st, i0 + (k & 1), j0 + (k >> 1), xc[k][0]);
+          put_halo<N, N>(s_st + P::PN, i0 + (k & 1), j0 + (k >> 1), xc[k][1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mv_node64<N, N>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
+        ++nmv64;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int di = k & 1, dj = k >> 1;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          double r = 0.0;
+          if (dof[k]) {
+            const double bk = bF_entry<N, N>(eb, KwF, di, dj, d, c);
+            r = bk - y[k][d];
+            red[2 * c] += r * r;
+            red[2 * c + 1] += bk * bk;
+          }
+          rf[c][k][d] = static_cast<float>(r);
+        }
+      }
+    }
+    if (!xzero) {
+#pragma unroll 1
+      for (int c = 0; c < MR_C; ++c) {
+        double xc[4][2];
+        ld_own(Xb + c * flen, xc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (!dof[k]) continue;
+          const int di = k & 1, dj = k >> 1;
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int i = 0; i < MR_C; ++i) {
+              red[2 * MR_C + i * MR_C + c] += bF_entry<N, N>(eb, KwF, di, dj, d, i) * xc[k][d];
+              red[2 * MR_C + c * MR_C + i] += xc[k][d] * static_cast<double>(rf[i][k][d]);
+            }
+        }
+      }
+    }
+    wg_sum<MR_NV, NW, MR_NV>(red, s_red, parity);
+    bool any = false;
+    float rsc[MR_C];   // 1 / ||r_c|| (FP32) for the columns that go on
+    double rnrm[MR_C];
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) {
+      const double rel = red[2 * c + 1] > 0.0 ? sqrt(red[2 * c] / red[2 * c + 1]) : 0.0;
+      const bool accept = red[2 * c + 1] == 0.0 || red[2 * c] <= tol2 * red[2 * c + 1];
+      act[c] = !accept && sweep < a.max_ir;
+      if (!act[c]) {
+        worst = rel > worst ? rel : worst;
+        if (!accept) all_ok = false;
+      }
+      any = any || act[c];
+      rnrm[c] = uni(sqrt(red[2 * c]));
+      rsc[c] = red[2 * c] > 0.0 ? static_cast<float>(1.0 / rnrm[c]) : 0.0f;
+    }
+    if (!any) {   // every column accepted (or given up): energy-form condensation
+      if (tid == 0) {
+        double* Cb = a.Cbar + static_cast<size_t>(b) * NF * NF;
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+#pragma unroll
+          for (int j = 0; j < NF; ++j)
+            Cb[i * NF + j] = (ssum * a.KFF64[i * NF + j] - red[2 * MR_C + i * MR_C + j]) / V;
+#pragma unroll   // x_r = 0: Phat = Pbar
+        for (int i = 0; i < NF; ++i) a.Phat[static_cast<size_t>(b) * NF + i] = a.Pbar[static_cast<size_t>(b) * NF + i];
+      }
+      break;
+    }
+    // ---- inner PCG of the active columns on r_c / ||r_c|| (FP32) ----------
+    // Every column passes through the transform and the operator (a column
+    // that is not active carries zeros); only the updates are per column.
+    unsigned actm = 0;   // active columns (uniform bit mask)
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) actm |= act[c] ? (1u << c) : 0u;
+    actm = __builtin_amdgcn_readfirstlane(actm);
+    const unsigned solvem = actm;
+    float xi[MR_C][4][2], pv[MR_C][4][2], qv[MR_C][4][2];
+    float gam0[MR_C], gam_old[MR_C];
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) {
+      gam0[c] = 0.0f;
+      gam_old[c] = 1.0f;
+      const float sc = (actm >> c) & 1u ? rsc[c] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          rf[c][k][d] = dof[k] ? rf[c][k][d] * sc : 0.0f;
+          xi[c][k][d] = pv[c][k][d] = qv[c][k][d] = 0.0f;
+        }
+    }
+    __syncthreads();   // the FP64 column's readers done before u and the transforms overwrite it
+#pragma unroll 1
+    for (int it = 0;; ++it) {
+      spectral_precond_mc<N>(rf, s_x, s_u, sreg, own, I, J);
+      __syncthreads();   // u visible (and every read of the transform fields done)
+      float gpart[MR_C], fo[MR_C][2][2][2];
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) {
+        gpart[c] = 0.0f;
+        float o[2][4];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) ld4(s_u + c * ZS + d * NN + 4 * b_own, o[d]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) gpart[c] = fma(rf[c][k][d], o[d][k], gpart[c]);
+        mv_modes_post<N, N, WG, float>(s_u + c * ZS, esc, mcI, s_x + c * 12 * WG, b_own, b_r, b_t, b_d, tid, fo[c]);
+      }
+      const float* rb = wsum_post_mc<NW>(gpart, s_red, parity);
+      __syncthreads();   // exchange slots and the r.u wave totals visible
+      float gam[MR_C];
+      wsum_collect_mc<NW>(rb, gam);
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) gam[c] = uni(gam[c]);
+      unsigned m = actm;
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) {
+        if (it == 0) gam0[c] = gam[c];
+        if (it >= a.max_it || !(gam[c] > tinI * gam0[c]) || !(gam[c] > 0.0f)) m &= ~(1u << c);
+      }
+      actm = __builtin_amdgcn_readfirstlane(m);
+      if (actm == 0) break;
+      float qpart[MR_C];
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) {
+        float wv[4][2];
+        mv_modes_gather<WG, float>(s_x + c * 12 * WG, fo[c], t_l, t_b, t_d, wv);
+        const float beta = (it == 0 || !((actm >> c) & 1u)) ? 0.0f : gam[c] / gam_old[c];
+        float uo[2][4];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) ld4(s_u + c * ZS + d * NN + 4 * b_own, uo[d]);
+        qpart[c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            pv[c][k][d] = fma_keep(pv[c][k][d], beta, uo[d][k]);
+            qv[c][k][d] = fma_keep(qv[c][k][d], beta, wv[k][d]);
+            qpart[c] = fma(pv[c][k][d], qv[c][k][d], qpart[c]);
+          }
+      }
+      const float* qb = wsum_post_mc<NW>(qpart, s_red, parity);
+      __syncthreads();
+      float pq[MR_C];
+      wsum_collect_mc<NW>(qb, pq);
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) pq[c] = uni(pq[c]);
+      m = actm;
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c)
+        if (!(pq[c] > 0.0f)) m &= ~(1u << c);   // exact solution or loss of definiteness
+      actm = __builtin_amdgcn_readfirstlane(m);
+#pragma unroll
+      for (int c = 0; c < MR_C; ++c) {
+        const bool on = (actm >> c) & 1u;
+        const float alpha = on ? gam[c] / pq[c] : 0.0f;
+        iters += on ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            xi[c][k][d] = fma(alpha, pv[c][k][d], xi[c][k][d]);
+            // (the pinned node's entry stays zero: it must not reach the transform)
+            rf[c][k][d] = (on && dof[k]) ? fma(-alpha, qv[c][k][d], rf[c][k][d]) : 0.0f;
+          }
+        if (on) gam_old[c] = gam[c];
+      }
+    }
+    // ---- x_c += ||r_c|| x_inner (FP64, own nodes in HBM) -------------------
+#pragma unroll
+    for (int c = 0; c < MR_C; ++c) {
+      if (!((solvem >> c) & 1u)) continue;   // accepted (or given up): unchanged
+      double v[4][2];
+      ld_own(Xb + c * flen, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) v[k][d] += rnrm[c] * static_cast<double>(xi[c][k][d]);
+      st_own(Xb + c * flen, v);
+    }
+    xzero = false;
+  }
+  if (tid == 0) {
+    a.relres[b] = worst;
+    a.iters[b] = static_cast<double>(iters);
+    a.mv64[b] = static_cast<double>(nmv64);
+    if (!all_ok) atomicAdd(a.fail_count, 1);
+  }
+}
+
+
 // Host: the spectral table of one class (mu = 1, lambda = rho, square
 // elements; the element size cancels in 2D).  The Q4 element stiffness by
 // 2x2 Gauss quadrature, its periodic symbol S(k) = sum_ab K_e[a][b]
@@ -1436,10 +1538,22 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
   constexpr int WG = wg_for(N1, N2);
   constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), FFT);
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
-  // the spectral preconditioner's complex field [N*N][2] aliases the exchange slots [3][WG][4]
-  static_assert(!FFT || 2 * N1 * N2 <= 12 * WG, "exchange slots too small for the spectral field");
   static_assert(!FFT || N1 != 48 || WG == 576, "the 48-element transform assumes one block per lane");
   auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT>;
+  if (lds > 64 * 1024)
+    FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(n_launch), dim3(WG), lds, s, a);
+  FE2_HIP_CHECK(hipGetLastError());
+  return FE2_OK;
+}
+
+template <int N>
+static int launch_mr(const Lin2DArgs& a, int n_launch, hipStream_t s) {
+  constexpr int WG = (N / 2) * (N / 2);
+  constexpr size_t lds = MrLds<N, WG>::total;
+  static_assert(lds <= 80 * 1024, "two work-groups per CU");
+  auto kern = &k_lin2d_mr<N, WG>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -1451,6 +1565,12 @@ static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 template <int N1, int N2>
 static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
+  if constexpr (N1 == N2 && (N1 == 16 || N1 == 32)) {
+    // the three columns of X_F in one loop (FP32 inner precision, spectral)
+    if ((a.flags & RVE_FFT) && (a.flags & RVE_MC) && precision != FE2_PREC_FP64 && nrhs == NF &&
+        !(a.flags & (RVE_RONLY | RVE_ASSEMBLE)) && a.fft_tab)
+      return launch_mr<N1>(a, n_launch, s);
+  }
   if constexpr (lin2d_spectral_size(N1, N2)) {
     if (a.flags & RVE_FFT) {
       if (!a.fft_tab || !a.fft_tab64) return set_error("spectral preconditioner table missing"), FE2_EINVAL;

@@ -146,6 +146,41 @@ def test_rows_a2_to_a6_at_nonzero_state(fe2, name, kw, prec):
     h.close()
 
 
+@pytest.mark.parametrize("name,kw", [("cfg2", dict(macro=(2, 1), rve=32)),
+                                     ("cfg3", dict(macro=(3, 3), resolutions=(16, 32, 48)))])
+@pytest.mark.parametrize("solver", ["fft", "fft_mc"])
+def test_reference_state_solve_one_and_three_columns(fe2, name, kw, solver):
+    """A Newton step from the reference state (r_b = 0: the n_F columns of
+    X_F only, x_r = 0) with the FP32 spectral solve, the columns one after
+    another ("fft") or together in one PCG loop ("fft_mc", 16 x 16 and
+    32 x 32 RVEs; the 48 x 48 class of the uneven batch falls back to one
+    column at a time): every column against the oracle's direct solution,
+    Cbar at 1e-10 and Phat = Pbar."""
+    p = small_problem(name, **kw)
+    h = fe2.fe2_setup(p, precision="fp32_ir", solver=solver, rve_tol=1e-13)
+    st, norms = fe2.fe2_newton_step(h, 1.0)
+    assert st == fe2.FE2_OK
+    nF = fe2.fe2_query(h, fe2.FE2_Q_NF)
+    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
+    off = fe2.fe2_query(h, fe2.FE2_Q_FIELD_OFFSETS)
+    sol = get(fe2, h, fe2.FE2_D_SOLUTION, flen * (nF + 1))
+    Cb = get(fe2, h, fe2.FE2_D_CBAR, p.n_rve * nF * nF).reshape(p.n_rve, nF, nF)
+    Ph = get(fe2, h, fe2.FE2_D_PHAT, p.n_rve * nF).reshape(p.n_rve, nF)
+    pbar = get(fe2, h, fe2.FE2_D_PBAR, p.n_rve * nF).reshape(p.n_rve, nF)
+    for b in range(p.n_rve):
+        c = R.homogenize_rve(p, b, np.zeros(nF))
+        s = c.system
+        fl = off[b + 1] - off[b]
+        assert rel(Cb[b], c.C) < 1e-10, (b, Cb[b], c.C)
+        assert np.array_equal(Ph[b], pbar[b])
+        Xb = sol[off[b] * (nF + 1):off[b + 1] * (nF + 1)].reshape(nF + 1, fl)
+        kap = kappa(s.K_ww)
+        for j in range(nF):
+            check_solution(s.K_ww, s.K_wF[:, j], Xb[j][s.free], c.X_F[:, j], 1e-13, kap)
+        assert np.abs(Xb[nF]).max() == 0.0   # x_r not solved
+    h.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
 def test_rows_a7_to_a10_one_newton_step(fe2, prec):
     """One generalized Newton iteration from a nonzero state with a pending
@@ -211,12 +246,12 @@ def test_cfg1_end_to_end_closed_form(fe2, prec):
     h.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
-def test_cfg2_reduced_end_to_end(fe2, prec):
+@pytest.mark.parametrize("prec,solver", [("fp64", "auto"), ("fp32_ir", "auto"), ("fp32_ir", "fft_mc")])
+def test_cfg2_reduced_end_to_end(fe2, prec, solver):
     """Configuration 2 recipe on a 4x4 macro mesh (64 RVEs of 32x32): the
     converged macro displacement and fluctuations match the oracle."""
     p = W.config("cfg2", macro=(4, 4))
-    h = fe2.fe2_setup(p, precision=prec, rve_tol=1e-11)
+    h = fe2.fe2_setup(p, precision=prec, solver=solver, rve_tol=1e-11)
     fe2.solve(h, p.load_factors)
     u, w = dz(p.n_dofs), dz(fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN))
     fe2.fe2_get_state(h, u, w)

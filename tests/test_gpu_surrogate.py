@@ -9,7 +9,9 @@
 * Trained on GPU-generated RVE solves, the network drives the Neo-Hookean
   configuration's load stepping with the RVE solve as fallback and judge:
   same macro displacement as the full monolithic solve within the judge's
-  tolerance, at a fraction of the time (the gain the network brings).
+  tolerance, both converged to the same macro tolerance, in less time (the
+  gain the network brings, reported with the data and training cost it has
+  to recover).
 """
 import time
 
@@ -77,15 +79,24 @@ def test_surrogate_training_and_gain_over_the_full_solve(libs):
     # held-out set
     pv = W.cfg5_material_points(512, rve=32, seed=W.generators.SEED_BASE + 51)
     _, Uv = W.surrogate_samples(512, seed=202)
+    t0 = time.perf_counter()
     Xv, Tv, okv, _, _ = S.rve_responses(pv, Uv)
+    t_data_v = time.perf_counter() - t0
     rms = sur.validation_rms(Xv, Tv, okv)
     print(f"data {t_data:.2f}s, training {sur.train_log['seconds']:.2f}s "
           f"loss {sur.train_log['final_loss']:.2e}, held-out rms {rms:.2e}")
     assert rms < 2e-2
 
-    # the Neo-Hookean configuration on an 8x8 macro mesh (256 RVEs of 32x32)
+    # the Neo-Hookean configuration on an 8x8 macro mesh (256 RVEs of 32x32),
+    # both runs converged to the same macro tolerance, 1e-6: the FP32
+    # network's stresses carry about 1e-7 relative noise, and the summed
+    # macro residual's noise floor grows with the mesh (about 4e-5 relative
+    # on 16x16), so 1e-6 is what the surrogate path meets here
     p = W.config("cfg5", macro=(8, 8))
-    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-10)
+    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6)
+    fe2.solve(hf, p.load_factors[:1])   # warm-up: kernels loaded, workspaces touched
+    hf.close()
+    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fe2.solve(hf, p.load_factors)
@@ -95,8 +106,6 @@ def test_surrogate_training_and_gain_over_the_full_solve(libs):
     fe2.fe2_get_state(hf, u=uf)
     hf.close()
 
-    # an FP32 network resolves the stress to about 1e-7 relative: the
-    # surrogate path converges the macro residual to 1e-6
     hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6, scheme="classical")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -107,9 +116,14 @@ def test_surrogate_training_and_gain_over_the_full_solve(libs):
     fe2.fe2_get_state(hs, u=us)
     hs.close()
     err_u = rel(us.cpu().numpy(), uf.cpu().numpy())
-    print(f"full {t_full:.3f}s, surrogate {t_sur:.3f}s (x{t_full / t_sur:.1f}), |du|/|u| {err_u:.2e}, "
-          f"judge max err {stats['max_err']}, rejected {stats['rejected']}, newton {stats['newton']}")
+    # what the network costs before it pays: data (training + held-out
+    # responses) and training, against the time it saves per solve
+    t_setup = t_data + t_data_v + sur.train_log["seconds"]
+    gain = t_full - t_sur
+    print(f"full {t_full:.3f}s, surrogate {t_sur:.3f}s (x{t_full / t_sur:.2f}), |du|/|u| {err_u:.2e}, "
+          f"judge max err {stats['max_err']}, rejected {stats['rejected']}, newton {stats['newton']}; "
+          f"data + training {t_setup:.2f}s, break-even after {t_setup / gain if gain > 0 else float('inf'):.0f} solves")
     assert stats["judge_calls"] >= 1
     assert err_u < 1e-2
-    assert t_sur < 0.5 * t_full
+    assert t_sur < t_full
     sur.close()
