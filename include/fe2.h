@@ -62,8 +62,14 @@ typedef enum fe2_status {
 
 enum { FE2_SMALL_STRAIN = 0, FE2_FINITE_STRAIN = 1 };
 enum { FE2_LINEAR_ISO = 0, FE2_NEO_HOOKE = 1, FE2_MOONEY_RIVLIN = 2 };
-enum { FE2_PREC_FP64 = 0, FE2_PREC_FP32_IR = 1 };
-enum { FE2_SOLVER_AUTO = 0, FE2_SOLVER_PCG_JACOBI = 1, FE2_SOLVER_PCG_FFT = 2, FE2_SOLVER_PCG_FFT_MC = 4 };
+enum { FE2_PREC_FP64 = 0, FE2_PREC_FP32_IR = 1, FE2_PREC_BF16_IR = 2 };
+enum {
+  FE2_SOLVER_AUTO = 0,
+  FE2_SOLVER_PCG_JACOBI = 1,
+  FE2_SOLVER_PCG_FFT = 2,
+  FE2_SOLVER_DENSE = 3,
+  FE2_SOLVER_PCG_FFT_MC = 4
+};
 enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
 /* Macro basis of the fluctuation: FE2_BASIS_DIRAC puts one RVE at every macro
  * Gauss point (Dirac approach, Eqs. (31)-(35)); FE2_BASIS_ELEMENT gives every
@@ -103,7 +109,12 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *  phase_params     [n_rve][2][n_phase_params]
  *  rve_size         side length of the cubic RVE cell (|Omega| = rve_size^dim)
  *  precision        FE2_PREC_FP64 (plain FP64 RVE solves) or FE2_PREC_FP32_IR
- *                   (FP32 PCG with FP64 residual refinement)
+ *                   (FP32 PCG with FP64 residual refinement).
+ *                   FE2_PREC_BF16_IR is declared and refused (FE2_ENOTSUP):
+ *                   refinement around a solve with unit roundoff u contracts
+ *                   only while cond(K_ww) * u < 1, and the RVE stiffnesses of
+ *                   the paper's configurations have cond(K_ww) far above
+ *                   1/u = 256 of bfloat16
  *  solver           preconditioner of the RVE PCG (2D small strain):
  *                   FE2_SOLVER_PCG_JACOBI (diagonal), FE2_SOLVER_PCG_FFT
  *                   (inverse of the periodic operator of a homogeneous
@@ -115,8 +126,16 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *                   another; FE2_SOLVER_PCG_FFT_MC is the same preconditioner
  *                   with the three columns of X_F in one PCG loop (FP32_IR,
  *                   16 x 16 and 32 x 32 RVEs, three right-hand sides; other
- *                   cases fall back to one column at a time).  3D and finite
- *                   strain use Jacobi; FFT there gives FE2_ENOTSUP
+ *                   cases fall back to one column at a time).  Finite
+ *                   strain (2D) takes FFT on square RVEs of 8, 16 or 32
+ *                   elements (reference medium: the small-strain limit of
+ *                   the stiffer phase); 3D uses Jacobi, FFT there gives
+ *                   FE2_ENOTSUP.  FE2_SOLVER_DENSE replaces the PCG by a
+ *                   direct solve: K_ww assembled densely in LDS, factored
+ *                   once per RVE by an FP32 Cholesky on the matrix cores and
+ *                   applied inside the FP64 refinement (2D small strain,
+ *                   FE2_PREC_FP32_IR, RVEs with 2 n1 n2 - 2 <= 128 unknowns
+ *                   and n1, n2 >= 3; else FE2_ENOTSUP)
  *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach
@@ -244,6 +263,7 @@ int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev,
  *   FE2_D_SOLUTION    [FIELD_LEN*(nF+1)] per RVE nF+1 consecutive fields:
  *                                        X_F columns then x_r (a5)
  *   FE2_D_RVE_ITERS   [n_rve] (as double) PCG iterations of the last solve
+ *                                        (FE2_SOLVER_DENSE: refinement sweeps)
  *   FE2_D_RVE_RELRES  [n_rve]            final relative FP64 residual
  *   FE2_D_MACRO_RHS   [n_nodes*dim]      condensed right-hand side
  *                                        sum G^T Phat - lambda f_ext (a7)

@@ -230,7 +230,8 @@ struct fe2_ctx {
     a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
-    a.flags = flags | (c.spectral ? RVE_FFT : 0) | (c.spectral && solver == FE2_SOLVER_PCG_FFT_MC ? RVE_MC : 0);
+    a.flags = flags | (c.spectral ? RVE_FFT : 0) | (c.spectral && solver == FE2_SOLVER_PCG_FFT_MC ? RVE_MC : 0) |
+              (solver == FE2_SOLVER_DENSE ? RVE_DENSE : 0);
     return a;
   }
 };
@@ -291,6 +292,8 @@ int validate(const fe2_problem_desc* d) {
   if (d->n_dir < 0 || (d->n_dir > 0 && (!d->dir_dofs || !d->dir_vals)))
     return set_error("bad Dirichlet arrays"), FE2_EINVAL;
   if (!(d->rve_size > 0.0)) return set_error("rve_size must be positive"), FE2_EINVAL;
+  if (d->precision == FE2_PREC_BF16_IR)   // cond(K_ww) * 2^-8 > 1: the refinement would not contract
+    return set_error("BF16 refinement cannot converge: cond(K_ww) of these RVEs exceeds 1/u = 256"), FE2_ENOTSUP;
   if (d->precision != FE2_PREC_FP64 && d->precision != FE2_PREC_FP32_IR)
     return set_error("unknown precision"), FE2_EINVAL;
   if (!(d->rve_tol > 0.0) || !(d->newton_tol >= 0.0)) return set_error("tolerances must be positive"), FE2_EINVAL;
@@ -405,8 +408,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
            FE2_EINVAL;
   if (h->kin != FE2_SMALL_STRAIN && !finite) return set_error("unknown kinematics"), FE2_EINVAL;
   if (h->solver != FE2_SOLVER_AUTO && h->solver != FE2_SOLVER_PCG_JACOBI && h->solver != FE2_SOLVER_PCG_FFT &&
-      h->solver != FE2_SOLVER_PCG_FFT_MC)
+      h->solver != FE2_SOLVER_PCG_FFT_MC && h->solver != FE2_SOLVER_DENSE)
     return set_error("unknown solver"), FE2_EINVAL;
+  if (h->solver == FE2_SOLVER_DENSE && (h->dim != 2 || finite || h->precision != FE2_PREC_FP32_IR))
+    return set_error("the dense RVE solve is implemented for 2D small strain in FE2_PREC_FP32_IR"), FE2_ENOTSUP;
   if ((h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC) && h->dim != 2)
     return set_error("the spectral preconditioner is implemented for 2D RVEs"), FE2_ENOTSUP;
   if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL)
@@ -462,6 +467,8 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
       return set_error("no compiled kernel for RVE resolution " + std::to_string(n1) + "x" + std::to_string(n2) +
                        (h->dim == 3 ? "x" + std::to_string(n3) : std::string())),
              FE2_ENOTSUP;
+    if (h->solver == FE2_SOLVER_DENSE && !lin2d_dense_size(n1, n2))
+      return set_error("the dense RVE solve needs n1, n2 >= 3 and 2 n1 n2 - 2 <= 128 unknowns"), FE2_ENOTSUP;
     if ((h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC) &&
         !(finite ? fin2d_spectral_size(n1, n2) : lin2d_spectral_size(n1, n2)))
       return set_error(finite ? "the finite-strain spectral preconditioner needs square RVEs of 8, 16 or 32 elements"

@@ -73,8 +73,9 @@ enum RveFlags : int {
   RVE_FFT = 16,       // homogeneous-reference (FFT) preconditioner
   RVE_RONLY = 32,     // solve the residual column only (x_r), no condensation;
                       // RVEs with rnorm2 <= thr2 are skipped (x_r = 0)
-  RVE_MC = 64         // spectral: the columns of X_F in one PCG loop where a
+  RVE_MC = 64,        // spectral: the columns of X_F in one PCG loop where a
                       // kernel for the size exists (else one after another)
+  RVE_DENSE = 128     // dense FP32 Cholesky on the matrix cores + FP64 refinement
 };
 
 // One launch handles the RVEs of one resolution class (same n1 x n2 and same
@@ -162,6 +163,9 @@ constexpr bool lin2d_spectral_size(int n1, int n2) {
 constexpr int lin2d_spectral_twiddles(int n) { return n == 48 ? 32 : n / 2; }
 void lin2d_spectral_table(int n, double rho, double* out);
 constexpr bool fin2d_spectral_size(int n1, int n2) { return n1 == n2 && (n1 == 8 || n1 == 16 || n1 == 32); }
+// Dense direct RVE solve (2D small strain): RVEs whose reduced stiffness
+// (2 n1 n2 - 2 unknowns, rounded up to 16) fits an LDS-resident FP32 factor
+constexpr bool lin2d_dense_size(int n1, int n2) { return n1 >= 3 && n2 >= 3 && 2 * n1 * n2 - 2 <= 128; }
 int launch_lin2d(const Lin2DArgs& a, int n_launch, int precision, int nrhs,
                  hipStream_t s);
 bool lin2d_supported(int n1, int n2);

@@ -6,6 +6,14 @@
 #include "fe2_internal.hpp"
 
 namespace fe2 {
+
+// LDS writes of this wave visible to its other lanes (no work-group barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 namespace rve2d {
 
 // Element q (0..3) around an owned node (di, dj): position of the element's

@@ -38,6 +38,7 @@
 
 #include "rve2d_common.hpp"
 #include "spectral2d.hpp"
+#include "dense2d.hpp"
 
 namespace fe2 {
 
@@ -345,9 +346,12 @@ __host__ __device__ constexpr size_t lin2d_xch_bytes(int n1, int n2, int wg, int
   return ((n1 | n2) & 1) == 0 && nrhs > 0 ? lin2d_xch_len(n1, n2, wg, spectral) * ti_bytes : 0;
 }
 __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, int nrhs, int ti_bytes,
-                                                       bool spectral = false) {
-  return lin2d_xch_offset(n1, n2, wg, nrhs) + lin2d_xch_bytes(n1, n2, wg, nrhs, ti_bytes, spectral) +
-         (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes + n1 + 2 : 0);   // twiddles, partner map
+                                                       bool spectral = false, bool dense = false) {
+  // the dense form takes the place of the exchange slots (its inner solve
+  // does not run the element-wise operator): factor, vector, scratch, flag
+  return dense ? lin2d_xch_offset(n1, n2, wg, nrhs) + 4 * dense2d::dense_floats(dense2d::dense_md(n1, n2)) + 16
+               : lin2d_xch_offset(n1, n2, wg, nrhs) + lin2d_xch_bytes(n1, n2, wg, nrhs, ti_bytes, spectral) +
+                     (spectral ? 2 * static_cast<size_t>(lin2d_spectral_twiddles(n1)) * ti_bytes + n1 + 2 : 0);   // twiddles, partner map
 }
 
 // The spectral FP32 form is held to three work-groups of 256 lanes per CU
@@ -355,7 +359,7 @@ __host__ __device__ constexpr size_t lin2d_lds_bytes_t(int n1, int n2, int wg, i
 template <typename TI, bool FFT, int WG>
 constexpr int kLin2dMinBlocks = (sizeof(TI) == 4 && FFT && WG == 256) ? 3 : (FFT && WG == 256) ? 2 : 1;
 
-template <typename TI, int NRHS, int N1, int N2, int WG, bool FFT>
+template <typename TI, int NRHS, int N1, int N2, int WG, bool FFT, bool DENSE = false>
 __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(const Lin2DArgs a) {
   using P = Pad<N1, N2>;
   constexpr int NW = WG / 64;
@@ -376,6 +380,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   TI* s_x = reinterpret_cast<TI*>(smem + lin2d_xch_offset(N1, N2, WG, NRHS));   // [3][WG][4] (even sizes)
   constexpr bool EVEN = ((N1 | N2) & 1) == 0;
   static_assert(!FFT || (EVEN && N1 == N2), "spectral preconditioner needs square power-of-two RVEs");
+  static_assert(!DENSE || (!FFT && sizeof(TI) == 4 && WG == 256), "dense solve: FP32 factor, 256 lanes");
   const TI* ftab = nullptr;
   if constexpr (FFT) {
     if constexpr (sizeof(TI) == 4) ftab = reinterpret_cast<const TI*>(a.fft_tab);
@@ -590,6 +595,25 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   if constexpr (FFT)
     spectral_setup<N1, TI>(sreg, ftab, s_x + lin2d_xch_bytes(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), true) / sizeof(TI),
                            own, I, J);
+  // dense form: K_ww assembled and factored once per RVE (FP32, matrix cores)
+  constexpr int MD = DENSE ? dense2d::dense_md(N1, N2) : 16;
+  float* dA = reinterpret_cast<float*>(smem + lin2d_xch_offset(N1, N2, WG, NRHS));
+  float* dv = dA + static_cast<size_t>(MD) * dense2d::dense_pitch(MD);
+  float* dscr = dv + MD;
+  int* dflag = reinterpret_cast<int*>(dscr + 256);
+  if constexpr (DENSE) {
+    dense2d::dense_assemble<N1, N2>(dA, s_sc, kv64);
+    if (!dense2d::dense_potrf<MD>(dA, dflag)) {   // K_ww not positive definite in FP32
+      if (tid == 0) {
+        atomicAdd(a.fail_count, 1);
+        a.relres[b] = __builtin_inf();
+        a.iters[b] = 0.0;
+        a.mv64[b] = 0.0;
+      }
+      return;
+    }
+    for (int t = tid; t < MD; t += WG) dv[t] = 0.0f;   // padding unknowns stay zero
+  }
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -669,8 +693,26 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       // its residual entry (which is left to drift) never enters r.u or w.u;
       // nodes of a block beyond the grid (odd sizes) get w = 0.  Convergence
       // is measured in the M^-1 norm, r.u <= tol_in^2 (r.u)_0.
+      TI xi[4][2];
+      if constexpr (DENSE) {
+        // the direct solve with the FP32 factor: r into the unknown vector,
+        // forward and backward substitution, the correction back
+        __syncthreads();   // the previous solve's readers of the vector are done
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            if (dof[k]) dv[dense2d::dof_of(node_of(k), d)] = ri[k][d];
+        __syncthreads();
+        dense2d::dense_solve<MD>(dA, dv, dscr);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 2; ++d) xi[k][d] = dof[k] ? dv[dense2d::dof_of(node_of(k), d)] : TI(0);
+        ++iters;
+      } else {
       __syncthreads();   // staging reads finished before s_p is written
-      TI xi[4][2], uv[4][2], pv[4][2], sv[4][2];
+      TI uv[4][2], pv[4][2], sv[4][2];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -831,6 +873,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
         den_old = den;
       }
       }
+      }   // (inner solve)
       // x64 += x_inner (FP64 accumulation in the output column)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -1533,13 +1576,13 @@ static constexpr int wg_for(int n1, int n2) {
   return 64 * ((((n1 + 1) / 2) * ((n2 + 1) / 2) + 63) / 64);
 }
 
-template <typename TI, int NRHS, int N1, int N2, bool FFT = false>
+template <typename TI, int NRHS, int N1, int N2, bool FFT = false, bool DENSE = false>
 static int launch_t(const Lin2DArgs& a, int n_launch, hipStream_t s) {
-  constexpr int WG = wg_for(N1, N2);
-  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), FFT);
+  constexpr int WG = DENSE ? 256 : wg_for(N1, N2);
+  constexpr size_t lds = lin2d_lds_bytes_t(N1, N2, WG, NRHS, static_cast<int>(sizeof(TI)), FFT, DENSE);
   static_assert(lds <= 160 * 1024, "RVE too large for the LDS-resident solver");
   static_assert(!FFT || N1 != 48 || WG == 576, "the 48-element transform assumes one block per lane");
-  auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT>;
+  auto kern = &k_lin2d<TI, NRHS, N1, N2, WG, FFT, DENSE>;
   if (lds > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -1565,6 +1608,15 @@ static int launch_mr(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 template <int N1, int N2>
 static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
+  if constexpr (lin2d_dense_size(N1, N2)) {
+    if (a.flags & RVE_DENSE) {
+      if (precision != FE2_PREC_FP32_IR) return set_error("the dense solve factors in FP32"), FE2_ENOTSUP;
+      return nrhs == NF ? launch_t<float, NF, N1, N2, false, true>(a, n_launch, s)
+                        : launch_t<float, NF + 1, N1, N2, false, true>(a, n_launch, s);
+    }
+  } else {
+    if (a.flags & RVE_DENSE) return set_error("no dense solve for this RVE size"), FE2_ENOTSUP;
+  }
   if constexpr (N1 == N2 && (N1 == 16 || N1 == 32)) {
     // the three columns of X_F in one loop (FP32 inner precision, spectral)
     if ((a.flags & RVE_FFT) && (a.flags & RVE_MC) && precision != FE2_PREC_FP64 && nrhs == NF &&

@@ -137,12 +137,6 @@ struct Tiles {
   static __device__ __forceinline__ int J_of(int t) { return ((t / (TW * TW)) / NT) * TW + (t % (TW * TW)) / TW; }
 };
 
-// LDS writes of this wave visible to its other lanes (no work-group barrier)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Work-group sum of per-lane partials split around a barrier that the
 // caller places (so that it can share it): wsum_post writes the wave totals

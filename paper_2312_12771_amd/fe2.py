@@ -28,8 +28,8 @@ FE2_OK, FE2_CONVERGED = 0, 1
 FE2_EINVAL, FE2_ENOMEM, FE2_EHIP, FE2_ENOCONV, FE2_ESTATE, FE2_ENOTSUP = -1, -2, -3, -4, -5, -6
 FE2_SMALL_STRAIN, FE2_FINITE_STRAIN = 0, 1
 FE2_LINEAR_ISO, FE2_NEO_HOOKE, FE2_MOONEY_RIVLIN = 0, 1, 2
-FE2_PREC_FP64, FE2_PREC_FP32_IR = 0, 1
-FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT, FE2_SOLVER_PCG_FFT_MC = 0, 1, 2, 4
+FE2_PREC_FP64, FE2_PREC_FP32_IR, FE2_PREC_BF16_IR = 0, 1, 2
+FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT, FE2_SOLVER_DENSE, FE2_SOLVER_PCG_FFT_MC = 0, 1, 2, 3, 4
 FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
 FE2_BASIS_DIRAC, FE2_BASIS_ELEMENT = 0, 1
 (FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
@@ -42,7 +42,7 @@ FE2_BASIS_DIRAC, FE2_BASIS_ELEMENT = 0, 1
 _KIN = {"small": FE2_SMALL_STRAIN, "finite": FE2_FINITE_STRAIN}
 _MAT = {"linear": FE2_LINEAR_ISO, "neohooke": FE2_NEO_HOOKE,
         "mooney_rivlin": FE2_MOONEY_RIVLIN}
-_PREC = {"fp64": FE2_PREC_FP64, "fp32_ir": FE2_PREC_FP32_IR}
+_PREC = {"fp64": FE2_PREC_FP64, "fp32_ir": FE2_PREC_FP32_IR, "bf16_ir": FE2_PREC_BF16_IR}
 
 
 class fe2_problem_desc(C.Structure):
@@ -232,7 +232,7 @@ def make_desc(problem, precision: str = "fp64", solver: str = "auto",
     d.rve_size = float(problem.rve_size)
     d.precision = _PREC[precision]
     d.solver = {"auto": FE2_SOLVER_AUTO, "jacobi": FE2_SOLVER_PCG_JACOBI,
-                "fft": FE2_SOLVER_PCG_FFT, "fft_mc": FE2_SOLVER_PCG_FFT_MC}[solver]
+                "fft": FE2_SOLVER_PCG_FFT, "fft_mc": FE2_SOLVER_PCG_FFT_MC, "dense": FE2_SOLVER_DENSE}[solver]
     d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL}[scheme]
     d.rve_tol, d.inner_tol, d.newton_tol, d.micro_tol = rve_tol, inner_tol, newton_tol, micro_tol
     d.max_pcg_it, d.max_ir, d.max_micro_it = max_pcg_it, max_ir, max_micro_it
