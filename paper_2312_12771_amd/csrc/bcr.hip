@@ -46,6 +46,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane-uniform read of lane src's value (two v_readlane) and a per-lane read
+// of lane src's value (two ds_bpermute) for FP64 data.
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), src);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double lane_take(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u >> 32));
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 // -- extraction of the blocks from lower band storage ------------------------
 __global__ void k_bcr_extract(const double* __restrict__ band, int n, int bw, int bs, int nb,
                               double* __restrict__ D, double* __restrict__ C) {
@@ -91,7 +106,7 @@ __global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __re
 // memory.  Wave 0 factors the diagonal tile and inverts it (lane r holds row
 // r; wave-synchronous exchange through LDS); all threads form the panel below
 // with the inverse and apply the trailing update in 4x4 register tiles.
-constexpr int PO_WG = 256;
+constexpr int PO_WG = 1024;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct GlobalTiles {
@@ -114,67 +129,63 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
 
 // Returns false when a pivot is not positive (info set, every thread returns).
 template <class M>
-__device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0, double* s_panel, double* s_ex,
-                           double* s_inv, double* s_rd, int* s_fail, int* __restrict__ info) {
+__device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0, double* s_panel, double* s_inv,
+                           int* s_fail, int* __restrict__ info) {
   const int tid = threadIdx.x;
   const int ld = A.ld;
   for (int p = 0; p < nt; ++p) {
     if (tid < 64) {
-      const int r = tid;
+      // The diagonal tile in the registers of one wave: lane l holds column
+      // s = l % 16, rows 4 g .. 4 g + 3 (g = l / 16), read from the lower
+      // triangle (the upper entries mirrored).  Right-looking Cholesky fused
+      // with the forward substitution L X = I that gives invL_pp: step c
+      // takes the pivot, the scaled column c (entries moved between lanes by
+      // ds_bpermute), the rank-one update of the trailing entries and the
+      // elimination of row c in X.
+      const int ln = tid, s = ln & 15, g = ln >> 4;
       double* Tpp = A.tile(p, p);
-      double a[BT];
+      double t4[4], x4[4];
 #pragma unroll
-      for (int c = 0; c < BT; ++c) a[c] = (r < BT && c <= r) ? Tpp[c * ld + r] : 0.0;
-      // Entries above the diagonal (c > r) are updated too and never read:
-      // one FMA per entry and step, no per-lane selects.
+      for (int t = 0; t < 4; ++t) {
+        const int r = 4 * g + t;
+        t4[t] = r >= s ? Tpp[s * ld + r] : Tpp[r * ld + s];
+        x4[t] = (r == s) ? 1.0 : 0.0;
+      }
       bool bad = false;
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
-        if (r < BT) s_ex[r] = a[c];
-        wave_sync();
-        const double d = s_ex[c];
-        double col[BT];
-#pragma unroll
-        for (int cc = c + 1; cc < BT; ++cc) col[cc] = s_ex[cc];
-        wave_sync();
-        if (!(d > 0.0)) {   // uniform: every lane read the same pivot
+        const int gc = c >> 2, tc = c & 3;
+        double piv = lane_read(t4[tc], c + 16 * gc);
+        if (!(piv > 0.0) && !bad) {   // uniform: every lane read the same pivot
           bad = true;
-          if (r == 0) {
+          if (ln == 0) {
             *s_fail = 1;
             atomicCAS(info, 0, col0 + p * BT + c + 1);
           }
-          break;
         }
-        const double inv_sd = rsqrt(d);
-        if (r == c) s_rd[c] = inv_sd;
-        const double t = a[c] * (inv_sd * inv_sd);   // A_rc / d
+        if (bad) piv = 1.0;   // the rest of the tile runs on (fully unrolled loop) and is discarded
+        const double rd = rsqrt(piv), sd = piv * rd;
+        // A[c][s] (= A[s][c]) from lane (s, c / 4); A[r][c] of own rows from lane (c, g)
+        const double lsc = lane_take(t4[tc], s + 16 * gc) * rd;
+        const double xc = lane_take(x4[tc], s + 16 * gc) * rd;
+        double lrc[4];
 #pragma unroll
-        for (int cc = c + 1; cc < BT; ++cc) a[cc] = fma(-t, col[cc], a[cc]);
-        a[c] = (r == c) ? d * inv_sd : a[c] * inv_sd;
+        for (int t = 0; t < 4; ++t) lrc[t] = lane_take(t4[t], c + 16 * g) * rd;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int r = 4 * g + t;
+          if (r > c && s > c) t4[t] = fma(-lrc[t], lsc, t4[t]);
+          if (r > c) x4[t] = fma(-lrc[t], xc, x4[t]);
+          if (s == c) t4[t] = (r == c) ? sd : (r > c ? lrc[t] : t4[t]);   // column c of L
+          if (r == c) x4[t] = xc;
+        }
       }
       if (!bad) {
-        if (r < BT) {
 #pragma unroll
-          for (int c = 0; c < BT; ++c) {
-            if (c <= r) Tpp[c * ld + r] = a[c];
-            s_ex[r * (BT + 1) + c] = (c <= r) ? a[c] : 0.0;
-          }
-        }
-        wave_sync();
-        // lane r < 16 solves L x = e_r (column r of the inverse), column by
-        // column so that the updates of one step are independent
-        if (r < BT) {
-          double x[BT];
-#pragma unroll
-          for (int i = 0; i < BT; ++i) x[i] = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-          for (int k = 0; k < BT; ++k) {
-            x[k] *= s_rd[k];
-#pragma unroll
-            for (int i = k + 1; i < BT; ++i) x[i] = fma(-s_ex[i * (BT + 1) + k], x[k], x[i]);
-          }
-#pragma unroll
-          for (int i = 0; i < BT; ++i) s_inv[r * BT + i] = (i >= r) ? x[i] : 0.0;
+        for (int t = 0; t < 4; ++t) {
+          const int r = 4 * g + t;
+          if (r >= s) Tpp[s * ld + r] = t4[t];
+          s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
         }
       }
     }
@@ -244,9 +255,7 @@ template <bool RESIDENT>
 __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, double* __restrict__ invL, int bs,
                                                      int first, int stride, int* __restrict__ info) {
   extern __shared__ __align__(16) double smem[];
-  __shared__ double s_ex[BT * (BT + 1)];
   __shared__ double s_inv[BT * BT];   // column-major
-  __shared__ double s_rd[BT];         // reciprocal pivots of the diagonal tile
   __shared__ int s_fail;
   const int j = first + stride * static_cast<int>(blockIdx.x);
   const int nt = bs / BT;
@@ -282,7 +291,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     }
     __syncthreads();
     const LdsTiles A{s_tiles};
-    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, s_rd, &s_fail, info)) return;
+    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_inv, &s_fail, info)) return;
 #pragma unroll 2
     for (int q = tid / (BT * BT); q < ntri; q += TPP) {
       const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
@@ -291,7 +300,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   } else {
     __syncthreads();
     const GlobalTiles A{Dj, bs};
-    potrf_core(A, Ij, nt, j * bs, s_panel, s_ex, s_inv, s_rd, &s_fail, info);
+    potrf_core(A, Ij, nt, j * bs, s_panel, s_inv, &s_fail, info);
   }
 }
 
