@@ -11,21 +11,27 @@ inputs (no dataset).
 One timed step = one monolithic Newton iteration from the reference state
 (a2-a10: macro gradients, RVE integration, residual norms, 16384 RVE solves
 and condensations, FP64 macro assembly, banded Cholesky solve, fluctuation
-update), preceded by a device-to-device reset of the state.  Two forms run:
-  * mixed: FP32 PCG + FP64 residual refinement, energy-form condensation,
-    rve_tol 5e-4 (the headline value; the C-bar error is quadratic in the
-    solve error and stays more than ten times inside the metric's 1e-6 of
-    plain FP64, which the accuracy block of the output reports);
-  * fp64:  the same solver in FP64 throughout, rve_tol 1e-7 (Cbar <= 1e-10).
+update), preceded by a device-to-device reset of the state.  Three forms run:
+  * mixed:   FP32 PCG + FP64 residual refinement, energy-form condensation,
+             rve_tol 5e-4 (the headline value; the C-bar error is quadratic
+             in the solve error and stays inside the metric's 1e-6 of plain
+             FP64, which the accuracy block of the output reports);
+  * fp64_eq: the same solver in FP64 throughout at the mixed form's rve_tol
+             (equal C-bar accuracy: the speed-up of FP32 alone);
+  * fp64:    FP64 throughout at rve_tol 1e-7 (C-bar <= 1e-10, the parity form).
 value = RVE solves/s of the mixed form (RVEs / GPU time of a2-a6, HIP
 events on the stream), ms_per_step = wall time of one macro Newton step.
 
 --workload selects another configuration for the same measurement (the
-default is the 2D workload above): cfg3 (uneven 16/32/48 batch on a 128x128
-macro mesh), cfg4 (3D hex8), cfg5 (finite-strain Neo-Hooke, first Newton
-iteration of the first load increment), cfg2_element (one RVE per macro
-element), cfg2_q9 (32x32 biquadratic Q9 macro elements with 3x3 Gauss
-points) or oned (the 1+1D bar of Sec. 5.1).
+default is the 2D workload above): cfg2_rve8 (the same with 8x8 RVEs; with
+--solver dense the RVE solves run the dense matrix-core Cholesky), cfg3
+(uneven 16/32/48 batch on a 128x128 macro mesh), cfg4 (3D hex8), cfg5
+(finite-strain Neo-Hooke, first Newton iteration of the first load
+increment), cfg5_full (the same, all ten load increments: one step = the
+whole load-stepped solve), cfg5_surrogate (the ten increments with the
+network surrogate of the RVE response against the plain monolithic solve),
+cfg2_element (one RVE per macro element), cfg2_q9 (32x32 biquadratic Q9
+macro elements with 3x3 Gauss points) or oned (the 1+1D bar of Sec. 5.1).
 """
 from __future__ import annotations
 
@@ -74,19 +80,43 @@ WORKLOADS = {
                       "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; first Newton iteration of the first of ten "
                       "load increments (u_x = 0.01)",
                  lam=0.1, tol=dict(mixed=1e-4, fp64=1e-7)),
+    "cfg2_rve8": dict(desc="the 2D linear workload with 8x8 RVEs: macro 64x64 Q4 (16384 RVEs), RVE 8x8 Q4 centred "
+                           "circle vf 0.3, E ratio lognormal(ln 10, 0.5) per macro element, nu 0.3, uniaxial 1e-3",
+                      base="cfg2", base_kw=dict(rve=8), lam=1.0, tol=dict(mixed=5e-4, fp64=1e-7)),
+    "cfg5_full": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
+                           "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; all ten load increments (u_x up to 0.1) "
+                           "to newton_tol 1e-5, generalized monolithic scheme",
+                      base="cfg5", full=True, newton_tol=1e-5, tol=dict(mixed=1e-8, fp64=1e-8)),
+    "cfg5_surrogate": dict(desc="2D plane-strain Neo-Hooke, macro 64x64 Q4 (16384 RVEs), RVE 32x32 Q4 circle radius "
+                                "U[0.15,0.35], shear moduli 1/20, lambda = 2 mu; all ten load increments to "
+                                "newton_tol 1e-5 with the RVE-response network (trained here on 4096 GPU RVE "
+                                "solves) judged by full RVE solves after the last increment, against the plain "
+                                "monolithic solve to the same tolerance",
+                           base="cfg5", surrogate=True, newton_tol=1e-5, tol=dict(mixed=1e-8)),
 }
+
+# kernel source files whose text the committed HBM counter summary is bound to
+TRAFFIC_SOURCES = ("rve_lin2d.hip", "rve2d_common.hpp", "spectral2d.hpp", "dense2d.hpp", "elem2d.hpp",
+                   "fe2_internal.hpp")
+
+
+def build_problem(name):
+    import workloads as W
+    wl = WORKLOADS[name]
+    p = W.config(wl.get("base", name), **wl.get("base_kw", {}))
+    if wl.get("element"):
+        p = W.element_basis(p)
+    return p
 
 
 def measured_traffic():
     """HBM bytes per launch of the RVE solve kernel from the committed
     counter summary (FETCH_SIZE / WRITE_SIZE passes scaled by a plain copy),
     valid only while the kernel source is the one that was profiled."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_lin2d_cfg2_hbm_traffic.md")
-    srcp = os.path.join(ROOT, "paper_2312_12771_amd", "csrc", "rve_lin2d.hip")
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and " " not in l.split(": ")[0])
-        sha = hashlib.sha256(open(srcp, "rb").read()).hexdigest()
+        sha = traffic_source_hash()
         if kv.get("kernel_source_sha256") != sha:
             return None
         return float(kv["traffic_bytes_per_launch"])
@@ -94,12 +124,20 @@ def measured_traffic():
         return None
 
 
+def traffic_source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        hsh.update(open(os.path.join(ROOT, "paper_2312_12771_amd", "csrc", f), "rb").read())
+    return hsh.hexdigest()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
-    h = fe2.fe2_setup(p, precision=precision, rve_tol=rve_tol, inner_tol=1e-5)
+def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="auto"):
+    h = fe2.fe2_setup(p, precision=precision, solver=solver, rve_tol=rve_tol, inner_tol=1e-5)
     ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
     flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
     zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
@@ -173,22 +211,163 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0):
     return out
 
 
-def cpu_baseline(p, seconds):
-    """The FP64 oracle (SciPy sparse LU per RVE) on the first RVEs of the same
-    workload, single-threaded, for about `seconds` of CPU time."""
+def _cpu_worker(task):
+    """One process of the CPU baseline: the FP64 oracle (SciPy sparse LU per
+    RVE, BLAS threads 1) on RVEs w, w + n, w + 2n, ... of the workload for
+    about `seconds`."""
+    name, w, nw, seconds = task
     from threadpoolctl import threadpool_limits
     from oracle import rve as R
-    cb = {}
+    p = build_problem(name)
     nF = R.n_macro_components(p.dim, p.kinematics)
+    # the reference state: zero macro strain, or F = I for finite strain
+    macro = np.eye(p.dim).ravel() if p.kinematics == "finite" else np.zeros(nF)
+    cb = {}
     with threadpool_limits(limits=1):
-        R.homogenize_rve(p, 0, np.zeros(nF))   # import/JIT warm-up outside the clock
+        R.homogenize_rve(p, w, macro)   # import/JIT warm-up outside the clock
         t0 = time.perf_counter()
-        b = 0
-        while b < p.n_rve and (time.perf_counter() - t0 < seconds or b < 8):
-            cb[b] = R.homogenize_rve(p, b, np.zeros(nF)).C
-            b += 1
+        b, n = w, 0
+        while b < p.n_rve and (time.perf_counter() - t0 < seconds or n < 2):
+            c = R.homogenize_rve(p, b, macro).C
+            if b < 64:
+                cb[b] = c
+            n += 1
+            b += nw
         el = time.perf_counter() - t0
-    return dict(value=len(cb) / el, n=len(cb), seconds=el, cbar=cb)
+    return n, el, cb
+
+
+def cpu_cores():
+    """Processes for the CPU baseline: one per physical core this process may
+    run on, at most 16 (the host share of one GPU)."""
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False) or 1
+    except ImportError:
+        phys = os.cpu_count() or 1
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(phys, avail, 16)), dict(nproc=os.cpu_count(), affinity=avail, physical_cores=phys)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, seconds):
+    """The FP64 oracle on a bounded sample of the same workload, one
+    single-threaded process per physical core (spawned: the children never
+    touch the GPU); the rate is the sum of the per-process rates."""
+    import multiprocessing as mp
+    nw, info = cpu_cores()
+    with mp.get_context("spawn").Pool(nw) as pool:
+        res = pool.map(_cpu_worker, [(name, w, nw, seconds) for w in range(nw)])
+    cb = {}
+    for _, _, c in res:
+        cb.update(c)
+    n = sum(r[0] for r in res)
+    return dict(value=sum(r[0] / r[1] for r in res), n=n, seconds=max(r[1] for r in res), cbar=cb, cores=nw,
+                info=info, model=cpu_model())
+
+
+def run_full(fe2, torch, p, precision, rve_tol, newton_tol, steps, warmup, solver="auto"):
+    """The whole load-stepped solve (every increment to newton_tol) as one
+    timed step, then an instrumented replay for GPU phase times and the
+    iteration counts of every Newton step."""
+    h = fe2.fe2_setup(p, precision=precision, solver=solver, rve_tol=rve_tol, inner_tol=1e-5, newton_tol=newton_tol)
+    ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
+    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
+    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
+
+    def one():
+        fe2.fe2_set_state(h, zu, zw, 0.0)
+        hist = []
+        fe2.solve(h, p.load_factors, history=hist)
+        return hist
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hist = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n = p.n_rve
+    fe2.fe2_set_state(h, zu, zw, 0.0)
+    fe2.fe2_set_profiling(h, True)
+    it_sum, mv_sum = np.zeros(n), np.zeros(n)
+    buf = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for k, lam in enumerate(p.load_factors):
+        for _ in range(len(hist[k])):
+            fe2.fe2_newton_step(h, lam)
+            fe2.fe2_get_data(h, fe2.FE2_D_RVE_ITERS, buf)
+            it_sum += buf.cpu().numpy()
+            fe2.fe2_get_data(h, fe2.FE2_D_RVE_MV64, buf)
+            mv_sum += buf.cpu().numpy()
+    prof = fe2.fe2_get_profile(h)
+    fe2.fe2_set_profiling(h, False)
+    u = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_state(h, u=u)
+    n_spec = fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES)
+    h.close()
+    newton = sum(len(x) for x in hist)
+    return dict(ms=ms, newton=newton, newton_per_increment=[len(x) for x in hist], iters=it_sum, mv64=mv_sum,
+                rve_solve_ms=prof[1], step_gpu_ms=prof[4], u=u.cpu().numpy(),
+                n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim,
+                spectral=np.full(n, n_spec > 0))
+
+
+def run_surrogate(fe2, torch, p, wl, steps, warmup):
+    """Train the RVE-response network on GPU RVE solves of the same phase
+    recipe, then time the load stepping with the network against the plain
+    monolithic solve to the same newton_tol."""
+    import workloads as W
+    from paper_2312_12771_amd import surrogate as S
+    t0 = time.perf_counter()
+    pt = W.cfg5_material_points(4096, rve=32)
+    _, U = W.surrogate_samples(4096, seed=101)
+    X, T, ok, _, _ = S.rve_responses(pt, U)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sur = S.Surrogate.train(X, T, ok, steps=3000)
+    tol = wl["newton_tol"]
+    full = run_full(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], tol, steps, warmup)
+    hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=wl["tol"]["mixed"], newton_tol=tol, scheme="classical")
+    ndof = fe2.fe2_query(hs, fe2.FE2_Q_NDOF)
+    flen = fe2.fe2_query(hs, fe2.FE2_Q_FIELD_LEN)
+    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
+
+    def one():
+        fe2.fe2_set_state(hs, zu, zw, 0.0)
+        return S.solve_with_surrogate(hs, sur, p.load_factors, judge_tol=2e-2, judge="last")
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    u = torch.zeros(ndof, dtype=torch.float64, device="cuda")
+    fe2.fe2_get_state(hs, u=u)
+    hs.close()
+    sur.close()
+    u = u.cpu().numpy()
+    t_setup = t_data + sur.train_log["seconds"]
+    gain_ms = full["ms"] - ms
+    return dict(ms=ms, newton=sum(st["newton"]), newton_per_increment=st["newton"], judge_max_err=max(st["max_err"]),
+                rejected=st["rejected"], full=full, data_s=t_data, train_s=sur.train_log["seconds"],
+                heldout=None, du_rel=float(np.abs(u - full["u"]).max() / np.abs(full["u"]).max()),
+                break_even=(t_setup / (gain_ms * 1e-3)) if gain_ms > 0 else None)
 
 
 def run_oned(args, fe2, torch, W, k=9, q=2):
@@ -241,6 +420,127 @@ def rel_frob(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def roofline_of(p, iters, mv64, n_dof_rve, spectral, k_ms, dtype, kernel, traffic=None, solver="auto"):
+    """Roofline of the RVE solve: the method's algorithmic flops (operator
+    and PCG vector work per DOF and inner iteration, the FP64 operator per
+    refinement residual or condensation) over the measured kernel time; the
+    spectral preconditioner's transforms are reported on their own.  The
+    dense solve counts its factorization (n^3 / 3 multiply-adds) and two
+    triangular solves per sweep on the matrix cores."""
+    op = FLOP_OPERATOR_DOF[(p.dim, p.kinematics)]
+    fp64_res = float(np.sum(mv64 * n_dof_rve) * (op + 2.0))
+    if solver == "dense":
+        n = n_dof_rve.astype(float)
+        main = float(np.sum(2.0 * n ** 3 / 3.0 + iters * 4.0 * n ** 2))
+        pre = 0.0
+        bound = "mfma"
+    else:
+        main = float(np.sum(iters * n_dof_rve) * (op + 13.0))
+        # forward and inverse 2D FFT of the packed field (5 N^2 log2 N^2 flops
+        # each over 2 N^2 DOFs) plus the symbol: 10 log2 n + 2 per DOF
+        pre = float(np.sum(np.where(spectral, iters * n_dof_rve * (2.0 + 10.0 * np.log2(p.rve_res[:, 0])), 0.0)))
+        bound = "alu"
+    flops = main + fp64_res
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    return dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s", frac=round(achieved / peak, 4),
+                traffic=traffic, kernel=kernel, kernel_ms=round(k_ms, 4), flop_per_launch=flops,
+                precond_flop_per_launch=pre, precond_tflops=round(pre / (k_ms * 1e-3) / 1e12, 3),
+                frac_incl_precond=round((flops + pre) / (k_ms * 1e-3) / 1e12 / peak, 4),
+                pcg_iters_per_rve=float(np.mean(iters)))
+
+
+KERNEL = {(2, "small"): "k_lin2d", (3, "small"): "k_lin3d", (2, "finite"): "k_fin2d"}
+
+
+def cpu_line(args, forms_cbar):
+    """cpu_baseline entry and the accuracy of each form against the oracle."""
+    cb = cpu_baseline(args.workload, args.cpu_seconds)
+    acc = {f"cbar_{k}_vs_oracle_max": max(rel_frob(c[b], cb["cbar"][b]) for b in cb["cbar"])
+           for k, c in forms_cbar.items()}
+    cpu = dict(value=round(cb["value"], 3), unit="RVE solves/s", cores=cb["cores"], kind="oracle",
+               sample=f"{cb['n']} RVEs of the same workload (process w of {cb['cores']} takes RVEs w, w + "
+                      f"{cb['cores']}, ...), SciPy sparse LU per RVE (FP64, all right-hand sides), "
+                      f"{cb['seconds']:.1f}s per process, BLAS threads 1 per process",
+               nproc=cb["info"]["nproc"], affinity=cb["info"]["affinity"],
+               physical_cores=cb["info"]["physical_cores"], cpu_model=cb["model"])
+    return cpu, acc
+
+
+def base_line(args, wl, p, value, ms, dtype, step, roof, cpu):
+    return {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "RVE solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "name": args.workload,
+                   "n_rve": p.n_rve, "rve": sorted({"x".join(map(str, r)) for r in p.rve_res.tolist()}),
+                   "macro_dofs": p.n_dofs, "step": step, "solver": args.solver, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
+def main_full(args, fe2, torch, wl, p):
+    forms = {}
+    for k in [f for f in ("mixed", "fp64") if f in args.forms]:
+        forms[k] = run_full(fe2, torch, p, "fp32_ir" if k == "mixed" else "fp64", wl["tol"][k], wl["newton_tol"],
+                            args.steps, args.warmup)
+        log(k, "full solve ms", forms[k]["ms"], "newton", forms[k]["newton_per_increment"])
+    head = forms.get("mixed") or forms["fp64"]
+    dtype = "f32" if "mixed" in forms else "f64"
+    roof = roofline_of(p, head["iters"], head["mv64"], head["n_dof_rve"], head["spectral"], head["rve_solve_ms"],
+                       dtype, KERNEL[(p.dim, p.kinematics)] + " (RVE solves of every Newton iteration of the solve)")
+    cpu, acc = (None, {}) if args.no_cpu else cpu_line(args, {})
+    if "mixed" in forms and "fp64" in forms:
+        acc["u_mixed_vs_fp64"] = float(np.abs(forms["mixed"]["u"] - forms["fp64"]["u"]).max()
+                                       / np.abs(forms["fp64"]["u"]).max())
+    line = base_line(args, wl, p, p.n_rve * head["newton"] / (head["ms"] * 1e-3), head["ms"],
+                     dtype + "+f64" if dtype == "f32" else "f64",
+                     "the whole load-stepped solve: ten increments, every Newton iteration (a2-a10) to newton_tol "
+                     f"{wl['newton_tol']:g}; value = RVE solves of all iterations / wall time", roof, cpu)
+    line["forms"] = {k: dict(full_solve_ms=round(f["ms"], 3), newton_iterations=f["newton"],
+                             newton_per_increment=f["newton_per_increment"],
+                             rve_solve_gpu_ms=round(f["rve_solve_ms"], 3),
+                             pcg_iters_per_rve_per_newton=float(np.mean(f["iters"]) / f["newton"]))
+                     for k, f in forms.items()}
+    line["accuracy"] = acc
+    if "mixed" in forms and "fp64" in forms:
+        line["speedup_mixed_vs_fp64"] = dict(full_solve=round(forms["fp64"]["ms"] / forms["mixed"]["ms"], 3))
+    print(json.dumps(line), flush=True)
+
+
+def main_surrogate(args, fe2, torch, wl, p):
+    r = run_surrogate(fe2, torch, p, wl, args.steps, args.warmup)
+    full = r["full"]
+    log("surrogate ms", r["ms"], "full ms", full["ms"], "newton", r["newton_per_increment"])
+    roof = roofline_of(p, full["iters"], full["mv64"], full["n_dof_rve"], full["spectral"], full["rve_solve_ms"],
+                       "f32", "k_fin2d (the plain monolithic solve the surrogate run is compared with)")
+    cpu, acc = (None, {}) if args.no_cpu else cpu_line(args, {})
+    line = base_line(args, wl, p, p.n_rve * r["newton"] / (r["ms"] * 1e-3), r["ms"], "f32+f64",
+                     "the whole load-stepped solve with the network at every material point inside the training "
+                     "range, classical scheme, newton_tol " f"{wl['newton_tol']:g}, one judge pass of full RVE "
+                     "solves after the last increment; value = material-point responses (network or RVE) of all "
+                     "iterations / wall time", roof, cpu)
+    line["surrogate"] = dict(solve_ms=round(r["ms"], 3), newton_per_increment=r["newton_per_increment"],
+                             plain_solve_ms=round(full["ms"], 3), plain_newton_per_increment=full["newton_per_increment"],
+                             speedup_vs_plain=round(full["ms"] / r["ms"], 3),
+                             u_rel_diff_vs_plain=r["du_rel"], judge_max_err=r["judge_max_err"],
+                             judge_rejected=r["rejected"], data_generation_s=round(r["data_s"], 3),
+                             training_s=round(r["train_s"], 3),
+                             break_even_solves=None if r["break_even"] is None else round(r["break_even"], 2))
+    line["accuracy"] = acc
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,7 +548,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--forms", default="mixed,fp64_eq,fp64")
+    ap.add_argument("--solver", default="auto", choices=["auto", "jacobi", "fft", "fft_mc", "dense"],
+                    help="RVE solver of the mixed form (fp64 forms use auto)")
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS) + ["oned"],
                     help="configuration to time (default: the 2D benchmark workload)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -270,10 +572,14 @@ def main():
         return
     t = time.perf_counter()
     wl = WORKLOADS[args.workload]
-    p = W.config(wl.get("base", args.workload), **wl.get("base_kw", {}))
-    if wl.get("element"):
-        p = W.element_basis(p)
+    p = build_problem(args.workload)
     log(f"workload {args.workload} built in {time.perf_counter() - t:.1f}s: {p.n_rve} RVEs")
+    if wl.get("surrogate"):
+        main_surrogate(args, fe2, torch, wl, p)
+        return
+    if wl.get("full"):
+        main_full(args, fe2, torch, wl, p)
+        return
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -285,89 +591,70 @@ def main():
         del src, dst
 
     forms = {}
-    if "fp64" in args.forms:
+    want = args.forms.split(",")
+    if "fp64" in want:
         forms["fp64"] = run_form(fe2, torch, p, "fp64", wl["tol"]["fp64"], args.steps, args.warmup, wl["lam"])
         log("fp64", forms["fp64"]["gpu_ms"], "wall", forms["fp64"]["wall_ms_per_step"])
-    if "mixed" in args.forms:
-        forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], args.steps, args.warmup, wl["lam"])
+    if "fp64_eq" in want:
+        forms["fp64_eq"] = run_form(fe2, torch, p, "fp64", wl["tol"]["mixed"], args.steps, args.warmup, wl["lam"])
+        log("fp64_eq", forms["fp64_eq"]["gpu_ms"], "wall", forms["fp64_eq"]["wall_ms_per_step"])
+    if "mixed" in want:
+        forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], args.steps, args.warmup, wl["lam"],
+                                  solver=args.solver)
         log("mixed", forms["mixed"]["gpu_ms"], "wall", forms["mixed"]["wall_ms_per_step"])
-    head = forms.get("mixed") or forms["fp64"]
-    head_dtype = "f32" if "mixed" in forms else "f64"
+    head_key = "mixed" if "mixed" in forms else ("fp64_eq" if "fp64_eq" in forms else "fp64")
+    head = forms[head_key]
+    head_dtype = "f32" if head_key == "mixed" else "f64"
 
     def rve_rate(f):
         return p.n_rve / ((f["gpu_ms"]["assemble_norms"] + f["gpu_ms"]["rve_solve"]) * 1e-3)
 
-    # roofline of the dominant kernel: the RVE solve launch (one per step)
-    k_ms = head["gpu_ms"]["rve_solve"]
-    op = FLOP_OPERATOR_DOF[(p.dim, p.kinematics)]
-    # per inner iteration and DOF: the operator, plus 13 (Jacobi,
-    # single-reduction recurrences) or 10 + 10 log2 n + 5 (spectral: standard
-    # PCG updates, forward and inverse 2D FFT of the packed field at
-    # 5 N^2 log2 N^2 flops each over 2 N^2 DOFs, the symbol at 10 flops per
-    # complex point; n = 48 counted by the same 5 N log2 N convention)
-    per_it = np.where(head["spectral"], op + 15.0 + 10.0 * np.log2(p.rve_res[:, 0]), op + 13.0)
-    flops = float(np.sum(head["iters"] * head["n_dof_rve"] * per_it)
-                  + np.sum(head["mv64"] * head["n_dof_rve"]) * (op + 2.0))
-    achieved = flops / (k_ms * 1e-3) / 1e12
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_TFLOPS[head_dtype],
-                unit="TFLOP/s", frac=round(achieved / PEAK_TFLOPS[head_dtype], 4),
-                traffic=measured_traffic() if args.workload == "cfg2" else None,
-                kernel={(2, "small"): "k_lin2d", (3, "small"): "k_lin3d", (2, "finite"): "k_fin2d"}[
-                    (p.dim, p.kinematics)] + " (RVE solve + condensation, all launches of the step)",
-                kernel_ms=round(k_ms, 4),
-                flop_per_launch=flops, pcg_iters_per_rve=float(np.mean(head["iters"])))
+    # roofline of the dominant kernel: the RVE solve launch (one per class and step)
+    roof = roofline_of(p, head["iters"], head["mv64"], head["n_dof_rve"], head["spectral"],
+                       head["gpu_ms"]["rve_solve"], head_dtype,
+                       KERNEL[(p.dim, p.kinematics)] + " (RVE solve + condensation, all launches of the step)",
+                       traffic=measured_traffic() if (args.workload == "cfg2" and head_key == "mixed"
+                                                      and args.solver == "auto") else None,
+                       solver=args.solver if head_key == "mixed" else "auto")
 
     acc = {}
-    if "mixed" in forms and "fp64" in forms:
-        errs = [rel_frob(forms["mixed"]["cbar"][b], forms["fp64"]["cbar"][b]) for b in range(p.n_rve)]
-        acc["cbar_mixed_vs_fp64_max"] = max(errs)
-        acc["meets_cbar_target_1e-6"] = bool(max(errs) <= 1e-6)
-        acc["u_mixed_vs_fp64"] = float(np.abs(forms["mixed"]["u"] - forms["fp64"]["u"]).max()
-                                       / np.abs(forms["fp64"]["u"]).max())
+    if "fp64" in forms:
+        for k in ("mixed", "fp64_eq"):
+            if k in forms:
+                errs = [rel_frob(forms[k]["cbar"][b], forms["fp64"]["cbar"][b]) for b in range(p.n_rve)]
+                acc[f"cbar_{k}_vs_fp64_max"] = max(errs)
+                acc[f"{k}_meets_cbar_target_1e-6"] = bool(max(errs) <= 1e-6)
+                acc[f"u_{k}_vs_fp64"] = float(np.abs(forms[k]["u"] - forms["fp64"]["u"]).max()
+                                              / np.abs(forms["fp64"]["u"]).max())
     cpu = None
     if not args.no_cpu:
-        cb = cpu_baseline(p, args.cpu_seconds)
-        for k, f in forms.items():
-            acc[f"cbar_{k}_vs_oracle_max"] = max(rel_frob(f["cbar"][b], cb["cbar"][b]) for b in cb["cbar"])
-        cpu = dict(value=round(cb["value"], 3), unit="RVE solves/s", cores=1, kind="oracle",
-                   sample=f"first {cb['n']} RVEs of the same workload, SciPy sparse LU per RVE "
-                          f"(FP64, 4 right-hand sides), {cb['seconds']:.1f}s, BLAS threads 1")
+        cpu, acc_cpu = cpu_line(args, {k: f["cbar"] for k, f in forms.items()})
+        acc.update(acc_cpu)
 
-    line = {
-        "metric": METRIC,
-        "value": round(rve_rate(head), 1),
-        "unit": "RVE solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(head["wall_ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": head_dtype + "+f64" if head_dtype == "f32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": wl["desc"], "name": args.workload,
-                   "n_rve": p.n_rve, "rve": sorted({"x".join(map(str, r)) for r in p.rve_res.tolist()}),
-                   "macro_dofs": p.n_dofs,
-                   "step": "one monolithic Newton iteration (a2-a10) from the reference state",
-                   "parallelism": "single GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "forms": {k: dict(rve_solves_per_s=round(rve_rate(f), 1),
-                          macro_newton_step_ms=round(f["wall_ms_per_step"], 4),
-                          macro_newton_step_ms_hip_graph=round(f["graph_ms"], 4),
-                          gpu_phase_ms={kk: round(v, 4) for kk, v in f["gpu_ms"].items()},
-                          pcg_iters_per_rve=float(np.mean(f["iters"])),
-                          worst_rve_relres=float(np.max(f["relres"])),
-                          full_solve_ms=round(f["solve_ms"], 3),
-                          full_solve_newton_iterations=f["newton_iterations"])
-                  for k, f in forms.items()},
-        "accuracy": acc,
-    }
-    if "mixed" in forms and "fp64" in forms:
-        line["speedup_mixed_vs_fp64"] = dict(
-            rve_solves=round(rve_rate(forms["mixed"]) / rve_rate(forms["fp64"]), 3),
-            newton_step=round(forms["fp64"]["wall_ms_per_step"] / forms["mixed"]["wall_ms_per_step"], 3))
+    line = base_line(args, wl, p, rve_rate(head), head["wall_ms_per_step"],
+                     head_dtype + "+f64" if head_dtype == "f32" else "f64",
+                     "one monolithic Newton iteration (a2-a10) from the reference state", roof, cpu)
+    line["forms"] = {k: dict(rve_solves_per_s=round(rve_rate(f), 1),
+                             rve_tol=wl["tol"]["fp64" if k == "fp64" else "mixed"],
+                             macro_newton_step_ms=round(f["wall_ms_per_step"], 4),
+                             macro_newton_step_ms_hip_graph=round(f["graph_ms"], 4),
+                             gpu_phase_ms={kk: round(v, 4) for kk, v in f["gpu_ms"].items()},
+                             pcg_iters_per_rve=float(np.mean(f["iters"])),
+                             worst_rve_relres=float(np.max(f["relres"])),
+                             full_solve_ms=round(f["solve_ms"], 3),
+                             full_solve_newton_iterations=f["newton_iterations"])
+                     for k, f in forms.items()}
+    line["accuracy"] = acc
+    if "mixed" in forms:
+        sp = {}
+        for k in ("fp64_eq", "fp64"):
+            if k in forms:
+                sp["vs_" + k] = dict(
+                    rve_solves=round(rve_rate(forms["mixed"]) / rve_rate(forms[k]), 3),
+                    newton_step=round(forms[k]["wall_ms_per_step"] / forms["mixed"]["wall_ms_per_step"], 3),
+                    full_solve=round(forms[k]["solve_ms"] / forms["mixed"]["solve_ms"], 3))
+        if sp:
+            line["speedup_mixed"] = sp
     print(json.dumps(line), flush=True)
 
 

@@ -57,20 +57,26 @@ __global__ void k_phase_fraction(int n_rve, const int64_t* __restrict__ off, con
   if (threadIdx.x == 0) phi[b] = static_cast<double>(part[0] + part[1] + part[2] + part[3]) / (o1 - o0);
 }
 
+// Network inputs of every point; a point is accepted while its features lie
+// inside the training range.  A point that leaves the range is banned for
+// the rest of the attachment (it stays on the RVE path), so that points at
+// the edge of the range cannot switch between the network and the RVE
+// solve from one Newton iteration to the next (a discontinuous residual).
 __global__ void k_surr_features(int n, const double* __restrict__ F, const double* __restrict__ phi,
-                                const double* __restrict__ norm, const int* __restrict__ banned,
+                                const double* __restrict__ norm, int* __restrict__ banned,
                                 float* __restrict__ X, int* __restrict__ accept) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   double x[4];
   features(F + 4 * static_cast<size_t>(b), phi[b], x);
-  bool in = !(banned && banned[b]);
+  bool range = true;
   for (int c = 0; c < 4; ++c) {
     const double lo = norm[c], hi = norm[4 + c];
-    in = in && x[c] >= lo && x[c] <= hi;
+    range = range && x[c] >= lo && x[c] <= hi;
     X[4 * static_cast<size_t>(b) + c] = static_cast<float>(2.0 * (x[c] - lo) / (hi - lo) - 1.0);
   }
-  accept[b] = in ? 1 : 0;
+  if (!range && banned) banned[b] = 1;
+  accept[b] = (range && !(banned && banned[b])) ? 1 : 0;
 }
 
 __global__ void k_surr_decode(int n, const float* __restrict__ Y, const double* __restrict__ norm,

@@ -9,7 +9,7 @@ namespace fe2 {
 constexpr int SURR_NIN = 4, SURR_NOUT = 9, SURR_NORM = 26;
 
 __global__ void k_phase_fraction(int n_rve, const int64_t* off, const uint8_t* phase, double* phi);
-__global__ void k_surr_features(int n, const double* F, const double* phi, const double* norm, const int* banned,
+__global__ void k_surr_features(int n, const double* F, const double* phi, const double* norm, int* banned,
                                 float* X, int* accept);
 __global__ void k_surr_decode(int n, const float* Y, const double* norm, const double* F, const int* accept,
                               double* Pbar, double* Phat, double* Cbar, double* rnorm2, double* surrP, double* surrC);

@@ -11,7 +11,9 @@
   same macro displacement as the full monolithic solve within the judge's
   tolerance, both converged to the same macro tolerance, in less time (the
   gain the network brings, reported with the data and training cost it has
-  to recover).
+  to recover).  The last increments take the material points at the edge of
+  the training range: a point that leaves the range stays on the RVE path
+  for the rest of the solve, which this mesh exercises.
 """
 import time
 
@@ -87,16 +89,16 @@ def test_surrogate_training_and_gain_over_the_full_solve(libs):
           f"loss {sur.train_log['final_loss']:.2e}, held-out rms {rms:.2e}")
     assert rms < 2e-2
 
-    # the Neo-Hookean configuration on an 8x8 macro mesh (256 RVEs of 32x32),
-    # both runs converged to the same macro tolerance, 1e-6: the FP32
-    # network's stresses carry about 1e-7 relative noise, and the summed
-    # macro residual's noise floor grows with the mesh (about 4e-5 relative
-    # on 16x16), so 1e-6 is what the surrogate path meets here
-    p = W.config("cfg5", macro=(8, 8))
-    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6)
+    # the Neo-Hookean configuration on a 32x32 macro mesh (4096 RVEs of
+    # 32x32), both runs converged to the same macro tolerance, 1e-5: the
+    # FP32 network's stresses carry about 1e-7 relative rounding, and the
+    # relative macro residual the surrogate path reaches grows with the mesh
+    # (about 2e-6 on 32x32 and 3e-6 on 64x64 in the first increment)
+    p = W.config("cfg5", macro=(32, 32))
+    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-5)
     fe2.solve(hf, p.load_factors[:1])   # warm-up: kernels loaded, workspaces touched
     hf.close()
-    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6)
+    hf = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fe2.solve(hf, p.load_factors)
@@ -106,7 +108,7 @@ def test_surrogate_training_and_gain_over_the_full_solve(libs):
     fe2.fe2_get_state(hf, u=uf)
     hf.close()
 
-    hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-6, scheme="classical")
+    hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=1e-8, newton_tol=1e-5, scheme="classical")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = S.solve_with_surrogate(hs, sur, p.load_factors, judge_tol=2e-2, judge="last")
