@@ -20,6 +20,15 @@ LIB_PATH = os.path.join(_HERE, "libfe2.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run paper_2312_12771_amd/build.py "
                       "(or __graft_entry__.build()) first")
+# torch (the provider of device buffers and streams) ships a HIP runtime
+# with the same soname as the system one: load it first, so that libfe2
+# binds to that runtime instead of torch then resolving to the system copy
+# (a process whose torch runs on another runtime than it was built with
+# finds no device)
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 FE2_ABI_VERSION = 4
 
