@@ -624,15 +624,19 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 #pragma unroll 1
   for (int kc = ronly ? NF : 0; kc < NRHS; ++kc) {
     double* xc = Xb + kc * flen;
-    bool xzero = !warm || kc >= NF;   // warm start: previous X_F; x_r from zero
-    if (xzero) {
+    // warm start: previous X_F; x_r from zero.  A column that starts from
+    // zero is not cleared in memory: the first correction is stored as the
+    // column (no read-modify-write), and a column that needs no correction
+    // is written as zeros when its loop ends
+    bool xzero = !warm || kc >= NF;
+    auto clear_col = [&]() {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (exists[k]) {
           xc[2 * node_of(k)] = 0.0;
           xc[2 * node_of(k) + 1] = 0.0;
         }
-    }
+    };
 #pragma unroll 1
     for (int sweep = 0;; ++sweep) {
       // FP64 residual r = b - K x of this column
@@ -675,11 +679,13 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       const double rel = red[1] > 0.0 ? sqrt(red[0] / red[1]) : 0.0;
       if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
         worst = rel > worst ? rel : worst;
+        if (xzero) clear_col();
         break;
       }
       if (sweep >= a.max_ir) {
         worst = rel > worst ? rel : worst;
         all_ok = false;
+        if (xzero) clear_col();
         break;
       }
       // ---- inner PCG on K d = r (precision TI, Jacobi preconditioner) -----
@@ -874,12 +880,17 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       }
       }
       }   // (inner solve)
-      // x64 += x_inner (FP64 accumulation in the output column)
+      // x64 += x_inner (FP64 accumulation in the output column; stored
+      // directly when the column started from zero)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 2; ++d)
-          if (exists[k]) xc[2 * node_of(k) + d] += rnrm * static_cast<double>(xi[k][d]);
+          if (exists[k]) {
+            const double dx = rnrm * static_cast<double>(xi[k][d]);
+            double* xp = xc + 2 * node_of(k) + d;
+            *xp = xzero ? dx : *xp + dx;
+          }
       xzero = false;
     }
   }
