@@ -70,7 +70,7 @@ enum {
   FE2_SOLVER_DENSE = 3,
   FE2_SOLVER_PCG_FFT_MC = 4
 };
-enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1 };
+enum { FE2_SCHEME_GENERALIZED = 0, FE2_SCHEME_CLASSICAL = 1, FE2_SCHEME_CLASSICAL_PLAIN = 2 };
 /* Macro basis of the fluctuation: FE2_BASIS_DIRAC puts one RVE at every macro
  * Gauss point (Dirac approach, Eqs. (31)-(35)); FE2_BASIS_ELEMENT gives every
  * macro element one fluctuation field shared by its Gauss points (the
@@ -136,7 +136,13 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *                   applied inside the FP64 refinement (2D small strain,
  *                   FE2_PREC_FP32_IR, RVEs with 2 n1 n2 - 2 <= 128 unknowns
  *                   and n1, n2 >= 3; else FE2_ENOTSUP)
- *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1)
+ *  scheme           FE2_SCHEME_GENERALIZED (Sec. 4.2) or _CLASSICAL (Sec. 4.1:
+ *                   every RVE equilibrated at the current macro state, the
+ *                   macro step on the condensed tangent, the fluctuations
+ *                   moved with the macro increment by w -= X_F dF); or
+ *                   _CLASSICAL_PLAIN, the same staggered scheme without that
+ *                   predictor (the fluctuations carried unchanged into the
+ *                   next inner loop)
  *  rve_tol          relative FP64 residual ||b - K x|| / ||b|| every RVE
  *                   solve must reach
  *  inner_tol        floor of the relative tolerance of one FP32 PCG sweep

@@ -243,14 +243,17 @@ def generalized_step(prob, geo, state: State, lam_target: float):
 
 
 def classical_step(prob, geo, state: State, lam_target: float, tol_micro=1e-13,
-                   max_micro=30, micro_hist=None):
+                   max_micro=30, micro_hist=None, predictor=True, micro_norm="absolute"):
     """One macro iteration of the classical staggered scheme, Eqs. (43)-(45):
     equilibrate every RVE at the current q, condense, solve the macro Schur
-    system, update q and predict w with dw_b = -X_F dF_b."""
+    system, update q and predict w with dw_b = -X_F dF_b (predictor=False:
+    the fluctuations go unchanged into the next inner loop, the plain
+    staggered reading).  micro_norm selects the inner criterion (see
+    R.equilibrate_rve)."""
     for b in range(prob.n_rve):
         Fb = macro_gradient(prob, geo, state.u, b)
         state.w[b], h = R.equilibrate_rve(prob, b, Fb, state.w[b], tol=tol_micro,
-                                          max_it=max_micro)
+                                          max_it=max_micro, norm=micro_norm)
         if micro_hist is not None:
             micro_hist.append(h)
     conds = linearize(prob, geo, state)
@@ -258,17 +261,18 @@ def classical_step(prob, geo, state: State, lam_target: float, tol_micro=1e-13,
     nrm = norms_of(prob, geo, conds, R_true, F_int)
     du_D = (lam_target - state.lam) * prob.dir_vals
     du = solve_macro(prob, K, -R_true, du_D)
-    for b, c in enumerate(conds):
-        e = b // geo.n_gp
-        dF = geo.Bs[b] @ du[geo.edofs[e]]
-        state.w[b] = state.w[b] + R.expand(c.system, -(c.X_F @ dF))
+    if predictor:
+        for b, c in enumerate(conds):
+            e = b // geo.n_gp
+            dF = geo.Bs[b] @ du[geo.edofs[e]]
+            state.w[b] = state.w[b] + R.expand(c.system, -(c.X_F @ dF))
     state.u = state.u + du
     state.lam = lam_target
     return nrm, du, conds
 
 
 def solve(prob, scheme="generalized", tol=1e-10, max_it=20, load_factors=None,
-          state: Optional[State] = None, diverge_at=1e10):
+          state: Optional[State] = None, diverge_at=1e10, classical_opts=None):
     """Load stepping with either Newton scheme.  Returns (state, history)
     where history[k] lists the norms per iteration of load step k; raises
     RuntimeError when ||R_macro|| exceeds ``diverge_at`` (the failure
@@ -284,7 +288,10 @@ def solve(prob, scheme="generalized", tol=1e-10, max_it=20, load_factors=None,
                 step = element_generalized_step if element else generalized_step
             else:
                 step = element_classical_step if element else classical_step
-            nrm = step(prob, geo, state, lam)[0]
+            if scheme != "generalized" and not element and classical_opts:
+                nrm = step(prob, geo, state, lam, **classical_opts)[0]
+            else:
+                nrm = step(prob, geo, state, lam)[0]
             h.append(nrm)
             if not np.isfinite(nrm.macro) or nrm.macro > diverge_at:
                 raise RuntimeError(f"diverged at load {lam}, iteration {it}")

@@ -306,24 +306,35 @@ def homogenize_rve(prob, b, macro, w_full: Optional[np.ndarray] = None) -> Conde
                                  macro, w_full, L))
 
 
-def equilibrate_rve(prob, b, macro, w_full=None, tol=1e-13, max_it=30):
+def equilibrate_rve(prob, b, macro, w_full=None, tol=1e-13, max_it=30, norm="absolute"):
     """Classical inner Newton of Sec. 4.1 at fixed macro gradient: iterate
     w <- w - K_ww^-1 r until ||r|| < tol * max(1, ||r_0||), or until ||r|| is
     at the FP64 rounding level 1e-14 * r_round of its evaluation (finite
     strain; the paper's tolerance can lie below that level).  Returns the
-    final periodic field and the residual history."""
+    final periodic field and the residual history.
+
+    norm="per_volume" is the other reading of the criterion of Sec. 5.2: the
+    residual of the volume-averaged weak form, ||r|| / |Omega|, against tol
+    with no relative factor and no rounding escape (the inner residuals of
+    Table 2 end near 2e-15, below the rounding level of ||r|| itself)."""
     res, ph, par, L = rve_problem_args(prob, b)
     w = np.zeros(int(np.prod(res)) * len(res)) if w_full is None else np.array(w_full, dtype=np.float64)
+    vol = float(L) ** len(res)   # |Omega| of the cubic cell of side L
     hist = []
     r0 = None
     for _ in range(max_it + 1):
         s = assemble_rve(res, ph, par, prob.kinematics, prob.material, macro, w, L)
         nr = float(np.linalg.norm(s.r))
-        hist.append(nr)
-        if r0 is None:
-            r0 = nr
-        if nr < tol * max(1.0, r0) or nr <= 1e-14 * s.r_round:
-            break
+        if norm == "per_volume":
+            hist.append(nr / vol)
+            if nr / vol < tol:
+                break
+        else:
+            hist.append(nr)
+            if r0 is None:
+                r0 = nr
+            if nr < tol * max(1.0, r0) or nr <= 1e-14 * s.r_round:
+                break
         dw = spla.spsolve(s.K_ww.tocsc(), s.r)
         w[s.free] -= dw
     return w, hist

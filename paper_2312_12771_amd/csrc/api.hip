@@ -428,9 +428,10 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     return set_error("the dense RVE solve is implemented for 2D small strain in FE2_PREC_FP32_IR"), FE2_ENOTSUP;
   if ((h->solver == FE2_SOLVER_PCG_FFT || h->solver == FE2_SOLVER_PCG_FFT_MC) && h->dim != 2)
     return set_error("the spectral preconditioner is implemented for 2D RVEs"), FE2_ENOTSUP;
-  if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL)
+  if (h->scheme != FE2_SCHEME_GENERALIZED && h->scheme != FE2_SCHEME_CLASSICAL &&
+      h->scheme != FE2_SCHEME_CLASSICAL_PLAIN)
     return set_error("unknown scheme"), FE2_EINVAL;
-  if (h->scheme == FE2_SCHEME_CLASSICAL && (!(h->micro_tol > 0.0) || h->max_micro_it <= 0))
+  if (h->scheme != FE2_SCHEME_GENERALIZED && (!(h->micro_tol > 0.0) || h->max_micro_it <= 0))
     return set_error("the classical scheme needs micro_tol > 0 and max_micro_it > 0"), FE2_EINVAL;
 
   // Per-RVE material parameters as the kernels read them: (lambda, mu) per
@@ -849,7 +850,7 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
 // configuration (right-hand sides, warm start, load factor and increment);
 // every buffer they touch belongs to the handle, so a cached graph stays
 // valid for the handle's lifetime.  Fills use kernels (no memset nodes).
-int update_impl(fe2_ctx* h, int use_xr, hipStream_t s);
+int update_impl(fe2_ctx* h, int use_xr, hipStream_t s, bool move_w = true);
 int graph_step_impl(fe2_ctx* h, int nrhs, double lam, double dlam, hipStream_t s) {
   const int flags = RVE_SOLVE | (h->have_solution ? RVE_WARM : 0);
   fe2_ctx::StepGraph* hit = nullptr;
@@ -891,10 +892,11 @@ int graph_step_impl(fe2_ctx* h, int nrhs, double lam, double dlam, hipStream_t s
   return FE2_OK;
 }
 
-int update_impl(fe2_ctx* h, int use_xr, hipStream_t s) {
+int update_impl(fe2_ctx* h, int use_xr, hipStream_t s, bool move_w) {
   MacroArgs m = h->margs();
   hipLaunchKernelGGL(k_axpy, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->ndof, h->du, h->u);
-  hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr, h->skip);
+  if (move_w)
+    hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr, h->skip);
   FE2_HIP_CHECK(hipGetLastError());
   return FE2_OK;
 }
@@ -1008,7 +1010,7 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
   };
   SkipReset reset{h};
   const bool surr = h->surr_net != nullptr;
-  const bool classical = surr || h->scheme == FE2_SCHEME_CLASSICAL;
+  const bool classical = surr || h->scheme != FE2_SCHEME_GENERALIZED;
   // a2-a4 at the current state (classical: after the inner equilibration;
   // surrogate: network at the accepted points, inner equilibration at the
   // others) and the residual norms (a10)
@@ -1045,8 +1047,8 @@ int fe2_newton_step(fe2_handle h, double load_factor, double* norms_host, void* 
     // a7-a8: macro assembly and banded Cholesky solve with the increment
     if ((rc = macro_solve_impl(h, load_factor, dlam, s))) return rc;
     mark(4);
-    // a9: update
-    if ((rc = update_impl(h, nrhs > h->nF, s))) return rc;
+    // a9: update (the plain staggered scheme moves only the macro field)
+    if ((rc = update_impl(h, nrhs > h->nF, s, surr || h->scheme != FE2_SCHEME_CLASSICAL_PLAIN))) return rc;
   }
   mark(5);
   FE2_HIP_CHECK(hipMemcpyAsync(h->flag_host, h->fail_count, sizeof(int), hipMemcpyDeviceToHost, s));

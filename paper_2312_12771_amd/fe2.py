@@ -39,7 +39,7 @@ FE2_SMALL_STRAIN, FE2_FINITE_STRAIN = 0, 1
 FE2_LINEAR_ISO, FE2_NEO_HOOKE, FE2_MOONEY_RIVLIN = 0, 1, 2
 FE2_PREC_FP64, FE2_PREC_FP32_IR, FE2_PREC_BF16_IR = 0, 1, 2
 FE2_SOLVER_AUTO, FE2_SOLVER_PCG_JACOBI, FE2_SOLVER_PCG_FFT, FE2_SOLVER_DENSE, FE2_SOLVER_PCG_FFT_MC = 0, 1, 2, 3, 4
-FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL = 0, 1
+FE2_SCHEME_GENERALIZED, FE2_SCHEME_CLASSICAL, FE2_SCHEME_CLASSICAL_PLAIN = 0, 1, 2
 FE2_BASIS_DIRAC, FE2_BASIS_ELEMENT = 0, 1
 (FE2_D_MACRO_GRAD, FE2_D_RESIDUAL, FE2_D_PBAR, FE2_D_SOLUTION, FE2_D_RVE_ITERS,
  FE2_D_RVE_RELRES, FE2_D_MACRO_RHS, FE2_D_MACRO_RTRUE, FE2_D_MACRO_DU,
@@ -242,7 +242,8 @@ def make_desc(problem, precision: str = "fp64", solver: str = "auto",
     d.precision = _PREC[precision]
     d.solver = {"auto": FE2_SOLVER_AUTO, "jacobi": FE2_SOLVER_PCG_JACOBI,
                 "fft": FE2_SOLVER_PCG_FFT, "fft_mc": FE2_SOLVER_PCG_FFT_MC, "dense": FE2_SOLVER_DENSE}[solver]
-    d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL}[scheme]
+    d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL,
+                "classical_plain": FE2_SCHEME_CLASSICAL_PLAIN}[scheme]
     d.rve_tol, d.inner_tol, d.newton_tol, d.micro_tol = rve_tol, inner_tol, newton_tol, micro_tol
     d.max_pcg_it, d.max_ir, d.max_micro_it = max_pcg_it, max_ir, max_micro_it
     d.macro_basis = {"dirac": FE2_BASIS_DIRAC, "element": FE2_BASIS_ELEMENT}[

@@ -1,16 +1,24 @@
 """Cook's membrane of Sec. 5.2 on the GPU (20x20 macro mesh, 1600 RVEs of
 30x30 with a centred cross, the two Mooney-Rivlin phases of Eq. (59)):
-Newton iterations per load step against Table 1 (tests/golden/paper_sec5.json).
+Newton iterations per load step against Table 1 (tests/golden/paper_sec5.json),
+with the paper's termination rule: a load step has converged once the macro
+residual is at most eps_macro = 1e-9 (absolute, N), and a run has failed once
+it exceeds 1e10.
 
-* Generalized scheme: 6 iterations per step with 2 load steps, 4 with 12 and
-  22, as printed.
-* Classical scheme with 22 load steps: 4 iterations per step, as printed.
+* Generalized scheme: 6 iterations per step with 2 load steps, 4 with 12, 22,
+  32 and 42, as printed; no convergence with a single load step, as the text
+  under Table 1 states.
+* Classical scheme (inner loop to eps_micro = 1e-13, then the macro step on
+  the condensed tangent and the predictor w -= X_F dF): 4 iterations per step
+  with 22, 32 and 42 load steps, as printed.
+* The paper's classical failures at 2 and 12 load steps are not reproduced:
+  with the predictor the scheme converges there (6 and 4 iterations).  The
+  plain staggered reading (no predictor) fails at 2 load steps, though not by
+  the paper's criterion: one RVE's inner loop stalls above 1e-13 until its
+  iteration cap; it converges at 12.
 
 Absolute residuals are not compared (the printed values are not reproducible
-from the stated data).  The paper also reports that the classical scheme
-diverges below 22 load steps; with the predictor of the staggered update and
-FP64 RVE solves this implementation converges there as well, so that part of
-Table 1 is not asserted.
+from the stated data).
 """
 import json
 import os
@@ -25,6 +33,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_sec5.json")))["cook"]
+T1 = GOLDEN["table1_newton_iterations"]
 
 
 @pytest.fixture(scope="module")
@@ -35,28 +44,62 @@ def fe2():
 
 
 def newton_counts(fe2, n_l, scheme):
+    """Iterations per load step until ||R_macro|| <= eps_macro (the library's
+    own relative test is switched off); raises RuntimeError when the macro
+    residual exceeds the failure bound or a step needs more than 25."""
+    print("cook", scheme, n_l, flush=True)
     p = W.config("cook", n_steps=n_l)
-    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-11, newton_tol=1e-10, micro_tol=GOLDEN["eps_micro"],
+    h = fe2.fe2_setup(p, precision="fp64", rve_tol=1e-11, newton_tol=0.0, micro_tol=GOLDEN["eps_micro"],
                       scheme=scheme)
-    hist = []
-    fe2.solve(h, p.load_factors, max_it=25, history=hist, diverge_at=GOLDEN["diverged_if_macro_residual_exceeds"])
-    h.close()
-    its = [len(x) - 1 for x in hist]
-    # the last residual of every step is at the absolute macro tolerance of Sec. 5.2
-    assert all(x[-1][1] <= GOLDEN["eps_macro"] for x in hist)
+    its = []
+    try:
+        for lam in p.load_factors:
+            for it in range(26):
+                _, nr = fe2.fe2_newton_step(h, lam)
+                if not np.isfinite(nr[1]) or nr[1] > GOLDEN["diverged_if_macro_residual_exceeds"]:
+                    raise RuntimeError(f"diverged at load {lam}")
+                if it >= 1 and nr[1] <= GOLDEN["eps_macro"]:
+                    its.append(it)
+                    break
+            else:
+                raise RuntimeError(f"no convergence at load {lam}")
+    finally:
+        h.close()
+    assert len(its) == n_l
     return its
 
 
-@pytest.mark.parametrize("n_l", [2, 12, 22])
+@pytest.mark.parametrize("n_l", [2, 12, 22, 32, 42])
 def test_generalized_newton_iterations_match_table_1(fe2, n_l):
-    t1 = GOLDEN["table1_newton_iterations"]
-    expected = t1["generalized"][t1["n_l"].index(n_l)]
     its = newton_counts(fe2, n_l, "generalized")
-    assert len(its) == n_l
-    assert max(its) == expected, its
+    assert max(its) == T1["generalized"][T1["n_l"].index(n_l)], its
 
 
-def test_classical_newton_iterations_match_table_1_at_22_steps(fe2):
-    t1 = GOLDEN["table1_newton_iterations"]
-    its = newton_counts(fe2, 22, "classical")
-    assert max(its) == t1["classical"][t1["n_l"].index(22)], its
+def test_generalized_does_not_converge_in_one_load_step(fe2):
+    """Text under Table 1: the generalized scheme needs at least 2 load steps.
+    In one step the first macro update drives material points to states where
+    the condensed macro tangent is no longer positive definite."""
+    assert GOLDEN["minimal_converging_n_l"]["generalized"] == 2
+    with pytest.raises((RuntimeError, fe2.FE2Error)):
+        newton_counts(fe2, 1, "generalized")
+
+
+@pytest.mark.parametrize("n_l", [22, 32, 42])
+def test_classical_newton_iterations_match_table_1(fe2, n_l):
+    its = newton_counts(fe2, n_l, "classical")
+    assert max(its) == T1["classical"][T1["n_l"].index(n_l)], its
+
+
+def test_classical_below_22_load_steps(fe2):
+    """Table 1 marks the classical scheme as failed with 2 and 12 load steps.
+    Recorded here as measured: with the predictor it converges (6 and 4
+    iterations, the generalized counts); without it (the plain staggered
+    reading) one RVE's inner loop stalls above 1e-13 at 2 load steps, while 12
+    converge."""
+    assert T1["classical"][T1["n_l"].index(2)] is None and T1["classical"][T1["n_l"].index(12)] is None
+    assert max(newton_counts(fe2, 2, "classical")) == 6
+    assert max(newton_counts(fe2, 12, "classical")) == 4
+    with pytest.raises(fe2.FE2Error) as e:
+        newton_counts(fe2, 2, "classical_plain")
+    assert e.value.status == fe2.FE2_ENOCONV
+    assert max(newton_counts(fe2, 12, "classical_plain")) == 4
