@@ -125,15 +125,6 @@ struct fe2_ctx {
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   std::vector<StepGraph> graphs;
-  // uneven batches: the RVE solves of the resolution classes run side by
-  // side, the most expensive class on the caller's stream and each other
-  // class on a stream of its own (fork and join by events, also inside a
-  // captured graph), so that the cheaper classes fill the compute units the
-  // tail of the largest launch leaves idle
-  std::vector<int> class_order;        // classes by estimated cost, largest first
-  std::vector<hipStream_t> side;       // one per class beyond the first
-  hipEvent_t ev_fork = nullptr;
-  std::vector<hipEvent_t> ev_join;
 
   MacroArgs margs() const {
     MacroArgs m{};
@@ -272,11 +263,6 @@ void free_ctx(fe2_ctx* h) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-  for (auto& st : h->side)
-    if (st) (void)hipStreamDestroy(st);
-  for (auto& e : h->ev_join)
-    if (e) (void)hipEventDestroy(e);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->flag_host) (void)hipHostFree(h->flag_host);
   delete h;
@@ -515,27 +501,6 @@ int setup_impl(fe2_ctx* h, const fe2_problem_desc* d, hipStream_t s) {
     }
     h->classes[ci].rves.push_back(b);
   }
-  // launch order and side streams of the class solves (default priority);
-  // cost estimate: RVEs x unknowns x n (PCG iterations grow with the side)
-  {
-    const int nc = static_cast<int>(h->classes.size());
-    std::vector<double> cost(nc);
-    for (int k = 0; k < nc; ++k) {
-      const auto& c = h->classes[k];
-      cost[k] = static_cast<double>(c.rves.size()) * c.n1 * c.n2 * std::max(c.n1, c.n2);
-      h->class_order.push_back(k);
-    }
-    std::stable_sort(h->class_order.begin(), h->class_order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    if (nc > 1) {
-      FE2_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-      h->side.assign(nc - 1, nullptr);
-      h->ev_join.assign(nc - 1, nullptr);
-      for (int k = 0; k < nc - 1; ++k) {
-        FE2_HIP_CHECK(hipStreamCreateWithFlags(&h->side[k], hipStreamNonBlocking));
-        FE2_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join[k], hipEventDisableTiming));
-      }
-    }
-  }
 
   int rc;
   if ((rc = upload(&h->X, d->X, static_cast<size_t>(h->n_nodes) * h->dim, s))) return rc;
@@ -707,20 +672,11 @@ int solve_impl(fe2_ctx* h, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, h->fail_count, static_cast<size_t>(1), 0);
   const int flags = RVE_SOLVE | (h->have_solution ? RVE_WARM : 0);
   h->have_solution = true;
-  const int nc = static_cast<int>(h->classes.size());
-  if (nc > 1) FE2_HIP_CHECK(hipEventRecord(h->ev_fork, s));
-  for (int k = 0; k < nc; ++k) {
-    const RveClass& c = h->classes[h->class_order[k]];
-    hipStream_t sk = s;
-    if (k > 0) {
-      sk = h->side[k - 1];
-      FE2_HIP_CHECK(hipStreamWaitEvent(sk, h->ev_fork, 0));
-    }
-    int rc = launch_class(h, c, flags, static_cast<int>(c.rves.size()), nrhs, sk);
+  for (auto& c : h->classes) {
+    const int n = static_cast<int>(c.rves.size());
+    int rc = launch_class(h, c, flags, n, nrhs, s);
     if (rc) return rc;
-    if (k > 0) FE2_HIP_CHECK(hipEventRecord(h->ev_join[k - 1], sk));
   }
-  for (int k = 1; k < nc; ++k) FE2_HIP_CHECK(hipStreamWaitEvent(s, h->ev_join[k - 1], 0));
   return FE2_OK;
 }
 
