@@ -114,10 +114,14 @@ struct GlobalTiles {
   int ld;
   __device__ double* tile(int ti, int tk) const { return base + static_cast<size_t>(tk) * BT * ld + ti * BT; }
 };
+// Lower-triangle tiles in LDS, column-major with a column pitch of BT + 1:
+// the sixteen columns a wave's tile access touches then fall on different
+// banks (with a pitch of BT they shared eight).
+constexpr int LDS_TILE = BT * (BT + 1);
 struct LdsTiles {
   double* base;
-  static constexpr int ld = BT;
-  __device__ double* tile(int ti, int tk) const { return base + (ti * (ti + 1) / 2 + tk) * (BT * BT); }
+  static constexpr int ld = BT + 1;
+  __device__ double* tile(int ti, int tk) const { return base + (ti * (ti + 1) / 2 + tk) * LDS_TILE; }
 };
 
 __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= q
@@ -248,7 +252,7 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
 // LDS bytes of the two variants
 __host__ __device__ constexpr size_t potrf_lds_global(int bs) { return static_cast<size_t>(bs) * (BT + 1) * 8; }
 __host__ __device__ constexpr size_t potrf_lds_resident(int bs) {
-  return potrf_lds_global(bs) + static_cast<size_t>((bs / BT) * (bs / BT + 1) / 2) * BT * BT * 8;
+  return potrf_lds_global(bs) + static_cast<size_t>((bs / BT) * (bs / BT + 1) / 2) * LDS_TILE * 8;
 }
 
 template <bool RESIDENT>
@@ -286,7 +290,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
 #pragma unroll
       for (int u = 0; u < LB; ++u) {
         const int q = q0 + u * TPP;
-        if (q < ntri) s_tiles[q * BT * BT + el] = v[u];
+        if (q < ntri) s_tiles[q * LDS_TILE + c * (BT + 1) + r] = v[u];
       }
     }
     __syncthreads();
@@ -295,7 +299,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
 #pragma unroll 2
     for (int q = tid / (BT * BT); q < ntri; q += TPP) {
       const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
-      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * BT * BT + el];
+      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * LDS_TILE + c * (BT + 1) + r];
     }
   } else {
     __syncthreads();
