@@ -136,8 +136,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="auto"):
+def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="auto", tuning=None):
     h = fe2.fe2_setup(p, precision=precision, solver=solver, rve_tol=rve_tol, inner_tol=1e-5)
+    if tuning is not None:
+        from paper_2312_12771_amd import tune
+        tune.apply(h, tuning, precision=precision, rve_tol=rve_tol)
     ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
     flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
     zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
@@ -186,6 +189,12 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="
     n_spec = fe2.fe2_query(h, fe2.FE2_Q_SPECTRAL_RVES)
     sq = (p.rve_res[:, 0] == p.rve_res[:, -1]) & np.isin(p.rve_res[:, 0], (8, 16, 32, 48))
     spectral = sq if (n_spec > 0 and p.dim == 2) else np.zeros(n, bool)
+    dense = np.full(n, solver == "dense")
+    if tuning is not None:   # per-class choices override the rule
+        for c in tuning["classes"]:
+            m = np.all(p.rve_res == np.asarray(c["res"]), axis=1)
+            spectral[m] = sq[m] & (c["choice"] in ("fft", "fft_mc", "auto"))
+            dense[m] = c["choice"] == "dense"
     assert int(spectral.sum()) == n_spec, (int(spectral.sum()), n_spec)
     # a full linear solve to the Newton tolerance (informational)
     fe2.fe2_set_state(h, zu, zw, 0.0)
@@ -206,7 +215,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="
         cbar=cbar.cpu().numpy().reshape(n, nF, nF),
         iters=iters.cpu().numpy(), mv64=mv64.cpu().numpy(), relres=relres.cpu().numpy(),
         newton_iterations=len(hist[0]), solve_ms=solve_ms, u=u.cpu().numpy(), graph_ms=graph_ms,
-        n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim, spectral=spectral)
+        n_dof_rve=p.dim * np.prod(p.rve_res, axis=1) - p.dim, spectral=spectral, dense=dense)
     h.close()
     return out
 
@@ -420,7 +429,7 @@ def rel_frob(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def roofline_of(p, iters, mv64, n_dof_rve, spectral, k_ms, dtype, kernel, traffic=None, solver="auto"):
+def roofline_of(p, iters, mv64, n_dof_rve, spectral, k_ms, dtype, kernel, traffic=None, dense=None):
     """Roofline of the RVE solve: the method's algorithmic flops (operator
     and PCG vector work per DOF and inner iteration, the FP64 operator per
     refinement residual or condensation) over the measured kernel time; the
@@ -429,17 +438,14 @@ def roofline_of(p, iters, mv64, n_dof_rve, spectral, k_ms, dtype, kernel, traffi
     triangular solves per sweep on the matrix cores."""
     op = FLOP_OPERATOR_DOF[(p.dim, p.kinematics)]
     fp64_res = float(np.sum(mv64 * n_dof_rve) * (op + 2.0))
-    if solver == "dense":
-        n = n_dof_rve.astype(float)
-        main = float(np.sum(2.0 * n ** 3 / 3.0 + iters * 4.0 * n ** 2))
-        pre = 0.0
-        bound = "mfma"
-    else:
-        main = float(np.sum(iters * n_dof_rve) * (op + 13.0))
-        # forward and inverse 2D FFT of the packed field (5 N^2 log2 N^2 flops
-        # each over 2 N^2 DOFs) plus the symbol: 10 log2 n + 2 per DOF
-        pre = float(np.sum(np.where(spectral, iters * n_dof_rve * (2.0 + 10.0 * np.log2(p.rve_res[:, 0])), 0.0)))
-        bound = "alu"
+    dense = np.zeros(len(iters), bool) if dense is None else np.asarray(dense)
+    n = n_dof_rve.astype(float)
+    # dense form: factorization and one triangular-solve pair per sweep
+    main = float(np.sum(np.where(dense, 2.0 * n ** 3 / 3.0 + iters * 4.0 * n ** 2, iters * n * (op + 13.0))))
+    # forward and inverse 2D FFT of the packed field (5 N^2 log2 N^2 flops
+    # each over 2 N^2 DOFs) plus the symbol: 10 log2 n + 2 per DOF
+    pre = float(np.sum(np.where(spectral, iters * n * (2.0 + 10.0 * np.log2(p.rve_res[:, 0])), 0.0)))
+    bound = "mfma" if dense.all() else "alu"
     flops = main + fp64_res
     achieved = flops / (k_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[dtype]
@@ -555,6 +561,11 @@ def main():
                     help="configuration to time (default: the 2D benchmark workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the per-class solver autotuner for this workload's mixed form first and save its "
+                         "table under paper_2312_12771_amd/tuning/")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="ignore the saved tuning table (every class runs --solver)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
@@ -590,6 +601,20 @@ def main():
         log("copy probe: 1 GiB read, 1 GiB written")
         del src, dst
 
+    # per-class solver choices of the autotuner for the mixed form: a saved
+    # table for this workload (same precision and rve_tol), or a fresh run
+    tuning = None
+    if args.solver == "auto" and not args.no_tuning:
+        from paper_2312_12771_amd import tune
+        if args.tune:
+            t0 = time.perf_counter()
+            tuning = tune.tune(p, args.workload, "fp32_ir", wl["tol"]["mixed"], wl["lam"])
+            log(f"tuned in {time.perf_counter() - t0:.1f}s ->", tune.save(tuning), json.dumps(tuning))
+        else:
+            tuning = tune.load(args.workload)
+        if tuning is not None and tuning["rve_tol"] != wl["tol"]["mixed"]:
+            tuning = None
+
     forms = {}
     want = args.forms.split(",")
     if "fp64" in want:
@@ -600,7 +625,7 @@ def main():
         log("fp64_eq", forms["fp64_eq"]["gpu_ms"], "wall", forms["fp64_eq"]["wall_ms_per_step"])
     if "mixed" in want:
         forms["mixed"] = run_form(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], args.steps, args.warmup, wl["lam"],
-                                  solver=args.solver)
+                                  solver=args.solver, tuning=tuning)
         log("mixed", forms["mixed"]["gpu_ms"], "wall", forms["mixed"]["wall_ms_per_step"])
     head_key = "mixed" if "mixed" in forms else ("fp64_eq" if "fp64_eq" in forms else "fp64")
     head = forms[head_key]
@@ -615,7 +640,7 @@ def main():
                        KERNEL[(p.dim, p.kinematics)] + " (RVE solve + condensation, all launches of the step)",
                        traffic=measured_traffic() if (args.workload == "cfg2" and head_key == "mixed"
                                                       and args.solver == "auto") else None,
-                       solver=args.solver if head_key == "mixed" else "auto")
+                       dense=head.get("dense"))
 
     acc = {}
     if "fp64" in forms:
@@ -634,6 +659,9 @@ def main():
     line = base_line(args, wl, p, rve_rate(head), head["wall_ms_per_step"],
                      head_dtype + "+f64" if head_dtype == "f32" else "f64",
                      "one monolithic Newton iteration (a2-a10) from the reference state", roof, cpu)
+    if tuning is not None and head_key == "mixed":
+        line["config"]["solver"] = "tuned per class: " + ", ".join(
+            f"{'x'.join(map(str, c['res']))} {c['choice']}" for c in tuning["classes"])
     line["forms"] = {k: dict(rve_solves_per_s=round(rve_rate(f), 1),
                              rve_tol=wl["tol"]["fp64" if k == "fp64" else "mixed"],
                              macro_newton_step_ms=round(f["wall_ms_per_step"], 4),

@@ -318,6 +318,19 @@ int fe2_set_profiling(fe2_handle h, int enable);
  * solve entry holds their sum; the other two are zero).  The classical
  * scheme and the surrogate always launch individually. */
 int fe2_set_graph(fe2_handle h, int enable);
+/* Per-class override of the RVE solver, the choice of an autotuner (Sec.
+ * 4.1: the RVE blocks of L are independent, so each resolution class may be
+ * solved its own way).  Every RVE class of resolution n1 x n2 (x n3 in 3D;
+ * n3 is ignored in 2D) runs with `solver` (FE2_SOLVER_*) instead of the
+ * handle's: the preconditioner (Jacobi or spectral) and the right-hand sides
+ * per PCG pass (FE2_SOLVER_PCG_FFT: one column at a time, _FFT_MC: the three
+ * columns of X_F together), or the dense form.  FE2_EINVAL when no class has
+ * that resolution or the solver is unknown; FE2_ENOTSUP when the class
+ * cannot run it (spectral tables are built at setup only for spectral sizes
+ * and solvers AUTO, FFT or FFT_MC; the dense form as in fe2_problem_desc).
+ * Cached step graphs are dropped.  Results change only within the solve
+ * tolerances. */
+int fe2_set_class_solver(fe2_handle h, int n1, int n2, int n3, int solver);
 int fe2_get_profile(fe2_handle h, double* out);
 
 /* Release all device memory of the handle (waits for its work). */

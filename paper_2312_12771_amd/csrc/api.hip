@@ -48,7 +48,8 @@ struct RveClass {
   std::vector<int> rves;
   int* d_list = nullptr;
   double* d_tab = nullptr;   // 2D: kv[10] | KwF[24] | KFF[9] | err | modes[10]
-  bool spectral = false;     // PCG with the spectral preconditioner (2D small strain)
+  bool spectral = false;     // spectral preconditioner tables built for the class
+  int solver = -1;           // per-class override of the handle's solver (-1: none)
   double* d_fft64 = nullptr; // its table, FP64 and FP32
   float* d_fft32 = nullptr;
 };
@@ -126,6 +127,13 @@ struct fe2_ctx {
   hipStream_t cap_stream = nullptr;
   std::vector<StepGraph> graphs;
 
+  // the solver a class runs with, and whether that uses the spectral tables
+  int class_solver(const RveClass& c) const { return c.solver >= 0 ? c.solver : solver; }
+  bool class_fft(const RveClass& c) const {
+    const int s = class_solver(c);
+    return c.spectral && (s == FE2_SOLVER_AUTO || s == FE2_SOLVER_PCG_FFT || s == FE2_SOLVER_PCG_FFT_MC);
+  }
+
   MacroArgs margs() const {
     MacroArgs m{};
     m.n_rve = n_rve;
@@ -192,7 +200,7 @@ struct fe2_ctx {
     a.max_ir = max_ir;
     a.fft_tab = c.d_fft32;
     a.fft_tab64 = c.d_fft64;
-    a.flags = flags | (c.spectral ? RVE_FFT : 0);
+    a.flags = flags | (class_fft(c) ? RVE_FFT : 0);
     return a;
   }
 
@@ -230,8 +238,9 @@ struct fe2_ctx {
     a.tol_in = precision == FE2_PREC_FP64 ? 0.5 * rve_tol : std::max(0.3 * rve_tol, inner_tol);
     a.max_it = max_pcg_it;
     a.max_ir = max_ir;
-    a.flags = flags | (c.spectral ? RVE_FFT : 0) | (c.spectral && solver == FE2_SOLVER_PCG_FFT_MC ? RVE_MC : 0) |
-              (solver == FE2_SOLVER_DENSE ? RVE_DENSE : 0);
+    a.flags = flags | (class_fft(c) ? RVE_FFT : 0) |
+              (class_fft(c) && class_solver(c) == FE2_SOLVER_PCG_FFT_MC ? RVE_MC : 0) |
+              (class_solver(c) == FE2_SOLVER_DENSE ? RVE_DENSE : 0);
     return a;
   }
 };
@@ -1321,7 +1330,7 @@ int fe2_query(fe2_handle h, int which, int64_t* out) {
     case FE2_Q_SPECTRAL_RVES: {
       int64_t n = 0;
       for (const auto& c : h->classes)
-        if (c.spectral) n += static_cast<int64_t>(c.rves.size());
+        if (h->class_fft(c)) n += static_cast<int64_t>(c.rves.size());
       *out = n;
       return FE2_OK;
     }
@@ -1339,6 +1348,36 @@ int fe2_set_profiling(fe2_handle h, int enable) {
     for (auto& e : h->ev) FE2_HIP_CHECK(hipEventCreate(&e));
   h->prof = enable != 0;
   for (double& v : h->prof_ms) v = 0.0;
+  return FE2_OK;
+}
+
+int fe2_set_class_solver(fe2_handle h, int n1, int n2, int n3, int solver) {
+  FE2_GUARD(h);
+  if (solver != FE2_SOLVER_AUTO && solver != FE2_SOLVER_PCG_JACOBI && solver != FE2_SOLVER_PCG_FFT &&
+      solver != FE2_SOLVER_PCG_FFT_MC && solver != FE2_SOLVER_DENSE)
+    return set_error("unknown solver"), FE2_EINVAL;
+  const bool finite = h->kin == FE2_FINITE_STRAIN;
+  int hits = 0;
+  for (const auto& c : h->classes) {
+    if (c.n1 != n1 || c.n2 != n2 || (h->dim == 3 && c.n1 != n3)) continue;
+    ++hits;
+    if ((solver == FE2_SOLVER_PCG_FFT || solver == FE2_SOLVER_PCG_FFT_MC) && !c.spectral)
+      return set_error("no spectral tables for this class (size, or a handle set up with FE2_SOLVER_PCG_JACOBI)"),
+             FE2_ENOTSUP;
+    if (solver == FE2_SOLVER_DENSE &&
+        (h->dim != 2 || finite || h->precision != FE2_PREC_FP32_IR || !lin2d_dense_size(n1, n2)))
+      return set_error("the dense RVE solve is implemented for 2D small strain in FE2_PREC_FP32_IR up to 128 unknowns"),
+             FE2_ENOTSUP;
+  }
+  if (!hits) return set_error("no RVE class of that resolution"), FE2_EINVAL;
+  for (auto& c : h->classes)
+    if (c.n1 == n1 && c.n2 == n2 && (h->dim != 3 || c.n1 == n3)) c.solver = solver;
+  // cached step graphs hold the old launches
+  for (auto& g : h->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  h->graphs.clear();
   return FE2_OK;
 }
 

@@ -120,6 +120,7 @@ _sig = {
     "fe2_surrogate_detach": (C.c_int, [_vp]),
     "fe2_surrogate_judge": (C.c_int, [_vp, C.c_double, _dp, C.POINTER(C.c_int), _vp]),
     "fe2_set_graph": (C.c_int, [_vp, C.c_int]),
+    "fe2_set_class_solver": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
     "fe2_band_solve": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
     "fe2_band_solve_noalloc": (C.c_int, [C.c_int, C.c_int, _vp, _vp, C.POINTER(C.c_int), _vp]),
     "fe2_spectral_table": (C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
@@ -240,8 +241,7 @@ def make_desc(problem, precision: str = "fp64", solver: str = "auto",
     d.phase_params = keep["pp"].ctypes.data_as(_dp)
     d.rve_size = float(problem.rve_size)
     d.precision = _PREC[precision]
-    d.solver = {"auto": FE2_SOLVER_AUTO, "jacobi": FE2_SOLVER_PCG_JACOBI,
-                "fft": FE2_SOLVER_PCG_FFT, "fft_mc": FE2_SOLVER_PCG_FFT_MC, "dense": FE2_SOLVER_DENSE}[solver]
+    d.solver = SOLVERS[solver]
     d.scheme = {"generalized": FE2_SCHEME_GENERALIZED, "classical": FE2_SCHEME_CLASSICAL,
                 "classical_plain": FE2_SCHEME_CLASSICAL_PLAIN}[scheme]
     d.rve_tol, d.inner_tol, d.newton_tol, d.micro_tol = rve_tol, inner_tol, newton_tol, micro_tol
@@ -568,6 +568,16 @@ def fe2_1d_query(h: Handle1D, which: int) -> int:
 
 def fe2_1d_get_state(h: Handle1D, phi=None, w=None, stream=None):
     _check(_lib.fe2_1d_get_state(h.ptr, _dev_ptr(phi), _dev_ptr(w), _stream_ptr(stream)), "fe2_1d_get_state")
+
+
+SOLVERS = {"auto": FE2_SOLVER_AUTO, "jacobi": FE2_SOLVER_PCG_JACOBI, "fft": FE2_SOLVER_PCG_FFT,
+           "fft_mc": FE2_SOLVER_PCG_FFT_MC, "dense": FE2_SOLVER_DENSE}
+
+
+def fe2_set_class_solver(h: Handle, res, solver: str):
+    """Per-class solver override for the RVEs of resolution `res` (see fe2.h)."""
+    r = [int(x) for x in res] + [1, 1]
+    return _check(_lib.fe2_set_class_solver(h.ptr, r[0], r[1], r[2], SOLVERS[solver]), "fe2_set_class_solver")
 
 
 def fe2_set_graph(h: Handle, enable: bool):
