@@ -614,6 +614,48 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     }
     for (int t = tid; t < MD; t += WG) dv[t] = 0.0f;   // padding unknowns stay zero
   }
+  // ---- a6 folded into the refinement (FP32 spectral solve) ----------------
+  // The energy-form entry E[i][j] = b_i . x_j + x_i . (b_j - K x_j) equals
+  // E[j][i] for symmetric K, whatever the solve error.  So column j, at the
+  // sweep that accepts it, supplies E[i][j] for i <= j from the K x_j and
+  // the staged x_j it has just used (x_i of the finished columns from HBM),
+  // and thread 0 writes C-bar entry (i, j) and its mirror; the residual
+  // column gives P-hat.  No separate FP64 pass per column.
+  constexpr bool FOLD = FFT && sizeof(TI) == 4;
+  double* Cb = a.Cbar + static_cast<size_t>(b) * NF * NF;
+  auto fold = [&](int jc, bool xz, const double (&rj)[4][2]) {
+    double g[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) g[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!dof[k]) continue;
+      const int di = k & 1, dj = k >> 1;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const double xj = xz ? 0.0 : s_st[d * P::PN + pidx[k]];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          if (jc < NF && i > jc) continue;   // from the mirror, when column i is accepted
+          const double xi = (i == jc) ? xj : Xb[i * flen + 2 * node_of(k) + d];
+          g[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj + xi * rj[k][d];
+        }
+      }
+    }
+    wg_sum<NF, NW, RED_NV>(g, s_red, parity);
+    if (tid == 0) {
+      if (jc < NF) {
+        for (int i = 0; i <= jc; ++i) {
+          const double v = (ssum * a.KFF64[i * NF + jc] - g[i]) / V;
+          Cb[i * NF + jc] = v;
+          Cb[jc * NF + i] = v;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) a.Phat[static_cast<size_t>(b) * NF + i] = (Pint[i] - g[i]) / V;
+      }
+    }
+  };
   const bool warm = (a.flags & RVE_WARM) != 0;
   const double tin2 = a.tol_in * a.tol_in;
   const double tol2 = a.tol * a.tol;
@@ -680,12 +722,18 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       if (red[1] == 0.0 || red[0] <= tol2 * red[1]) {
         worst = rel > worst ? rel : worst;
         if (xzero) clear_col();
+        if constexpr (FOLD) {
+          if (!ronly) fold(kc, xzero, r64);
+        }
         break;
       }
       if (sweep >= a.max_ir) {
         worst = rel > worst ? rel : worst;
         all_ok = false;
         if (xzero) clear_col();
+        if constexpr (FOLD) {
+          if (!ronly) fold(kc, xzero, r64);
+        }
         break;
       }
       // ---- inner PCG on K d = r (precision TI, Jacobi preconditioner) -----
@@ -917,9 +965,8 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   // ---- a6: condensation (energy form) from a final FP64 pass -------------
   //   G1[i][j] = b_i . x_j,  G2[i][j] = x_i . (b_j - K x_j), one column j
   //   at a time; thread 0 writes Cbar column j (or Phat for j = NF)
-  double* Cb = a.Cbar + static_cast<size_t>(b) * NF * NF;
 #pragma unroll 1
-  for (int jc = 0; jc < NRHS; ++jc) {
+  for (int jc = 0; jc < (FOLD ? 0 : NRHS); ++jc) {
     const double* xc = Xb + jc * flen;
     __syncthreads();   // global writes of X visible, staging free
     stage(xc);
