@@ -860,8 +860,8 @@ int graph_step_impl(fe2_ctx* h, int nrhs, double lam, double dlam, hipStream_t s
 int update_impl(fe2_ctx* h, int use_xr, hipStream_t s, bool move_w) {
   MacroArgs m = h->margs();
   hipLaunchKernelGGL(k_axpy, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->ndof, h->du, h->u);
-  if (move_w)
-    hipLaunchKernelGGL(k_update_w, dim3(h->n_rve), dim3(256), 0, s, m, h->du, h->foff, h->Xs, h->w, use_xr, h->skip);
+  if (move_w && launch_update_w(m, static_cast<int>(h->n_rve), h->du, h->foff, h->Xs, h->w, use_xr, h->skip, s))
+    return set_error("field update: unsupported nF or element"), FE2_ENOTSUP;
   FE2_HIP_CHECK(hipGetLastError());
   return FE2_OK;
 }

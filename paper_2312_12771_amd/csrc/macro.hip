@@ -623,32 +623,78 @@ __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__
 
 // a9: dF_b = B_b du_e (element basis: Bbar_e du_e); w_b -= x_r + X_F dF_b
 // (generalized) or X_F dF_b (classical predictor).  One work-group per RVE.
-__global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
-                           const double* __restrict__ X, double* __restrict__ w, int use_xr,
-                           const int* __restrict__ skip) {
+// The products B_b[i][col] du_col run on one thread each (one dependent
+// connectivity -> displacement load per thread instead of a chain of nd), and
+// the first chunk of the RVE's columns is loaded before they are summed, so
+// the stream over X and w does not wait for dF.  Every thread sums dF[i] over
+// col in order from the shared products (same value on every thread).
+template <int NF>
+__global__ void __launch_bounds__(256) k_update_w(MacroArgs m, const double* __restrict__ du,
+                                                  const int64_t* __restrict__ foff, const double* __restrict__ X,
+                                                  double* __restrict__ w, int use_xr, const int* __restrict__ skip) {
+  constexpr int U = 4;   // elements per thread and chunk
   const int b = blockIdx.x;
   if (skip && skip[b]) return;
-  __shared__ double dF[9];
+  __shared__ double part[kUpdateMaxProducts];
   const int e = elem_of_rve(m, b);
   const int nd = m.nen * m.dim;
-  if (threadIdx.x < m.nF) {
-    const int i = threadIdx.x;
-    double v = 0.0;
-    for (int col = 0; col < nd; ++col) {
-      const int node = m.conn[e * m.nen + col / m.dim];
-      v += rve_B(m, b, i, col) * du[node * m.dim + col % m.dim];
-    }
-    dF[i] = v;
+  for (int t = threadIdx.x; t < NF * nd; t += blockDim.x) {
+    const int i = t / nd, col = t % nd;
+    const int node = m.conn[e * m.nen + col / m.dim];
+    part[t] = rve_B(m, b, i, col) * du[node * m.dim + col % m.dim];
   }
-  __syncthreads();
   const int64_t fo = foff[b];
   const int64_t flen = foff[b + 1] - fo;
-  const double* Xb = X + fo * (m.nF + 1);
-  for (int64_t t = threadIdx.x; t < flen; t += blockDim.x) {
-    double dw = use_xr ? Xb[m.nF * flen + t] : 0.0;
-    for (int j = 0; j < m.nF; ++j) dw += Xb[j * flen + t] * dF[j];
-    w[fo + t] -= dw;
+  const double* Xb = X + fo * (NF + 1);
+  const int64_t step = static_cast<int64_t>(U) * blockDim.x;
+  double xv[U][NF + 1], wv[U];
+  auto load = [&](int64_t t0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = t0 + static_cast<int64_t>(u) * blockDim.x;
+      const bool in = t < flen;
+      wv[u] = in ? w[fo + t] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) xv[u][j] = in ? Xb[j * flen + t] : 0.0;
+      xv[u][NF] = in && use_xr ? Xb[NF * flen + t] : 0.0;
+    }
+  };
+  int64_t t0 = threadIdx.x;
+  load(t0);
+  __syncthreads();
+  double dF[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double v = 0.0;
+    for (int col = 0; col < nd; ++col) v += part[i * nd + col];
+    dF[i] = v;
   }
+  while (true) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = t0 + static_cast<int64_t>(u) * blockDim.x;
+      double dw = xv[u][NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) dw += xv[u][j] * dF[j];
+      if (t < flen) w[fo + t] = wv[u] - dw;
+    }
+    t0 += step;
+    if (t0 >= flen) break;
+    load(t0);
+  }
+}
+
+int launch_update_w(const MacroArgs& m, int n_rve, const double* du, const int64_t* foff, const double* X,
+                    double* w, int use_xr, const int* skip, hipStream_t s) {
+  if (m.nF * m.nen * m.dim > kUpdateMaxProducts) return -1;
+  switch (m.nF) {
+    case 3: hipLaunchKernelGGL(k_update_w<3>, dim3(n_rve), dim3(256), 0, s, m, du, foff, X, w, use_xr, skip); break;
+    case 4: hipLaunchKernelGGL(k_update_w<4>, dim3(n_rve), dim3(256), 0, s, m, du, foff, X, w, use_xr, skip); break;
+    case 6: hipLaunchKernelGGL(k_update_w<6>, dim3(n_rve), dim3(256), 0, s, m, du, foff, X, w, use_xr, skip); break;
+    case 9: hipLaunchKernelGGL(k_update_w<9>, dim3(n_rve), dim3(256), 0, s, m, du, foff, X, w, use_xr, skip); break;
+    default: return -1;
+  }
+  return 0;
 }
 
 // Classical inner loop (Sec. 4.1): per-RVE stopping threshold

@@ -62,9 +62,11 @@ int bcr_max_bandwidth();
 // matrix is not positive definite; ws: bcr_workspace_doubles(p) doubles.
 int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* info, hipStream_t s);
 __global__ void k_axpy(int n, const double* __restrict__ x, double* __restrict__ y);
-__global__ void k_update_w(MacroArgs m, const double* __restrict__ du, const int64_t* __restrict__ foff,
-                           const double* __restrict__ X, double* __restrict__ w, int use_xr,
-                           const int* __restrict__ skip);
+// a9 update of the RVE fields (one work-group per RVE); -1 for an nF or
+// element beyond the kernel's shared product table
+constexpr int kUpdateMaxProducts = 256;
+int launch_update_w(const MacroArgs& m, int n_rve, const double* du, const int64_t* foff, const double* X,
+                    double* w, int use_xr, const int* skip, hipStream_t s);
 __global__ void k_micro_thr(int n_rve, const double* __restrict__ rnorm2, const double* __restrict__ rsize2, double tol,
                             double* __restrict__ thr2);
 __global__ void k_count_above(int n_rve, const double* __restrict__ rnorm2,

@@ -400,6 +400,13 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     kvI[t] = static_cast<TI>(kv64[t]);
   }
   const double* KwF = a.KwF64;   // [8][NF], uniform
+  // assembly-only instantiation: the K_wF table read here, ahead of the first
+  // barrier, so that its uniform reads are scalar loads held in SGPRs
+  double kwf0[NRHS == 0 ? 8 * NF : 1];
+  if constexpr (NRHS == 0) {
+#pragma unroll
+    for (int t = 0; t < 8 * NF; ++t) kwf0[t] = KwF[t];
+  }
   TI mcI[10];
 #pragma unroll
   for (int t = 0; t < 10; ++t) mcI[t] = EVEN ? static_cast<TI>(a.modes64[t]) : TI(0);
@@ -443,6 +450,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   const double* par = a.params + static_cast<size_t>(b) * 4;
   const double mu0 = par[1], mu1 = par[3];
   const uint8_t* ph = a.phase + a.phase_off[b];
+  const int64_t fo = a.foff[b];
   double ssum = 0.0;
   // every load of the thread in flight at once, then the LDS writes (a loop
   // that waits for each load before the next would serialise the latencies)
@@ -453,6 +461,19 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     const int e = tid + q * WG;
     phv[q] = e < NN ? ph[e] : uint8_t(0);
   }
+  // assembly-only instantiation: the field w_b is loaded together with the
+  // phase ids (one 16-byte load per node; fields start at even offsets) and
+  // staged behind the same barrier
+  constexpr bool PRE_W = NRHS == 0;
+  const bool pre_w = PRE_W && (a.flags & RVE_ASSEMBLE);
+  double2 wpre[PRE_W ? PE : 1];
+  if constexpr (PRE_W) {
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int n = tid + q * WG;
+      if (pre_w && n < NN) wpre[q] = reinterpret_cast<const double2*>(a.w + fo)[n];
+    }
+  }
 #pragma unroll
   for (int q = 0; q < PE; ++q) {
     const int e = tid + q * WG;
@@ -460,8 +481,18 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     const double s = phv[q] ? mu1 : mu0;
     const int i = e % N1, j = e / N1;
     put_halo<N1, N2>(s_sc, i, j, s);
-    put_halo<N1, N2>(s_sc32, i, j, static_cast<float>(s));
+    if constexpr (sizeof(TI) == 4) put_halo<N1, N2>(s_sc32, i, j, static_cast<float>(s));
     ssum += s;
+  }
+  if constexpr (PRE_W) {
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int n = tid + q * WG;
+      if (!pre_w || n >= NN) continue;
+      const int i = n % N1, j = n / N1;
+      put_halo<N1, N2>(s_st, i, j, wpre[q].x);
+      put_halo<N1, N2>(s_st + P::PN, i, j, wpre[q].y);
+    }
   }
   __syncthreads();
   const double* eb = s_sc + base;
@@ -469,7 +500,6 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   if constexpr (sizeof(TI) == 4) ebI = reinterpret_cast<const TI*>(s_sc32 + base);
   else ebI = reinterpret_cast<const TI*>(s_sc + base);
 
-  const int64_t fo = a.foff[b];
   constexpr int64_t flen = 2 * NN;
   double* Xb = a.X + fo * (NF + 1);
   const double V = a.volume;
@@ -478,61 +508,54 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   for (int j = 0; j < NF; ++j) eps[j] = a.macro[static_cast<size_t>(b) * NF + j];
 
   auto stage = [&](const double* src) {   // periodic field -> padded FP64 staging
-    if constexpr (NRHS == 0) {
-      // assembly only: one 16-byte load per node (fields start at even
-      // offsets), all in flight before the LDS writes.  The solve
-      // instantiations keep the plain loop, whose registers do not add to
-      // the PCG's.
-      double2 v[PE];
-#pragma unroll
-      for (int q = 0; q < PE; ++q) {
-        const int n = tid + q * WG;
-        if (n < NN) v[q] = reinterpret_cast<const double2*>(src)[n];
-      }
-#pragma unroll
-      for (int q = 0; q < PE; ++q) {
-        const int n = tid + q * WG;
-        if (n >= NN) continue;
-        const int i = n % N1, j = n / N1;
-        put_halo<N1, N2>(s_st, i, j, v[q].x);
-        put_halo<N1, N2>(s_st + P::PN, i, j, v[q].y);
-      }
-    } else {
-      for (int n = tid; n < NN; n += WG) {
-        const int i = n % N1, j = n / N1;
-        put_halo<N1, N2>(s_st, i, j, src[2 * n]);
-        put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
-      }
+    // (the solve instantiations keep the plain loop, whose registers do not
+    // add to the PCG's; the assembly-only one staged w_b with the phase ids)
+    for (int n = tid; n < NN; n += WG) {
+      const int i = n % N1, j = n / N1;
+      put_halo<N1, N2>(s_st, i, j, src[2 * n]);
+      put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
     }
   };
 
   // ---- a3: residual and stress integral at (eps_b, w_b) ------------------
   double Pint[NF];
-  if (a.flags & RVE_ASSEMBLE) {
-    stage(a.w + fo);
-    __syncthreads();
+  auto bf_at = [&](int di, int dj, int d, int j) {
+    if constexpr (NRHS == 0) return bF_entry<N1, N2>(eb, kwf0, di, dj, d, j);
+    else return bF_entry<N1, N2>(eb, KwF, di, dj, d, j);
+  };
+  // (only the assembly-only instantiation assembles: the host never sends
+  // RVE_ASSEMBLE with right-hand sides)
+  if (pre_w) {
+    if constexpr (!PRE_W) {
+      stage(a.w + fo);
+      __syncthreads();
+    }
     double y[4][2];
     #pragma unroll
     for (int k = 0; k < 4; ++k) mv_node64<N1, N2>(s_st + base, eb, kv64, k & 1, k >> 1, y[k]);
     double red[5] = {0.0, 0.0, 0.0, 0.0, ssum};
+    // no lane-dependent branch surrounds the K_wF reads: nodes the thread
+    // does not hold are masked by selects
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (!exists[k]) continue;
       const int di = k & 1, dj = k >> 1;
+      double rv2[2];
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
-        double rv = 0.0;
-        if (dof[k]) {
-          rv = y[k][d];
+        double bf[NF];
 #pragma unroll
-          for (int j = 0; j < NF; ++j) rv += bF_entry<N1, N2>(eb, KwF, di, dj, d, j) * eps[j];
-        }
-        a.r[fo + 2 * node_of(k) + d] = rv;
-        red[0] += rv * rv;
+        for (int j = 0; j < NF; ++j) bf[j] = bf_at(di, dj, d, j);
+        double rv = y[k][d];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) rv += bf[j] * eps[j];
+        rv = dof[k] ? rv : 0.0;
+        rv2[d] = rv;
         const double wv = s_st[d * P::PN + pidx[k]];
+        red[0] += exists[k] ? rv * rv : 0.0;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) red[1 + j] += bF_entry<N1, N2>(eb, KwF, di, dj, d, j) * wv;
+        for (int j = 0; j < NF; ++j) red[1 + j] += exists[k] ? bf[j] * wv : 0.0;
       }
+      if (exists[k]) *reinterpret_cast<double2*>(a.r + fo + 2 * node_of(k)) = make_double2(rv2[0], rv2[1]);
     }
     wg_sum<5, NW, RED_NV>(red, s_red, parity);
     ssum = red[4];
@@ -1666,6 +1689,7 @@ static int launch_mr(const Lin2DArgs& a, int n_launch, hipStream_t s) {
 template <int N1, int N2>
 static int launch_n(const Lin2DArgs& a, int n_launch, int precision, int nrhs, hipStream_t s) {
   if (nrhs == 0) return launch_t<double, 0, N1, N2>(a, n_launch, s);   // assemble only (FP64)
+  if (a.flags & RVE_ASSEMBLE) return set_error("assembly runs without right-hand sides"), FE2_EINVAL;
   if constexpr (lin2d_dense_size(N1, N2)) {
     if (a.flags & RVE_DENSE) {
       if (precision != FE2_PREC_FP32_IR) return set_error("the dense solve factors in FP32"), FE2_ENOTSUP;
