@@ -294,13 +294,19 @@ __device__ __forceinline__ double elem_scale(const double* __restrict__ eb, int 
 }
 
 // Column j of K_wF at owned node (di, dj), component d; KwF is the uniform
-// [8][NF] element table in global memory (read through scalar loads).
+// [8][NF] element table in global memory, read-only for the whole launch.
+// It is read through the constant address space, so that its reads are
+// scalar loads into SGPRs wherever they sit (a plain global pointer read
+// after a barrier or a store becomes a vector load, serialised through
+// whatever VGPRs are left in the register-bound solve instantiations).
+using const_f64 = __attribute__((address_space(4))) const double;
 template <int N1, int N2>
 __device__ __forceinline__ double bF_entry(const double* __restrict__ eb, const double* __restrict__ KwF,
                                            int di, int dj, int d, int j) {
+  const const_f64* K = (const const_f64*)KwF;
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) s += elem_scale<N1, N2>(eb, di, dj, q) * KwF[(2 * elem_cc(q) + d) * NF + j];
+  for (int q = 0; q < 4; ++q) s += elem_scale<N1, N2>(eb, di, dj, q) * K[(2 * elem_cc(q) + d) * NF + j];
   return s;
 }
 
@@ -400,13 +406,6 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     kvI[t] = static_cast<TI>(kv64[t]);
   }
   const double* KwF = a.KwF64;   // [8][NF], uniform
-  // assembly-only instantiation: the K_wF table read here, ahead of the first
-  // barrier, so that its uniform reads are scalar loads held in SGPRs
-  double kwf0[NRHS == 0 ? 8 * NF : 1];
-  if constexpr (NRHS == 0) {
-#pragma unroll
-    for (int t = 0; t < 8 * NF; ++t) kwf0[t] = KwF[t];
-  }
   TI mcI[10];
 #pragma unroll
   for (int t = 0; t < 10; ++t) mcI[t] = EVEN ? static_cast<TI>(a.modes64[t]) : TI(0);
@@ -519,10 +518,6 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 
   // ---- a3: residual and stress integral at (eps_b, w_b) ------------------
   double Pint[NF];
-  auto bf_at = [&](int di, int dj, int d, int j) {
-    if constexpr (NRHS == 0) return bF_entry<N1, N2>(eb, kwf0, di, dj, d, j);
-    else return bF_entry<N1, N2>(eb, KwF, di, dj, d, j);
-  };
   // (only the assembly-only instantiation assembles: the host never sends
   // RVE_ASSEMBLE with right-hand sides)
   if (pre_w) {
@@ -544,7 +539,7 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       for (int d = 0; d < 2; ++d) {
         double bf[NF];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) bf[j] = bf_at(di, dj, d, j);
+        for (int j = 0; j < NF; ++j) bf[j] = bF_entry<N1, N2>(eb, KwF, di, dj, d, j);
         double rv = y[k][d];
 #pragma unroll
         for (int j = 0; j < NF; ++j) rv += bf[j] * eps[j];
