@@ -507,12 +507,27 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   for (int j = 0; j < NF; ++j) eps[j] = a.macro[static_cast<size_t>(b) * NF + j];
 
   auto stage = [&](const double* src) {   // periodic field -> padded FP64 staging
-    // (the solve instantiations keep the plain loop, whose registers do not
-    // add to the PCG's; the assembly-only one staged w_b with the phase ids)
-    for (int n = tid; n < NN; n += WG) {
-      const int i = n % N1, j = n / N1;
-      put_halo<N1, N2>(s_st, i, j, src[2 * n]);
-      put_halo<N1, N2>(s_st + P::PN, i, j, src[2 * n + 1]);
+    // one 16-byte load per node (columns start at even offsets); above 32^2
+    // two nodes' loads are in flight before their LDS writes (a
+    // load-then-write loop waits out an L2 round trip per load; at 32^2 the
+    // second load's registers cost more spills than the wait saves).  The
+    // assembly-only instantiation staged w_b with the phase ids.
+    constexpr int SU = N1 * N2 > 1024 ? 2 : 1;
+    for (int n0 = tid; n0 < NN; n0 += SU * WG) {
+      double2 v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int n = n0 + u * WG;
+        if (n < NN) v[u] = reinterpret_cast<const double2*>(src)[n];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int n = n0 + u * WG;
+        if (n >= NN) continue;
+        const int i = n % N1, j = n / N1;
+        put_halo<N1, N2>(s_st, i, j, v[u].x);
+        put_halo<N1, N2>(s_st + P::PN, i, j, v[u].y);
+      }
     }
   };
 
@@ -645,19 +660,36 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
     double g[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) g[i] = 0.0;
+    double xj[4][2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (!dof[k]) continue;
-      const int di = k & 1, dj = k >> 1;
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const double xj = xz ? 0.0 : s_st[d * P::PN + pidx[k]];
+      for (int d = 0; d < 2; ++d) xj[k][d] = (xz || !dof[k]) ? 0.0 : s_st[d * P::PN + pidx[k]];
+    // one column i at a time: its four own-node (x, y) pairs are loaded
+    // together (16-byte loads, no lane-dependent branch around them; a
+    // node the thread does not hold reads node 0), then summed in the order
+    // k, d as for column jc itself
 #pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          if (jc < NF && i > jc) continue;   // from the mirror, when column i is accepted
-          const double xi = (i == jc) ? xj : Xb[i * flen + 2 * node_of(k) + d];
-          g[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj + xi * rj[k][d];
+    for (int i = 0; i < NF; ++i) {
+      if (jc < NF && i > jc) continue;   // from the mirror, when column i is accepted
+      double xi[4][2];
+      if (i == jc) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xi[k][0] = xj[k][0], xi[k][1] = xj[k][1];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 v = *reinterpret_cast<const double2*>(Xb + i * flen + 2 * (exists[k] ? node_of(k) : 0));
+          xi[k][0] = v.x;
+          xi[k][1] = v.y;
         }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!dof[k]) continue;
+        const int di = k & 1, dj = k >> 1;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) g[i] += bF_entry<N1, N2>(eb, KwF, di, dj, d, i) * xj[k][d] + xi[k][d] * rj[k][d];
       }
     }
     wg_sum<NF, NW, RED_NV>(g, s_red, parity);
