@@ -456,9 +456,9 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
   constexpr int PE = (NN + WG - 1) / WG;   // elements (and nodes) per thread
   uint8_t phv[PE];
 #pragma unroll
-  for (int q = 0; q < PE; ++q) {
+  for (int q = 0; q < PE; ++q) {   // (clamped index: no branch around the loads)
     const int e = tid + q * WG;
-    phv[q] = e < NN ? ph[e] : uint8_t(0);
+    phv[q] = ph[e < NN ? e : NN - 1];
   }
   // assembly-only instantiation: the field w_b is loaded together with the
   // phase ids (one 16-byte load per node; fields start at even offsets) and
@@ -1328,9 +1328,9 @@ __global__ void __launch_bounds__(WG, 2) k_lin2d_mr(const Lin2DArgs a) {
   constexpr int PE = (NN + WG - 1) / WG;
   uint8_t phv[PE];
 #pragma unroll
-  for (int q = 0; q < PE; ++q) {
+  for (int q = 0; q < PE; ++q) {   // (clamped index: no branch around the loads)
     const int e = tid + q * WG;
-    phv[q] = e < NN ? ph[e] : uint8_t(0);
+    phv[q] = ph[e < NN ? e : NN - 1];
   }
 #pragma unroll
   for (int q = 0; q < PE; ++q) {
