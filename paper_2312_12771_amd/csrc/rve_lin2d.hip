@@ -666,9 +666,11 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
 #pragma unroll
       for (int d = 0; d < 2; ++d) xj[k][d] = (xz || !dof[k]) ? 0.0 : s_st[d * P::PN + pidx[k]];
     // one column i at a time: its four own-node (x, y) pairs are loaded
-    // together (16-byte loads, no lane-dependent branch around them; a
-    // node the thread does not hold reads node 0), then summed in the order
-    // k, d as for column jc itself
+    // together (16-byte loads, no lane-dependent branch around them, at
+    // constant offsets from one address for even sizes, where every
+    // thread's block lies inside the RVE; for odd sizes a node the thread
+    // does not hold reads node 0), then summed in the order k, d as for
+    // column jc itself
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       if (jc < NF && i > jc) continue;   // from the mirror, when column i is accepted
@@ -679,7 +681,8 @@ __global__ void __launch_bounds__(WG, (kLin2dMinBlocks<TI, FFT, WG>)) k_lin2d(co
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const double2 v = *reinterpret_cast<const double2*>(Xb + i * flen + 2 * (exists[k] ? node_of(k) : 0));
+          const double2 v =
+              *reinterpret_cast<const double2*>(Xb + i * flen + 2 * ((EVEN || exists[k]) ? node_of(k) : 0));
           xi[k][0] = v.x;
           xi[k][1] = v.y;
         }
