@@ -6,9 +6,10 @@
   with the residual driven to 1e-13, and the spectral-RVE count follows
   the choices.  Refusals: a variant the class cannot run, a resolution with
   no class, an unknown solver.
-* Tuner: on a small uneven batch it times every variant of every class,
-  keeps the fastest, and its table applied to a fresh handle gives the
-  same C-bar (within the solve tolerance) as the default choice.
+* Tuner: on a small uneven batch it times every variant of every class and
+  keeps the fastest (the default unless another is faster by over 1 %);
+  its table applied to a fresh handle gives the same C-bar (within the
+  solve tolerance) as the default choice.
 """
 import numpy as np
 import pytest
@@ -83,7 +84,11 @@ def test_tuner_table_applies(fe2):
           table["rve_solve_ms_default"], table["rve_solve_ms_tuned"])
     assert {tuple(c["res"]) for c in table["classes"]} == {(16, 16), (32, 32), (48, 48)}
     for c in table["classes"]:
-        assert c["choice"] in c["ms"] and c["ms"][c["choice"]] == min(c["ms"].values())
+        best = min(c["ms"].values())
+        assert c["choice"] in c["ms"]
+        # the fastest, or the default when the fastest is within the margin
+        assert c["ms"][c["choice"]] == best or (c["choice"] == tune.default_of(c["ms"]) and
+                                               best > (1.0 - tune.MARGIN) * c["ms"][c["choice"]])
         assert "dense" not in c["ms"]                         # none of these sizes runs it
         assert "fft_mc" in c["ms"] and "jacobi" in c["ms"]
     u = 1e-3 * np.random.default_rng(5).standard_normal(p.n_dofs)
