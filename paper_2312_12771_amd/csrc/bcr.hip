@@ -102,8 +102,9 @@ __global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __re
 // -- potrf: one work-group per eliminated block -------------------------------
 // Right-looking Cholesky in 16-column panels.  When the lower triangle of the
 // block fits in LDS (tile-packed 16x16 column-major tiles) it is factored
-// there and written back once; larger blocks are factored in place in global
-// memory.  Wave 0 factors the diagonal tile and inverts it (lane r holds row
+// there and written back once; for larger blocks the first steps run in
+// place in global memory until the trailing triangle fits, which is then
+// factored in LDS.  Wave 0 factors the diagonal tile and inverts it (lane r holds row
 // r; wave-synchronous exchange through LDS); all threads form the panel below
 // with the inverse and apply the trailing update in 4x4 register tiles.
 constexpr int PO_WG = 1024;
@@ -120,8 +121,12 @@ struct GlobalTiles {
 constexpr int LDS_TILE = BT * (BT + 1);
 struct LdsTiles {
   double* base;
+  int o = 0;   // the tiles held: o <= tk <= ti (the trailing triangle from step o on)
   static constexpr int ld = BT + 1;
-  __device__ double* tile(int ti, int tk) const { return base + (ti * (ti + 1) / 2 + tk) * LDS_TILE; }
+  __device__ double* tile(int ti, int tk) const {
+    const int a = ti - o, c = tk - o;
+    return base + (a * (a + 1) / 2 + c) * LDS_TILE;
+  }
 };
 
 __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= q
@@ -133,11 +138,12 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
 
 // Returns false when a pivot is not positive (info set, every thread returns).
 template <class M>
-__device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0, double* s_panel, double* s_inv,
-                           int* s_fail, int* __restrict__ info) {
+__device__ __forceinline__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int p_begin, int p_end,
+                                           int col0, double* s_panel, double* s_inv, int* s_fail,
+                                           int* __restrict__ info) {
   const int tid = threadIdx.x;
   const int ld = A.ld;
-  for (int p = 0; p < nt; ++p) {
+  for (int p = p_begin; p < p_end; ++p) {
     if (tid < 64) {
       // The diagonal tile in the registers of one wave: lane l holds column
       // s = l % 16, rows 4 g .. 4 g + 3 (g = l / 16), read from the lower
@@ -251,13 +257,17 @@ __device__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int col0
 
 // LDS bytes of the two variants
 __host__ __device__ constexpr size_t potrf_lds_global(int bs) { return static_cast<size_t>(bs) * (BT + 1) * 8; }
-__host__ __device__ constexpr size_t potrf_lds_resident(int bs) {
-  return potrf_lds_global(bs) + static_cast<size_t>((bs / BT) * (bs / BT + 1) / 2) * LDS_TILE * 8;
+// with the trailing triangle of m tile rows in LDS
+__host__ __device__ constexpr size_t potrf_lds_resident(int bs, int m) {
+  return potrf_lds_global(bs) + static_cast<size_t>(m * (m + 1) / 2) * LDS_TILE * 8;
 }
 
+// RESIDENT: steps p < p0 run on the tiles in global memory, then the
+// trailing triangle (tiles p0 <= tk <= ti) is loaded into LDS, factored there
+// and written back once (p0 = 0 when the whole lower triangle fits).
 template <bool RESIDENT>
 __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, double* __restrict__ invL, int bs,
-                                                     int first, int stride, int* __restrict__ info) {
+                                                     int first, int stride, int p0, int* __restrict__ info) {
   extern __shared__ __align__(16) double smem[];
   __shared__ double s_inv[BT * BT];   // column-major
   __shared__ int s_fail;
@@ -269,8 +279,14 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   double* s_panel = smem;   // [bs][BT + 1] (padded rows)
   if (tid == 0) s_fail = 0;
   if constexpr (RESIDENT) {
+    if (p0 > 0) {
+      __syncthreads();
+      const GlobalTiles G{Dj, bs};
+      if (!potrf_core(G, Ij, nt, 0, p0, j * bs, s_panel, s_inv, &s_fail, info)) return;
+    }
     double* s_tiles = smem + bs * (BT + 1);
-    const int ntri = nt * (nt + 1) / 2;
+    const int m = nt - p0;
+    const int ntri = m * (m + 1) / 2;
     // one element of a tile per thread, PO_WG / 256 tiles per pass
     constexpr int TPP = PO_WG / (BT * BT);
     const int el = tid % (BT * BT), c = el >> 4, r = el & 15;
@@ -284,7 +300,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
         const int q = q0 + u * TPP;
         if (q < ntri) {
           const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
-          v[u] = Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r];
+          v[u] = Dj[static_cast<size_t>((tk + p0) * BT + c) * bs + (ti + p0) * BT + r];
         }
       }
 #pragma unroll
@@ -294,17 +310,17 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
       }
     }
     __syncthreads();
-    const LdsTiles A{s_tiles};
-    if (!potrf_core(A, Ij, nt, j * bs, s_panel, s_inv, &s_fail, info)) return;
+    const LdsTiles A{s_tiles, p0};
+    if (!potrf_core(A, Ij, nt, p0, nt, j * bs, s_panel, s_inv, &s_fail, info)) return;
 #pragma unroll 2
     for (int q = tid / (BT * BT); q < ntri; q += TPP) {
       const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
-      Dj[static_cast<size_t>(tk * BT + c) * bs + ti * BT + r] = s_tiles[q * LDS_TILE + c * (BT + 1) + r];
+      Dj[static_cast<size_t>((tk + p0) * BT + c) * bs + (ti + p0) * BT + r] = s_tiles[q * LDS_TILE + c * (BT + 1) + r];
     }
   } else {
     __syncthreads();
     const GlobalTiles A{Dj, bs};
-    potrf_core(A, Ij, nt, j * bs, s_panel, s_inv, &s_fail, info);
+    potrf_core(A, Ij, nt, 0, nt, j * bs, s_panel, s_inv, &s_fail, info);
   }
 }
 
@@ -592,9 +608,14 @@ int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* 
   const int np = nb * bs;
   hipLaunchKernelGGL(k_bcr_copy_in, dim3((np + 255) / 256), dim3(256), 0, s, y, p.n, np, F);
   const size_t lds_tr = static_cast<size_t>(bs) * BT * sizeof(double);
-  // factor in LDS when the block's lower triangle fits next to the panel
-  const bool resident = potrf_lds_resident(bs) + 8 * 1024 <= 160 * 1024;
-  const size_t lds_po = resident ? potrf_lds_resident(bs) : potrf_lds_global(bs);
+  // factor in LDS the trailing triangle of as many tile rows as fit next to
+  // the panel (all nt when the block's whole lower triangle does; the steps
+  // before it run on the tiles in global memory)
+  int m_lds = nt;
+  while (m_lds > 0 && potrf_lds_resident(bs, m_lds) + 8 * 1024 > 160 * 1024) --m_lds;
+  const bool resident = m_lds >= 2;
+  const int p0 = resident ? nt - m_lds : 0;
+  const size_t lds_po = resident ? potrf_lds_resident(bs, m_lds) : potrf_lds_global(bs);
   auto potrf = resident ? k_bcr_potrf<true> : k_bcr_potrf<false>;
   if (lds_po + 8 * 1024 > 64 * 1024)
     FE2_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(potrf), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -608,14 +629,14 @@ int bcr_solve(const BcrPlan& p, double* ws, const double* band, double* y, int* 
     const int nact = (nb - 1) / h + 1;
     if (nact == 1) break;
     const int nodd = nact / 2, neven = (nact + 1) / 2;
-    hipLaunchKernelGGL(potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, info);
+    hipLaunchKernelGGL(potrf, dim3(nodd), dim3(PO_WG), lds_po, s, D, IL, bs, h, 2 * h, p0, info);
     hipLaunchKernelGGL(k_bcr_trsm, dim3(3 * nt + 1, nodd), dim3(TR_WG), lds_tr, s, D, IL, C, G, LI, F, bs, nb, h,
                        2 * h, h, 0);
     hipLaunchKernelGGL(k_bcr_schur, dim3(ntri + nt * nt + nt, neven), dim3(SC_WG), 0, s, G, D, C, F, bs, nb, h);
     h *= 2;
   }
   const int htop = h;
-  hipLaunchKernelGGL(potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, info);
+  hipLaunchKernelGGL(potrf, dim3(1), dim3(PO_WG), lds_po, s, D, IL, bs, 0, 0, p0, info);
   hipLaunchKernelGGL(k_bcr_trsm, dim3(nt + 1, 1), dim3(TR_WG), lds_tr, s, D, IL, C, G, LI, F, bs, nb, 0, 0, 0, 1);
   hipLaunchKernelGGL(k_bcr_back_t, dim3(nt, 1), dim3(BK_WG), 0, s, G, F, T, bs, nb, 0, 0, 0, 1);
   hipLaunchKernelGGL(k_bcr_back_x, dim3(nt, 1), dim3(BK_WG), 0, s, LI, T, F, bs, 0, 0);
