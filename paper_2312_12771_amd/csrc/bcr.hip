@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
 // right-hand side (one column; the other 15 stay zero); a block with no
 // neighbours (the last one left) runs only the last nt + 1.
 constexpr int TR_WG = 64;
-constexpr int TR_UNROLL = 4;   // MFMAs whose L operand loads are issued together
+constexpr int TR_UNROLL = 16;   // MFMAs whose L operand loads are issued together (four tiles)
 
 __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D, const double* __restrict__ invL,
                                                     const double* __restrict__ C, double* __restrict__ G,
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
 // product with a single column: the other 15 columns of the B operand are
 // zero.
 constexpr int SC_WG = 64;
-constexpr int SC_UNROLL = 4;   // MFMAs whose operand loads are issued together
+constexpr int SC_UNROLL = 8;   // MFMAs whose operand loads are issued together
 
 __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ G, double* __restrict__ D,
                                                      double* __restrict__ C, double* __restrict__ F, int bs, int nb,
