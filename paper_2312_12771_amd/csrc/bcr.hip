@@ -459,44 +459,72 @@ __global__ void __launch_bounds__(SC_WG) k_bcr_schur(const double* __restrict__ 
     ta = q - ntri - nt * nt;
     tb = 0;
   }
-  // contributions: (A columns, B columns or vector)
-  const double* Ap[2];
-  const double* Bp[2];
+  // contributions: (A columns, B columns or vector), at most two
+  const double *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
   int ncon = 0;
   if (has_l) {   // G_r(i-h) on the left
     const double* Gl = G + static_cast<size_t>(jl) * 2 * per;
-    Ap[ncon] = Gl + per + static_cast<size_t>(ta) * BT * bs;
-    Bp[ncon] = kind == 0 ? Gl + per + static_cast<size_t>(tb) * BT * bs
-             : kind == 1 ? Gl + static_cast<size_t>(tb) * BT * bs
-                         : F + static_cast<size_t>(jl) * bs;
-    ++ncon;
+    A0 = Gl + per + static_cast<size_t>(ta) * BT * bs;
+    B0 = kind == 0 ? Gl + per + static_cast<size_t>(tb) * BT * bs
+       : kind == 1 ? Gl + static_cast<size_t>(tb) * BT * bs
+                   : F + static_cast<size_t>(jl) * bs;
+    ncon = 1;
   }
   if (has_r && kind != 1) {   // G_l(i+h)
     const double* Gr = G + static_cast<size_t>(jr) * 2 * per;
-    Ap[ncon] = Gr + static_cast<size_t>(ta) * BT * bs;
-    Bp[ncon] = kind == 0 ? Gr + static_cast<size_t>(tb) * BT * bs : F + static_cast<size_t>(jr) * bs;
+    const double* a = Gr + static_cast<size_t>(ta) * BT * bs;
+    const double* bb = kind == 0 ? Gr + static_cast<size_t>(tb) * BT * bs : F + static_cast<size_t>(jr) * bs;
+    if (ncon == 0) {
+      A0 = a;
+      B0 = bb;
+    } else {
+      A1 = a;
+      B1 = bb;
+    }
     ++ncon;
   }
   if (ncon == 0) return;
   const int ln = threadIdx.x, lr = ln & 15, lk = ln >> 4;
   const bool vec = kind == 2;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int cn = 0; cn < ncon; ++cn) {
-    // lane (lr, lk) reads column lr of the A block and column lr of the B
-    // block (entry lk + k0 of each); a vector B is read by the lr = 0 lanes
-    const double* pa = Ap[cn] + static_cast<size_t>(lr) * bs + lk;
-    const double* pb = vec ? Bp[cn] + lk : Bp[cn] + static_cast<size_t>(lr) * bs + lk;
-    for (int k0 = 0; k0 < bs; k0 += 4 * SC_UNROLL) {
-      double xa[SC_UNROLL], xb[SC_UNROLL];
+  // Within each 16-wide slab of the summation index, lane (lr, lk) supplies
+  // entries 4 lk .. 4 lk + 3 of column lr of the A block and of the B block,
+  // one per MFMA of the slab: the four MFMAs together still contract the
+  // slab's 16 entries once, and each lane reads its four as one 32-byte
+  // load (four lanes cover a 128-byte line) instead of four strided ones.
+  // bs is a multiple of 16.  A vector B is read by the lr = 0 lanes.
+  constexpr int SU = SC_UNROLL / 4;   // slabs per batch of loads
 #pragma unroll
-      for (int u = 0; u < SC_UNROLL; ++u) {
-        const int k = k0 + 4 * u;
+  for (int cn = 0; cn < 2; ++cn) {
+    if (cn >= ncon) break;
+    const double* Aq = cn == 0 ? A0 : A1;
+    const double* Bq = cn == 0 ? B0 : B1;
+    const double* pa = Aq + static_cast<size_t>(lr) * bs + 4 * lk;
+    const double* pb = vec ? Bq + 4 * lk : Bq + static_cast<size_t>(lr) * bs + 4 * lk;
+    const bool bload = !vec || lr == 0;
+    for (int k0 = 0; k0 < bs; k0 += BT * SU) {
+      double2 xa[SU][2], xb[SU][2];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        // a slab past the end reads slab 0 (a valid address) and is zeroed
+        const int k = k0 + BT * u;
         const bool in = k < bs;
-        xa[u] = in ? pa[k] : 0.0;
-        xb[u] = (in && (!vec || lr == 0)) ? pb[k] : 0.0;
+        const int kc = in ? k : 0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const double2 va = reinterpret_cast<const double2*>(pa + kc)[hh];
+          const double2 vb = reinterpret_cast<const double2*>(pb + kc)[hh];
+          xa[u][hh] = make_double2(in ? va.x : 0.0, in ? va.y : 0.0);
+          xb[u][hh] = make_double2(in && bload ? vb.x : 0.0, in && bload ? vb.y : 0.0);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < SC_UNROLL; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
+      for (int u = 0; u < SU; ++u) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][0].x, xb[u][0].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][0].y, xb[u][0].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][1].x, xb[u][1].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][1].y, xb[u][1].y, acc, 0, 0, 0);
+      }
     }
   }
 #pragma unroll
