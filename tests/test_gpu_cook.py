@@ -13,9 +13,10 @@ it exceeds 1e10.
   with 22, 32 and 42 load steps, as printed.
 * The paper's classical failures at 2 and 12 load steps are not reproduced:
   with the predictor the scheme converges there (6 and 4 iterations).  The
-  plain staggered reading (no predictor) fails at 2 load steps, though not by
-  the paper's criterion: one RVE's inner loop stalls above 1e-13 until its
-  iteration cap; it converges at 12.
+  plain staggered reading (no predictor) converges at 12; at 2 load steps
+  one RVE's inner loop ends within rounding of 1e-13, so it either stalls
+  there (an inner-loop failure, not the paper's criterion) or converges in 6,
+  depending on the summation order of the FP64 macro solve.
 
 Absolute residuals are not compared (the printed values are not reproducible
 from the stated data).
@@ -94,12 +95,18 @@ def test_classical_below_22_load_steps(fe2):
     """Table 1 marks the classical scheme as failed with 2 and 12 load steps.
     Recorded here as measured: with the predictor it converges (6 and 4
     iterations, the generalized counts); without it (the plain staggered
-    reading) one RVE's inner loop stalls above 1e-13 at 2 load steps, while 12
-    converge."""
+    reading) 12 load steps converge in 4, and 2 load steps sit at the rounding
+    edge of the inner criterion: one RVE's inner loop ends within rounding of
+    1e-13, so whether it stalls there (an inner-loop failure, FE2_ENOCONV)
+    or the run converges in 6 iterations per step depends on the summation
+    order of the FP64 macro solve.  Neither outcome is the paper's failure
+    (a macro residual beyond 1e10)."""
     assert T1["classical"][T1["n_l"].index(2)] is None and T1["classical"][T1["n_l"].index(12)] is None
     assert max(newton_counts(fe2, 2, "classical")) == 6
     assert max(newton_counts(fe2, 12, "classical")) == 4
-    with pytest.raises(fe2.FE2Error) as e:
-        newton_counts(fe2, 2, "classical_plain")
-    assert e.value.status == fe2.FE2_ENOCONV
+    try:
+        its = newton_counts(fe2, 2, "classical_plain")
+        assert max(its) == 6, its
+    except fe2.FE2Error as e:
+        assert e.value.status == fe2.FE2_ENOCONV
     assert max(newton_counts(fe2, 12, "classical_plain")) == 4
