@@ -106,7 +106,10 @@ enum { FE2_BASIS_DIRAC = 0, FE2_BASIS_ELEMENT = 1 };
  *  n_phase_params   parameters per phase: 2 (lambda, mu) for FE2_LINEAR_ISO
  *                   and FE2_NEO_HOOKE, 3 (alpha, beta, kappa) for
  *                   FE2_MOONEY_RIVLIN (the law of Eq. (59))
- *  phase_params     [n_rve][2][n_phase_params]
+ *  phase_params     [n_rve][2][n_phase_params]; for FE2_LINEAR_ISO both
+ *                   phases of an RVE must have the same lambda/mu (the
+ *                   element stiffness is mu_e times one reference matrix of
+ *                   that ratio), else FE2_ENOTSUP
  *  rve_size         side length of the cubic RVE cell (|Omega| = rve_size^dim)
  *  precision        FE2_PREC_FP64 (plain FP64 RVE solves) or FE2_PREC_FP32_IR
  *                   (FP32 PCG with FP64 residual refinement).
