@@ -4,7 +4,9 @@ the C ABI, against a dense FP64 solve of the same matrix.
 Block cyclic reduction cuts the matrix into blocks of the bandwidth rounded up
 to 16; the cases cover one block, a ragged last block, block counts that are
 not powers of two, bandwidths below, at and just above a tile boundary, the
-2D macro tangent's size (8450 unknowns, half bandwidth 133) with a
+three factor placements (a block's lower triangle in LDS; its first steps in
+global memory and the trailing triangle in LDS; all of it in global memory),
+the 2D macro tangent's size (8450 unknowns, half bandwidth 133) with a
 grid-Laplacian-like matrix, and the non-positive-definite report.
 """
 import numpy as np
@@ -49,8 +51,11 @@ def solve_gpu(fe2, n, bw, band, b, allow=False):
     return st, piv, x.cpu().numpy(), bd.cpu().numpy()
 
 
+# (2187, 275): blocks of 18 tile rows, factored first in global memory and
+# then with the trailing triangle in LDS; (2300, 1100): blocks too wide for
+# any tile of the triangle next to the panel, factored in global memory
 @pytest.mark.parametrize("n,bw", [(1, 0), (7, 0), (16, 15), (17, 3), (100, 7), (301, 16), (513, 17),
-                                  (1000, 33), (2187, 275)])
+                                  (1000, 33), (2187, 275), (2300, 1100)])
 def test_band_solve_matches_dense(fe2, n, bw):
     A = random_spd_band(n, bw, seed=n + bw)
     b = np.random.default_rng(1).standard_normal(n)
