@@ -568,7 +568,7 @@ def main():
                     help="ignore the saved tuning table (every class runs --solver)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(the RVE batch would shard by macro elements across GPUs)", file=sys.stderr)
         sys.exit(2)
 
