@@ -743,13 +743,18 @@ __global__ void __launch_bounds__(WG, kFinMinBlocks<TI>) k_fin2d(const Fin2DArgs
       g[i] = kfx[i];
       g[NF + i] = 0.0;
     }
+    // column by column: the thread's NPT (x, y) pairs of column i are read
+    // together (16-byte loads at a clamped node index, no lane-dependent
+    // branch around them), then added in node order
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      if (!node_ok(k)) continue;
-      const int n = tid + k * WG;
+    for (int i = 0; i < NF; ++i) {
+      double2 xv[NPT];
 #pragma unroll
-      for (int i = 0; i < NF; ++i)
-        g[NF + i] += Xb[i * flen + 2 * n] * res[k][0] + Xb[i * flen + 2 * n + 1] * res[k][1];
+      for (int k = 0; k < NPT; ++k)
+        xv[k] = *reinterpret_cast<const double2*>(Xb + i * flen + 2 * (node_ok(k) ? tid + k * WG : 0));
+#pragma unroll
+      for (int k = 0; k < NPT; ++k)
+        if (node_ok(k)) g[NF + i] += xv[k].x * res[k][0] + xv[k].y * res[k][1];
     }
     wg_sum<2 * NF, NW, RED_NV>(g, s_red, parity);
     if (tid == 0) {
