@@ -142,12 +142,9 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="
         from paper_2312_12771_amd import tune
         tune.apply(h, tuning, precision=precision, rve_tol=rve_tol)
     ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
-    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
-    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
-    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
 
     def step():
-        fe2.fe2_set_state(h, zu, zw, 0.0)
+        fe2.fe2_reset_state(h, 0.0)
         st, _ = fe2.fe2_newton_step(h, lam)
         assert st == fe2.FE2_OK
 
@@ -197,7 +194,7 @@ def run_form(fe2, torch, p, precision, rve_tol, steps, warmup, lam=1.0, solver="
             dense[m] = c["choice"] == "dense"
     assert int(spectral.sum()) == n_spec, (int(spectral.sum()), n_spec)
     # a full linear solve to the Newton tolerance (informational)
-    fe2.fe2_set_state(h, zu, zw, 0.0)
+    fe2.fe2_reset_state(h, 0.0)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     hist = []
@@ -290,12 +287,9 @@ def run_full(fe2, torch, p, precision, rve_tol, newton_tol, steps, warmup, solve
     iteration counts of every Newton step."""
     h = fe2.fe2_setup(p, precision=precision, solver=solver, rve_tol=rve_tol, inner_tol=1e-5, newton_tol=newton_tol)
     ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
-    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
-    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
-    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
 
     def one():
-        fe2.fe2_set_state(h, zu, zw, 0.0)
+        fe2.fe2_reset_state(h, 0.0)
         hist = []
         fe2.solve(h, p.load_factors, history=hist)
         return hist
@@ -309,7 +303,7 @@ def run_full(fe2, torch, p, precision, rve_tol, newton_tol, steps, warmup, solve
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     n = p.n_rve
-    fe2.fe2_set_state(h, zu, zw, 0.0)
+    fe2.fe2_reset_state(h, 0.0)
     fe2.fe2_set_profiling(h, True)
     it_sum, mv_sum = np.zeros(n), np.zeros(n)
     buf = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -350,12 +344,9 @@ def run_surrogate(fe2, torch, p, wl, steps, warmup):
     full = run_full(fe2, torch, p, "fp32_ir", wl["tol"]["mixed"], tol, steps, warmup)
     hs = fe2.fe2_setup(p, precision="fp32_ir", rve_tol=wl["tol"]["mixed"], newton_tol=tol, scheme="classical")
     ndof = fe2.fe2_query(hs, fe2.FE2_Q_NDOF)
-    flen = fe2.fe2_query(hs, fe2.FE2_Q_FIELD_LEN)
-    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
-    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
 
     def one():
-        fe2.fe2_set_state(hs, zu, zw, 0.0)
+        fe2.fe2_reset_state(hs, 0.0)
         return S.solve_with_surrogate(hs, sur, p.load_factors, judge_tol=2e-2, judge="last")
 
     for _ in range(warmup):

@@ -264,6 +264,14 @@ int fe2_get_state(fe2_handle h, double* u_dev, double* w_dev, void* stream);
 int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev,
                   double load_factor, void* stream);
 
+/* Return to the reference state: q - X = 0 and every fluctuation w_b = 0
+ * (the undeformed configuration of Sec. 2, where the first generalized
+ * Newton iteration starts), at load factor `load_factor`.  The same result
+ * as fe2_set_state with zero vectors, written by fill kernels on `stream`
+ * (nothing read, nothing allocated, safe to capture in a HIP graph).  The
+ * next RVE solve starts from zero. */
+int fe2_reset_state(fe2_handle h, double load_factor, void* stream);
+
 /* Intermediate results of the last assembly / condensation / step, copied to
  * caller memory:
  *   FE2_D_MACRO_GRAD  [n_rve][nF]        eps_b or F_b (a2)

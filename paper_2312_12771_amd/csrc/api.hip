@@ -1262,6 +1262,18 @@ int fe2_set_state(fe2_handle h, const double* u_dev, const double* w_dev, double
   return FE2_OK;
 }
 
+int fe2_reset_state(fe2_handle h, double load_factor, void* stream) {
+  FE2_GUARD(h);
+  h->have_solution = false;   // a new state: start the next solve from zero
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(h->ndof, 256)), dim3(256), 0, s, h->u, static_cast<size_t>(h->ndof), 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(std::min<unsigned>(4096, nblk(h->field_len, 256))), dim3(256), 0, s, h->w,
+                     static_cast<size_t>(h->field_len), 0.0);
+  FE2_HIP_CHECK(hipGetLastError());
+  h->lam = load_factor;
+  return FE2_OK;
+}
+
 int fe2_get_data(fe2_handle h, int which, double* dst, void* stream) {
   FE2_GUARD(h);
   if (!dst) return set_error("null destination"), FE2_EINVAL;

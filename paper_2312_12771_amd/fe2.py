@@ -98,6 +98,7 @@ _sig = {
     "fe2_equilibrate_rve": (C.c_int, [_vp, C.POINTER(C.c_int), _vp]),
     "fe2_get_state": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fe2_set_state": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp]),
+    "fe2_reset_state": (C.c_int, [_vp, C.c_double, _vp]),
     "fe2_get_data": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "fe2_query": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int64)]),
     "fe2_destroy": (C.c_int, [_vp]),
@@ -377,6 +378,10 @@ def fe2_get_state(h: Handle, u=None, w=None, stream=None):
 def fe2_set_state(h: Handle, u=None, w=None, load_factor: float = 0.0, stream=None):
     return _check(_lib.fe2_set_state(h.ptr, _dev_ptr(u), _dev_ptr(w), float(load_factor),
                                      _stream_ptr(stream)), "fe2_set_state")
+
+
+def fe2_reset_state(h: Handle, load_factor: float = 0.0, stream=None):
+    return _check(_lib.fe2_reset_state(h.ptr, float(load_factor), _stream_ptr(stream)), "fe2_reset_state")
 
 
 def fe2_get_data(h: Handle, which: int, dst, stream=None):

@@ -61,15 +61,11 @@ def classes_of(problem):
 def _rve_phase_ms(h, torch, lam, reps):
     """GPU time of the RVE solve phase of one Newton step from the reference
     state (fastest of reps)."""
-    ndof = fe2.fe2_query(h, fe2.FE2_Q_NDOF)
-    flen = fe2.fe2_query(h, fe2.FE2_Q_FIELD_LEN)
-    zu = torch.zeros(ndof, dtype=torch.float64, device="cuda")
-    zw = torch.zeros(flen, dtype=torch.float64, device="cuda")
-    fe2.fe2_set_state(h, zu, zw, 0.0)
+    fe2.fe2_reset_state(h, 0.0)
     fe2.fe2_newton_step(h, lam)   # warm-up: kernels loaded
     best = float("inf")
     for _ in range(reps):
-        fe2.fe2_set_state(h, zu, zw, 0.0)
+        fe2.fe2_reset_state(h, 0.0)
         fe2.fe2_set_profiling(h, True)
         fe2.fe2_newton_step(h, lam)
         prof = fe2.fe2_get_profile(h)
