@@ -797,7 +797,7 @@ int macro_solve_impl(fe2_ctx* h, double lam, double dlam, hipStream_t s) {
   const int nd = h->nen * h->dim;
   const size_t ne_rows = static_cast<size_t>(h->n_elems) * nd;
   hipLaunchKernelGGL(k_macro_elem_vec, dim3(nblk(ne_rows, 128)), dim3(128), 0, s, m, h->Phat, h->f_hat, h->u);
-  hipLaunchKernelGGL(k_macro_elem_mat, dim3(nblk(ne_rows, 64)), dim3(64), 0, s, m, h->Cbar, h->ke);
+  launch_macro_elem_mat(m, h->Cbar, h->ke, s);
   hipLaunchKernelGGL(k_macro_rows_vec, dim3(nblk(h->ndof, 128)), dim3(128), 0, s, m, h->f_true, h->f_hat, lam,
                      static_cast<double*>(nullptr), static_cast<double*>(nullptr), h->rhs);
   const size_t nband = static_cast<size_t>(h->ndof) * (h->bw + 1);

@@ -517,6 +517,70 @@ __device__ __noinline__ void elem_mat_row_element(const MacroArgs& m, const doub
 
 // a7 (part): element tangents  k = sum_g wdet B^T Cbar B (Dirac basis) or
 // the element-basis form above, one thread per (element, row).
+// Gradient operator with the element's dimension and kinematics fixed at
+// compile time (the values macro_B computes for them).
+template <int DIM, bool FINITE>
+__device__ __forceinline__ double macro_B_t(const double* __restrict__ d, int i, int c) {
+  if constexpr (FINITE) {
+    return i / DIM == c ? d[i % DIM] : 0.0;
+  } else if constexpr (DIM == 2) {
+    return i == 0 ? (c == 0 ? d[0] : 0.0) : i == 1 ? (c == 1 ? d[1] : 0.0) : (c == 0 ? d[1] : d[0]);
+  } else {
+    switch (i) {   // [11, 22, 33, 23, 13, 12]
+      case 0: return c == 0 ? d[0] : 0.0;
+      case 1: return c == 1 ? d[1] : 0.0;
+      case 2: return c == 2 ? d[2] : 0.0;
+      case 3: return c == 1 ? d[2] : (c == 2 ? d[1] : 0.0);
+      case 4: return c == 0 ? d[2] : (c == 2 ? d[0] : 0.0);
+      default: return c == 0 ? d[1] : (c == 1 ? d[0] : 0.0);
+    }
+  }
+}
+
+// Row `row` of the element matrix, Dirac basis, the sizes fixed at compile
+// time so that the row and the products stay in registers; the same sums in
+// the same order as the general path of k_macro_elem_mat.
+template <int DIM, int NEN, int NF, bool FINITE>
+__device__ __forceinline__ void elem_mat_row_dirac(const MacroArgs& m, const double* __restrict__ Cb, int e, int row,
+                                                   double* __restrict__ out) {
+  constexpr int ND = NEN * DIM;
+  double acc[ND];
+#pragma unroll
+  for (int c = 0; c < ND; ++c) acc[c] = 0.0;
+  const int ra = row / DIM, rc = row % DIM;
+  for (int g = 0; g < m.n_gp; ++g) {
+    const int b = e * m.n_gp + g;
+    const double* C = Cb + static_cast<size_t>(b) * NF * NF;
+    const double* dN = m.dNdX + static_cast<size_t>(b) * NEN * DIM;
+    double dr[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) dr[k] = dN[ra * DIM + k];
+    double tj[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) s2 += macro_B_t<DIM, FINITE>(dr, i, rc) * C[i * NF + j];
+      tj[j] = s2 * m.wdet[b];
+    }
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) {
+      double da[DIM];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) da[k] = dN[a * DIM + k];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) s2 += tj[j] * macro_B_t<DIM, FINITE>(da, j, c);
+        acc[a * DIM + c] += s2;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < ND; ++c) out[c] = acc[c];
+}
+
 __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke) {
   const int nd = m.nen * m.dim;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -545,6 +609,29 @@ __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, dou
     }
   }
   for (int c = 0; c < nd; ++c) ke[static_cast<size_t>(t) * nd + c] = acc[c];
+}
+
+template <int DIM, int NEN, int NF, bool FINITE>
+__global__ void k_macro_elem_mat_t(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke) {
+  constexpr int ND = NEN * DIM;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_elems * ND) return;
+  elem_mat_row_dirac<DIM, NEN, NF, FINITE>(m, Cb, t / ND, t % ND, ke + static_cast<size_t>(t) * ND);
+}
+
+void launch_macro_elem_mat(const MacroArgs& m, const double* Cb, double* ke, hipStream_t s) {
+  const int nd = m.nen * m.dim;
+  const dim3 grid(static_cast<unsigned>((static_cast<size_t>(m.n_elems) * nd + 63) / 64)), block(64);
+  const bool fin = m.kin == FE2_FINITE_STRAIN;
+  if (m.basis != FE2_BASIS_ELEMENT) {   // sized kernels for the 2D element types (3D hex8 would spill)
+    if (m.dim == 2 && m.nen == 4 && !fin && m.nF == 3)
+      { hipLaunchKernelGGL((k_macro_elem_mat_t<2, 4, 3, false>), grid, block, 0, s, m, Cb, ke); return; }
+    if (m.dim == 2 && m.nen == 4 && fin && m.nF == 4)
+      { hipLaunchKernelGGL((k_macro_elem_mat_t<2, 4, 4, true>), grid, block, 0, s, m, Cb, ke); return; }
+    if (m.dim == 2 && m.nen == 9 && !fin && m.nF == 3)
+      { hipLaunchKernelGGL((k_macro_elem_mat_t<2, 9, 3, false>), grid, block, 0, s, m, Cb, ke); return; }
+  }
+  hipLaunchKernelGGL(k_macro_elem_mat, grid, block, 0, s, m, Cb, ke);
 }
 
 // Row-wise residual gather: R_true = F_int - lam f_ext, F_int, and the

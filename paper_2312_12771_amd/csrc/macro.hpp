@@ -40,6 +40,9 @@ __global__ void k_macro_grad(MacroArgs m, const double* __restrict__ u, double* 
 __global__ void k_macro_elem_vec(MacroArgs m, const double* __restrict__ P, double* __restrict__ f,
                                  const double* __restrict__ u);
 __global__ void k_macro_elem_mat(MacroArgs m, const double* __restrict__ Cb, double* __restrict__ ke);
+// the element matrices (a7): a sized kernel for the element types in use,
+// the general one otherwise
+void launch_macro_elem_mat(const MacroArgs& m, const double* Cb, double* ke, hipStream_t s);
 __global__ void k_macro_rows_vec(MacroArgs m, const double* __restrict__ f_true,
                                  const double* __restrict__ f_hat, double lam,
                                  double* __restrict__ r_true, double* __restrict__ f_int,
