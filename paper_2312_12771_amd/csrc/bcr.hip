@@ -104,9 +104,12 @@ __global__ void k_bcr_copy_out(const double* __restrict__ F, int n, double* __re
 // block fits in LDS (tile-packed 16x16 column-major tiles) it is factored
 // there and written back once; for larger blocks the first steps run in
 // place in global memory until the trailing triangle fits, which is then
-// factored in LDS.  Wave 0 factors the diagonal tile and inverts it (lane r holds row
-// r; wave-synchronous exchange through LDS); all threads form the panel below
-// with the inverse and apply the trailing update in 4x4 register tiles.
+// factored in LDS.  Wave 0 factors the diagonal tile and inverts it (the tile
+// in its registers, exchanges between lanes); all waves form the panel below
+// with the inverse and apply the trailing update in 16x16 MFMA tiles.  With
+// lookahead: during the trailing update of step p wave 0 updates diagonal
+// tile p + 1 first and factors it while the other waves update the rest, so
+// the diagonal factor leaves the critical path and a step needs two barriers.
 constexpr int PO_WG = 1024;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -136,71 +139,84 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
   return a;
 }
 
+// Factor diagonal tile p in place and write its inverse to s_inv; wave 0
+// only.  A pivot that is not positive sets *s_fail and info (the caller
+// checks *s_fail after its next barrier).
+template <class M>
+__device__ __forceinline__ void potrf_diag(const M& A, int p, int col0, double* s_inv, int* s_fail,
+                                           int* __restrict__ info) {
+  const int ld = A.ld;
+  const int tid = threadIdx.x;
+  // The diagonal tile in the registers of one wave: lane l holds column
+  // s = l % 16, rows 4 g .. 4 g + 3 (g = l / 16), read from the lower
+  // triangle (the upper entries mirrored).  Right-looking Cholesky fused
+  // with the forward substitution L X = I that gives invL_pp: step c
+  // takes the pivot, the scaled column c (entries moved between lanes by
+  // ds_bpermute), the rank-one update of the trailing entries and the
+  // elimination of row c in X.
+  const int ln = tid, s = ln & 15, g = ln >> 4;
+  double* Tpp = A.tile(p, p);
+  double t4[4], x4[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = 4 * g + t;
+    t4[t] = r >= s ? Tpp[s * ld + r] : Tpp[r * ld + s];
+    x4[t] = (r == s) ? 1.0 : 0.0;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < BT; ++c) {
+    const int gc = c >> 2, tc = c & 3;
+    double piv = lane_read(t4[tc], c + 16 * gc);
+    if (!(piv > 0.0) && !bad) {   // uniform: every lane read the same pivot
+      bad = true;
+      if (ln == 0) {
+        *s_fail = 1;
+        atomicCAS(info, 0, col0 + p * BT + c + 1);
+      }
+    }
+    if (bad) piv = 1.0;   // the rest of the tile runs on (fully unrolled loop) and is discarded
+    const double rd = rsqrt(piv), sd = piv * rd;
+    // A[c][s] (= A[s][c]) from lane (s, c / 4); A[r][c] of own rows from lane (c, g)
+    const double lsc = lane_take(t4[tc], s + 16 * gc) * rd;
+    const double xc = lane_take(x4[tc], s + 16 * gc) * rd;
+    double lrc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lrc[t] = lane_take(t4[t], c + 16 * g) * rd;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 4 * g + t;
+      if (r > c && s > c) t4[t] = fma(-lrc[t], lsc, t4[t]);
+      if (r > c) x4[t] = fma(-lrc[t], xc, x4[t]);
+      if (s == c) t4[t] = (r == c) ? sd : (r > c ? lrc[t] : t4[t]);   // column c of L
+      if (r == c) x4[t] = xc;
+    }
+  }
+  if (!bad) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 4 * g + t;
+      if (r >= s) Tpp[s * ld + r] = t4[t];
+      s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
+    }
+  }
+}
+
 // Returns false when a pivot is not positive (info set, every thread returns).
+// diag_done: tile p_begin was already factored (and s_inv holds its inverse)
+// by the lookahead of an earlier call.
 template <class M>
 __device__ __forceinline__ bool potrf_core(const M& A, double* __restrict__ Ij, int nt, int p_begin, int p_end,
                                            int col0, double* s_panel, double* s_inv, int* s_fail,
-                                           int* __restrict__ info) {
+                                           int* __restrict__ info, bool diag_done) {
   const int tid = threadIdx.x;
   const int ld = A.ld;
-  for (int p = p_begin; p < p_end; ++p) {
-    if (tid < 64) {
-      // The diagonal tile in the registers of one wave: lane l holds column
-      // s = l % 16, rows 4 g .. 4 g + 3 (g = l / 16), read from the lower
-      // triangle (the upper entries mirrored).  Right-looking Cholesky fused
-      // with the forward substitution L X = I that gives invL_pp: step c
-      // takes the pivot, the scaled column c (entries moved between lanes by
-      // ds_bpermute), the rank-one update of the trailing entries and the
-      // elimination of row c in X.
-      const int ln = tid, s = ln & 15, g = ln >> 4;
-      double* Tpp = A.tile(p, p);
-      double t4[4], x4[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = 4 * g + t;
-        t4[t] = r >= s ? Tpp[s * ld + r] : Tpp[r * ld + s];
-        x4[t] = (r == s) ? 1.0 : 0.0;
-      }
-      bool bad = false;
-#pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        const int gc = c >> 2, tc = c & 3;
-        double piv = lane_read(t4[tc], c + 16 * gc);
-        if (!(piv > 0.0) && !bad) {   // uniform: every lane read the same pivot
-          bad = true;
-          if (ln == 0) {
-            *s_fail = 1;
-            atomicCAS(info, 0, col0 + p * BT + c + 1);
-          }
-        }
-        if (bad) piv = 1.0;   // the rest of the tile runs on (fully unrolled loop) and is discarded
-        const double rd = rsqrt(piv), sd = piv * rd;
-        // A[c][s] (= A[s][c]) from lane (s, c / 4); A[r][c] of own rows from lane (c, g)
-        const double lsc = lane_take(t4[tc], s + 16 * gc) * rd;
-        const double xc = lane_take(x4[tc], s + 16 * gc) * rd;
-        double lrc[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) lrc[t] = lane_take(t4[t], c + 16 * g) * rd;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = 4 * g + t;
-          if (r > c && s > c) t4[t] = fma(-lrc[t], lsc, t4[t]);
-          if (r > c) x4[t] = fma(-lrc[t], xc, x4[t]);
-          if (s == c) t4[t] = (r == c) ? sd : (r > c ? lrc[t] : t4[t]);   // column c of L
-          if (r == c) x4[t] = xc;
-        }
-      }
-      if (!bad) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = 4 * g + t;
-          if (r >= s) Tpp[s * ld + r] = t4[t];
-          s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
-        }
-      }
-    }
+  if (!diag_done && p_begin < p_end) {
+    if (tid < 64) potrf_diag(A, p_begin, col0, s_inv, s_fail, info);
     __syncthreads();
     if (*s_fail) return false;
+  }
+  for (int p = p_begin; p < p_end; ++p) {
     // the inverse tile goes out after the barrier (its stores complete
     // during the panel phase instead of delaying wave 0)
     static_assert(PO_WG >= BT * BT && PO_WG % (BT * BT) == 0, "one inverse entry per thread");
@@ -239,7 +255,7 @@ __device__ __forceinline__ bool potrf_core(const M& A, double* __restrict__ Ij, 
     const int ntiles = m * (m + 1) / 2;
     const int wv = tid >> 6, ln = tid & 63;
     const int lr = ln & 15, lk = ln >> 4;
-    for (int q = wv; q < ntiles; q += PO_WG / 64) {
+    auto update = [&](int q) {
       const int ta = tri_row(q), tb = q - ta * (ta + 1) / 2;
       const double* pa = s_panel + (ta * BT + lr) * (BT + 1) + lk;
       const double* pb = s_panel + (tb * BT + lr) * (BT + 1) + lk;
@@ -249,8 +265,20 @@ __device__ __forceinline__ bool potrf_core(const M& A, double* __restrict__ Ij, 
       double* Tab = A.tile(p + 1 + ta, p + 1 + tb);
 #pragma unroll
       for (int j = 0; j < 4; ++j) Tab[lr * ld + lk + 4 * j] -= acc[j];
+    };
+    // lookahead: wave 0 updates the next diagonal tile (q = 0) and factors
+    // it while the other waves update the rest of the trailing triangle
+    if (wv == 0) {
+      if (m > 0) {
+        update(0);
+        __threadfence_block();   // the tile's new entries, written by other lanes, before the wave reads them
+        potrf_diag(A, p + 1, col0, s_inv, s_fail, info);
+      }
+    } else {
+      for (int q = wv; q < ntiles; q += PO_WG / 64 - 1) update(q);
     }
     __syncthreads();
+    if (*s_fail) return false;
   }
   return true;
 }
@@ -282,7 +310,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     if (p0 > 0) {
       __syncthreads();
       const GlobalTiles G{Dj, bs};
-      if (!potrf_core(G, Ij, nt, 0, p0, j * bs, s_panel, s_inv, &s_fail, info)) return;
+      if (!potrf_core(G, Ij, nt, 0, p0, j * bs, s_panel, s_inv, &s_fail, info, false)) return;
     }
     double* s_tiles = smem + bs * (BT + 1);
     const int m = nt - p0;
@@ -311,7 +339,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     }
     __syncthreads();
     const LdsTiles A{s_tiles, p0};
-    if (!potrf_core(A, Ij, nt, p0, nt, j * bs, s_panel, s_inv, &s_fail, info)) return;
+    if (!potrf_core(A, Ij, nt, p0, nt, j * bs, s_panel, s_inv, &s_fail, info, p0 > 0)) return;
 #pragma unroll 2
     for (int q = tid / (BT * BT); q < ntri; q += TPP) {
       const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
@@ -320,7 +348,7 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
   } else {
     __syncthreads();
     const GlobalTiles A{Dj, bs};
-    potrf_core(A, Ij, nt, 0, nt, j * bs, s_panel, s_inv, &s_fail, info);
+    potrf_core(A, Ij, nt, 0, nt, j * bs, s_panel, s_inv, &s_fail, info, false);
   }
 }
 
