@@ -54,12 +54,6 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
-__device__ __forceinline__ double lane_take(double v, int src) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u & 0xffffffffu));
-  const unsigned hi = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u >> 32));
-  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
-}
 
 // -- extraction of the blocks from lower band storage ------------------------
 __global__ void k_bcr_extract(const double* __restrict__ band, int n, int bw, int bs, int nb,
@@ -139,22 +133,72 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
   return a;
 }
 
+// Cross-lane moves of the diagonal factor, register to register (no LDS
+// trip).  Lanes form four rows of 16; lane (s, g) = s + 16 g.
+// From lane (N, g) of the same row: DPP row_newbcast.
+template <int N>
+__device__ __forceinline__ double from_row_lane(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u), 0x150 + N, 0xf, 0xf, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u >> 32), 0x150 + N, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+// From lane (s, R) of row R, same position: the 16-lane swap copies the even
+// rows over the odd ones (or the odd over the even), the 32-lane swap then
+// copies one half over the other.
+template <int R>
+__device__ __forceinline__ unsigned from_row32(unsigned v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const unsigned e = (R & 1) ? a[1] : a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(e, e, false, false);
+  return (R & 2) ? b[1] : b[0];
+}
+template <int R>
+__device__ __forceinline__ double from_row(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = from_row32<R>(static_cast<unsigned>(u)), hi = from_row32<R>(static_cast<unsigned>(u >> 32));
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// Column step C of the diagonal factor (below): pivot, scaled column C of L,
+// rank-one update of the trailing entries, elimination of row C in X.  A
+// pivot that is not positive records C in fail_c (uniform); from then on the
+// pivots are taken as 1 and the tile is discarded.
+template <int C>
+__device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], int s, int g, int& fail_c) {
+  constexpr int GC = C >> 2, TC = C & 3;
+  double piv = lane_read(t4[TC], C + 16 * GC);
+  if (!(piv > 0.0) && fail_c < 0) fail_c = C;
+  if (fail_c >= 0) piv = 1.0;
+  const double rd = rsqrt(piv), sd = piv * rd;
+  // A[C][s] (= A[s][C]) and X[C][s] from lane (s, C / 4); A[r][C] of own rows from lane (C, g)
+  const double lsc = from_row<GC>(t4[TC]) * rd;
+  const double xc = from_row<GC>(x4[TC]) * rd;
+  double lrc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) lrc[t] = from_row_lane<C>(t4[t]) * rd;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = 4 * g + t;
+    if (r > C && s > C) t4[t] = fma(-lrc[t], lsc, t4[t]);
+    if (r > C) x4[t] = fma(-lrc[t], xc, x4[t]);
+    if (s == C) t4[t] = (r == C) ? sd : (r > C ? lrc[t] : t4[t]);   // column C of L
+    if (r == C) x4[t] = xc;
+  }
+  if constexpr (C + 1 < BT) diag_cols<C + 1>(t4, x4, s, g, fail_c);
+}
+
 // Factor diagonal tile p in place and write its inverse to s_inv; wave 0
-// only.  A pivot that is not positive sets *s_fail and info (the caller
-// checks *s_fail after its next barrier).
+// only.  The tile sits in the registers of the wave: lane (s, g) holds
+// column s, rows 4 g .. 4 g + 3, read from the lower triangle (the upper
+// entries mirrored).  Right-looking Cholesky fused with the forward
+// substitution L X = I that gives invL_pp.  A pivot that is not positive sets
+// *s_fail and info (the caller checks *s_fail after its next barrier).
 template <class M>
 __device__ __forceinline__ void potrf_diag(const M& A, int p, int col0, double* s_inv, int* s_fail,
                                            int* __restrict__ info) {
   const int ld = A.ld;
-  const int tid = threadIdx.x;
-  // The diagonal tile in the registers of one wave: lane l holds column
-  // s = l % 16, rows 4 g .. 4 g + 3 (g = l / 16), read from the lower
-  // triangle (the upper entries mirrored).  Right-looking Cholesky fused
-  // with the forward substitution L X = I that gives invL_pp: step c
-  // takes the pivot, the scaled column c (entries moved between lanes by
-  // ds_bpermute), the rank-one update of the trailing entries and the
-  // elimination of row c in X.
-  const int ln = tid, s = ln & 15, g = ln >> 4;
+  const int ln = threadIdx.x, s = ln & 15, g = ln >> 4;
   double* Tpp = A.tile(p, p);
   double t4[4], x4[4];
 #pragma unroll
@@ -163,42 +207,20 @@ __device__ __forceinline__ void potrf_diag(const M& A, int p, int col0, double* 
     t4[t] = r >= s ? Tpp[s * ld + r] : Tpp[r * ld + s];
     x4[t] = (r == s) ? 1.0 : 0.0;
   }
-  bool bad = false;
-#pragma unroll
-  for (int c = 0; c < BT; ++c) {
-    const int gc = c >> 2, tc = c & 3;
-    double piv = lane_read(t4[tc], c + 16 * gc);
-    if (!(piv > 0.0) && !bad) {   // uniform: every lane read the same pivot
-      bad = true;
-      if (ln == 0) {
-        *s_fail = 1;
-        atomicCAS(info, 0, col0 + p * BT + c + 1);
-      }
+  int fail_c = -1;
+  diag_cols<0>(t4, x4, s, g, fail_c);
+  if (fail_c >= 0) {
+    if (ln == 0) {
+      *s_fail = 1;
+      atomicCAS(info, 0, col0 + p * BT + fail_c + 1);
     }
-    if (bad) piv = 1.0;   // the rest of the tile runs on (fully unrolled loop) and is discarded
-    const double rd = rsqrt(piv), sd = piv * rd;
-    // A[c][s] (= A[s][c]) from lane (s, c / 4); A[r][c] of own rows from lane (c, g)
-    const double lsc = lane_take(t4[tc], s + 16 * gc) * rd;
-    const double xc = lane_take(x4[tc], s + 16 * gc) * rd;
-    double lrc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) lrc[t] = lane_take(t4[t], c + 16 * g) * rd;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = 4 * g + t;
-      if (r > c && s > c) t4[t] = fma(-lrc[t], lsc, t4[t]);
-      if (r > c) x4[t] = fma(-lrc[t], xc, x4[t]);
-      if (s == c) t4[t] = (r == c) ? sd : (r > c ? lrc[t] : t4[t]);   // column c of L
-      if (r == c) x4[t] = xc;
-    }
+    return;
   }
-  if (!bad) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = 4 * g + t;
-      if (r >= s) Tpp[s * ld + r] = t4[t];
-      s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
-    }
+  for (int t = 0; t < 4; ++t) {
+    const int r = 4 * g + t;
+    if (r >= s) Tpp[s * ld + r] = t4[t];
+    s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
   }
 }
 
