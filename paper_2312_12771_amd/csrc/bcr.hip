@@ -143,48 +143,49 @@ __device__ __forceinline__ double from_row_lane(double v) {
   const unsigned hi = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u >> 32), 0x150 + N, 0xf, 0xf, false);
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
-// From lane (s, R) of row R, same position: the 16-lane swap copies the even
-// rows over the odd ones (or the odd over the even), the 32-lane swap then
-// copies one half over the other.
-template <int R>
-__device__ __forceinline__ unsigned from_row32(unsigned v) {
-  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  const unsigned e = (R & 1) ? a[1] : a[0];
-  const auto b = __builtin_amdgcn_permlane32_swap(e, e, false, false);
-  return (R & 2) ? b[1] : b[0];
-}
-template <int R>
-__device__ __forceinline__ double from_row(double v) {
+// From lane src, any row: ds_bpermute (through the LDS crossbar; its latency
+// overlaps the pivot's reciprocal square root).
+__device__ __forceinline__ double lane_take(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = from_row32<R>(static_cast<unsigned>(u)), hi = from_row32<R>(static_cast<unsigned>(u >> 32));
+  const unsigned lo = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_ds_bpermute(4 * src, static_cast<int>(u >> 32));
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
 // Column step C of the diagonal factor (below): pivot, scaled column C of L,
 // rank-one update of the trailing entries, elimination of row C in X.  A
 // pivot that is not positive records C in fail_c (uniform); from then on the
-// pivots are taken as 1 and the tile is discarded.
+// pivots are taken as 1 and the tile is discarded.  Each wave64 VALU
+// instruction takes four cycles on the 16-lane SIMD and the steps are
+// serial, so the step is written for few instructions: the multipliers are
+// masked once (an update with a zero multiplier leaves the entry as it is),
+// and lane column C is scaled whole, since its entries above the diagonal are
+// not read after this step.
 template <int C>
 __device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], int s, int g, int& fail_c) {
   constexpr int GC = C >> 2, TC = C & 3;
   double piv = lane_read(t4[TC], C + 16 * GC);
   if (!(piv > 0.0) && fail_c < 0) fail_c = C;
   if (fail_c >= 0) piv = 1.0;
-  const double rd = rsqrt(piv), sd = piv * rd;
   // A[C][s] (= A[s][C]) and X[C][s] from lane (s, C / 4); A[r][C] of own rows from lane (C, g)
-  const double lsc = from_row<GC>(t4[TC]) * rd;
-  const double xc = from_row<GC>(x4[TC]) * rd;
-  double lrc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) lrc[t] = from_row_lane<C>(t4[t]) * rd;
+  const double asc = lane_take(t4[TC], s + 16 * GC);
+  const double xsc = lane_take(x4[TC], s + 16 * GC);
+  const double rd = rsqrt(piv);
+  const double lsc = s > C ? asc * rd : 0.0;
+  const double xc = xsc * rd;
+  const bool g_gt = g > GC, g_ge = g >= GC;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int r = 4 * g + t;
-    if (r > C && s > C) t4[t] = fma(-lrc[t], lsc, t4[t]);
-    if (r > C) x4[t] = fma(-lrc[t], xc, x4[t]);
-    if (s == C) t4[t] = (r == C) ? sd : (r > C ? lrc[t] : t4[t]);   // column C of L
-    if (r == C) x4[t] = xc;
+    const bool r_gt = t > TC ? g_ge : g_gt;   // row 4 g + t below row C
+    const double a_rc = from_row_lane<C>(t4[t]);   // every lane runs the move; its source row shares r_gt
+    const double lrc = r_gt ? a_rc * rd : 0.0;
+    t4[t] = fma(-lrc, lsc, t4[t]);
+    x4[t] = fma(-lrc, xc, x4[t]);
   }
+  const double cs = s == C ? rd : 1.0;   // column C of L: the column times rd (its diagonal piv * rd)
+#pragma unroll
+  for (int t = 0; t < 4; ++t) t4[t] *= cs;
+  if (g == GC) x4[TC] = xc;
   if constexpr (C + 1 < BT) diag_cols<C + 1>(t4, x4, s, g, fail_c);
 }
 
