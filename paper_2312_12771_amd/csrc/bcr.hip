@@ -338,31 +338,48 @@ __global__ void __launch_bounds__(PO_WG) k_bcr_potrf(double* __restrict__ D, dou
     double* s_tiles = smem + bs * (BT + 1);
     const int m = nt - p0;
     const int ntri = m * (m + 1) / 2;
-    // one element of a tile per thread, PO_WG / 256 tiles per pass
+    // With the whole triangle resident, wave 0 copies tile 0 and factors it
+    // while waves 4.. load the other tiles (the factor of the first tile
+    // then overlaps the load instead of following it).
+    const bool early = p0 == 0;
+    if (early && tid < 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e2 = tid + 64 * u, cc = e2 >> 4, rr = e2 & 15;
+        s_tiles[cc * (BT + 1) + rr] = Dj[static_cast<size_t>(cc) * bs + rr];
+      }
+      __threadfence_block();
+      potrf_diag(LdsTiles{s_tiles, 0}, 0, j * bs, s_inv, &s_fail, info);
+    }
+    // one element of a tile per thread, one tile per 256 threads and pass
     constexpr int TPP = PO_WG / (BT * BT);
     const int el = tid % (BT * BT), c = el >> 4, r = el & 15;
+    const int grp = tid / (BT * BT) - (early ? 1 : 0), ngrp = TPP - (early ? 1 : 0), q_first = early ? 1 : 0;
     // the loads of a batch of tiles are all issued before the first is
     // stored, so their latencies overlap
     constexpr int LB = 16;
-    for (int q0 = tid / (BT * BT); q0 < ntri; q0 += LB * TPP) {
-      double v[LB];
+    if (grp >= 0) {
+      for (int q0 = q_first + grp; q0 < ntri; q0 += LB * ngrp) {
+        double v[LB];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int q = q0 + u * TPP;
-        if (q < ntri) {
-          const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
-          v[u] = Dj[static_cast<size_t>((tk + p0) * BT + c) * bs + (ti + p0) * BT + r];
+        for (int u = 0; u < LB; ++u) {
+          const int q = q0 + u * ngrp;
+          if (q < ntri) {
+            const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
+            v[u] = Dj[static_cast<size_t>((tk + p0) * BT + c) * bs + (ti + p0) * BT + r];
+          }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int q = q0 + u * TPP;
-        if (q < ntri) s_tiles[q * LDS_TILE + c * (BT + 1) + r] = v[u];
+        for (int u = 0; u < LB; ++u) {
+          const int q = q0 + u * ngrp;
+          if (q < ntri) s_tiles[q * LDS_TILE + c * (BT + 1) + r] = v[u];
+        }
       }
     }
     __syncthreads();
+    if (s_fail) return;
     const LdsTiles A{s_tiles, p0};
-    if (!potrf_core(A, Ij, nt, p0, nt, j * bs, s_panel, s_inv, &s_fail, info, p0 > 0)) return;
+    if (!potrf_core(A, Ij, nt, p0, nt, j * bs, s_panel, s_inv, &s_fail, info, true)) return;
 #pragma unroll 2
     for (int q = tid / (BT * BT); q < ntri; q += TPP) {
       const int ti = tri_row(q), tk = q - ti * (ti + 1) / 2;
