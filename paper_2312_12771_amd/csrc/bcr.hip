@@ -139,8 +139,9 @@ __device__ __forceinline__ int tri_row(int q) {   // largest a with a(a+1)/2 <= 
 template <int N>
 __device__ __forceinline__ double from_row_lane(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u), 0x150 + N, 0xf, 0xf, false);
-  const unsigned hi = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u >> 32), 0x150 + N, 0xf, 0xf, false);
+  // every lane of every row is a valid source: no old value to keep
+  const unsigned lo = __builtin_amdgcn_mov_dpp(static_cast<int>(u & 0xffffffffu), 0x150 + N, 0xf, 0xf, true);
+  const unsigned hi = __builtin_amdgcn_mov_dpp(static_cast<int>(u >> 32), 0x150 + N, 0xf, 0xf, true);
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 // From lane src, any row: ds_bpermute (through the LDS crossbar; its latency
@@ -173,12 +174,11 @@ __device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], int 
   const double rd = rsqrt(piv);
   const double lsc = s > C ? asc * rd : 0.0;
   const double xc = xsc * rd;
-  const bool g_gt = g > GC, g_ge = g >= GC;
+  // rd masked to the rows below row C: for t > C % 4 those of g >= C / 4, else g > C / 4
+  const double rd_gt = g > GC ? rd : 0.0, rd_ge = g >= GC ? rd : 0.0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const bool r_gt = t > TC ? g_ge : g_gt;   // row 4 g + t below row C
-    const double a_rc = from_row_lane<C>(t4[t]);   // every lane runs the move; its source row shares r_gt
-    const double lrc = r_gt ? a_rc * rd : 0.0;
+    const double lrc = from_row_lane<C>(t4[t]) * (t > TC ? rd_ge : rd_gt);
     t4[t] = fma(-lrc, lsc, t4[t]);
     x4[t] = fma(-lrc, xc, x4[t]);
   }
