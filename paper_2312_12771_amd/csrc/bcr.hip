@@ -453,6 +453,12 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
   }
   wave_sync();
   for (int i = i0; i < nt; ++i) {
+    // invL_ii (column-major: entry (r, c) at Ij[i*256 + c*16 + r]) depends on
+    // nothing computed here: its loads go out first and land during the
+    // product below
+    double il[BT / 4];
+#pragma unroll
+    for (int kk = 0; kk < BT; kk += 4) il[kk / 4] = Ij[i * BT * BT + (kk + lk) * BT + lr];
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     // sum_{k<i} L_ik X_k: L is column-major (entry (r, k) at Lj[k * bs + r])
     const double* lcol = Lj + static_cast<size_t>(lk) * bs + i * BT + lr;
@@ -475,12 +481,11 @@ __global__ void __launch_bounds__(TR_WG) k_bcr_trsm(const double* __restrict__ D
       s_s[rr * BT + lr] = s_x[(i * BT + rr) * BT + lr] - acc[q];
     }
     wave_sync();
-    // X_i = invL_ii S_i (invL_ii column-major: entry (r, c) at Ij[i*256 + c*16 + r])
+    // X_i = invL_ii S_i
     v4d x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < BT; kk += 4)
-      x = __builtin_amdgcn_mfma_f64_16x16x4f64(Ij[i * BT * BT + (kk + lk) * BT + lr], s_s[(kk + lk) * BT + lr], x, 0,
-                                               0, 0);
+      x = __builtin_amdgcn_mfma_f64_16x16x4f64(il[kk / 4], s_s[(kk + lk) * BT + lr], x, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) s_x[(i * BT + lk + 4 * q) * BT + lr] = x[q];
     wave_sync();
