@@ -160,10 +160,11 @@ __device__ __forceinline__ double lane_take(double v, int src) {
 // instruction takes four cycles on the 16-lane SIMD and the steps are
 // serial, so the step is written for few instructions: the multipliers are
 // masked once (an update with a zero multiplier leaves the entry as it is),
-// and lane column C is scaled whole, since its entries above the diagonal are
-// not read after this step.
+// and lane column C keeps its entries unscaled: nothing changes or reads them
+// after this step, so the factor's write-back scales them by the rd kept in
+// dsc (the same products).
 template <int C>
-__device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], int s, int g, int& fail_c) {
+__device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], double& dsc, int s, int g, int& fail_c) {
   constexpr int GC = C >> 2, TC = C & 3;
   double piv = lane_read(t4[TC], C + 16 * GC);
   if (!(piv > 0.0) && fail_c < 0) fail_c = C;
@@ -182,11 +183,9 @@ __device__ __forceinline__ void diag_cols(double (&t4)[4], double (&x4)[4], int 
     t4[t] = fma(-lrc, lsc, t4[t]);
     x4[t] = fma(-lrc, xc, x4[t]);
   }
-  const double cs = s == C ? rd : 1.0;   // column C of L: the column times rd (its diagonal piv * rd)
-#pragma unroll
-  for (int t = 0; t < 4; ++t) t4[t] *= cs;
+  if (s == C) dsc = rd;   // column C of L: the column times rd (its diagonal piv * rd)
   if (g == GC) x4[TC] = xc;
-  if constexpr (C + 1 < BT) diag_cols<C + 1>(t4, x4, s, g, fail_c);
+  if constexpr (C + 1 < BT) diag_cols<C + 1>(t4, x4, dsc, s, g, fail_c);
 }
 
 // Factor diagonal tile p in place and write its inverse to s_inv; wave 0
@@ -209,7 +208,8 @@ __device__ __forceinline__ void potrf_diag(const M& A, int p, int col0, double* 
     x4[t] = (r == s) ? 1.0 : 0.0;
   }
   int fail_c = -1;
-  diag_cols<0>(t4, x4, s, g, fail_c);
+  double dsc = 1.0;
+  diag_cols<0>(t4, x4, dsc, s, g, fail_c);
   if (fail_c >= 0) {
     if (ln == 0) {
       *s_fail = 1;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void potrf_diag(const M& A, int p, int col0, double* 
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int r = 4 * g + t;
-    if (r >= s) Tpp[s * ld + r] = t4[t];
+    if (r >= s) Tpp[s * ld + r] = t4[t] * dsc;
     s_inv[s * BT + r] = x4[t];   // column-major; zero above the diagonal
   }
 }
